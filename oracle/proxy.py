@@ -1,0 +1,181 @@
+"""Frustum culling and the confidence-interval screen proxy (float64).
+
+TEST INFRASTRUCTURE: see the package docstring.
+
+Sec. 3.3 (Eqs. 16-21) and App. D: a Gaussian is rasterised as the oriented
+bounding rectangle of the screen-space ellipse on which its isolated opacity
+1 - exp(-tau_bar) equals the confidence level c, with tau_bar replaced by the
+erf-free form and Sigma approximated along the view vector.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from .geometry import DT, camera_matrices, quat_to_rot
+
+
+@dataclass
+class Proxy:
+    mean2d: torch.Tensor     # [n,2] ellipse centre (pixels)
+    axes: torch.Tensor       # [n,2,2] rows: unit eigenvectors e_1, e_2 of Sigma_2d
+    half: torch.Tensor       # [n,2] half side lengths sqrt(lambda_k)
+    valid: torch.Tensor      # [n] bool: not culled and a real ellipse
+    ambiguous: torch.Tensor  # [n] bool: a cull/ellipse decision is within rounding
+    kappa: torch.Tensor      # [n]
+    quad: torch.Tensor       # [n] mean^T A mean (camera frame)
+
+
+def screen_proxy(scene_t, cam, conf_c: float) -> Proxy:
+    """Per-Gaussian culling and proxy.
+
+    Culling (Sec. 3.3): the bounding sphere (mean, r = max diag S) is tested
+    against the near plane z = t_n and the four side planes; the centre must
+    also lie beyond the near plane, and the proxy must be a real ellipse
+    (App. D: 0 < kappa < mean^T A mean, W_2x2 negative definite).
+
+    Proxy (Eqs. 17-21, App. D), in camera coordinates with A = Sigma^-1:
+        C     = -log(1 - c) sqrt(u^T A u) / sqrt(2 pi),  u = mean / |mean|
+        kappa = 2 (log C - log w) + mean^T A mean
+        m = K^-T A mean,  M = K^-T A K^-1,  W = m m^T - kappa M
+        mean2d = -W22^-1 w21,  Sigma2d = (mean2d^T W22 mean2d - w33) W22^-1
+    and the rectangle spans sqrt(lambda_k) e_k over the eigenpairs of Sigma2d.
+    """
+    r_wc, t_wc, _ = camera_matrices(cam)
+    means, scales, quats, dens = (scene_t[k].detach() for k in
+                                  ("means", "scales", "quats", "densities"))
+    mu_c = means @ r_wc.T + t_wc
+    rot_c = r_wc @ quat_to_rot(quats)
+    a = rot_c @ torch.diag_embed(1.0 / scales ** 2) @ rot_c.transpose(-1, -2)
+
+    # --- culling with the bounding sphere -----------------------------------
+    radius = scales.max(dim=-1).values
+    w_img, h_img = cam.width, cam.height
+    normals = torch.tensor([[cam.fx, 0.0, cam.cx], [-cam.fx, 0.0, w_img - cam.cx],
+                            [0.0, cam.fy, cam.cy], [0.0, -cam.fy, h_img - cam.cy]], dtype=DT)
+    normals = normals / normals.norm(dim=-1, keepdim=True)
+    side = mu_c @ normals.T + radius[:, None]           # >= 0: not wholly outside
+    near_sphere = mu_c[:, 2] + radius - cam.t_near       # >= 0: not wholly in front of t_n
+    near_centre = mu_c[:, 2] - cam.t_near               # > 0 required
+    in_frustum = (side >= 0).all(-1) & (near_sphere >= 0) & (near_centre > 0)
+
+    # --- confidence-interval conic -------------------------------------------
+    u = mu_c / mu_c.norm(dim=-1, keepdim=True)
+    uau = torch.einsum("ni,nij,nj->n", u, a, u)
+    big_c = -math.log(1.0 - conf_c) * torch.sqrt(uau) / math.sqrt(2.0 * math.pi)
+    quad = torch.einsum("ni,nij,nj->n", mu_c, a, mu_c)
+    kappa = 2.0 * (torch.log(big_c) - torch.log(dens)) + quad
+    kinv = torch.tensor([[1.0 / cam.fx, 0.0, -cam.cx / cam.fx],
+                         [0.0, 1.0 / cam.fy, -cam.cy / cam.fy],
+                         [0.0, 0.0, 1.0]], dtype=DT)
+    m = (kinv.T @ (a @ mu_c.unsqueeze(-1))).squeeze(-1)
+    big_m = kinv.T @ a @ kinv
+    w = m.unsqueeze(-1) * m.unsqueeze(-2) - kappa[:, None, None] * big_m
+    w22 = w[:, :2, :2]
+    w21 = w[:, :2, 2]
+    w33 = w[:, 2, 2]
+    # W22 negative definite <=> trace < 0 and det > 0
+    det22 = w22[:, 0, 0] * w22[:, 1, 1] - w22[:, 0, 1] * w22[:, 1, 0]
+    tr22 = w22[:, 0, 0] + w22[:, 1, 1]
+    ell_ok = (kappa > 0) & (kappa < quad) & (det22 > 0) & (tr22 < 0)
+    safe = torch.where(ell_ok[:, None, None], w22, -torch.eye(2, dtype=DT).expand_as(w22))
+    w22_inv = torch.linalg.inv(safe)
+    mean2d = -(w22_inv @ w21.unsqueeze(-1)).squeeze(-1)
+    s2 = torch.einsum("ni,nij,nj->n", mean2d, safe, mean2d) - w33
+    ell_ok = ell_ok & (s2 < 0)
+    sigma2d = s2[:, None, None] * w22_inv
+    sigma2d = torch.where(ell_ok[:, None, None], sigma2d, torch.eye(2, dtype=DT).expand_as(sigma2d))
+    lam, vec = torch.linalg.eigh(sigma2d)
+    half = torch.sqrt(lam.clamp_min(0.0))
+    axes = vec.transpose(-1, -2)  # rows are eigenvectors
+
+    valid = in_frustum & ell_ok
+    # decisions within float32 rounding of their threshold
+    rel = 1e-5
+    amb = ((side.abs() < rel * (mu_c.norm(dim=-1, keepdim=True) + radius[:, None])).any(-1)
+           | (near_centre.abs() < rel * (1 + mu_c.norm(dim=-1)))
+           | ((quad - kappa).abs() < 1e-3) | (kappa.abs() < 1e-3))
+    return Proxy(mean2d, axes, half, valid, amb, kappa, quad)
+
+
+def rect_margin(proxy: Proxy, gidx: torch.Tensor, px: torch.Tensor, py: torch.Tensor):
+    """Signed distance (pixels) of the pixel centre inside the oriented
+    rectangle: min_k (sqrt(lambda_k) - |(p - mean2d) . e_k|); >= 0 covers."""
+    p = torch.stack([px.to(DT) + 0.5, py.to(DT) + 0.5], dim=-1) - proxy.mean2d[gidx]
+    proj = (proxy.axes[gidx] @ p.unsqueeze(-1)).squeeze(-1).abs()
+    return (proxy.half[gidx] - proj).min(dim=-1).values
+
+
+def covering_pairs(proxy: Proxy, cam, pix_x: torch.Tensor, pix_y: torch.Tensor,
+                   margin_tol: float = 2e-3, full_coverage: bool = False,
+                   chunk: int = 1 << 22):
+    """Pairs (pixel slot, Gaussian) with the pixel centre inside the Gaussian's
+    rectangle (the proxy the paper rasterises; App. D).
+
+    ``pix_x``/``pix_y`` list the pixels to evaluate (slot = position in the
+    list). Also returns a per-slot flag for pixels where some coverage
+    decision is within ``margin_tol`` pixels of a rectangle edge or the
+    Gaussian's cull decision is within rounding (the parity protocol excludes
+    those)."""
+    n_pix = pix_x.shape[0]
+    n_g = proxy.valid.shape[0]
+    if full_coverage:
+        slot = torch.arange(n_pix).repeat_interleave(n_g)
+        gid = torch.arange(n_g).repeat(n_pix)
+        return slot, gid, torch.zeros(n_pix, dtype=torch.bool)
+    g_ok = torch.nonzero(proxy.valid | proxy.ambiguous).squeeze(-1)
+    # axis-aligned extent of each rectangle, dilated by the tolerance
+    ext = (proxy.axes[g_ok].abs() * proxy.half[g_ok][:, :, None]).sum(1) + margin_tol
+    lo = proxy.mean2d[g_ok] - ext
+    hi = proxy.mean2d[g_ok] + ext
+    # candidate pixels of each Gaussian: those in the pixel list whose centre
+    # lies in its dilated box; a dense lookup from image position to slot.
+    slot_of = torch.full((cam.height, cam.width), -1, dtype=torch.long)
+    slot_of[pix_y, pix_x] = torch.arange(n_pix)
+    x0 = torch.ceil(lo[:, 0] - 0.5).clamp(0, cam.width - 1).long()
+    x1 = torch.floor(hi[:, 0] - 0.5).clamp(-1, cam.width - 1).long()
+    y0 = torch.ceil(lo[:, 1] - 0.5).clamp(0, cam.height - 1).long()
+    y1 = torch.floor(hi[:, 1] - 0.5).clamp(-1, cam.height - 1).long()
+    nx = (x1 - x0 + 1).clamp_min(0)
+    ny = (y1 - y0 + 1).clamp_min(0)
+    cnt = nx * ny
+    slots, gids, amb_slots = [], [], []
+    # enumerate boxes in chunks of Gaussians whose total box area fits `chunk`
+    csum = torch.cumsum(cnt, 0)
+    start = 0
+    while start < g_ok.shape[0]:
+        base = csum[start - 1] if start > 0 else torch.tensor(0)
+        stop = int(torch.searchsorted(csum, base + chunk, right=True))
+        stop = max(stop, start + 1)
+        sel = torch.arange(start, stop)
+        c = cnt[sel]
+        total = int(c.sum())
+        if total > 0:
+            owner = sel.repeat_interleave(c)
+            first = torch.cumsum(c, 0) - c
+            local = torch.arange(total) - first.repeat_interleave(c)
+            xx = x0[owner] + local % nx[owner]
+            yy = y0[owner] + local // nx[owner]
+            sl = slot_of[yy, xx]
+            keep = sl >= 0
+            owner, xx, yy, sl = owner[keep], xx[keep], yy[keep], sl[keep]
+            g = g_ok[owner]
+            marg = rect_margin(proxy, g, xx, yy)
+            cov = (marg >= 0) & proxy.valid[g]
+            slots.append(sl[cov])
+            gids.append(g[cov])
+            amb = (marg.abs() < margin_tol) | (proxy.ambiguous[g] & (marg >= -margin_tol))
+            amb_slots.append(sl[amb])
+        start = stop
+    slot = torch.cat(slots) if slots else torch.zeros(0, dtype=torch.long)
+    gid = torch.cat(gids) if gids else torch.zeros(0, dtype=torch.long)
+    # order by (slot, gid)
+    order = torch.argsort(slot * n_g + gid)
+    ambiguous = torch.zeros(n_pix, dtype=torch.bool)
+    if amb_slots:
+        a = torch.cat(amb_slots)
+        ambiguous[a] = True
+    return slot[order], gid[order], ambiguous

@@ -1,0 +1,183 @@
+"""Forward pass over a set of pixels, and its gradient by float64 autograd.
+
+TEST INFRASTRUCTURE: see the package docstring.
+
+Per pixel (Sec. 3, App. B/D): the Gaussians whose proxy rectangle covers the
+pixel centre contribute their warped moments (Eqs. 10-12) to the pixel's
+moment vector; each of them is then integrated with the quadrature of Eq. 7
+against the optical depth reconstructed from those moments, and the sums of
+(r, g, b, 1)-weighted contributions are rescaled by Eq. 15.  Everything is
+additive over Gaussians, so the result does not depend on their order.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+from typing import Dict, Optional
+
+import numpy as np
+import torch
+
+from .bounds import bound_tau
+from .geometry import DT, camera_matrices, pixel_directions, quat_to_rot, ray_gaussian, sh_rgb
+from .moments import particle_moments, warp
+from .proxy import covering_pairs, screen_proxy
+from .quadrature import particle_quadrature, rescale
+
+PARAMS = ("means", "scales", "quats", "densities", "colors")
+
+
+def scene_tensors(scene, requires_grad: bool = False) -> Dict[str, torch.Tensor]:
+    """float64 leaf tensors of the scene parameters."""
+    out = {}
+    for k in PARAMS:
+        t = torch.as_tensor(np.asarray(getattr(scene, k)), dtype=DT).clone()
+        t.requires_grad_(requires_grad)
+        out[k] = t
+    return out
+
+
+@dataclass
+class PixelResult:
+    image: torch.Tensor      # [P,3]
+    s_rgb: torch.Tensor      # [P,3]  sum_i q_i rgb_i
+    opacity: torch.Tensor    # [P]    O = sum_i q_i
+    moments: torch.Tensor    # [P,K+1] in the pixel's moment variable
+    centre: torch.Tensor     # [P] warp value at the pixel's moment origin
+    scale: torch.Tensor      # [P] warp scale of the pixel's moment variable
+    ambiguous: torch.Tensor  # [P] bool (parity protocol)
+    n_pairs: int
+    pair_slot: torch.Tensor
+    pair_gid: torch.Tensor
+    pair_q: torch.Tensor
+
+
+def _standardised_basis(slot, mu, sigma, omega, t_near, n_pix):
+    """The affine moment variable y = (g_hat - centre) / scale with centre and
+    scale the mean and standard deviation of the pixel's (linearised) warped
+    density.  The bounds do not depend on this choice (an increasing affine
+    change of variable maps canonical representations onto each other); it
+    only keeps the Hankel matrix well conditioned."""
+    with torch.no_grad():
+        raw = particle_moments(mu, sigma, omega, t_near, 2, 0.0, 1.0)
+        acc = torch.zeros(n_pix, 3, dtype=DT).index_add_(0, slot, raw)
+        m0 = acc[:, 0]
+        ok = m0 > 0
+        m0s = torch.where(ok, m0, torch.ones_like(m0))
+        mean = acc[:, 1] / m0s
+        var = (acc[:, 2] / m0s - mean * mean).clamp_min(0.0)
+        scale = torch.sqrt(var)
+        scale = torch.where(ok & (scale > 0), scale, torch.ones_like(scale))
+        mean = torch.where(ok, mean, torch.zeros_like(mean))
+    return mean, scale
+
+
+def render_pixels(scene_t, scene, cam, opts, px: torch.Tensor, py: torch.Tensor,
+                  proxy=None, margin_tol: float = 2e-3) -> PixelResult:
+    """Render the listed pixels (all pairs of each listed pixel are formed, so
+    every listed pixel is complete)."""
+    n_pix = px.shape[0]
+    k_mom = opts.n_moments
+    n_half = k_mom // 2
+    t_near = cam.t_near
+    if proxy is None:
+        proxy = screen_proxy(scene_t, cam, opts.conf_c)
+    slot, gid, amb = covering_pairs(proxy, cam, px, py, margin_tol=margin_tol,
+                                    full_coverage=opts.full_coverage)
+    _, _, origin = camera_matrices(cam)
+
+    means = scene_t["means"]
+    rgb_all = sh_rgb(scene_t["colors"], scene.sh_degree, means, origin)
+    d = pixel_directions(cam, px[slot], py[slot])
+    rot = quat_to_rot(scene_t["quats"][gid])
+    mu, sigma, omega = ray_gaussian(origin, d, means[gid], rot, scene_t["scales"][gid],
+                                    scene_t["densities"][gid])
+
+    centre, scale = _standardised_basis(slot, mu, sigma, omega, t_near, n_pix)
+    mom_pair = particle_moments(mu, sigma, omega, t_near, k_mom, centre[slot], scale[slot])
+    mom = torch.zeros(n_pix, k_mom + 1, dtype=DT).index_add(0, slot, mom_pair)
+
+    n_edge = opts.n_intervals + 1
+    mom_q = mom[slot].repeat_interleave(n_edge, dim=0)
+
+    def tau_at(y):
+        tau, _, _ = bound_tau(mom_q, y.reshape(-1), n_half, opts.beta)
+        return tau.reshape(y.shape)
+
+    def warp_y(t):
+        return (warp(t, t_near) - centre[slot][:, None]) / scale[slot][:, None]
+
+    if slot.shape[0] > 0:
+        q, _, _ = particle_quadrature(mu, sigma, omega, tau_at, t_near, opts.kappa,
+                                      opts.n_intervals, warp_y)
+    else:
+        q = torch.zeros(0, dtype=DT)
+    s_rgb = torch.zeros(n_pix, 3, dtype=DT).index_add(0, slot, q[:, None] * rgb_all[gid])
+    o = torch.zeros(n_pix, dtype=DT).index_add(0, slot, q)
+    image = rescale(mom[:, 0], s_rgb, o, opts.eps, cam.background)
+    return PixelResult(image, s_rgb, o, mom, centre, scale, amb, int(slot.shape[0]),
+                       slot, gid, q)
+
+
+def _pixel_chunks(cam, px, py, max_pixels):
+    for s in range(0, px.shape[0], max_pixels):
+        yield s, px[s:s + max_pixels], py[s:s + max_pixels]
+
+
+def render_image(scene, cam, opts, pixels: Optional[np.ndarray] = None,
+                 max_pixels: int = 4096):
+    """Forward render of ``pixels`` (flat indices y * W + x; default: the
+    whole image). Returns a dict of numpy arrays: image [P,3], s_rgb [P,3],
+    opacity [P], moments [P,K+1], ambiguous [P], n_pairs."""
+    scene_t = scene_tensors(scene)
+    proxy = screen_proxy(scene_t, cam, opts.conf_c)
+    if pixels is None:
+        pixels = np.arange(cam.width * cam.height)
+    pix = torch.as_tensor(np.asarray(pixels), dtype=torch.long)
+    px_all, py_all = pix % cam.width, pix // cam.width
+    outs = {k: [] for k in ("image", "s_rgb", "opacity", "moments", "centre",
+                            "scale", "ambiguous")}
+    n_pairs = 0
+    with torch.no_grad():
+        for _, px, py in _pixel_chunks(cam, px_all, py_all, max_pixels):
+            r = render_pixels(scene_t, scene, cam, opts, px, py, proxy=proxy)
+            outs["image"].append(r.image)
+            outs["s_rgb"].append(r.s_rgb)
+            outs["opacity"].append(r.opacity)
+            outs["moments"].append(r.moments)
+            outs["centre"].append(r.centre)
+            outs["scale"].append(r.scale)
+            outs["ambiguous"].append(r.ambiguous)
+            n_pairs += r.n_pairs
+    res = {k: torch.cat(v).numpy() for k, v in outs.items()}
+    res["n_pairs"] = n_pairs
+    return res
+
+
+def render_backward(scene, cam, opts, grad_image: np.ndarray,
+                    pixels: Optional[np.ndarray] = None, max_pixels: int = 2048):
+    """Gradient of sum(grad_image * image) with respect to the scene
+    parameters (means, scales, quats, densities, colors), by float64 autograd
+    of the forward pass.  Coverage sets and each pixel's moment variable are
+    held fixed (the proxy is not differentiated, and the bounds do not depend
+    on the moment variable)."""
+    scene_t = scene_tensors(scene, requires_grad=True)
+    proxy = screen_proxy(scene_t, cam, opts.conf_c)
+    if pixels is None:
+        pixels = np.arange(cam.width * cam.height)
+    pix = torch.as_tensor(np.asarray(pixels), dtype=torch.long)
+    px_all, py_all = pix % cam.width, pix // cam.width
+    g_img = torch.as_tensor(np.asarray(grad_image), dtype=DT).reshape(-1, 3)
+    grads = {k: torch.zeros_like(v) for k, v in scene_t.items()}
+    image = []
+    for s, px, py in _pixel_chunks(cam, px_all, py_all, max_pixels):
+        r = render_pixels(scene_t, scene, cam, opts, px, py, proxy=proxy)
+        loss = (r.image * g_img[s:s + px.shape[0]]).sum()
+        gs = torch.autograd.grad(loss, [scene_t[k] for k in PARAMS], allow_unused=True)
+        for k, g in zip(PARAMS, gs):
+            if g is not None:
+                grads[k] += g
+        image.append(r.image.detach())
+    out = {k: v.numpy() for k, v in grads.items()}
+    out["image"] = torch.cat(image).numpy()
+    return out
