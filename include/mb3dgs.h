@@ -1,0 +1,149 @@
+/*
+ * mb3dgs.h -- C ABI of the MI355X (gfx950) rendering path of moment-based
+ * order-independent 3D Gaussian splatting (arXiv 2512.11800).
+ *
+ * The library renders a set of 3D Gaussians (mean, scale, rotation,
+ * non-negative density weight, colour or SH coefficients; Sec. 3.1) from one
+ * or more pinhole cameras. Per pixel it accumulates warped power moments of
+ * the optical depth in closed form (Sec. 3.2, Eqs. 10-12), reconstructs the
+ * optical depth from them with moment bounds (Sec. 3.2), integrates each
+ * covering Gaussian with the piecewise-constant quadrature of Eq. 7 (App. B)
+ * and rescales by the true opacity (Eq. 15). Gaussians are rasterised through
+ * the confidence-interval proxy of Sec. 3.3 (Eqs. 16-21, App. D).
+ * The backward pass is the two-stage adjoint of Sec. 3.3 (Eq. 22): an adjoint
+ * moment per pixel, then one reduction of per-Gaussian gradients.
+ *
+ * Conventions shared by every entry point:
+ *  - All float arrays are float32, row-major, densely packed.
+ *  - Pointers marked "device" must be device memory of the current HIP device;
+ *    "host" pointers are read during the call only.
+ *  - The caller owns and allocates every buffer; the library never allocates
+ *    or frees device memory and never writes its inputs.
+ *  - Every call is enqueued asynchronously on `stream` (a hipStream_t; NULL
+ *    is the default stream), except mb_prepare which waits for one count.
+ *  - Return value 0 (MB_OK) or a negative MB_ERR_* code; the message of the
+ *    last error of the calling thread is available from mb_last_error().
+ *    No exception or abort crosses the ABI.
+ *  - Calls on distinct workspaces may run concurrently.
+ */
+#ifndef MB3DGS_H
+#define MB3DGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MB_OK 0
+#define MB_ERR_ARG (-1)          /* invalid argument (null pointer, bad size) */
+#define MB_ERR_UNSUPPORTED (-2)  /* unsupported option (K, N, SH degree, ...) */
+#define MB_ERR_WORKSPACE (-3)    /* workspace too small for this call         */
+#define MB_ERR_HIP (-4)          /* a HIP runtime call or kernel launch failed */
+
+#define MB_MAX_CAMERAS 16
+#define MB_SAVED_FLOATS_PER_PIXEL 8
+
+/* Gaussians (Sec. 3.1). All pointers device, n >= 0.
+ *  means     [n,3]  world-space mean mu_i
+ *  scales    [n,3]  linear per-axis scales (> 0), S = diag(scales)
+ *  quats     [n,4]  rotation quaternion (w, x, y, z); normalised inside, and
+ *                   gradients include the normalisation
+ *  densities [n]    density weight w_i >= 0 (the caller applies softplus)
+ *  colors    [n,3] RGB when sh_degree = -1, else [n,(sh_degree+1)^2,3] real
+ *                   SH coefficients; emission = max(0, sum_lm f_lm Y_lm(v) + 1/2)
+ *                   with v = normalize(mean - camera origin). */
+typedef struct mb_gaussians {
+  int32_t n;
+  int32_t sh_degree; /* -1 (RGB) or 0..3 */
+  const float *means, *scales, *quats, *densities, *colors;
+} mb_gaussians;
+
+/* Pinhole camera. world_to_cam = [R | t] row-major 3x4, x_cam = R x + t,
+ * OpenCV axes (x right, y down, z forward). Pixel (x, y) has its centre at
+ * (x + 1/2, y + 1/2) and ray direction normalize(K^-1 (x+1/2, y+1/2, 1)).
+ * t_near is the near integration bound t_n; the far bound is infinity. */
+typedef struct mb_camera {
+  float world_to_cam[12];
+  float fx, fy, cx, cy;
+  int32_t width, height;
+  float t_near;
+  float background[3];
+} mb_camera;
+
+/* Method options. Defaults (mb_default_options) are the paper's printed
+ * constants where it gives them. */
+typedef struct mb_options {
+  int32_t n_moments;   /* K power moments beyond m_0: 4 or 6 (K+1 values)   */
+  int32_t n_intervals; /* N quadrature intervals (N+1 edges): 3 or 5         */
+  float kappa;         /* sample spread of the edges, App. B (3)             */
+  float conf_c;        /* confidence level c of the proxy, App. D (0.01)     */
+  float beta;          /* interpolation between the bounds, Sec. 3.2 (0.25)  */
+  float eps;           /* clamp of Eq. 15's denominator (1e-6)               */
+  int32_t recon;       /* 0: moment bounds; 1: learned surrogate (K = 6)     */
+  const void *surrogate; /* device weights (mb_mlp layout) when recon = 1    */
+  int32_t full_coverage; /* debug: every Gaussian covers every pixel        */
+  int32_t reserved;
+} mb_options;
+
+void mb_default_options(mb_options *opts);
+const char *mb_last_error(void);
+int32_t mb_version(void);
+
+/* Workspace sizes. The Gaussian workspace holds per-(camera, Gaussian)
+ * records and tile counts; the pair workspace holds the per-tile lists for
+ * n_entries (camera, tile, Gaussian) entries and the backward partials.
+ * Both are caller-allocated device memory, 256-byte aligned. */
+size_t mb_gauss_workspace_bytes(int32_t n, int32_t n_cams);
+size_t mb_pair_workspace_bytes(int64_t n_entries, int32_t n_cams, int32_t width,
+                               int32_t height);
+
+/* Screen proxies only (App. D), for inspection: per Gaussian writes
+ * proxy[n,8] = (centre_x, centre_y, e1_x, e1_y, half_1, half_2, valid, 0)
+ * where the oriented rectangle is centre + a e1 + b e2, |a| <= half_1,
+ * |b| <= half_2, e2 = (-e1_y, e1_x); valid = 0 for culled Gaussians.
+ * proxy: device, caller-allocated. */
+int mb_project(const mb_gaussians *g, const mb_camera *cam, const mb_options *opts,
+               float *proxy, void *stream);
+
+/* Stage 1 of a render (Sec. 3.3 culling and proxy): per camera and Gaussian,
+ * the screen proxy, the ray-space coefficients and the number of 16x16 tiles
+ * its rectangle overlaps. Waits on `stream` once to return the total number
+ * of (camera, tile, Gaussian) entries in *n_entries (host pointer). gws must
+ * hold mb_gauss_workspace_bytes(g->n, n_cams) bytes. All cameras share one
+ * image size. */
+int mb_prepare(const mb_gaussians *g, const mb_camera *cams, int32_t n_cams,
+               const mb_options *opts, void *gws, size_t gws_bytes,
+               int64_t *n_entries, void *stream);
+
+/* Forward render (Sec. 3.2-3.3, Eqs. 7, 10-12, 15) after mb_prepare with the
+ * same arguments. pws must hold mb_pair_workspace_bytes(n_entries, ...).
+ *  image [C,H,W,3]  device, written: the rescaled radiance of Eq. 15
+ *  saved [C,H,W,8]  device, written: per-pixel state for the backward pass
+ *                   (sum q_i rgb_i, O, moment-variable origin and scale, m_0,
+ *                   a flag for pixels whose Hankel matrix needed a fallback,
+ *                   and the covering count). */
+int mb_render_forward(const mb_gaussians *g, const mb_camera *cams, int32_t n_cams,
+                      const mb_options *opts, void *gws, size_t gws_bytes, void *pws,
+                      size_t pws_bytes, int64_t n_entries, float *image, float *saved,
+                      void *stream);
+
+/* Backward pass (Sec. 3.3, Eq. 22, App. D adjoint rendering) after
+ * mb_render_forward with the same arguments and workspaces. Per-pixel moments
+ * are recomputed, not stored.
+ *  saved       [C,H,W,8] device, from mb_render_forward
+ *  grad_image  [C,H,W,3] device, dL/dimage
+ *  g_means [n,3], g_scales [n,3], g_quats [n,4], g_densities [n],
+ *  g_colors (same shape as colors): device, overwritten with dL/dparameter
+ *  summed over all cameras. Culled Gaussians receive zero. */
+int mb_render_backward(const mb_gaussians *g, const mb_camera *cams, int32_t n_cams,
+                       const mb_options *opts, void *gws, size_t gws_bytes, void *pws,
+                       size_t pws_bytes, int64_t n_entries, const float *saved,
+                       const float *grad_image, float *g_means, float *g_scales,
+                       float *g_quats, float *g_densities, float *g_colors, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MB3DGS_H */

@@ -131,6 +131,8 @@ def covering_pairs(proxy: Proxy, cam, pix_x: torch.Tensor, pix_y: torch.Tensor,
     ext = (proxy.axes[g_ok].abs() * proxy.half[g_ok][:, :, None]).sum(1) + margin_tol
     lo = proxy.mean2d[g_ok] - ext
     hi = proxy.mean2d[g_ok] + ext
+    if n_pix <= 4096:
+        return _pairs_by_pixel(proxy, g_ok, lo, hi, pix_x, pix_y, margin_tol, n_g)
     # candidate pixels of each Gaussian: those in the pixel list whose centre
     # lies in its dilated box; a dense lookup from image position to slot.
     slot_of = torch.full((cam.height, cam.width), -1, dtype=torch.long)
@@ -178,4 +180,28 @@ def covering_pairs(proxy: Proxy, cam, pix_x: torch.Tensor, pix_y: torch.Tensor,
     if amb_slots:
         a = torch.cat(amb_slots)
         ambiguous[a] = True
+    return slot[order], gid[order], ambiguous
+
+
+def _pairs_by_pixel(proxy, g_ok, lo, hi, pix_x, pix_y, margin_tol, n_g):
+    """Same pairs as ``covering_pairs`` for a short pixel list: each pixel is
+    tested against every Gaussian whose dilated box contains its centre."""
+    slots, gids, ambiguous = [], [], torch.zeros(pix_x.shape[0], dtype=torch.bool)
+    for s in range(pix_x.shape[0]):
+        u = float(pix_x[s]) + 0.5
+        v = float(pix_y[s]) + 0.5
+        cand = g_ok[(lo[:, 0] <= u) & (hi[:, 0] >= u) & (lo[:, 1] <= v) & (hi[:, 1] >= v)]
+        if cand.numel() == 0:
+            continue
+        xs = pix_x[s].expand(cand.shape[0])
+        ys = pix_y[s].expand(cand.shape[0])
+        marg = rect_margin(proxy, cand, xs, ys)
+        cov = (marg >= 0) & proxy.valid[cand]
+        slots.append(torch.full((int(cov.sum()),), s, dtype=torch.long))
+        gids.append(cand[cov])
+        if bool(((marg.abs() < margin_tol) | (proxy.ambiguous[cand] & (marg >= -margin_tol))).any()):
+            ambiguous[s] = True
+    slot = torch.cat(slots) if slots else torch.zeros(0, dtype=torch.long)
+    gid = torch.cat(gids) if gids else torch.zeros(0, dtype=torch.long)
+    order = torch.argsort(slot * n_g + gid)
     return slot[order], gid[order], ambiguous

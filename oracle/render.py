@@ -125,10 +125,11 @@ def _pixel_chunks(cam, px, py, max_pixels):
 
 
 def render_image(scene, cam, opts, pixels: Optional[np.ndarray] = None,
-                 max_pixels: int = 4096):
+                 max_pixels: int = 4096, margin_tol: float = 2e-3):
     """Forward render of ``pixels`` (flat indices y * W + x; default: the
     whole image). Returns a dict of numpy arrays: image [P,3], s_rgb [P,3],
-    opacity [P], moments [P,K+1], ambiguous [P], n_pairs."""
+    opacity [P], moments [P,K+1], ambiguous [P] (a coverage decision within
+    ``margin_tol`` pixels of a rectangle edge), n_pairs."""
     scene_t = scene_tensors(scene)
     proxy = screen_proxy(scene_t, cam, opts.conf_c)
     if pixels is None:
@@ -140,7 +141,8 @@ def render_image(scene, cam, opts, pixels: Optional[np.ndarray] = None,
     n_pairs = 0
     with torch.no_grad():
         for _, px, py in _pixel_chunks(cam, px_all, py_all, max_pixels):
-            r = render_pixels(scene_t, scene, cam, opts, px, py, proxy=proxy)
+            r = render_pixels(scene_t, scene, cam, opts, px, py, proxy=proxy,
+                              margin_tol=margin_tol)
             outs["image"].append(r.image)
             outs["s_rgb"].append(r.s_rgb)
             outs["opacity"].append(r.opacity)

@@ -1,0 +1,311 @@
+// C ABI of the rendering path: argument checks, workspace layout and the
+// launch sequence of each entry point (see include/mb3dgs.h).
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "kernels.h"
+
+using namespace mb;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* where) {
+  return fail(MB_ERR_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Carves consecutive 256-byte aligned regions out of a workspace.
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(void* p) : base(static_cast<char*>(p)) {}
+  template <class T>
+  T* take(size_t count) {
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off = align_up(off + count * sizeof(T));
+    return p;
+  }
+};
+
+struct GaussWs {
+  float4* rec;
+  int4* tbox;
+  int* counts;
+  int* offsets;
+  int* scan_tmp;
+  int* total;
+  size_t bytes;
+};
+
+GaussWs carve_gauss(void* p, int64_t n, int n_cams) {
+  Carver c(p);
+  int64_t m = n * n_cams;
+  GaussWs w;
+  w.rec = c.take<float4>((size_t)m * kRecF4);
+  w.tbox = c.take<int4>((size_t)m);
+  w.counts = c.take<int>((size_t)m);
+  w.offsets = c.take<int>((size_t)m);
+  w.scan_tmp = c.take<int>(scan_tmp_ints(m));
+  w.total = c.take<int>(1);
+  w.bytes = c.off;
+  return w;
+}
+
+struct PairWs {
+  uint32_t *keys_a, *keys_b;
+  int *vals_a, *vals_b, *entry_rec, *sorted_rec, *inv, *radix_tmp;
+  int2* ranges;
+  float* partials;
+  size_t bytes;
+};
+
+PairWs carve_pairs(void* p, int64_t e, int n_keys) {
+  Carver c(p);
+  PairWs w;
+  w.keys_a = c.take<uint32_t>((size_t)e);
+  w.keys_b = c.take<uint32_t>((size_t)e);
+  w.vals_a = c.take<int>((size_t)e);
+  w.vals_b = c.take<int>((size_t)e);
+  w.entry_rec = c.take<int>((size_t)e);
+  w.sorted_rec = c.take<int>((size_t)e);
+  w.inv = c.take<int>((size_t)e);
+  w.radix_tmp = c.take<int>(radix_tmp_ints(e));
+  w.ranges = c.take<int2>((size_t)n_keys);
+  w.partials = c.take<float>((size_t)e * kGradStride);
+  w.bytes = c.off;
+  return w;
+}
+
+int tiles_of(int px) { return (px + kTile - 1) / kTile; }
+
+int check_common(const mb_gaussians* g, const mb_camera* cams, int n_cams, const mb_options* o) {
+  if (!g || !cams || !o) return fail(MB_ERR_ARG, "null gaussians, cameras or options");
+  if (g->n < 0) return fail(MB_ERR_ARG, "negative Gaussian count %d", g->n);
+  if (g->n > 0 && (!g->means || !g->scales || !g->quats || !g->densities || !g->colors))
+    return fail(MB_ERR_ARG, "null Gaussian parameter pointer");
+  if (g->sh_degree < -1 || g->sh_degree > 3) return fail(MB_ERR_UNSUPPORTED, "SH degree %d not in -1..3", g->sh_degree);
+  if (n_cams < 1 || n_cams > MB_MAX_CAMERAS) return fail(MB_ERR_ARG, "camera count %d not in 1..%d", n_cams, MB_MAX_CAMERAS);
+  for (int i = 0; i < n_cams; ++i) {
+    const mb_camera& c = cams[i];
+    if (c.width <= 0 || c.height <= 0 || c.width > 16384 || c.height > 16384)
+      return fail(MB_ERR_ARG, "camera %d: image size %dx%d out of range", i, c.width, c.height);
+    if (c.width != cams[0].width || c.height != cams[0].height)
+      return fail(MB_ERR_ARG, "camera %d: all cameras must share one image size", i);
+    if (!(c.fx > 0.f) || !(c.fy > 0.f) || !(c.t_near > 0.f))
+      return fail(MB_ERR_ARG, "camera %d: focal lengths and t_near must be positive", i);
+  }
+  if (o->n_moments != 4 && o->n_moments != 6) return fail(MB_ERR_UNSUPPORTED, "n_moments %d: only 4 and 6", o->n_moments);
+  if (o->n_intervals != 3 && o->n_intervals != 5)
+    return fail(MB_ERR_UNSUPPORTED, "n_intervals %d: only 3 and 5", o->n_intervals);
+  if (!(o->conf_c > 0.f && o->conf_c < 1.f)) return fail(MB_ERR_ARG, "conf_c must be in (0, 1)");
+  if (!(o->kappa >= 1.f)) return fail(MB_ERR_ARG, "kappa must be >= 1");
+  if (!(o->eps > 0.f)) return fail(MB_ERR_ARG, "eps must be positive");
+  if (o->recon != 0) return fail(MB_ERR_UNSUPPORTED, "recon %d not available in this entry point", o->recon);
+  int64_t keys = (int64_t)tiles_of(cams[0].width) * tiles_of(cams[0].height) * n_cams;
+  if (keys >= (1ll << 30)) return fail(MB_ERR_ARG, "too many tiles");
+  if ((int64_t)g->n * n_cams >= (1ll << 31)) return fail(MB_ERR_ARG, "too many Gaussian-camera pairs");
+  return MB_OK;
+}
+
+CamSet make_cams(const mb_camera* cams, int n_cams) {
+  CamSet s;
+  memset(&s, 0, sizeof(s));
+  s.n_cams = n_cams;
+  for (int i = 0; i < n_cams; ++i) {
+    const mb_camera& m = cams[i];
+    CamConst& c = s.c[i];
+    for (int r = 0; r < 3; ++r) {
+      for (int k = 0; k < 3; ++k) c.r[r * 3 + k] = m.world_to_cam[r * 4 + k];
+      c.t[r] = m.world_to_cam[r * 4 + 3];
+    }
+    for (int k = 0; k < 3; ++k) {  // origin = -R^T t
+      double o = 0.0;
+      for (int r = 0; r < 3; ++r) o -= (double)c.r[r * 3 + k] * (double)c.t[r];
+      c.o[k] = (float)o;
+    }
+    c.fx = m.fx; c.fy = m.fy; c.cx = m.cx; c.cy = m.cy; c.tn = m.t_near;
+    for (int k = 0; k < 3; ++k) c.bg[k] = m.background[k];
+    c.width = m.width; c.height = m.height;
+  }
+  return s;
+}
+
+float conf_term(float c) { return (float)std::log(-std::log1p(-(double)c) / std::sqrt(2.0 * M_PI)); }
+
+// Standard-normal quantile by Newton's method on the normal CDF
+// Phi(x) = erfc(-x / sqrt2) / 2 (App. B sample spacing).
+double normal_quantile(double u) {
+  double x = 0.0;
+  for (int it = 0; it < 100; ++it) {
+    double f = 0.5 * std::erfc(-x / std::sqrt(2.0)) - u;
+    double d = std::exp(-0.5 * x * x) / std::sqrt(2.0 * M_PI);
+    double step = f / d;
+    x -= step;
+    if (std::fabs(step) < 1e-15 * (1.0 + std::fabs(x))) break;
+  }
+  return x;
+}
+
+void fill_quantiles(const mb_options* o, float* xq, float* eq) {
+  int nq = o->n_intervals + 1;
+  for (int j = 0; j < 8; ++j) { xq[j] = 0.f; eq[j] = 0.f; }
+  for (int j = 0; j < nq; ++j) {
+    // midpoint reading of "uniformly spaced samples on [0, 1]"
+    double x = normal_quantile((j + 0.5) / nq);
+    xq[j] = (float)x;
+    eq[j] = (float)std::exp(-0.5 * (double)o->kappa * o->kappa * x * x);
+  }
+}
+
+int key_bits(int64_t n_keys) {
+  int b = 1;
+  while ((1ll << b) < n_keys) ++b;
+  return b;
+}
+
+}  // namespace
+
+extern "C" {
+
+void mb_default_options(mb_options* o) {
+  if (!o) return;
+  memset(o, 0, sizeof(*o));
+  o->n_moments = 4;
+  o->n_intervals = 3;
+  o->kappa = 3.f;
+  o->conf_c = 0.01f;
+  o->beta = 0.25f;
+  o->eps = 1e-6f;
+}
+
+const char* mb_last_error(void) { return g_err.c_str(); }
+
+int32_t mb_version(void) { return 1; }
+
+size_t mb_gauss_workspace_bytes(int32_t n, int32_t n_cams) {
+  if (n < 0 || n_cams < 1) return 0;
+  return carve_gauss(nullptr, n, n_cams).bytes;
+}
+
+size_t mb_pair_workspace_bytes(int64_t n_entries, int32_t n_cams, int32_t width, int32_t height) {
+  if (n_entries < 0 || n_cams < 1 || width <= 0 || height <= 0) return 0;
+  int n_keys = tiles_of(width) * tiles_of(height) * n_cams;
+  return carve_pairs(nullptr, n_entries, n_keys).bytes;
+}
+
+int mb_project(const mb_gaussians* g, const mb_camera* cam, const mb_options* o, float* proxy, void* stream) {
+  int rc = check_common(g, cam, 1, o);
+  if (rc) return rc;
+  if (g->n > 0 && !proxy) return fail(MB_ERR_ARG, "null proxy output");
+  PrepArgs a;
+  memset(&a, 0, sizeof(a));
+  a.means = g->means; a.scales = g->scales; a.quats = g->quats; a.dens = g->densities; a.colors = g->colors;
+  a.n = g->n; a.sh_degree = g->sh_degree;
+  a.tiles_x = tiles_of(cam->width); a.tiles_y = tiles_of(cam->height);
+  a.conf_term = conf_term(o->conf_c);
+  a.full_coverage = o->full_coverage;
+  a.proxy_out = proxy;
+  CamSet cs = make_cams(cam, 1);
+  hipError_t e = launch_preprocess(a, cs, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "mb_project");
+  return MB_OK;
+}
+
+int mb_prepare(const mb_gaussians* g, const mb_camera* cams, int32_t n_cams, const mb_options* o, void* gws,
+               size_t gws_bytes, int64_t* n_entries, void* stream) {
+  int rc = check_common(g, cams, n_cams, o);
+  if (rc) return rc;
+  if (!n_entries) return fail(MB_ERR_ARG, "null n_entries");
+  GaussWs w = carve_gauss(gws, g->n, n_cams);
+  if (!gws || gws_bytes < w.bytes)
+    return fail(MB_ERR_WORKSPACE, "Gaussian workspace needs %zu bytes, got %zu", w.bytes, gws_bytes);
+  hipStream_t s = (hipStream_t)stream;
+  PrepArgs a;
+  memset(&a, 0, sizeof(a));
+  a.means = g->means; a.scales = g->scales; a.quats = g->quats; a.dens = g->densities; a.colors = g->colors;
+  a.n = g->n; a.sh_degree = g->sh_degree;
+  a.tiles_x = tiles_of(cams[0].width); a.tiles_y = tiles_of(cams[0].height);
+  a.conf_term = conf_term(o->conf_c);
+  a.full_coverage = o->full_coverage;
+  a.rec = w.rec; a.tbox = w.tbox; a.counts = w.counts;
+  CamSet cs = make_cams(cams, n_cams);
+  hipError_t e = launch_preprocess(a, cs, s);
+  if (e != hipSuccess) return hip_fail(e, "preprocess");
+  e = launch_scan(w.counts, w.offsets, (int64_t)g->n * n_cams, w.scan_tmp, w.total, s);
+  if (e != hipSuccess) return hip_fail(e, "scan");
+  int total = 0;
+  e = hipMemcpyAsync(&total, w.total, sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e != hipSuccess) return hip_fail(e, "count readback");
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "count readback sync");
+  if (total < 0) return fail(MB_ERR_ARG, "tile entry count overflow");
+  *n_entries = total;
+  return MB_OK;
+}
+
+int mb_render_forward(const mb_gaussians* g, const mb_camera* cams, int32_t n_cams, const mb_options* o, void* gws,
+                      size_t gws_bytes, void* pws, size_t pws_bytes, int64_t n_entries, float* image, float* saved,
+                      void* stream) {
+  int rc = check_common(g, cams, n_cams, o);
+  if (rc) return rc;
+  if (!image || !saved) return fail(MB_ERR_ARG, "null image or saved output");
+  if (n_entries < 0) return fail(MB_ERR_ARG, "negative n_entries");
+  GaussWs w = carve_gauss(gws, g->n, n_cams);
+  if (!gws || gws_bytes < w.bytes)
+    return fail(MB_ERR_WORKSPACE, "Gaussian workspace needs %zu bytes, got %zu", w.bytes, gws_bytes);
+  int tx = tiles_of(cams[0].width), ty = tiles_of(cams[0].height);
+  int n_keys = tx * ty * n_cams;
+  PairWs p = carve_pairs(pws, n_entries, n_keys);
+  if (!pws || pws_bytes < p.bytes)
+    return fail(MB_ERR_WORKSPACE, "pair workspace needs %zu bytes, got %zu", p.bytes, pws_bytes);
+  hipStream_t s = (hipStream_t)stream;
+  CamSet cs = make_cams(cams, n_cams);
+
+  EmitArgs ea;
+  ea.rec = w.rec; ea.tbox = w.tbox; ea.offsets = w.offsets; ea.counts = w.counts;
+  ea.n = g->n; ea.n_cams = n_cams; ea.tiles_x = tx; ea.tiles_y = ty; ea.full_coverage = o->full_coverage;
+  ea.keys = p.keys_a; ea.vals = p.vals_a; ea.entry_rec = p.entry_rec;
+  hipError_t e = launch_emit(ea, s);
+  if (e != hipSuccess) return hip_fail(e, "emit");
+  e = launch_radix_sort(p.keys_a, p.vals_a, p.keys_b, p.vals_b, n_entries, key_bits(n_keys), p.radix_tmp, s);
+  if (e != hipSuccess) return hip_fail(e, "sort");
+  e = launch_finish_lists(p.keys_a, p.vals_a, p.entry_rec, n_entries, p.sorted_rec, p.inv, p.ranges, n_keys, s);
+  if (e != hipSuccess) return hip_fail(e, "lists");
+
+  RenderArgs ra;
+  memset(&ra, 0, sizeof(ra));
+  ra.rec = w.rec; ra.sorted_rec = p.sorted_rec; ra.ranges = p.ranges;
+  ra.image = image; ra.saved = saved;
+  ra.tiles_x = tx; ra.tiles_y = ty; ra.n_cams = n_cams; ra.full_coverage = o->full_coverage;
+  ra.kappa = o->kappa; ra.beta = o->beta; ra.eps = o->eps;
+  fill_quantiles(o, ra.xq, ra.eq);
+  e = launch_render_forward(ra, cs, o->n_moments, o->n_intervals, s);
+  if (e != hipSuccess) return hip_fail(e, "render_forward");
+  return MB_OK;
+}
+
+int mb_render_backward(const mb_gaussians* g, const mb_camera* cams, int32_t n_cams, const mb_options* o, void* gws,
+                       size_t gws_bytes, void* pws, size_t pws_bytes, int64_t n_entries, const float* saved,
+                       const float* grad_image, float* g_means, float* g_scales, float* g_quats,
+                       float* g_densities, float* g_colors, void* stream) {
+  return fail(MB_ERR_UNSUPPORTED, "backward pass not built yet");
+}
+
+}  // extern "C"

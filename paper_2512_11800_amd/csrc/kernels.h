@@ -1,0 +1,67 @@
+// Host-side launch wrappers of the rendering kernels (one translation unit
+// each); all enqueue on the given stream and return hipError_t.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace mb {
+
+struct PrepArgs {
+  const float *means, *scales, *quats, *dens, *colors;
+  int n, sh_degree, tiles_x, tiles_y;
+  float conf_term;  // log(-log(1 - c) / sqrt(2 pi))
+  int full_coverage;
+  float4* rec;      // [C*n*6] render records
+  int4* tbox;       // [C*n] tile box (tx0, ty0, tx1, ty1)
+  int* counts;      // [C*n] overlapped tiles
+  float* proxy_out; // optional [n*8] (camera 0)
+};
+
+hipError_t launch_preprocess(const PrepArgs& a, const CamSet& cams, hipStream_t s);
+
+struct EmitArgs {
+  const float4* rec;
+  const int4* tbox;
+  const int* offsets;  // [C*n] exclusive scan of counts
+  const int* counts;   // [C*n] tiles counted by the preprocess kernel
+  int n, n_cams, tiles_x, tiles_y, full_coverage;
+  uint32_t* keys;      // [E] tile key cam * T + tile
+  int* vals;           // [E] entry index
+  int* entry_rec;      // [E] record index cam * n + g
+};
+hipError_t launch_emit(const EmitArgs& a, hipStream_t s);
+
+// exclusive scan of int32 counts (n items) into out (n items), total in *total.
+// tmp must hold scan_tmp_ints(n) ints.
+size_t scan_tmp_ints(int64_t n);
+hipError_t launch_scan(const int* in, int* out, int64_t n, int* tmp, int* total, hipStream_t s);
+
+// stable LSD radix sort of (keys, vals) on the low `bits` bits of keys.
+// Buffers *_a hold the input and receive the output; *_b are scratch.
+size_t radix_tmp_ints(int64_t n);
+hipError_t launch_radix_sort(uint32_t* keys_a, int* vals_a, uint32_t* keys_b, int* vals_b,
+                             int64_t n, int bits, int* tmp, hipStream_t s);
+
+// after the sort: sorted_rec[i] = entry_rec[vals[i]], inv[vals[i]] = i,
+// ranges[key] = [first, last+1) over the sorted keys (ranges zeroed first).
+hipError_t launch_finish_lists(const uint32_t* keys, const int* vals, const int* entry_rec,
+                               int64_t n, int* sorted_rec, int* inv, int2* ranges,
+                               int n_keys, hipStream_t s);
+
+struct RenderArgs {
+  const float4* rec;
+  const int* sorted_rec;
+  const int2* ranges;
+  float* image;   // [C,H,W,3]
+  float* saved;   // [C,H,W,8]
+  int tiles_x, tiles_y, n_cams, full_coverage;
+  float kappa, beta, eps;
+  float xq[8];    // standard-normal edge quantiles
+  float eq[8];    // exp(-kappa^2 xq^2 / 2)
+};
+hipError_t launch_render_forward(const RenderArgs& a, const CamSet& cams, int n_moments,
+                                 int n_intervals, hipStream_t s);
+
+}  // namespace mb

@@ -1,0 +1,197 @@
+// Moment-bound reconstruction of the optical depth at a query (Sec. 3.2),
+// per pixel and per query, in float32 registers.
+//
+// Per pixel the Hankel matrix H of the normalised moments b = m / m_0 is
+// factored once (H = L L^T, in double) and L^-1 is kept. For a query y:
+//   z = L^-1 v(y),  w_0 = 1 / |z|^2           (weight of the atom at y)
+//   c = L^-T z = H^-1 v(y)                     (kernel polynomial K(x) = c . v(x))
+//   x_i: the n real roots of K                 (other atoms)
+//   w_i = 1 / |L^-1 v(x_i)|^2                  (Christoffel numbers; equal to
+//                                               the Vandermonde solve)
+//   F = sum_{x_i < y} w_i + beta w_0           (= (1-beta) L + beta U, normalised)
+// and the optical depth is m_0 F.
+#pragma once
+#include "common.h"
+
+namespace mb {
+
+template <int NH>
+struct LInv {
+  float l[(NH + 1) * (NH + 2) / 2];  // rows of lower-triangular L^-1, packed
+};
+
+// L^-1 v(x) for v(x) = (1, x, .., x^NH)
+template <int NH>
+__device__ __forceinline__ void linv_apply(const LInv<NH>& L, float x, float* z) {
+  float p[NH + 1];
+  p[0] = 1.f;
+#pragma unroll
+  for (int k = 1; k <= NH; ++k) p[k] = p[k - 1] * x;
+  int o = 0;
+#pragma unroll
+  for (int i = 0; i <= NH; ++i) {
+    float s = 0.f;
+#pragma unroll
+    for (int j = 0; j <= i; ++j) s += L.l[o + j] * p[j];
+    z[i] = s;
+    o += i + 1;
+  }
+}
+
+template <int NH>
+__device__ __forceinline__ float christoffel(const LInv<NH>& L, float x) {
+  float z[NH + 1];
+  linv_apply<NH>(L, x, z);
+  float s = 0.f;
+#pragma unroll
+  for (int i = 0; i <= NH; ++i) s += z[i] * z[i];
+  return fast_rcp(s);
+}
+
+// c = L^-T z
+template <int NH>
+__device__ __forceinline__ void linv_t_apply(const LInv<NH>& L, const float* z, float* c) {
+#pragma unroll
+  for (int j = 0; j <= NH; ++j) c[j] = 0.f;
+  int o = 0;
+#pragma unroll
+  for (int i = 0; i <= NH; ++i) {
+#pragma unroll
+    for (int j = 0; j <= i; ++j) c[j] += L.l[o + j] * z[i];
+    o += i + 1;
+  }
+}
+
+// Real roots of c0 + c1 x + c2 x^2 (stable form).
+__device__ __forceinline__ void roots2(const float* c, float* x) {
+  float disc = fmaxf(c[1] * c[1] - 4.f * c[2] * c[0], 0.f);
+  float sq = sqrtf(disc);
+  float q = -0.5f * (c[1] + copysignf(sq, c[1]));
+  x[0] = q / c[2];
+  x[1] = c[0] / q;
+}
+
+// Real roots of c0 + c1 x + c2 x^2 + c3 x^3 (three real roots for a positive
+// definite Hankel matrix): trigonometric solution, then Newton polishing.
+__device__ __forceinline__ void roots3(const float* c, float* x) {
+  float inv = 1.f / c[3];
+  float a = c[2] * inv, b = c[1] * inv, cc = c[0] * inv;
+  float a3 = a * (1.f / 3.f);
+  float q = a3 * a3 - b * (1.f / 3.f);
+  float r = a3 * a3 * a3 - 0.5f * a3 * b + 0.5f * cc;
+  q = fmaxf(q, 0.f);
+  float sq = sqrtf(q);
+  float den = q * sq;
+  float arg = den > 0.f ? fminf(fmaxf(r / den, -1.f), 1.f) : 0.f;
+  float th = acosf(arg) * (1.f / 3.f);
+  const float two_pi_3 = 2.0943951023931953f;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    float xk = -2.f * sq * cosf(th + two_pi_3 * (float)k) - a3;
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+      float p = ((c[3] * xk + c[2]) * xk + c[1]) * xk + c[0];
+      float dp = (3.f * c[3] * xk + 2.f * c[2]) * xk + c[1];
+      float st = p / dp;
+      xk = (dp != 0.f && isfinite(st)) ? xk - st : xk;
+    }
+    x[k] = xk;
+  }
+}
+
+struct Canon3 {  // canonical representation at one query, n <= 3
+  float x[3];
+  float w[3];
+  float w0;
+};
+
+// Normalised interpolated bound F(y) = sum_{x_i<y} w_i + beta w_0.
+template <int NH>
+__device__ __forceinline__ float bound_F(const LInv<NH>& L, float y, float beta, Canon3* out = nullptr) {
+  float z[NH + 1], c[NH + 1], x[NH];
+  linv_apply<NH>(L, y, z);
+  float zz = 0.f;
+#pragma unroll
+  for (int i = 0; i <= NH; ++i) zz += z[i] * z[i];
+  float w0 = fast_rcp(zz);
+  linv_t_apply<NH>(L, z, c);
+  if (NH == 2) roots2(c, x); else roots3(c, x);
+  float lo = 0.f;
+#pragma unroll
+  for (int i = 0; i < NH; ++i) {
+    float wi = christoffel<NH>(L, x[i]);
+    bool below = x[i] < y;
+    wi = isfinite(wi) ? wi : 0.f;
+    lo += below ? wi : 0.f;
+    if (out) { out->x[i] = x[i]; out->w[i] = wi; }
+  }
+  if (out) out->w0 = w0;
+  return lo + beta * w0;
+}
+
+// Per-pixel factorisation of the Hankel matrix of b (b_0 = 1). Returns false
+// (and regularises the diagonal) when H is not numerically positive definite.
+template <int NH>
+__device__ __forceinline__ bool hankel_factor(const double* b, LInv<NH>& out) {
+  constexpr int M = NH + 1;
+  double h[M][M];
+#pragma unroll
+  for (int i = 0; i < M; ++i)
+#pragma unroll
+    for (int j = 0; j < M; ++j) h[i][j] = b[i + j];
+  bool ok = true;
+  double lc[M][M];
+  for (int attempt = 0; attempt < 3; ++attempt) {
+    ok = true;
+#pragma unroll
+    for (int i = 0; i < M; ++i)
+#pragma unroll
+      for (int j = 0; j < M; ++j) lc[i][j] = 0.0;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      double s = h[j][j];
+#pragma unroll
+      for (int k = 0; k < j; ++k) s -= lc[j][k] * lc[j][k];
+      if (!(s > 1e-14 * h[j][j])) { ok = false; s = 1e-14 * h[j][j] + 1e-300; }
+      double d = sqrt(s);
+      lc[j][j] = d;
+#pragma unroll
+      for (int i = j + 1; i < M; ++i) {
+        double t = h[i][j];
+#pragma unroll
+        for (int k = 0; k < j; ++k) t -= lc[i][k] * lc[j][k];
+        lc[i][j] = t / d;
+      }
+    }
+    if (ok) break;
+    // fallback: bias the diagonal (1e-6, then 1e-3 relative); flagged to the caller
+    double bias = attempt == 0 ? 1e-6 : 1e-3;
+#pragma unroll
+    for (int i = 0; i < M; ++i) h[i][i] *= (1.0 + bias);
+  }
+  // invert the lower-triangular factor
+  double li[M][M];
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+#pragma unroll
+    for (int j = 0; j < M; ++j) li[i][j] = 0.0;
+    li[i][i] = 1.0 / lc[i][i];
+#pragma unroll
+    for (int j = 0; j < i; ++j) {
+      double s = 0.0;
+#pragma unroll
+      for (int k = j; k < i; ++k) s += lc[i][k] * li[k][j];
+      li[i][j] = -s / lc[i][i];
+    }
+  }
+  int o = 0;
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+#pragma unroll
+    for (int j = 0; j <= i; ++j) out.l[o + j] = (float)li[i][j];
+    o += i + 1;
+  }
+  return ok;
+}
+
+}  // namespace mb

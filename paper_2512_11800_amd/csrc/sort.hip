@@ -1,0 +1,236 @@
+// Device-wide exclusive scan and a stable LSD radix sort used to build the
+// per-tile Gaussian lists. No depth sort is needed: the moment and quadrature
+// passes are order independent (Sec. 3.3), so lists are ordered by tile only,
+// and by entry index inside a tile (stable), which keeps results bitwise
+// reproducible.
+#include "kernels.h"
+
+namespace mb {
+
+constexpr int kItems = 8;                  // items per thread
+constexpr int kChunk = kBlock * kItems;    // items per block
+
+__device__ __forceinline__ int wave_inclusive_sum(int v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    int u = __shfl_up(v, d, 64);
+    if (lane >= d) v += u;
+  }
+  return v;
+}
+
+// exclusive prefix of v over the 256 threads of the block; *total gets the sum
+__device__ __forceinline__ int block_exclusive_sum(int v, int* lds4, int* total) {
+  int inc = wave_inclusive_sum(v);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 63) lds4[wave] = inc;
+  __syncthreads();
+  int off = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    int s = lds4[w];
+    off += (w < wave) ? s : 0;
+    tot += s;
+  }
+  __syncthreads();
+  *total = tot;
+  return off + inc - v;
+}
+
+__global__ __launch_bounds__(256) void k_scan_reduce(const int* in, int64_t n, int* sums) {
+  int64_t base = (int64_t)blockIdx.x * kChunk + threadIdx.x * kItems;
+  int s = 0;
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    int64_t i = base + k;
+    s += (i < n) ? in[i] : 0;
+  }
+  __shared__ int lds[4];
+  int tot;
+  block_exclusive_sum(s, lds, &tot);
+  if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+// single block: exclusive scan of `sums[0..m)` in place, total to *total
+__global__ __launch_bounds__(256) void k_scan_top(int* sums, int64_t m, int* total) {
+  int64_t per = (m + kBlock - 1) / kBlock;
+  int64_t b0 = threadIdx.x * per;
+  int s = 0;
+  for (int64_t k = 0; k < per; ++k) {
+    int64_t i = b0 + k;
+    if (i < m) s += sums[i];
+  }
+  __shared__ int lds[4];
+  int tot;
+  int off = block_exclusive_sum(s, lds, &tot);
+  for (int64_t k = 0; k < per; ++k) {
+    int64_t i = b0 + k;
+    if (i < m) {
+      int v = sums[i];
+      sums[i] = off;
+      off += v;
+    }
+  }
+  if (threadIdx.x == 0 && total != nullptr) *total = tot;
+}
+
+__global__ __launch_bounds__(256) void k_scan_down(const int* in, int* out, int64_t n, const int* sums) {
+  int64_t base = (int64_t)blockIdx.x * kChunk + threadIdx.x * kItems;
+  int v[kItems];
+  int s = 0;
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    int64_t i = base + k;
+    v[k] = (i < n) ? in[i] : 0;
+    s += v[k];
+  }
+  __shared__ int lds[4];
+  int tot;
+  int off = block_exclusive_sum(s, lds, &tot) + sums[blockIdx.x];
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    int64_t i = base + k;
+    if (i < n) out[i] = off;
+    off += v[k];
+  }
+}
+
+size_t scan_tmp_ints(int64_t n) { return (size_t)((n + kChunk - 1) / kChunk) + 1; }
+
+hipError_t launch_scan(const int* in, int* out, int64_t n, int* tmp, int* total, hipStream_t s) {
+  int64_t nb = (n + kChunk - 1) / kChunk;
+  if (nb == 0) {
+    if (total) return hipMemsetAsync(total, 0, sizeof(int), s);
+    return hipSuccess;
+  }
+  hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kBlock), 0, s, in, n, tmp);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, s, tmp, nb, total);
+  hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kBlock), 0, s, in, out, n, tmp);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Radix sort, 8-bit digits. Per pass: block histograms (digit-major), their
+// exclusive scan, then a stable scatter in which every block walks its chunk
+// in index order, 256 items per round, ranking equal digits inside a wave
+// with ballots and across waves through LDS counters.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_radix_hist(const uint32_t* keys, int64_t n, int shift,
+                                                    int* hist, int nblocks) {
+  __shared__ int h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  int64_t base = (int64_t)blockIdx.x * kChunk;
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    int64_t i = base + r * kBlock + threadIdx.x;
+    if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1);
+  }
+  __syncthreads();
+  hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* keys_in, const int* vals_in,
+                                                       uint32_t* keys_out, int* vals_out, int64_t n,
+                                                       int shift, const int* offsets, int nblocks) {
+  __shared__ int running[256];
+  __shared__ int wave_cnt[4][256];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  running[tid] = offsets[(int64_t)tid * nblocks + blockIdx.x];
+#pragma unroll
+  for (int w = 0; w < 4; ++w) wave_cnt[w][tid] = 0;
+  __syncthreads();
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  int64_t base = (int64_t)blockIdx.x * kChunk;
+  for (int r = 0; r < kItems; ++r) {
+    int64_t i = base + r * kBlock + tid;
+    bool valid = i < n;
+    uint32_t key = valid ? keys_in[i] : 0u;
+    int val = valid ? vals_in[i] : 0;
+    uint32_t d = (key >> shift) & 255u;
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+      bool b = (d >> bit) & 1u;
+      uint64_t m = __ballot(b);
+      peers &= b ? m : ~m;
+    }
+    int rank = __popcll(peers & lt);
+    if (valid && rank == 0) wave_cnt[wave][d] = __popcll(peers);
+    __syncthreads();
+    if (valid) {
+      int pos = running[d] + rank;
+#pragma unroll
+      for (int w = 0; w < 4; ++w) pos += (w < wave) ? wave_cnt[w][d] : 0;
+      keys_out[pos] = key;
+      vals_out[pos] = val;
+    }
+    __syncthreads();
+    running[tid] += wave_cnt[0][tid] + wave_cnt[1][tid] + wave_cnt[2][tid] + wave_cnt[3][tid];
+#pragma unroll
+    for (int w = 0; w < 4; ++w) wave_cnt[w][tid] = 0;
+    __syncthreads();
+  }
+}
+
+size_t radix_tmp_ints(int64_t n) {
+  int64_t nb = (n + kChunk - 1) / kChunk;
+  return (size_t)(256 * nb) + scan_tmp_ints(256 * nb) + 1;
+}
+
+hipError_t launch_radix_sort(uint32_t* keys_a, int* vals_a, uint32_t* keys_b, int* vals_b, int64_t n,
+                             int bits, int* tmp, hipStream_t s) {
+  if (n <= 1) return hipSuccess;
+  int64_t nb = (n + kChunk - 1) / kChunk;
+  int* hist = tmp;
+  int* scan_tmp = tmp + 256 * nb;
+  int passes = (bits + 7) / 8;
+  uint32_t *kin = keys_a, *kout = keys_b;
+  int *vin = vals_a, *vout = vals_b;
+  for (int p = 0; p < passes; ++p) {
+    int shift = 8 * p;
+    hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(kBlock), 0, s, kin, n, shift, hist, (int)nb);
+    hipError_t e = launch_scan(hist, hist, 256 * nb, scan_tmp, nullptr, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(kBlock), 0, s, kin, vin, kout, vout, n,
+                       shift, hist, (int)nb);
+    uint32_t* tk = kin; kin = kout; kout = tk;
+    int* tv = vin; vin = vout; vout = tv;
+  }
+  if (kin != keys_a) {
+    hipError_t e = hipMemcpyAsync(keys_a, kin, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(vals_a, vin, n * sizeof(int), hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_fill_ranges(int2* ranges, int n_keys) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_keys) ranges[i] = make_int2(0, 0);
+}
+
+__global__ __launch_bounds__(256) void k_finish(const uint32_t* keys, const int* vals, const int* entry_rec,
+                                                int64_t n, int* sorted_rec, int* inv, int2* ranges) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int v = vals[i];
+  sorted_rec[i] = entry_rec[v];
+  inv[v] = (int)i;
+  uint32_t key = keys[i];
+  if (i == 0 || keys[i - 1] != key) ranges[key].x = (int)i;
+  if (i == n - 1 || keys[i + 1] != key) ranges[key].y = (int)(i + 1);
+}
+
+hipError_t launch_finish_lists(const uint32_t* keys, const int* vals, const int* entry_rec, int64_t n,
+                               int* sorted_rec, int* inv, int2* ranges, int n_keys, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_ranges, dim3((n_keys + 255) / 256), dim3(256), 0, s, ranges, n_keys);
+  if (n > 0)
+    hipLaunchKernelGGL(k_finish, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, keys, vals, entry_rec,
+                       n, sorted_rec, inv, ranges);
+  return hipGetLastError();
+}
+
+}  // namespace mb

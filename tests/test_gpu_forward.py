@@ -1,0 +1,130 @@
+"""Forward parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Bar: max-abs image error <= 1e-4 in float32 over the pixels the parity
+protocol keeps (pixels whose coverage decision lies within the measured
+proxy discrepancy of a rectangle edge are excluded and counted)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+from tests.gpu_helpers import compare, gpu_render, log, proxy_error
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+
+
+def _margin(pe):
+    return max(1e-4, 4.0 * (pe["centre"] + pe["half"] + pe["axis_px"]))
+
+
+def test_proxies_match_oracle():
+    scene, cams, opts = W.w1_small()
+    pe = proxy_error(scene, cams[0], opts)
+    log("[proxy] W1", pe)
+    assert pe["mismatch"] <= pe["amb"]
+    assert pe["centre"] < 1e-3 and pe["half"] < 1e-3 and pe["axis_px"] < 1e-3
+    scene2, cams2, opts2 = W.w2_clusters(n=100_000)
+    pe2 = proxy_error(scene2, cams2[0], opts2)
+    log("[proxy] W2 subset", pe2)
+    assert pe2["mismatch"] <= max(pe2["amb"], 2)
+    assert pe2["centre"] < 5e-3 and pe2["half"] < 5e-3
+
+
+@pytest.mark.parametrize("k_mom", [4, 6])
+def test_w1_full_image(k_mom):
+    scene, cams, opts = W.w1_small()
+    opts.n_moments = k_mom
+    img, saved, st = gpu_render(scene, cams, opts)
+    pe = proxy_error(scene, cams[0], opts)
+    tol_m = _margin(pe)
+    # exclusions at the measured proxy discrepancy
+    ref2 = oracle.render_image(scene, cams[0], opts, margin_tol=tol_m)
+    log(f"[w1 K={k_mom}] entries={st.n_entries} pairs={ref2['n_pairs']} margin={tol_m:.2e}")
+    mx, worst = compare(img[0].reshape(-1, 3), ref2, f"W1 K={k_mom}")
+    assert mx <= TOL
+    # the saved opacity sum and m0 agree too
+    m0_err = np.abs(saved[0].reshape(-1, 8)[:, 6] - ref2["moments"][:, 0])
+    keep = ~ref2["ambiguous"]
+    log(f"[w1 K={k_mom}] m0 max_abs={m0_err[keep].max():.3e}")
+    assert m0_err[keep].max() < 1e-4 * max(1.0, ref2["moments"][:, 0].max())
+
+
+def _sample_pixels(scene, cam, n_random=150, n_dense=150, seed=0):
+    rng = np.random.default_rng(seed)
+    rnd = rng.integers(0, cam.width * cam.height, n_random)
+    # pixels at the projections of random Gaussian means (dense regions)
+    idx = rng.integers(0, scene.n, 4 * n_dense)
+    r = cam.world_to_cam[:, :3].astype(np.float64)
+    t = cam.world_to_cam[:, 3].astype(np.float64)
+    mc = scene.means[idx].astype(np.float64) @ r.T + t
+    ok = mc[:, 2] > 0.5
+    u = cam.fx * mc[ok, 0] / mc[ok, 2] + cam.cx
+    v = cam.fy * mc[ok, 1] / mc[ok, 2] + cam.cy
+    inside = (u >= 0) & (u < cam.width) & (v >= 0) & (v < cam.height)
+    dense = (np.floor(v[inside]).astype(int) * cam.width + np.floor(u[inside]).astype(int))[:n_dense]
+    return np.unique(np.concatenate([rnd, dense]))
+
+
+@pytest.mark.parametrize("k_mom", [4, 6])
+def test_w2_full_size_sampled(k_mom):
+    """500k Gaussians at 1920x1080, the configuration the benchmark times;
+    the oracle computes a sample of pixels one by one."""
+    scene, cams, opts = W.w2_clusters(n_moments=k_mom)
+    cam = cams[0]
+    img, saved, st = gpu_render(scene, cams, opts)
+    pix = _sample_pixels(scene, cam)
+    pe = proxy_error(scene, cam, opts)
+    log(f"[w2 K={k_mom}] proxy", pe)
+    ref = oracle.render_image(scene, cam, opts, pixels=pix, margin_tol=_margin(pe))
+    log(f"[w2 K={k_mom}] entries={st.n_entries} sampled={len(pix)} pairs={ref['n_pairs']}")
+    mx, worst = compare(img[0].reshape(-1, 3)[pix], ref, f"W2 K={k_mom}")
+    assert mx <= TOL
+
+
+def test_deterministic_and_order_invariant():
+    scene, cams, opts = W.w1_small()
+    a, _, _ = gpu_render(scene, cams, opts)
+    b, _, _ = gpu_render(scene, cams, opts)
+    assert np.array_equal(a, b)
+    perm = np.random.default_rng(1).permutation(scene.n)
+    c, _, _ = gpu_render(scene.subset(perm), cams, opts)
+    log(f"[order] max diff under permutation {np.abs(a - c).max():.3e}")
+    assert np.abs(a - c).max() < 2e-5
+
+
+def test_empty_scene_and_single_gaussian():
+    scene, cams, opts = W.w1_small()
+    cams[0].background = (0.1, 0.2, 0.3)
+    empty = scene.subset(np.arange(0))
+    img, saved, st = gpu_render(empty, cams, opts)
+    assert st.n_entries == 0
+    assert np.allclose(img, np.array([0.1, 0.2, 0.3]), atol=0)
+    one = scene.subset(np.array([5]))
+    img1, _, _ = gpu_render(one, cams, opts)
+    ref = oracle.render_image(one, cams[0], opts)
+    mx, _ = compare(img1[0].reshape(-1, 3), ref, "single Gaussian")
+    assert mx <= TOL
+
+
+def test_ragged_image_and_camera_batch():
+    scene, _, opts = W.w1_small()
+    cams = [W.camera_on_axis(3.0, 100, 75), W.camera_look_at((2.0, 1.0, -2.5), (0, 0, 0), (0, 1, 0), 100, 75)]
+    batch, _, _ = gpu_render(scene, cams, opts)
+    for i, cam in enumerate(cams):
+        single, _, _ = gpu_render(scene, [cam], opts)
+        assert np.array_equal(batch[i], single[0])
+        ref = oracle.render_image(scene, cam, opts)
+        mx, _ = compare(single[0].reshape(-1, 3), ref, f"ragged 100x75 cam{i}")
+        assert mx <= TOL
+
+
+def test_errors_are_raised_not_crashed():
+    import paper_2512_11800_amd as M
+    scene, cams, opts = W.w1_small()
+    g = M.Gaussians.from_scene(scene)
+    opts.n_moments = 8
+    with pytest.raises(M.MbError):
+        M.render_forward(g, cams, opts)
