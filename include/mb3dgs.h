@@ -120,10 +120,12 @@ int mb_prepare(const mb_gaussians *g, const mb_camera *cams, int32_t n_cams,
 /* Forward render (Sec. 3.2-3.3, Eqs. 7, 10-12, 15) after mb_prepare with the
  * same arguments. pws must hold mb_pair_workspace_bytes(n_entries, ...).
  *  image [C,H,W,3]  device, written: the rescaled radiance of Eq. 15
- *  saved [C,H,W,8]  device, written: per-pixel state for the backward pass
- *                   (sum q_i rgb_i, O, moment-variable origin and scale, m_0,
- *                   a flag for pixels whose Hankel matrix needed a fallback,
- *                   and the covering count). */
+ *  saved [C,H,W,8]  device, written: per-pixel state for the backward pass:
+ *                   [0..2] sum_i q_i rgb_i, [3] O = sum_i q_i, [4] depth of the
+ *                   moment-variable origin, [5] its warp scale, [6] m_0,
+ *                   [7] number of covering Gaussians n, or -(n + 1) when the
+ *                   pixel's Hankel matrix was not numerically positive
+ *                   definite and a diagonal bias was added. */
 int mb_render_forward(const mb_gaussians *g, const mb_camera *cams, int32_t n_cams,
                       const mb_options *opts, void *gws, size_t gws_bytes, void *pws,
                       size_t pws_bytes, int64_t n_entries, float *image, float *saved,
@@ -142,6 +144,18 @@ int mb_render_backward(const mb_gaussians *g, const mb_camera *cams, int32_t n_c
                        size_t pws_bytes, int64_t n_entries, const float *saved,
                        const float *grad_image, float *g_means, float *g_scales,
                        float *g_quats, float *g_densities, float *g_colors, void *stream);
+
+/* Stage timing. While enabled, every entry point records HIP events around
+ * each of its stages on its stream (a small per-process overhead).
+ * mb_profile_read waits for the recorded events, writes up to `max` stage
+ * totals in milliseconds to ms[] and launch counts to calls[] (both host,
+ * may be NULL), clears the record and returns the number of stages
+ * (MB_STAGE_COUNT). Stages, in order: preprocess, scan, emit, sort, lists,
+ * render_forward, render_backward, gradients, mlp. Not thread safe with
+ * concurrent renders. */
+#define MB_STAGE_COUNT 9
+void mb_profile_enable(int32_t on);
+int32_t mb_profile_read(double *ms, int64_t *calls, int32_t max);
 
 #ifdef __cplusplus
 }

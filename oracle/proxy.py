@@ -109,9 +109,23 @@ def rect_margin(proxy: Proxy, gidx: torch.Tensor, px: torch.Tensor, py: torch.Te
     return (proxy.half[gidx] - proj).min(dim=-1).values
 
 
+def _decision_tol(proxy: Proxy, gidx, px, py, margin_tol, orient_eps):
+    """Per-pair width of the band of ambiguous coverage decisions: a fixed
+    margin plus the motion of the rectangle's edges under a rotation of its
+    axes by orient_eps / (1 - lambda_1/lambda_2) (the axes of a nearly circular
+    ellipse are ill-conditioned; for a circle every orientation is valid)."""
+    if orient_eps <= 0:
+        return margin_tol
+    h = proxy.half[gidx]
+    ratio = (h[:, 0] / h[:, 1].clamp_min(1e-300)) ** 2
+    dtheta = (orient_eps / (1 - ratio).clamp_min(1e-12)).clamp_max(math.pi)
+    p = torch.stack([px.to(DT) + 0.5, py.to(DT) + 0.5], dim=-1) - proxy.mean2d[gidx]
+    return margin_tol + dtheta * p.norm(dim=-1)
+
+
 def covering_pairs(proxy: Proxy, cam, pix_x: torch.Tensor, pix_y: torch.Tensor,
                    margin_tol: float = 2e-3, full_coverage: bool = False,
-                   chunk: int = 1 << 22):
+                   chunk: int = 1 << 22, orient_eps: float = 0.0):
     """Pairs (pixel slot, Gaussian) with the pixel centre inside the Gaussian's
     rectangle (the proxy the paper rasterises; App. D).
 
@@ -129,10 +143,16 @@ def covering_pairs(proxy: Proxy, cam, pix_x: torch.Tensor, pix_y: torch.Tensor,
     g_ok = torch.nonzero(proxy.valid | proxy.ambiguous).squeeze(-1)
     # axis-aligned extent of each rectangle, dilated by the tolerance
     ext = (proxy.axes[g_ok].abs() * proxy.half[g_ok][:, :, None]).sum(1) + margin_tol
+    if orient_eps > 0:
+        # room for the band of a rotated rectangle around its corners
+        h = proxy.half[g_ok]
+        ratio = (h[:, 0] / h[:, 1].clamp_min(1e-300)) ** 2
+        dtheta = (orient_eps / (1 - ratio).clamp_min(1e-12)).clamp_max(math.pi)
+        ext = ext + (dtheta * (h[:, 0] + h[:, 1]))[:, None]
     lo = proxy.mean2d[g_ok] - ext
     hi = proxy.mean2d[g_ok] + ext
     if n_pix <= 4096:
-        return _pairs_by_pixel(proxy, g_ok, lo, hi, pix_x, pix_y, margin_tol, n_g)
+        return _pairs_by_pixel(proxy, g_ok, lo, hi, pix_x, pix_y, margin_tol, n_g, orient_eps)
     # candidate pixels of each Gaussian: those in the pixel list whose centre
     # lies in its dilated box; a dense lookup from image position to slot.
     slot_of = torch.full((cam.height, cam.width), -1, dtype=torch.long)
@@ -169,7 +189,8 @@ def covering_pairs(proxy: Proxy, cam, pix_x: torch.Tensor, pix_y: torch.Tensor,
             cov = (marg >= 0) & proxy.valid[g]
             slots.append(sl[cov])
             gids.append(g[cov])
-            amb = (marg.abs() < margin_tol) | (proxy.ambiguous[g] & (marg >= -margin_tol))
+            tol = _decision_tol(proxy, g, xx, yy, margin_tol, orient_eps)
+            amb = (marg.abs() < tol) | (proxy.ambiguous[g] & (marg >= -tol))
             amb_slots.append(sl[amb])
         start = stop
     slot = torch.cat(slots) if slots else torch.zeros(0, dtype=torch.long)
@@ -183,7 +204,7 @@ def covering_pairs(proxy: Proxy, cam, pix_x: torch.Tensor, pix_y: torch.Tensor,
     return slot[order], gid[order], ambiguous
 
 
-def _pairs_by_pixel(proxy, g_ok, lo, hi, pix_x, pix_y, margin_tol, n_g):
+def _pairs_by_pixel(proxy, g_ok, lo, hi, pix_x, pix_y, margin_tol, n_g, orient_eps=0.0):
     """Same pairs as ``covering_pairs`` for a short pixel list: each pixel is
     tested against every Gaussian whose dilated box contains its centre."""
     slots, gids, ambiguous = [], [], torch.zeros(pix_x.shape[0], dtype=torch.bool)
@@ -199,7 +220,8 @@ def _pairs_by_pixel(proxy, g_ok, lo, hi, pix_x, pix_y, margin_tol, n_g):
         cov = (marg >= 0) & proxy.valid[cand]
         slots.append(torch.full((int(cov.sum()),), s, dtype=torch.long))
         gids.append(cand[cov])
-        if bool(((marg.abs() < margin_tol) | (proxy.ambiguous[cand] & (marg >= -margin_tol))).any()):
+        tol = _decision_tol(proxy, cand, xs, ys, margin_tol, orient_eps)
+        if bool(((marg.abs() < tol) | (proxy.ambiguous[cand] & (marg >= -tol))).any()):
             ambiguous[s] = True
     slot = torch.cat(slots) if slots else torch.zeros(0, dtype=torch.long)
     gid = torch.cat(gids) if gids else torch.zeros(0, dtype=torch.long)

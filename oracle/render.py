@@ -73,7 +73,7 @@ def _standardised_basis(slot, mu, sigma, omega, t_near, n_pix):
 
 
 def render_pixels(scene_t, scene, cam, opts, px: torch.Tensor, py: torch.Tensor,
-                  proxy=None, margin_tol: float = 2e-3) -> PixelResult:
+                  proxy=None, margin_tol: float = 2e-3, orient_eps: float = 0.0) -> PixelResult:
     """Render the listed pixels (all pairs of each listed pixel are formed, so
     every listed pixel is complete)."""
     n_pix = px.shape[0]
@@ -83,7 +83,7 @@ def render_pixels(scene_t, scene, cam, opts, px: torch.Tensor, py: torch.Tensor,
     if proxy is None:
         proxy = screen_proxy(scene_t, cam, opts.conf_c)
     slot, gid, amb = covering_pairs(proxy, cam, px, py, margin_tol=margin_tol,
-                                    full_coverage=opts.full_coverage)
+                                    full_coverage=opts.full_coverage, orient_eps=orient_eps)
     _, _, origin = camera_matrices(cam)
 
     means = scene_t["means"]
@@ -125,11 +125,12 @@ def _pixel_chunks(cam, px, py, max_pixels):
 
 
 def render_image(scene, cam, opts, pixels: Optional[np.ndarray] = None,
-                 max_pixels: int = 4096, margin_tol: float = 2e-3):
+                 max_pixels: int = 4096, margin_tol: float = 2e-3, orient_eps: float = 0.0):
     """Forward render of ``pixels`` (flat indices y * W + x; default: the
     whole image). Returns a dict of numpy arrays: image [P,3], s_rgb [P,3],
     opacity [P], moments [P,K+1], ambiguous [P] (a coverage decision within
-    ``margin_tol`` pixels of a rectangle edge), n_pairs."""
+    ``margin_tol`` pixels of a rectangle edge, widened for nearly circular
+    proxies by ``orient_eps``), n_pairs."""
     scene_t = scene_tensors(scene)
     proxy = screen_proxy(scene_t, cam, opts.conf_c)
     if pixels is None:
@@ -142,7 +143,7 @@ def render_image(scene, cam, opts, pixels: Optional[np.ndarray] = None,
     with torch.no_grad():
         for _, px, py in _pixel_chunks(cam, px_all, py_all, max_pixels):
             r = render_pixels(scene_t, scene, cam, opts, px, py, proxy=proxy,
-                              margin_tol=margin_tol)
+                              margin_tol=margin_tol, orient_eps=orient_eps)
             outs["image"].append(r.image)
             outs["s_rgb"].append(r.s_rgb)
             outs["opacity"].append(r.opacity)

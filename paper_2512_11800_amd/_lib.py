@@ -19,6 +19,9 @@ MB_ERR_WORKSPACE = -3
 MB_ERR_HIP = -4
 MB_MAX_CAMERAS = 16
 MB_SAVED_FLOATS_PER_PIXEL = 8
+MB_STAGE_COUNT = 9
+STAGES = ("preprocess", "scan", "emit", "sort", "lists", "render_forward", "render_backward",
+          "gradients", "mlp")
 
 
 class MbGaussians(ctypes.Structure):
@@ -61,6 +64,8 @@ SIGNATURES = [
     ("mb_render_forward", c_int32, [POINTER(MbGaussians), POINTER(MbCamera), c_int32,
                                     POINTER(MbOptions), c_void_p, c_size_t, c_void_p, c_size_t,
                                     c_int64, c_void_p, c_void_p, c_void_p]),
+    ("mb_profile_enable", None, [c_int32]),
+    ("mb_profile_read", c_int32, [POINTER(ctypes.c_double), POINTER(c_int64), c_int32]),
     ("mb_render_backward", c_int32, [POINTER(MbGaussians), POINTER(MbCamera), c_int32,
                                      POINTER(MbOptions), c_void_p, c_size_t, c_void_p, c_size_t,
                                      c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
@@ -89,3 +94,15 @@ def check(rc: int):
     if rc != MB_OK:
         msg = load().mb_last_error()
         raise MbError(rc, msg.decode() if msg else "")
+
+
+def profile_enable(on: bool = True):
+    load().mb_profile_enable(1 if on else 0)
+
+
+def profile_read():
+    """Stage totals since the last read: {stage: (ms, calls)} (waits for them)."""
+    ms = (ctypes.c_double * MB_STAGE_COUNT)()
+    calls = (c_int64 * MB_STAGE_COUNT)()
+    load().mb_profile_read(ms, calls, MB_STAGE_COUNT)
+    return {name: (ms[i], calls[i]) for i, name in enumerate(STAGES)}

@@ -4,13 +4,54 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
+#include <vector>
 
 #include "kernels.h"
 
 using namespace mb;
 
 namespace {
+
+// ---------------------------------------------------------------------------
+// Stage timing with HIP events on the caller's stream (mb_profile_*).
+// ---------------------------------------------------------------------------
+enum Stage { S_PREPROCESS = 0, S_SCAN, S_EMIT, S_SORT, S_LISTS, S_RENDER_FWD, S_RENDER_BWD, S_GRADS, S_MLP };
+
+struct Profiler {
+  std::mutex mu;
+  bool on = false;
+  struct Rec { int stage; hipEvent_t a, b; };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t get() {
+    if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+};
+Profiler g_prof;
+
+struct StageTimer {
+  int stage;
+  hipStream_t s;
+  hipEvent_t a = nullptr, b = nullptr;
+  StageTimer(int st, hipStream_t str) : stage(st), s(str) {
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    if (!g_prof.on) return;
+    a = g_prof.get();
+    b = g_prof.get();
+    if (a && b) hipEventRecord(a, s);
+  }
+  ~StageTimer() {
+    if (!a || !b) return;
+    hipEventRecord(b, s);
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    g_prof.recs.push_back({stage, a, b});
+  }
+};
 
 thread_local std::string g_err;
 
@@ -197,6 +238,37 @@ void mb_default_options(mb_options* o) {
 
 const char* mb_last_error(void) { return g_err.c_str(); }
 
+void mb_profile_enable(int32_t on) {
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  g_prof.on = on != 0;
+}
+
+int32_t mb_profile_read(double* ms, int64_t* calls, int32_t max) {
+  std::vector<Profiler::Rec> recs;
+  {
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    recs.swap(g_prof.recs);
+  }
+  double tot[MB_STAGE_COUNT] = {0};
+  int64_t cnt[MB_STAGE_COUNT] = {0};
+  for (auto& r : recs) {
+    float t = 0.f;
+    if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
+      tot[r.stage] += t;
+      cnt[r.stage] += 1;
+    }
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    for (auto& r : recs) { g_prof.pool.push_back(r.a); g_prof.pool.push_back(r.b); }
+  }
+  for (int i = 0; i < MB_STAGE_COUNT && i < max; ++i) {
+    if (ms) ms[i] = tot[i];
+    if (calls) calls[i] = cnt[i];
+  }
+  return MB_STAGE_COUNT;
+}
+
 int32_t mb_version(void) { return 1; }
 
 size_t mb_gauss_workspace_bytes(int32_t n, int32_t n_cams) {
@@ -246,9 +318,16 @@ int mb_prepare(const mb_gaussians* g, const mb_camera* cams, int32_t n_cams, con
   a.full_coverage = o->full_coverage;
   a.rec = w.rec; a.tbox = w.tbox; a.counts = w.counts;
   CamSet cs = make_cams(cams, n_cams);
-  hipError_t e = launch_preprocess(a, cs, s);
+  hipError_t e;
+  {
+    StageTimer t(S_PREPROCESS, s);
+    e = launch_preprocess(a, cs, s);
+  }
   if (e != hipSuccess) return hip_fail(e, "preprocess");
-  e = launch_scan(w.counts, w.offsets, (int64_t)g->n * n_cams, w.scan_tmp, w.total, s);
+  {
+    StageTimer t(S_SCAN, s);
+    e = launch_scan(w.counts, w.offsets, (int64_t)g->n * n_cams, w.scan_tmp, w.total, s);
+  }
   if (e != hipSuccess) return hip_fail(e, "scan");
   int total = 0;
   e = hipMemcpyAsync(&total, w.total, sizeof(int), hipMemcpyDeviceToHost, s);
@@ -282,11 +361,21 @@ int mb_render_forward(const mb_gaussians* g, const mb_camera* cams, int32_t n_ca
   ea.rec = w.rec; ea.tbox = w.tbox; ea.offsets = w.offsets; ea.counts = w.counts;
   ea.n = g->n; ea.n_cams = n_cams; ea.tiles_x = tx; ea.tiles_y = ty; ea.full_coverage = o->full_coverage;
   ea.keys = p.keys_a; ea.vals = p.vals_a; ea.entry_rec = p.entry_rec;
-  hipError_t e = launch_emit(ea, s);
+  hipError_t e;
+  {
+    StageTimer t(S_EMIT, s);
+    e = launch_emit(ea, s);
+  }
   if (e != hipSuccess) return hip_fail(e, "emit");
-  e = launch_radix_sort(p.keys_a, p.vals_a, p.keys_b, p.vals_b, n_entries, key_bits(n_keys), p.radix_tmp, s);
+  {
+    StageTimer t(S_SORT, s);
+    e = launch_radix_sort(p.keys_a, p.vals_a, p.keys_b, p.vals_b, n_entries, key_bits(n_keys), p.radix_tmp, s);
+  }
   if (e != hipSuccess) return hip_fail(e, "sort");
-  e = launch_finish_lists(p.keys_a, p.vals_a, p.entry_rec, n_entries, p.sorted_rec, p.inv, p.ranges, n_keys, s);
+  {
+    StageTimer t(S_LISTS, s);
+    e = launch_finish_lists(p.keys_a, p.vals_a, p.entry_rec, n_entries, p.sorted_rec, p.inv, p.ranges, n_keys, s);
+  }
   if (e != hipSuccess) return hip_fail(e, "lists");
 
   RenderArgs ra;
@@ -296,7 +385,10 @@ int mb_render_forward(const mb_gaussians* g, const mb_camera* cams, int32_t n_ca
   ra.tiles_x = tx; ra.tiles_y = ty; ra.n_cams = n_cams; ra.full_coverage = o->full_coverage;
   ra.kappa = o->kappa; ra.beta = o->beta; ra.eps = o->eps;
   fill_quantiles(o, ra.xq, ra.eq);
-  e = launch_render_forward(ra, cs, o->n_moments, o->n_intervals, s);
+  {
+    StageTimer t(S_RENDER_FWD, s);
+    e = launch_render_forward(ra, cs, o->n_moments, o->n_intervals, s);
+  }
   if (e != hipSuccess) return hip_fail(e, "render_forward");
   return MB_OK;
 }

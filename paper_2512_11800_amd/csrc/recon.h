@@ -71,9 +71,31 @@ __device__ __forceinline__ void roots2(const float* c, float* x) {
   x[1] = c[0] / q;
 }
 
+__device__ __forceinline__ float cubic_newton(const float* c, float x, int iters) {
+  for (int it = 0; it < iters; ++it) {
+    float p = ((c[3] * x + c[2]) * x + c[1]) * x + c[0];
+    float dp = (3.f * c[3] * x + 2.f * c[2]) * x + c[1];
+    float st = p / dp;
+    x = (dp != 0.f && isfinite(st)) ? x - st : x;
+  }
+  return x;
+}
+
 // Real roots of c0 + c1 x + c2 x^2 + c3 x^3 (three real roots for a positive
-// definite Hankel matrix): trigonometric solution, then Newton polishing.
+// definite Hankel matrix). The trigonometric solution is accurate only for the
+// root of largest magnitude when the roots span a wide range (c3 -> 0 sends
+// one atom of the canonical representation to infinity), so that root is
+// taken from it, polished, divided out from the low-order end (stable for a
+// large root) and the remaining quadratic is solved in its stable form; all
+// roots get Newton steps on the full cubic.
 __device__ __forceinline__ void roots3(const float* c, float* x) {
+  float scale = fabsf(c[0]) + fabsf(c[1]) + fabsf(c[2]) + fabsf(c[3]);
+  if (!(fabsf(c[3]) > 1e-12f * scale)) {
+    // degree drop: one atom at infinity (zero weight)
+    roots2(c, x);
+    x[2] = copysignf(1e30f, -c[2] * c[3]);
+    return;
+  }
   float inv = 1.f / c[3];
   float a = c[2] * inv, b = c[1] * inv, cc = c[0] * inv;
   float a3 = a * (1.f / 3.f);
@@ -85,18 +107,24 @@ __device__ __forceinline__ void roots3(const float* c, float* x) {
   float arg = den > 0.f ? fminf(fmaxf(r / den, -1.f), 1.f) : 0.f;
   float th = acosf(arg) * (1.f / 3.f);
   const float two_pi_3 = 2.0943951023931953f;
+  float big = 0.f;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     float xk = -2.f * sq * cosf(th + two_pi_3 * (float)k) - a3;
-#pragma unroll
-    for (int it = 0; it < 2; ++it) {
-      float p = ((c[3] * xk + c[2]) * xk + c[1]) * xk + c[0];
-      float dp = (3.f * c[3] * xk + 2.f * c[2]) * xk + c[1];
-      float st = p / dp;
-      xk = (dp != 0.f && isfinite(st)) ? xk - st : xk;
-    }
-    x[k] = xk;
+    big = fabsf(xk) > fabsf(big) ? xk : big;
   }
+  big = cubic_newton(c, big, 2);
+  // p(x) = (x - big)(A x^2 + B x + C), matched from the constant term up
+  float ib = 1.f / big;
+  float cq = -c[0] * ib;
+  float bq = (cq - c[1]) * ib;
+  float aq = (bq - c[2]) * ib;
+  float qc[3] = {cq, bq, aq};
+  float x2[2];
+  roots2(qc, x2);
+  x[0] = big;
+  x[1] = cubic_newton(c, x2[0], 2);
+  x[2] = cubic_newton(c, x2[1], 2);
 }
 
 struct Canon3 {  // canonical representation at one query, n <= 3
@@ -115,7 +143,7 @@ __device__ __forceinline__ float bound_F(const LInv<NH>& L, float y, float beta,
   for (int i = 0; i <= NH; ++i) zz += z[i] * z[i];
   float w0 = fast_rcp(zz);
   linv_t_apply<NH>(L, z, c);
-  if (NH == 2) roots2(c, x); else roots3(c, x);
+  if constexpr (NH == 2) roots2(c, x); else roots3(c, x);
   float lo = 0.f;
 #pragma unroll
   for (int i = 0; i < NH; ++i) {

@@ -215,6 +215,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
 
   // ---- pass 2: quadrature ---------------------------------------------------
   float sr = 0.f, sg = 0.f, sb = 0.f, so = 0.f;
+  int n_cov = 0;
   for (int b = rg.x; b < rg.y; b += kBlock) {
     int nb = min(kBlock, rg.y - b);
     __syncthreads();
@@ -227,6 +228,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
       if (cov) {
         RayG g = ray_params(st, j, dx, dy, lam);
         float q = particle_quadrature<NH, NQ>(g, pb, L, m0, tn, a);
+        ++n_cov;
         float4 f5 = st.f[5][j];
         sr += q * f5.y;
         sg += q * f5.z;
@@ -248,7 +250,8 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
   out[2] = alpha * sb * inv_o + tr * c.bg[2];
   float4* sv = reinterpret_cast<float4*>(a.saved + pix * MB_SAVED_FLOATS_PER_PIXEL);
   sv[0] = make_float4(sr, sg, sb, so);
-  sv[1] = make_float4(tc, sd, m0, fallback ? 1.f : 0.f);
+  // covering count; stored as -(count + 1) when the Hankel factor needed a fallback
+  sv[1] = make_float4(tc, sd, m0, fallback ? -(float)(n_cov + 1) : (float)n_cov);
 }
 
 hipError_t launch_render_forward(const RenderArgs& a, const CamSet& cams, int n_moments, int n_intervals,

@@ -37,13 +37,24 @@ def proxy_error(scene, cam, opts):
     both = keep_o & keep_g
     c_err = np.abs(gp[both, :2] - op.mean2d.numpy()[both]).max(initial=0.0)
     h_err = np.abs(gp[both, 4:6] - op.half.numpy()[both]).max(initial=0.0)
-    align = np.abs((gp[both, 2:4] * op.axes.numpy()[both, 0]).sum(-1))
-    a_err = np.abs(1 - align).max(initial=0.0)
-    h_scale = np.maximum(op.half.numpy()[both].max(-1), 1.0)
-    ax_err = (np.sqrt(np.maximum(0, 1 - align ** 2)) * h_scale).max(initial=0.0)
+    eg = gp[both, 2:4]
+    eo = op.axes.numpy()[both, 0]
+    # sine of the angle between the axes from the cross product (accurate for
+    # small angles, unlike sqrt(1 - cos^2) of float32 unit vectors)
+    angle = np.abs(eg[:, 0] * eo[:, 1] - eg[:, 1] * eo[:, 0]) / (
+        np.linalg.norm(eg, axis=1) * np.linalg.norm(eo, axis=1))
+    h = op.half.numpy()[both]
+    # axis angle error relative to the conditioning of the eigenvectors
+    orient = (angle * (1 - (h[:, 0] / np.maximum(h[:, 1], 1e-300)) ** 2)).max(initial=0.0)
     mismatch = int((keep_o & ~keep_g).sum())
-    return dict(centre=c_err, half=h_err, axis=a_err, axis_px=ax_err, mismatch=mismatch,
-                amb=int(op.ambiguous.numpy().sum()), n_keep=int(both.sum()))
+    return dict(centre=c_err, half=h_err, orient=orient, angle=angle.max(initial=0.0),
+                mismatch=mismatch, amb=int(op.ambiguous.numpy().sum()), n_keep=int(both.sum()))
+
+
+def tolerances(pe):
+    """Exclusion band for the parity protocol from the measured proxy
+    discrepancy: (margin in pixels, orientation epsilon)."""
+    return max(1e-4, 4.0 * (pe["centre"] + pe["half"])), max(1e-6, 4.0 * pe["orient"])
 
 
 def compare(img_gpu, res_oracle, label, tol=1e-4):

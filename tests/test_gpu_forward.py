@@ -9,15 +9,11 @@ import torch
 
 import oracle
 import workloads as W
-from tests.gpu_helpers import compare, gpu_render, log, proxy_error
+from tests.gpu_helpers import compare, gpu_render, log, proxy_error, tolerances
 
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-4
-
-
-def _margin(pe):
-    return max(1e-4, 4.0 * (pe["centre"] + pe["half"] + pe["axis_px"]))
 
 
 def test_proxies_match_oracle():
@@ -25,12 +21,12 @@ def test_proxies_match_oracle():
     pe = proxy_error(scene, cams[0], opts)
     log("[proxy] W1", pe)
     assert pe["mismatch"] <= pe["amb"]
-    assert pe["centre"] < 1e-3 and pe["half"] < 1e-3 and pe["axis_px"] < 1e-3
+    assert pe["centre"] < 1e-3 and pe["half"] < 1e-3 and pe["orient"] < 1e-5
     scene2, cams2, opts2 = W.w2_clusters(n=100_000)
     pe2 = proxy_error(scene2, cams2[0], opts2)
     log("[proxy] W2 subset", pe2)
     assert pe2["mismatch"] <= max(pe2["amb"], 2)
-    assert pe2["centre"] < 5e-3 and pe2["half"] < 5e-3
+    assert pe2["centre"] < 5e-3 and pe2["half"] < 5e-3 and pe2["orient"] < 1e-5
 
 
 @pytest.mark.parametrize("k_mom", [4, 6])
@@ -39,10 +35,11 @@ def test_w1_full_image(k_mom):
     opts.n_moments = k_mom
     img, saved, st = gpu_render(scene, cams, opts)
     pe = proxy_error(scene, cams[0], opts)
-    tol_m = _margin(pe)
+    tol_m, tol_o = tolerances(pe)
     # exclusions at the measured proxy discrepancy
-    ref2 = oracle.render_image(scene, cams[0], opts, margin_tol=tol_m)
-    log(f"[w1 K={k_mom}] entries={st.n_entries} pairs={ref2['n_pairs']} margin={tol_m:.2e}")
+    ref2 = oracle.render_image(scene, cams[0], opts, margin_tol=tol_m, orient_eps=tol_o)
+    log(f"[w1 K={k_mom}] entries={st.n_entries} pairs={ref2['n_pairs']} margin={tol_m:.2e} "
+        f"orient={tol_o:.2e}")
     mx, worst = compare(img[0].reshape(-1, 3), ref2, f"W1 K={k_mom}")
     assert mx <= TOL
     # the saved opacity sum and m0 agree too
@@ -78,7 +75,8 @@ def test_w2_full_size_sampled(k_mom):
     pix = _sample_pixels(scene, cam)
     pe = proxy_error(scene, cam, opts)
     log(f"[w2 K={k_mom}] proxy", pe)
-    ref = oracle.render_image(scene, cam, opts, pixels=pix, margin_tol=_margin(pe))
+    tol_m, tol_o = tolerances(pe)
+    ref = oracle.render_image(scene, cam, opts, pixels=pix, margin_tol=tol_m, orient_eps=tol_o)
     log(f"[w2 K={k_mom}] entries={st.n_entries} sampled={len(pix)} pairs={ref['n_pairs']}")
     mx, worst = compare(img[0].reshape(-1, 3)[pix], ref, f"W2 K={k_mom}")
     assert mx <= TOL
