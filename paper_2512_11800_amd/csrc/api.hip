@@ -129,7 +129,7 @@ PairWs carve_pairs(void* p, int64_t e, int n_keys) {
   w.inv = c.take<int>((size_t)e);
   w.radix_tmp = c.take<int>(radix_tmp_ints(e));
   w.ranges = c.take<int2>((size_t)n_keys);
-  w.partials = c.take<float>((size_t)e * kGradStride);
+  w.partials = c.take<float>((size_t)e * 4 * kGradStride);  // one slot per (entry, wave)
   w.bytes = c.off;
   return w;
 }
@@ -397,7 +397,46 @@ int mb_render_backward(const mb_gaussians* g, const mb_camera* cams, int32_t n_c
                        size_t gws_bytes, void* pws, size_t pws_bytes, int64_t n_entries, const float* saved,
                        const float* grad_image, float* g_means, float* g_scales, float* g_quats,
                        float* g_densities, float* g_colors, void* stream) {
-  return fail(MB_ERR_UNSUPPORTED, "backward pass not built yet");
+  int rc = check_common(g, cams, n_cams, o);
+  if (rc) return rc;
+  if (!saved || !grad_image) return fail(MB_ERR_ARG, "null saved state or image gradient");
+  if (g->n > 0 && (!g_means || !g_scales || !g_quats || !g_densities || !g_colors))
+    return fail(MB_ERR_ARG, "null gradient output");
+  if (n_entries < 0) return fail(MB_ERR_ARG, "negative n_entries");
+  GaussWs w = carve_gauss(gws, g->n, n_cams);
+  if (!gws || gws_bytes < w.bytes)
+    return fail(MB_ERR_WORKSPACE, "Gaussian workspace needs %zu bytes, got %zu", w.bytes, gws_bytes);
+  int tx = tiles_of(cams[0].width), ty = tiles_of(cams[0].height);
+  int n_keys = tx * ty * n_cams;
+  PairWs p = carve_pairs(pws, n_entries, n_keys);
+  if (!pws || pws_bytes < p.bytes)
+    return fail(MB_ERR_WORKSPACE, "pair workspace needs %zu bytes, got %zu", p.bytes, pws_bytes);
+  hipStream_t s = (hipStream_t)stream;
+  CamSet cs = make_cams(cams, n_cams);
+  RenderArgs ra;
+  memset(&ra, 0, sizeof(ra));
+  ra.rec = w.rec; ra.sorted_rec = p.sorted_rec; ra.ranges = p.ranges;
+  ra.tiles_x = tx; ra.tiles_y = ty; ra.n_cams = n_cams; ra.full_coverage = o->full_coverage;
+  ra.kappa = o->kappa; ra.beta = o->beta; ra.eps = o->eps;
+  fill_quantiles(o, ra.xq, ra.eq);
+  hipError_t e;
+  {
+    StageTimer t(S_RENDER_BWD, s);
+    e = launch_render_backward(ra, saved, grad_image, p.vals_a, p.partials, cs, o->n_moments, o->n_intervals, s);
+  }
+  if (e != hipSuccess) return hip_fail(e, "render_backward");
+  GradArgs ga;
+  ga.means = g->means; ga.scales = g->scales; ga.quats = g->quats; ga.dens = g->densities; ga.colors = g->colors;
+  ga.n = g->n; ga.sh_degree = g->sh_degree;
+  ga.counts = w.counts; ga.offsets = w.offsets; ga.partials = p.partials;
+  ga.g_means = g_means; ga.g_scales = g_scales; ga.g_quats = g_quats; ga.g_dens = g_densities;
+  ga.g_colors = g_colors;
+  {
+    StageTimer t(S_GRADS, s);
+    e = launch_grad_finalize(ga, cs, s);
+  }
+  if (e != hipSuccess) return hip_fail(e, "gradients");
+  return MB_OK;
 }
 
 }  // extern "C"

@@ -26,6 +26,7 @@ constexpr int kRecF4 = 6;  // one render record = 6 float4
 constexpr float kPi = 3.14159265358979323846f;
 constexpr float kSqrtHalfPi = 1.2533141373155003f;  // sqrt(pi/2)
 constexpr float kInvSqrt2 = 0.7071067811865476f;
+constexpr double kMinDepth = 1e-20;  // optical depth below which a pixel is empty
 
 // Render record fields (float index inside the 24-float record).
 enum RecField {

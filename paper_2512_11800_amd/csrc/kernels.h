@@ -64,4 +64,18 @@ struct RenderArgs {
 hipError_t launch_render_forward(const RenderArgs& a, const CamSet& cams, int n_moments,
                                  int n_intervals, hipStream_t s);
 
+hipError_t launch_render_backward(const RenderArgs& r, const float* saved, const float* grad_image,
+                                  const int* sorted_k, float* partials, const CamSet& cams, int n_moments,
+                                  int n_intervals, hipStream_t s);
+
+struct GradArgs {
+  const float *means, *scales, *quats, *dens, *colors;
+  int n, sh_degree;
+  const int* counts;     // [C*n]
+  const int* offsets;    // [C*n]
+  const float* partials; // [E,4,kGradStride]
+  float *g_means, *g_scales, *g_quats, *g_dens, *g_colors;
+};
+hipError_t launch_grad_finalize(const GradArgs& a, const CamSet& cams, hipStream_t s);
+
 }  // namespace mb

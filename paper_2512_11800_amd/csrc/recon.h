@@ -157,6 +157,83 @@ __device__ __forceinline__ float bound_F(const LInv<NH>& L, float y, float beta,
   return lo + beta * w0;
 }
 
+// Canonical representation at y with its atoms (for the adjoint): returns F
+// and fills the other atoms x_i, the flags x_i < y and the weight w_0 at y.
+template <int NH>
+__device__ __forceinline__ float canon_at(const LInv<NH>& L, float y, float beta, float* x, bool* below,
+                                          float& w0) {
+  float z[NH + 1], c[NH + 1];
+  linv_apply<NH>(L, y, z);
+  float zz = 0.f;
+#pragma unroll
+  for (int i = 0; i <= NH; ++i) zz += z[i] * z[i];
+  w0 = fast_rcp(zz);
+  linv_t_apply<NH>(L, z, c);
+  if constexpr (NH == 2) roots2(c, x); else roots3(c, x);
+  float lo = 0.f;
+#pragma unroll
+  for (int i = 0; i < NH; ++i) {
+    float wi = christoffel<NH>(L, x[i]);
+    wi = isfinite(wi) ? wi : 0.f;
+    below[i] = x[i] < y;
+    lo += below[i] ? wi : 0.f;
+  }
+  return lo + beta * w0;
+}
+
+// Adjoint of F(y; b) = sum_{x_i < y} w_i + beta w_0 through the moment
+// equations sum_i w_i x_i^k = b_k (k = 0..2n, x_0 = y): the polynomial
+// Lambda of degree 2n with Lambda(x_i) = [x_i < y], Lambda'(x_i) = 0 (i >= 1)
+// and Lambda(y) = beta has coefficients dF/db_k, and dF/dy = -w_0 Lambda'(y).
+// Built by Hermite interpolation (Newton divided differences on the nodes
+// x_1, x_1, .., x_n, x_n, y), then expanded to monomial coefficients.
+template <int NH>
+__device__ __forceinline__ void hermite_adjoint(float y, const float* xs, const bool* below, float beta,
+                                                float* lam, float& dlam_y) {
+  constexpr int NN = 2 * NH + 1;
+  float z[NN], f[NN], coef[NN];
+#pragma unroll
+  for (int i = 0; i < NH; ++i) {
+    // atoms sent towards infinity carry no weight; keep the arithmetic finite
+    float xi = fminf(fmaxf(xs[i], -1e6f), 1e6f);
+    z[2 * i] = xi;
+    z[2 * i + 1] = xi;
+    f[2 * i] = below[i] ? 1.f : 0.f;
+    f[2 * i + 1] = f[2 * i];
+  }
+  z[NN - 1] = y;
+  f[NN - 1] = beta;
+  coef[0] = f[0];
+#pragma unroll
+  for (int order = 1; order < NN; ++order) {
+#pragma unroll
+    for (int a = 0; a + order < NN; ++a) {
+      float dz = z[a + order] - z[a];
+      f[a] = dz != 0.f ? (f[a + 1] - f[a]) / dz : 0.f;  // equal nodes: zero slope
+    }
+    coef[order] = f[0];
+  }
+  // Newton form -> monomial coefficients
+  float p[NN];
+#pragma unroll
+  for (int k = 0; k < NN; ++k) p[k] = 0.f;
+  p[0] = coef[NN - 1];
+#pragma unroll
+  for (int k = NN - 2; k >= 0; --k) {
+    const int deg = NN - 2 - k;  // degree of p before multiplying by (x - z_k)
+    p[deg + 1] = p[deg];
+#pragma unroll
+    for (int d = deg; d >= 1; --d) p[d] = p[d - 1] - z[k] * p[d];
+    p[0] = coef[k] - z[k] * p[0];
+  }
+  float dl = 0.f;
+#pragma unroll
+  for (int k = NN - 1; k >= 1; --k) dl = dl * y + (float)k * p[k];
+#pragma unroll
+  for (int k = 0; k < NN; ++k) lam[k] = p[k];
+  dlam_y = dl;
+}
+
 // Per-pixel factorisation of the Hankel matrix of b (b_0 = 1). Returns false
 // (and regularises the diagonal) when H is not numerically positive definite.
 template <int NH>
@@ -169,7 +246,7 @@ __device__ __forceinline__ bool hankel_factor(const double* b, LInv<NH>& out) {
     for (int j = 0; j < M; ++j) h[i][j] = b[i + j];
   bool ok = true;
   double lc[M][M];
-  for (int attempt = 0; attempt < 3; ++attempt) {
+  for (int attempt = 0; attempt < 5; ++attempt) {
     ok = true;
 #pragma unroll
     for (int i = 0; i < M; ++i)
@@ -192,10 +269,17 @@ __device__ __forceinline__ bool hankel_factor(const double* b, LInv<NH>& out) {
       }
     }
     if (ok) break;
-    // fallback: bias the diagonal (1e-6, then 1e-3 relative); flagged to the caller
-    double bias = attempt == 0 ? 1e-6 : 1e-3;
+    // fallback: bias the diagonal (1e-6 .. 1 relative); flagged to the caller
+    const double bias = attempt == 0 ? 1e-6 : attempt == 1 ? 1e-3 : attempt == 2 ? 1e-1 : 1.0;
 #pragma unroll
-    for (int i = 0; i < M; ++i) h[i][i] *= (1.0 + bias);
+    for (int i = 0; i < M; ++i) h[i][i] = h[i][i] * (1.0 + bias) + 1e-30;
+  }
+  if (!ok) {
+    // still indefinite: keep the arithmetic finite with the identity
+#pragma unroll
+    for (int i = 0; i < M; ++i)
+#pragma unroll
+      for (int j = 0; j < M; ++j) lc[i][j] = i == j ? 1.0 : 0.0;
   }
   // invert the lower-triangular factor
   double li[M][M];

@@ -1,0 +1,415 @@
+// Backward render: the two-stage adjoint of Sec. 3.3 (Eq. 22, App. D), one
+// workgroup per 16x16 tile as in the forward pass.
+//   pass 1   recompute the pixel's moments (no per-sample state is stored);
+//   setup    Hankel factor; the derivative of the Eq. 15 rescaling is folded
+//            in: a = g (1 - e^-m0) / max(eps, O), b = dL/dO, e0 = dL/dm0;
+//   pass 2   Adjoint-Moment stage: dm = e0 e_0 + sum_i (a . c_i + b) dq_i/dm,
+//            through the quadrature (Eq. 7) and the adjoint of the moment
+//            bounds at every interval edge;
+//   pass 3   Gradient stage: per pair (a . c_i + b) dq_i/dtheta_i + dm . dm_i/dtheta_i
+//            for theta = (mu, Sigma, omega), chained to the record
+//            coefficients, summed over the wave's 64 pixels and written to
+//            one slot per (list entry, wave); a per-Gaussian kernel then sums
+//            the slots (one reduction, no atomics, deterministic).
+#include "render_common.h"
+
+namespace mb {
+
+// Quadrature of one Gaussian with the state its adjoint needs.
+template <int NH, int NQ>
+struct QuadState {
+  float t[NQ], y[NQ], w0[NQ], F[NQ], tau[NQ], T[NQ], sr[NQ], off[NQ];
+  float x[NQ][NH];
+  bool below[NQ][NH];
+  bool cl[NQ];
+  float dt[NQ], ph[NQ], dph[NQ], A[NQ];
+  float q;
+};
+
+__device__ __forceinline__ float dphi_fn(float x) {
+  // d/dx (1 - e^-x)/x = (e^-x - phi(x)) / x
+  if (fabsf(x) < 1e-3f) return -0.5f + x * (1.f / 3.f - x * 0.125f);
+  return (expf(-x) + expm1f(-x) / x) / x;
+}
+
+template <int NH, int NQ>
+__device__ __forceinline__ void quad_state(const RayG& g, const PixelBasis& pb, const LInv<NH>& L, float m0,
+                                           float tn, const RenderArgs& a, QuadState<NH, NQ>& s) {
+  float dtc = g.mu - pb.tc;
+#pragma unroll
+  for (int j = 0; j < NQ; ++j) {
+    s.off[j] = a.kappa * g.sig * a.xq[j];
+    float t = g.mu + s.off[j];
+    s.cl[j] = t < tn;
+    float dtj = s.cl[j] ? (tn - pb.tc) : (dtc + s.off[j]);
+    s.t[j] = s.cl[j] ? tn : t;
+    s.y[j] = warp_y(pb, s.t[j], dtj);
+    s.F[j] = canon_at<NH>(L, s.y[j], a.beta, s.x[j], s.below[j], s.w0[j]);
+    s.tau[j] = m0 * s.F[j];
+    s.T[j] = expf(-s.tau[j]);
+    float r = (s.t[j] - g.mu) * fast_rcp(g.sig);
+    s.sr[j] = s.cl[j] ? expf(-0.5f * r * r) : a.eq[j];
+  }
+  s.q = 0.f;
+#pragma unroll
+  for (int j = 0; j < NQ; ++j) s.A[j] = 0.f;
+#pragma unroll
+  for (int j = 0; j + 1 < NQ; ++j) {
+    s.dt[j] = s.cl[j + 1] ? 0.f : (s.cl[j] ? (g.mu + s.off[j + 1] - tn) : (s.off[j + 1] - s.off[j]));
+    float dtau = s.tau[j + 1] - s.tau[j];
+    s.ph[j] = phi_fn(dtau);
+    s.dph[j] = dphi_fn(dtau);
+    float tds = s.T[j] * s.dt[j] * g.omega * s.sr[j];
+    s.q += tds * s.ph[j];
+    // dq/dtau_j and dq/dtau_{j+1} of this interval's term
+    s.A[j] -= tds * (s.ph[j] + s.dph[j]);
+    s.A[j + 1] += tds * s.dph[j];
+  }
+}
+
+// sum_k dm[k] * d m_k / d(mu, Sigma, omega) for the moments of Eqs. 10-12
+template <int K>
+__device__ __forceinline__ void moment_grads(const RayG& g, const PixelBasis& pb, float tn, const float* dmv,
+                                             float* out) {
+  const float c = kSqrtHalfPi;
+  float mus = fmaxf(g.mu, tn);
+  float ys = warp_y(pb, mus, mus - pb.tc);
+  float yp = warp_dy(pb, mus);
+  float G = ys + yp * (g.mu - mus), Gp = yp;
+  float dG[3] = {Gp, 0.f, 0.f};
+  float q = 1.f + 0.8f * g.mu;
+  float d2 = g.mu > tn ? -3.f * pb.amp / (q * q * q * sqrtf(q)) : 0.f;  // y''(mu)
+  float dGp[3] = {d2, 0.f, 0.f};
+  float is = fast_rcp(g.sig);
+  float bn = (tn - g.mu) * kInvSqrt2 * is;
+  float dbn[3] = {-kInvSqrt2 * is, -bn * is, 0.f};
+  float E = expf(-bn * bn);
+  float ec = erfcf(bn);
+  const float two_rsqrt_pi = 1.1283791670955126f;
+  float m0 = g.omega * g.sig * c * ec;
+  float s2 = g.sig * g.sig;
+  float bnd = Gp * g.omega * s2 * E;
+  float dm0[3], dE[3], dbnd[3];
+#pragma unroll
+  for (int v = 0; v < 3; ++v) {
+    dE[v] = -2.f * bn * E * dbn[v];
+    float dec = -two_rsqrt_pi * E * dbn[v];
+    dm0[v] = c * g.omega * g.sig * dec;
+  }
+  dm0[1] += c * g.omega * ec;
+  dm0[2] += c * g.sig * ec;
+  float ds2[3] = {0.f, 2.f * g.sig, 0.f};
+  float dom[3] = {0.f, 0.f, 1.f};
+#pragma unroll
+  for (int v = 0; v < 3; ++v)
+    dbnd[v] = dGp[v] * g.omega * s2 * E + Gp * dom[v] * s2 * E + Gp * g.omega * ds2[v] * E +
+              Gp * g.omega * s2 * dE[v];
+  float m1 = G * m0 + bnd;
+  float dm1[3];
+#pragma unroll
+  for (int v = 0; v < 3; ++v) {
+    dm1[v] = dG[v] * m0 + G * dm0[v] + dbnd[v];
+    out[v] = dmv[0] * dm0[v] + dmv[1] * dm1[v];
+  }
+  float un = G + Gp * (tn - g.mu);
+  float dun[3];
+#pragma unroll
+  for (int v = 0; v < 3; ++v) dun[v] = dG[v] + dGp[v] * (tn - g.mu) - (v == 0 ? Gp : 0.f);
+  float v2 = Gp * Gp * s2;
+  float dv2[3];
+#pragma unroll
+  for (int v = 0; v < 3; ++v) dv2[v] = 2.f * Gp * dGp[v] * s2 + Gp * Gp * ds2[v];
+  float unp = un, dunp[3] = {dun[0], dun[1], dun[2]};
+  float pm2 = m0, pm1 = m1, dpm2[3] = {dm0[0], dm0[1], dm0[2]}, dpm1[3] = {dm1[0], dm1[1], dm1[2]};
+#pragma unroll
+  for (int k = 2; k <= K; ++k) {
+    float km = (float)(k - 1);
+    float mk = G * pm1 + km * v2 * pm2 + bnd * unp;
+    float dmk[3];
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+      dmk[v] = dG[v] * pm1 + G * dpm1[v] + km * (dv2[v] * pm2 + v2 * dpm2[v]) + dbnd[v] * unp + bnd * dunp[v];
+      out[v] += dmv[k] * dmk[v];
+    }
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+      dunp[v] = dunp[v] * un + unp * dun[v];
+      dpm2[v] = dpm1[v];
+      dpm1[v] = dmk[v];
+    }
+    unp *= un;
+    pm2 = pm1;
+    pm1 = mk;
+  }
+}
+
+struct BwdArgs {
+  RenderArgs r;
+  const float* saved;       // [C,H,W,8]
+  const float* grad_image;  // [C,H,W,3]
+  const int* sorted_k;      // [E] entry index of each sorted list position
+  float* partials;          // [E,4,kGradStride]
+};
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
+template <int K, int NQ>
+__global__ __launch_bounds__(256) void k_render_bwd(BwdArgs ba, CamSet cams) {
+  constexpr int NH = K / 2;
+  const RenderArgs& a = ba.r;
+  __shared__ Stage st;
+  __shared__ int sk[kBlock];
+  const int tiles_per_cam = a.tiles_x * a.tiles_y;
+  const int n_keys = tiles_per_cam * a.n_cams;
+  const int key = remap_xcd(blockIdx.x, gridDim.x);
+  if (key >= n_keys) return;
+  const int ci = key / tiles_per_cam;
+  const int tile = key - ci * tiles_per_cam;
+  const int ty = tile / a.tiles_x, tx = tile - ty * a.tiles_x;
+  const CamConst& c = cams.c[ci];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int px = tx * kTile + (wave & 1) * 8 + (lane & 7);
+  const int py = ty * kTile + (wave >> 1) * 8 + (lane >> 3);
+  const bool inside = px < c.width && py < c.height;
+  const float u = (float)px + 0.5f, v = (float)py + 0.5f;
+  const float rx = (u - c.cx) / c.fx, ry = (v - c.cy) / c.fy;
+  const float lam = sqrtf(1.f + rx * rx + ry * ry);
+  const float tn = c.tn;
+  const int2 rg = a.ranges[key];
+  const size_t pix = inside ? ((size_t)ci * c.height + py) * c.width + px : 0;
+
+  float sv[8] = {0.f, 0.f, 0.f, 0.f, tn + 1.f, 1.f, 0.f, 0.f};
+  float gi[3] = {0.f, 0.f, 0.f};
+  if (inside) {
+    const float4* sp = reinterpret_cast<const float4*>(ba.saved + pix * MB_SAVED_FLOATS_PER_PIXEL);
+    float4 s0 = sp[0], s1 = sp[1];
+    sv[0] = s0.x; sv[1] = s0.y; sv[2] = s0.z; sv[3] = s0.w;
+    sv[4] = s1.x; sv[5] = s1.y; sv[6] = s1.z; sv[7] = s1.w;
+    gi[0] = ba.grad_image[pix * 3];
+    gi[1] = ba.grad_image[pix * 3 + 1];
+    gi[2] = ba.grad_image[pix * 3 + 2];
+  }
+  const PixelBasis pb = make_basis(sv[4], sv[5], tn);
+
+  // ---- pass 1: recompute the moments (identical to the forward pass) -------
+  double acc[K + 1];
+#pragma unroll
+  for (int k = 0; k <= K; ++k) acc[k] = 0.0;
+  for (int b = rg.x; b < rg.y; b += kBlock) {
+    int nb = min(kBlock, rg.y - b);
+    __syncthreads();
+    load_batch(st, a.rec, a.sorted_rec, b, nb);
+    __syncthreads();
+    for (int j = 0; j < nb; ++j) {
+      float dx, dy;
+      bool cov = covers(st, j, u, v, inside, dx, dy);
+      if (__ballot(cov) == 0) continue;
+      if (cov) {
+        RayG g = ray_params(st, j, dx, dy, lam);
+        float m[K + 1];
+        particle_moments<K>(g, pb, tn, m);
+#pragma unroll
+        for (int k = 0; k <= K; ++k) acc[k] += (double)m[k];
+      }
+    }
+  }
+  const float m0 = (float)acc[0];
+  const bool live = acc[0] > kMinDepth;  // as in the forward pass
+  LInv<NH> L;
+  float bk[K + 1];
+  bk[0] = 1.f;
+  if (live) {
+    double bn[K + 1];
+    bn[0] = 1.0;
+#pragma unroll
+    for (int k = 1; k <= K; ++k) {
+      bn[k] = acc[k] / acc[0];
+      bk[k] = (float)bn[k];
+    }
+    hankel_factor<NH>(bn, L);
+  } else {
+#pragma unroll
+    for (int k = 1; k <= K; ++k) bk[k] = 0.f;
+#pragma unroll
+    for (int i = 0; i < (NH + 1) * (NH + 2) / 2; ++i) L.l[i] = 0.f;
+  }
+
+  // ---- Eq. 15 adjoint, folded into the two stages -------------------------
+  const float alpha = -expm1f(-m0);
+  const float oc = fmaxf(a.eps, sv[3]);
+  float ga[3], gb, e0;
+  {
+    float gs = gi[0] * sv[0] + gi[1] * sv[1] + gi[2] * sv[2];
+    float gbg = gi[0] * c.bg[0] + gi[1] * c.bg[1] + gi[2] * c.bg[2];
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) ga[ch] = gi[ch] * alpha / oc;
+    gb = sv[3] > a.eps ? -gs * alpha / (sv[3] * sv[3]) : 0.f;
+    e0 = expf(-m0) * (gs / oc - gbg);
+  }
+
+  const bool active = inside && live;
+  // ---- pass 2: adjoint moments ---------------------------------------------
+  float dm[K + 1];
+#pragma unroll
+  for (int k = 0; k <= K; ++k) dm[k] = 0.f;
+  dm[0] = (inside && live) ? e0 : 0.f;
+  for (int b = rg.x; b < rg.y; b += kBlock) {
+    int nb = min(kBlock, rg.y - b);
+    __syncthreads();
+    load_batch(st, a.rec, a.sorted_rec, b, nb);
+    __syncthreads();
+    for (int j = 0; j < nb; ++j) {
+      float dx, dy;
+      bool cov = covers(st, j, u, v, active, dx, dy);
+      if (__ballot(cov) == 0) continue;
+      if (cov) {
+        RayG g = ray_params(st, j, dx, dy, lam);
+        QuadState<NH, NQ> s;
+        quad_state<NH, NQ>(g, pb, L, m0, tn, a, s);
+        float4 f5 = st.f[5][j];
+        float gbar = ga[0] * f5.y + ga[1] * f5.z + ga[2] * f5.w + gb;
+#pragma unroll
+        for (int e = 0; e < NQ; ++e) {
+          float lamk[2 * NH + 1], dl;
+          hermite_adjoint<NH>(s.y[e], s.x[e], s.below[e], a.beta, lamk, dl);
+          float wgt = gbar * s.A[e];
+          float lb = 0.f;
+#pragma unroll
+          for (int k = 1; k <= K; ++k) {
+            dm[k] += wgt * lamk[k];
+            lb += lamk[k] * bk[k];
+          }
+          dm[0] += wgt * (s.F[e] - lb);
+        }
+      }
+    }
+  }
+
+  // ---- pass 3: per-pair gradients, one reduction per (entry, wave) ---------
+  for (int b = rg.x; b < rg.y; b += kBlock) {
+    int nb = min(kBlock, rg.y - b);
+    __syncthreads();
+    load_batch(st, a.rec, a.sorted_rec, b, nb);
+    if (tid < nb) sk[tid] = ba.sorted_k[b + tid];
+    __syncthreads();
+    for (int j = 0; j < nb; ++j) {
+      float dx, dy;
+      bool cov = covers(st, j, u, v, active, dx, dy);
+      float4* slot = reinterpret_cast<float4*>(ba.partials + ((size_t)sk[j] * 4 + wave) * kGradStride);
+      if (__ballot(cov) == 0) {
+        if (lane == 0) {
+#pragma unroll
+          for (int f = 0; f < kGradStride / 4; ++f) slot[f] = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+        continue;
+      }
+      float gr[G_COUNT];
+#pragma unroll
+      for (int f = 0; f < G_COUNT; ++f) gr[f] = 0.f;
+      if (cov) {
+        RayG g = ray_params(st, j, dx, dy, lam);
+        QuadState<NH, NQ> s;
+        quad_state<NH, NQ>(g, pb, L, m0, tn, a, s);
+        float4 f5 = st.f[5][j];
+        float gbar = ga[0] * f5.y + ga[1] * f5.z + ga[2] * f5.w + gb;
+        // dq / d(mu, Sigma, omega) at fixed moments
+        float dq0 = 0.f, dq1 = 0.f, dq2 = 0.f;
+#pragma unroll
+        for (int e = 0; e < NQ; ++e) {
+          float lamk[2 * NH + 1], dl;
+          hermite_adjoint<NH>(s.y[e], s.x[e], s.below[e], a.beta, lamk, dl);
+          float dtau_dt = -m0 * s.w0[e] * dl * warp_dy(pb, s.t[e]);
+          float dtdmu = s.cl[e] ? 0.f : 1.f;
+          float dtdsig = s.cl[e] ? 0.f : a.kappa * a.xq[e];
+          dq0 += s.A[e] * dtau_dt * dtdmu;
+          dq1 += s.A[e] * dtau_dt * dtdsig;
+        }
+#pragma unroll
+        for (int e = 0; e + 1 < NQ; ++e) {
+          float cdt = s.T[e] * s.ph[e] * g.omega * s.sr[e];
+          float dmu0 = s.cl[e] ? 0.f : 1.f, dmu1 = s.cl[e + 1] ? 0.f : 1.f;
+          float dsg0 = s.cl[e] ? 0.f : a.kappa * a.xq[e], dsg1 = s.cl[e + 1] ? 0.f : a.kappa * a.xq[e + 1];
+          dq0 += cdt * (dmu1 - dmu0);
+          dq1 += cdt * (dsg1 - dsg0);
+          float cs = s.T[e] * s.dt[e] * s.ph[e];
+          if (s.cl[e]) {
+            float r = (s.t[e] - g.mu) * fast_rcp(g.sig);
+            float sj = g.omega * s.sr[e];
+            dq0 += cs * sj * r / g.sig;
+            dq1 += cs * sj * r * r / g.sig;
+          }
+          dq2 += cs * s.sr[e];
+        }
+        float gm[3];
+        moment_grads<K>(g, pb, tn, dm, gm);
+        float gmu = gbar * dq0 + gm[0];
+        float gsig = gbar * dq1 + gm[1];
+        float gom = gbar * dq2 + gm[2];
+        // (mu, Sigma, omega) -> record coefficients (see ray_params)
+        float4 f2 = st.f[2][j], f3 = st.f[3][j], f4 = st.f[4][j];
+        float d = f2.x + 2.f * (f2.y * dx + f2.z * dy) + f2.w * dx * dx + 2.f * f3.x * dx * dy + f3.y * dy * dy;
+        float x = f4.y * dx * dx + 2.f * f4.z * dx * dy + f4.w * dy * dy;
+        float id = fast_rcp(d);
+        float ek = expf(-0.5f * x * id);
+        float gE = gmu * lam * id;
+        float gD = -gmu * g.mu * id - 0.5f * gsig * g.sig * id + 0.5f * gom * g.omega * x * id * id;
+        float gX = -0.5f * gom * g.omega * id;
+        gr[G_D0] = gD;
+        gr[G_D1X] = 2.f * gD * dx;
+        gr[G_D1Y] = 2.f * gD * dy;
+        gr[G_D2XX] = gD * dx * dx;
+        gr[G_D2XY] = 2.f * gD * dx * dy;
+        gr[G_D2YY] = gD * dy * dy;
+        gr[G_E0] = gE;
+        gr[G_EX] = gE * dx;
+        gr[G_EY] = gE * dy;
+        gr[G_XXX] = gX * dx * dx;
+        gr[G_XXY] = 2.f * gX * dx * dy;
+        gr[G_XYY] = gX * dy * dy;
+        float gdx = 2.f * gD * (f2.y + f2.w * dx + f3.x * dy) + gE * f3.w + 2.f * gX * (f4.y * dx + f4.z * dy);
+        float gdy = 2.f * gD * (f2.z + f3.x * dx + f3.y * dy) + gE * f4.x + 2.f * gX * (f4.z * dx + f4.w * dy);
+        gr[G_P0X] = -gdx;
+        gr[G_P0Y] = -gdy;
+        gr[G_W] = gom * ek;
+        gr[G_CR] = s.q * ga[0];
+        gr[G_CG] = s.q * ga[1];
+        gr[G_CB] = s.q * ga[2];
+      }
+#pragma unroll
+      for (int f = 0; f < G_COUNT; ++f) gr[f] = wave_sum(gr[f]);
+      if (lane == 0) {
+        slot[0] = make_float4(gr[0], gr[1], gr[2], gr[3]);
+        slot[1] = make_float4(gr[4], gr[5], gr[6], gr[7]);
+        slot[2] = make_float4(gr[8], gr[9], gr[10], gr[11]);
+        slot[3] = make_float4(gr[12], gr[13], gr[14], gr[15]);
+        slot[4] = make_float4(gr[16], gr[17], 0.f, 0.f);
+      }
+    }
+  }
+}
+
+hipError_t launch_render_backward(const RenderArgs& r, const float* saved, const float* grad_image,
+                                  const int* sorted_k, float* partials, const CamSet& cams, int n_moments,
+                                  int n_intervals, hipStream_t s) {
+  BwdArgs ba{r, saved, grad_image, sorted_k, partials};
+  int n_keys = r.tiles_x * r.tiles_y * r.n_cams;
+  int nblocks = ((n_keys + 7) / 8) * 8;
+  dim3 grid(nblocks), block(kBlock);
+#define MB_LAUNCH(KK, NN)                                                         \
+  if (n_moments == KK && n_intervals == NN) {                                     \
+    hipLaunchKernelGGL((k_render_bwd<KK, NN + 1>), grid, block, 0, s, ba, cams); \
+    return hipGetLastError();                                                     \
+  }
+  MB_LAUNCH(4, 3)
+  MB_LAUNCH(6, 3)
+  MB_LAUNCH(4, 5)
+  MB_LAUNCH(6, 5)
+#undef MB_LAUNCH
+  return hipErrorInvalidValue;
+}
+
+}  // namespace mb

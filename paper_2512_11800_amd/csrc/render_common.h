@@ -1,0 +1,118 @@
+// Per-pair building blocks shared by the forward and backward render
+// kernels: LDS staging of render records, the coverage test, the ray-space
+// Gaussian, the warped moments and the per-Gaussian quadrature.
+#pragma once
+#include "kernels.h"
+#include "recon.h"
+
+namespace mb {
+
+struct Stage {
+  float4 f[kRecF4][kBlock];
+};
+
+struct RayG {
+  float mu, sig, omega;
+};
+
+__device__ __forceinline__ int remap_xcd(int bid, int nblocks) {
+  // blocks are dispatched round-robin over the 8 XCDs; give each XCD a
+  // contiguous run of tiles so neighbouring tiles share its L2
+  int per = nblocks >> 3;
+  return (bid & 7) * per + (bid >> 3);
+}
+
+__device__ __forceinline__ void load_batch(Stage& st, const float4* rec, const int* sorted_rec, int b, int nb) {
+  int tid = threadIdx.x;
+  if (tid < nb) {
+    const float4* src = rec + (size_t)sorted_rec[b + tid] * kRecF4;
+#pragma unroll
+    for (int k = 0; k < kRecF4; ++k) st.f[k][tid] = src[k];
+  }
+}
+
+__device__ __forceinline__ bool covers(const Stage& st, int j, float u, float v, bool inside, float& dx,
+                                       float& dy) {
+  float4 f0 = st.f[0][j], f1 = st.f[1][j];
+  dx = u - f0.x;
+  dy = v - f0.y;
+  float ax = dx - f0.z, ay = dy - f0.w;
+  float c1 = ax * f1.x + ay * f1.y;
+  float c2 = -ax * f1.y + ay * f1.x;
+  return inside && fabsf(c1) <= f1.z && fabsf(c2) <= f1.w;
+}
+
+// Eqs. 4-6 for the pixel ray in the projected-mean frame (see common.h)
+__device__ __forceinline__ RayG ray_params(const Stage& st, int j, float dx, float dy, float lam) {
+  float4 f2 = st.f[2][j], f3 = st.f[3][j], f4 = st.f[4][j];
+  float w = st.f[5][j].x;
+  float d = f2.x + 2.f * (f2.y * dx + f2.z * dy) + f2.w * dx * dx + 2.f * f3.x * dx * dy + f3.y * dy * dy;
+  float e = f3.z + f3.w * dx + f4.x * dy;
+  float x = f4.y * dx * dx + 2.f * f4.z * dx * dy + f4.w * dy * dy;
+  float id = fast_rcp(d);
+  RayG g;
+  g.mu = lam * e * id;
+  g.sig = lam * fast_rsq(d);
+  g.omega = w * expf(-0.5f * x * id);
+  return g;
+}
+
+// warped moments of one ray Gaussian, Eqs. 10-12 (t_f -> inf), in the pixel's
+// moment variable; the boundary term enters with '+' (App. C)
+template <int K>
+__device__ __forceinline__ void particle_moments(const RayG& g, const PixelBasis& pb, float tn, float* m) {
+  float mus = fmaxf(g.mu, tn);
+  float ys = warp_y(pb, mus, mus - pb.tc);
+  float yp = warp_dy(pb, mus);
+  float gg = ys + yp * (g.mu - mus);
+  float is = fast_rcp(g.sig);
+  float bn = (tn - g.mu) * kInvSqrt2 * is;
+  float e = expf(-bn * bn);
+  float s2 = g.sig * g.sig;
+  m[0] = g.omega * g.sig * kSqrtHalfPi * erfcf(bn);
+  float bnd = yp * g.omega * s2 * e;
+  m[1] = gg * m[0] + bnd;
+  float un = gg + yp * (tn - g.mu);
+  float unp = un;
+  float v2 = yp * yp * s2;
+#pragma unroll
+  for (int k = 2; k <= K; ++k) {
+    m[k] = gg * m[k - 1] + (float)(k - 1) * v2 * m[k - 2] + bnd * unp;
+    unp *= un;
+  }
+}
+
+__device__ __forceinline__ float phi_fn(float x) {
+  // (1 - e^-x) / x, continued by its series near 0
+  return fabsf(x) < 1e-4f ? 1.f - x * (0.5f - x * (1.f / 6.f)) : -expm1f(-x) / x;
+}
+
+// Quadrature of Eq. 7 for one Gaussian against the pixel's bounds; returns q.
+template <int NH, int NQ>
+__device__ __forceinline__ float particle_quadrature(const RayG& g, const PixelBasis& pb, const LInv<NH>& L,
+                                                     float m0, float tn, const RenderArgs& a) {
+  float tau[NQ], off[NQ], sj[NQ];
+  bool cl[NQ];
+  float dtc = g.mu - pb.tc;
+#pragma unroll
+  for (int j = 0; j < NQ; ++j) {
+    off[j] = a.kappa * g.sig * a.xq[j];
+    float t = g.mu + off[j];
+    cl[j] = t < tn;
+    float dt = cl[j] ? (tn - pb.tc) : (dtc + off[j]);
+    t = cl[j] ? tn : t;
+    float y = warp_y(pb, t, dt);
+    tau[j] = m0 * bound_F<NH>(L, y, a.beta);
+    float r = (t - g.mu) * fast_rcp(g.sig);
+    sj[j] = g.omega * (cl[j] ? expf(-0.5f * r * r) : a.eq[j]);
+  }
+  float q = 0.f;
+#pragma unroll
+  for (int j = 0; j + 1 < NQ; ++j) {
+    float delta = cl[j + 1] ? 0.f : (cl[j] ? (g.mu + off[j + 1] - tn) : (off[j + 1] - off[j]));
+    q += expf(-tau[j]) * delta * phi_fn(tau[j + 1] - tau[j]) * sj[j];
+  }
+  return q;
+}
+
+}  // namespace mb

@@ -32,7 +32,22 @@ def proxy_error(scene, cam, opts):
     gp = M.project(g, cam, opts).cpu().numpy().astype(np.float64)
     op = screen_proxy(scene_tensors(scene), cam, opts.conf_c)
     keep_o = op.valid.numpy()
+    # the GPU keeps a Gaussian only if its rectangle's box reaches a pixel centre
+    ext = (np.abs(op.axes.numpy()) * op.half.numpy()[:, :, None]).sum(1)
+    m2 = op.mean2d.numpy()
+    x0 = np.ceil(m2[:, 0] - ext[:, 0] - 0.5)
+    x1 = np.floor(m2[:, 0] + ext[:, 0] - 0.5)
+    y0 = np.ceil(m2[:, 1] - ext[:, 1] - 0.5)
+    y1 = np.floor(m2[:, 1] + ext[:, 1] - 0.5)
+    on_screen = ((np.maximum(x0, 0) <= np.minimum(x1, cam.width - 1))
+                 & (np.maximum(y0, 0) <= np.minimum(y1, cam.height - 1)))
+    near_edge = ((np.abs(x0 - (cam.width - 1)) <= 1) | (np.abs(x1) <= 1)
+                 | (np.abs(y0 - (cam.height - 1)) <= 1) | (np.abs(y1) <= 1))
     keep_g = gp[:, 6] > 0
+    amb_o = op.ambiguous.numpy()
+    # decisions that must agree: clearly on screen, or culled by the oracle
+    mismatch_n = int((keep_o & on_screen & ~near_edge & ~keep_g & ~amb_o).sum()
+                     + (keep_g & ~keep_o & ~amb_o).sum())
     # the GPU also drops Gaussians whose rectangle misses the image
     both = keep_o & keep_g
     c_err = np.abs(gp[both, :2] - op.mean2d.numpy()[both]).max(initial=0.0)
@@ -46,7 +61,7 @@ def proxy_error(scene, cam, opts):
     h = op.half.numpy()[both]
     # axis angle error relative to the conditioning of the eigenvectors
     orient = (angle * (1 - (h[:, 0] / np.maximum(h[:, 1], 1e-300)) ** 2)).max(initial=0.0)
-    mismatch = int((keep_o & ~keep_g).sum())
+    mismatch = mismatch_n
     return dict(centre=c_err, half=h_err, orient=orient, angle=angle.max(initial=0.0),
                 mismatch=mismatch, amb=int(op.ambiguous.numpy().sum()), n_keep=int(both.sum()))
 

@@ -20,12 +20,12 @@ def test_proxies_match_oracle():
     scene, cams, opts = W.w1_small()
     pe = proxy_error(scene, cams[0], opts)
     log("[proxy] W1", pe)
-    assert pe["mismatch"] <= pe["amb"]
+    assert pe["mismatch"] == 0
     assert pe["centre"] < 1e-3 and pe["half"] < 1e-3 and pe["orient"] < 1e-5
     scene2, cams2, opts2 = W.w2_clusters(n=100_000)
     pe2 = proxy_error(scene2, cams2[0], opts2)
     log("[proxy] W2 subset", pe2)
-    assert pe2["mismatch"] <= max(pe2["amb"], 2)
+    assert pe2["mismatch"] == 0
     assert pe2["centre"] < 5e-3 and pe2["half"] < 5e-3 and pe2["orient"] < 1e-5
 
 
@@ -79,6 +79,19 @@ def test_w2_full_size_sampled(k_mom):
     ref = oracle.render_image(scene, cam, opts, pixels=pix, margin_tol=tol_m, orient_eps=tol_o)
     log(f"[w2 K={k_mom}] entries={st.n_entries} sampled={len(pix)} pairs={ref['n_pairs']}")
     mx, worst = compare(img[0].reshape(-1, 3)[pix], ref, f"W2 K={k_mom}")
+    assert mx <= TOL
+
+
+@pytest.mark.parametrize("k_mom", [4, 6])
+def test_full_coverage_subset(k_mom):
+    """Every Gaussian on every pixel (debug coverage of the gradient checks):
+    pixels far from all Gaussians have optical depths near float32 underflow."""
+    scene, cams, opts = W.w3_fd_subset()
+    opts.n_moments = k_mom
+    img, saved, st = gpu_render(scene, cams, opts)
+    assert np.all(np.isfinite(img))
+    ref = oracle.render_image(scene, cams[0], opts)
+    mx, _ = compare(img[0].reshape(-1, 3), ref, f"full coverage K={k_mom}")
     assert mx <= TOL
 
 
