@@ -61,6 +61,14 @@ struct CamSet {
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float fast_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 
+// erfc with an exact shortcut: for b < -3.9, erfc(b) = 2 - erfc(-b) with
+// erfc(-b) < 4e-8, below half an ulp of 2, so the float result is 2 exactly.
+// Most ray Gaussians lie far beyond the near plane (b << 0) and skip erfcf.
+__device__ __forceinline__ float erfc_fast(float b) {
+  if (b < -3.9f) return 2.f;
+  return erfcf(b);
+}
+
 // ---------------------------------------------------------------------------
 // Minimal forward-mode dual number (one tangent) for the per-Gaussian chain
 // rule of the backward pass: the same templated code computes the record
@@ -225,7 +233,7 @@ __device__ __forceinline__ float warp_y(const PixelBasis& b, float t, float dt) 
   float q15 = q * sq;
   float num = (q + b.p) * q + b.p * b.p;
   float den = (q15 + b.p15) * (b.p15 * q15);
-  return b.amp * dt * num / den;
+  return b.amp * dt * num * fast_rcp(den);
 }
 
 // dy/dt at depth t: 1.5 amp q^-2.5

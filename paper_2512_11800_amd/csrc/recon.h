@@ -67,8 +67,8 @@ __device__ __forceinline__ void roots2(const float* c, float* x) {
   float disc = fmaxf(c[1] * c[1] - 4.f * c[2] * c[0], 0.f);
   float sq = sqrtf(disc);
   float q = -0.5f * (c[1] + copysignf(sq, c[1]));
-  x[0] = q / c[2];
-  x[1] = c[0] / q;
+  x[0] = q * fast_rcp(c[2]);
+  x[1] = c[0] * fast_rcp(q);
 }
 
 __device__ __forceinline__ float cubic_newton(const float* c, float x, int iters) {

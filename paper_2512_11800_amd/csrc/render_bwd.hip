@@ -46,9 +46,9 @@ __device__ __forceinline__ void quad_state(const RayG& g, const PixelBasis& pb, 
     s.y[j] = warp_y(pb, s.t[j], dtj);
     s.F[j] = canon_at<NH>(L, s.y[j], a.beta, s.x[j], s.below[j], s.w0[j]);
     s.tau[j] = m0 * s.F[j];
-    s.T[j] = expf(-s.tau[j]);
+    s.T[j] = __expf(-s.tau[j]);
     float r = (s.t[j] - g.mu) * fast_rcp(g.sig);
-    s.sr[j] = s.cl[j] ? expf(-0.5f * r * r) : a.eq[j];
+    s.sr[j] = s.cl[j] ? __expf(-0.5f * r * r) : a.eq[j];
   }
   s.q = 0.f;
 #pragma unroll
@@ -83,8 +83,8 @@ __device__ __forceinline__ void moment_grads(const RayG& g, const PixelBasis& pb
   float is = fast_rcp(g.sig);
   float bn = (tn - g.mu) * kInvSqrt2 * is;
   float dbn[3] = {-kInvSqrt2 * is, -bn * is, 0.f};
-  float E = expf(-bn * bn);
-  float ec = erfcf(bn);
+  float E = __expf(-bn * bn);
+  float ec = erfc_fast(bn);
   const float two_rsqrt_pi = 1.1283791670955126f;
   float m0 = g.omega * g.sig * c * ec;
   float s2 = g.sig * g.sig;
@@ -354,7 +354,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(BwdArgs ba, CamSet cams) {
         float d = f2.x + 2.f * (f2.y * dx + f2.z * dy) + f2.w * dx * dx + 2.f * f3.x * dx * dy + f3.y * dy * dy;
         float x = f4.y * dx * dx + 2.f * f4.z * dx * dy + f4.w * dy * dy;
         float id = fast_rcp(d);
-        float ek = expf(-0.5f * x * id);
+        float ek = __expf(-0.5f * x * id);
         float gE = gmu * lam * id;
         float gD = -gmu * g.mu * id - 0.5f * gsig * g.sig * id + 0.5f * gom * g.omega * x * id * id;
         float gX = -0.5f * gom * g.omega * id;

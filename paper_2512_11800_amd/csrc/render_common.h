@@ -53,7 +53,7 @@ __device__ __forceinline__ RayG ray_params(const Stage& st, int j, float dx, flo
   RayG g;
   g.mu = lam * e * id;
   g.sig = lam * fast_rsq(d);
-  g.omega = w * expf(-0.5f * x * id);
+  g.omega = w * __expf(-0.5f * x * id);
   return g;
 }
 
@@ -67,9 +67,9 @@ __device__ __forceinline__ void particle_moments(const RayG& g, const PixelBasis
   float gg = ys + yp * (g.mu - mus);
   float is = fast_rcp(g.sig);
   float bn = (tn - g.mu) * kInvSqrt2 * is;
-  float e = expf(-bn * bn);
+  float e = __expf(-bn * bn);
   float s2 = g.sig * g.sig;
-  m[0] = g.omega * g.sig * kSqrtHalfPi * erfcf(bn);
+  m[0] = g.omega * g.sig * kSqrtHalfPi * erfc_fast(bn);
   float bnd = yp * g.omega * s2 * e;
   m[1] = gg * m[0] + bnd;
   float un = gg + yp * (tn - g.mu);
@@ -104,13 +104,13 @@ __device__ __forceinline__ float particle_quadrature(const RayG& g, const PixelB
     float y = warp_y(pb, t, dt);
     tau[j] = m0 * bound_F<NH>(L, y, a.beta);
     float r = (t - g.mu) * fast_rcp(g.sig);
-    sj[j] = g.omega * (cl[j] ? expf(-0.5f * r * r) : a.eq[j]);
+    sj[j] = g.omega * (cl[j] ? __expf(-0.5f * r * r) : a.eq[j]);
   }
   float q = 0.f;
 #pragma unroll
   for (int j = 0; j + 1 < NQ; ++j) {
     float delta = cl[j + 1] ? 0.f : (cl[j] ? (g.mu + off[j + 1] - tn) : (off[j + 1] - off[j]));
-    q += expf(-tau[j]) * delta * phi_fn(tau[j + 1] - tau[j]) * sj[j];
+    q += __expf(-tau[j]) * delta * phi_fn(tau[j + 1] - tau[j]) * sj[j];
   }
   return q;
 }
