@@ -145,6 +145,32 @@ int mb_render_backward(const mb_gaussians *g, const mb_camera *cams, int32_t n_c
                        const float *grad_image, float *g_means, float *g_scales,
                        float *g_quats, float *g_densities, float *g_colors, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Learned surrogate of the moment -> optical-depth reconstruction (not part of
+ * the paper): a 7 -> 64 -> 64 -> 1 MLP, tanh-GELU hidden layers, output
+ * F = sigmoid(.) in (0, 1) standing for the normalised bound interpolation of
+ * Sec. 3.2, so the optical depth is m_0 F. Weights and activations bf16,
+ * accumulation fp32 (matrix cores).
+ *  theta   [P] fp32 parameters, P = mb_mlp_param_count(), in the order
+ *          W1[64][7], b1[64], W2[64][64] (out, in), b2[64], w3[64], b3.
+ *  packed  mb_mlp_packed_bytes() bytes: bf16 kernel copy made by mb_mlp_pack.
+ *  x       [n][8] fp32 rows: 6 moment features, the query, and m_0 (used by
+ *          the loss only). All device pointers.
+ * mb_mlp_forward writes F [n]. mb_mlp_loss_grad evaluates the loss
+ * mean_i (exp(-m0_i F_i) - t_i)^2 against target transmittances t [n] and
+ * writes its gradient grad [P] and (if not NULL) the loss [1]; ws must hold
+ * mb_mlp_workspace_bytes(n) bytes. mb_adam_step applies one Adam update
+ * (step counts from 1) to theta with moments m, v [count]. */
+int32_t mb_mlp_param_count(void);
+size_t mb_mlp_packed_bytes(void);
+size_t mb_mlp_workspace_bytes(int64_t batch);
+int mb_mlp_pack(const float *theta, void *packed, void *stream);
+int mb_mlp_forward(const void *packed, const float *x, int64_t n, float *f_out, void *stream);
+int mb_mlp_loss_grad(const void *packed, const float *x, const float *t_target, int64_t n, float *grad,
+                     float *loss, void *ws, size_t ws_bytes, void *stream);
+int mb_adam_step(float *theta, float *m, float *v, const float *grad, int64_t count, int32_t step,
+                 float lr, float beta1, float beta2, float eps, void *stream);
+
 /* Stage timing. While enabled, every entry point records HIP events around
  * each of its stages on its stream (a small per-process overhead).
  * mb_profile_read waits for the recorded events, writes up to `max` stage

@@ -64,6 +64,15 @@ SIGNATURES = [
     ("mb_render_forward", c_int32, [POINTER(MbGaussians), POINTER(MbCamera), c_int32,
                                     POINTER(MbOptions), c_void_p, c_size_t, c_void_p, c_size_t,
                                     c_int64, c_void_p, c_void_p, c_void_p]),
+    ("mb_mlp_param_count", c_int32, []),
+    ("mb_mlp_packed_bytes", c_size_t, []),
+    ("mb_mlp_workspace_bytes", c_size_t, [c_int64]),
+    ("mb_mlp_pack", c_int32, [c_void_p, c_void_p, c_void_p]),
+    ("mb_mlp_forward", c_int32, [c_void_p, c_void_p, c_int64, c_void_p, c_void_p]),
+    ("mb_mlp_loss_grad", c_int32, [c_void_p, c_void_p, c_void_p, c_int64, c_void_p, c_void_p,
+                                   c_void_p, c_size_t, c_void_p]),
+    ("mb_adam_step", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_int64, c_int32,
+                               c_float, c_float, c_float, c_float, c_void_p]),
     ("mb_profile_enable", None, [c_int32]),
     ("mb_profile_read", c_int32, [POINTER(ctypes.c_double), POINTER(c_int64), c_int32]),
     ("mb_render_backward", c_int32, [POINTER(MbGaussians), POINTER(MbCamera), c_int32,

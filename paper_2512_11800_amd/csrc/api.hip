@@ -439,4 +439,58 @@ int mb_render_backward(const mb_gaussians* g, const mb_camera* cams, int32_t n_c
   return MB_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Learned surrogate of the reconstruction (MLP, bf16 weights, fp32 accumulation)
+// ---------------------------------------------------------------------------
+int32_t mb_mlp_param_count(void) { return mlp_param_count(); }
+size_t mb_mlp_packed_bytes(void) { return mlp_packed_bytes(); }
+size_t mb_mlp_workspace_bytes(int64_t batch) { return batch < 0 ? 0 : mlp_workspace_bytes(batch); }
+
+int mb_mlp_pack(const float* theta, void* packed, void* stream) {
+  if (!theta || !packed) return fail(MB_ERR_ARG, "null parameter or packed-weight pointer");
+  hipError_t e;
+  {
+    StageTimer t(S_MLP, (hipStream_t)stream);
+    e = launch_mlp_pack(theta, packed, (hipStream_t)stream);
+  }
+  return e == hipSuccess ? MB_OK : hip_fail(e, "mlp_pack");
+}
+
+int mb_mlp_forward(const void* packed, const float* x, int64_t n, float* f_out, void* stream) {
+  if (n < 0) return fail(MB_ERR_ARG, "negative batch");
+  if (n > 0 && (!packed || !x || !f_out)) return fail(MB_ERR_ARG, "null MLP argument");
+  hipError_t e;
+  {
+    StageTimer t(S_MLP, (hipStream_t)stream);
+    e = launch_mlp_forward(packed, x, n, f_out, (hipStream_t)stream);
+  }
+  return e == hipSuccess ? MB_OK : hip_fail(e, "mlp_forward");
+}
+
+int mb_mlp_loss_grad(const void* packed, const float* x, const float* t_target, int64_t n, float* grad, float* loss,
+                     void* ws, size_t ws_bytes, void* stream) {
+  if (n <= 0) return fail(MB_ERR_ARG, "batch must be positive");
+  if (!packed || !x || !t_target || !grad) return fail(MB_ERR_ARG, "null MLP argument");
+  size_t need = mlp_workspace_bytes(n);
+  if (!ws || ws_bytes < need) return fail(MB_ERR_WORKSPACE, "MLP workspace needs %zu bytes, got %zu", need, ws_bytes);
+  hipError_t e;
+  {
+    StageTimer t(S_MLP, (hipStream_t)stream);
+    e = launch_mlp_loss_grad(packed, x, t_target, n, grad, loss, (float*)ws, (hipStream_t)stream);
+  }
+  return e == hipSuccess ? MB_OK : hip_fail(e, "mlp_loss_grad");
+}
+
+int mb_adam_step(float* theta, float* m, float* v, const float* grad, int64_t count, int32_t step, float lr,
+                 float beta1, float beta2, float eps, void* stream) {
+  if (count <= 0 || !theta || !m || !v || !grad) return fail(MB_ERR_ARG, "bad Adam arguments");
+  if (step < 1) return fail(MB_ERR_ARG, "Adam step counts from 1");
+  hipError_t e;
+  {
+    StageTimer t(S_MLP, (hipStream_t)stream);
+    e = launch_adam(theta, m, v, grad, count, step, lr, beta1, beta2, eps, (hipStream_t)stream);
+  }
+  return e == hipSuccess ? MB_OK : hip_fail(e, "adam");
+}
+
 }  // extern "C"

@@ -78,4 +78,15 @@ struct GradArgs {
 };
 hipError_t launch_grad_finalize(const GradArgs& a, const CamSet& cams, hipStream_t s);
 
+// learned surrogate (mlp.hip)
+int mlp_param_count();
+size_t mlp_packed_bytes();
+size_t mlp_workspace_bytes(int64_t n);
+hipError_t launch_mlp_pack(const float* theta, void* packed, hipStream_t s);
+hipError_t launch_mlp_forward(const void* packed, const float* x, int64_t n, float* f, hipStream_t s);
+hipError_t launch_mlp_loss_grad(const void* packed, const float* x, const float* t, int64_t n, float* grad,
+                                float* loss, float* ws, hipStream_t s);
+hipError_t launch_adam(float* th, float* m, float* v, const float* g, int64_t count, int step, float lr, float b1,
+                       float b2, float eps, hipStream_t s);
+
 }  // namespace mb

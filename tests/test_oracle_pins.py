@@ -583,3 +583,60 @@ def test_bounds_invariant_under_affine_moment_variable(n):
     t1, _, _ = bound_tau(m1[None].expand(25, -1), _t(etas), n, 0.25)
     t2, _, _ = bound_tau(m2[None].expand(25, -1), _t((etas - a) / bsc), n, 0.25)
     assert torch.allclose(t1, t2, atol=1e-10)
+
+
+# ---------------------------------------------------------------------------
+# Surrogate reference (not in the paper): pinned to finite differences and to
+# torch float64 autograd of the same network.
+# ---------------------------------------------------------------------------
+
+def _mlp_batch(n, seed):
+    rng = np.random.default_rng(seed)
+    x = np.concatenate([rng.normal(0, 1, (n, 6)), rng.uniform(-4, 4, (n, 1)),
+                        rng.uniform(0.05, 3, (n, 1))], axis=1)
+    t = rng.uniform(0, 1, n)
+    return x, t
+
+
+def test_surrogate_reference_gradient_vs_finite_differences():
+    from oracle import surrogate as S
+    theta = S.init_params(3)
+    x, t = _mlp_batch(40, 4)
+    loss, g = S.loss_grad(theta, x, t, bf16_mode=False)
+    rng = np.random.default_rng(5)
+    for i in rng.choice(S.N_PARAMS, 25, replace=False):
+        h = 1e-6
+        tp = theta.copy(); tp[i] += h
+        tm = theta.copy(); tm[i] -= h
+        fd = (S.loss_grad(tp, x, t, False)[0] - S.loss_grad(tm, x, t, False)[0]) / (2 * h)
+        assert g[i] == pytest.approx(fd, rel=1e-5, abs=1e-10)
+
+
+def test_surrogate_reference_vs_torch_autograd():
+    from oracle import surrogate as S
+    theta = S.init_params(7)
+    x, t = _mlp_batch(64, 8)
+    loss, g = S.loss_grad(theta, x, t, bf16_mode=False)
+    th = torch.tensor(theta, requires_grad=True)
+    p, o = {}, 0
+    for k, s in S.SIZES.items():
+        n = int(np.prod(s))
+        p[k] = th[o:o + n].reshape(s)
+        o += n
+    xt = torch.tensor(x)
+    gelu = lambda v: 0.5 * v * (1 + torch.tanh(S.GELU_C * (v + S.GELU_A * v ** 3)))
+    a1 = gelu(xt[:, :7] @ p["W1"].T + p["b1"])
+    a2 = gelu(a1 @ p["W2"].T + p["b2"])
+    f = torch.sigmoid(a2 @ p["w3"] + p["b3"][0])
+    lt = ((torch.exp(-xt[:, 7] * f) - torch.tensor(t)) ** 2).mean()
+    lt.backward()
+    assert float(lt) == pytest.approx(loss, rel=1e-12)
+    assert np.allclose(th.grad.numpy(), g, rtol=1e-9, atol=1e-14)
+
+
+def test_bf16_rounding_is_nearest_even():
+    from oracle.surrogate import bf16
+    assert bf16(1.0) == 1.0
+    assert bf16(1.0 + 2 ** -8) == 1.0          # tie -> even
+    assert bf16(1.0 + 3 * 2 ** -8) == 1.0 + 2 ** -6  # tie -> even (up)
+    assert bf16(1.0 + 2 ** -8 + 2 ** -12) == 1.0 + 2 ** -7
