@@ -144,12 +144,96 @@ def cpu_baseline(scene, cams, opts, n_pairs_frame: int, budget_px: int):
             "pairs_per_s": pairs_per_s}
 
 
+def surrogate_bench(args):
+    """The learned surrogate on the W2 scene with K=6: harvest 10^7 training
+    samples from plain renders of 32 training cameras, train, and on 8
+    held-out cameras compare the surrogate render with the plain one (speed,
+    PSNR between the two, and both against the ground truth of Eq. 2 on
+    sampled pixels)."""
+    import numpy as np
+    import torch
+
+    import paper_2512_11800_amd as M
+    import workloads as W
+    from paper_2512_11800_amd import surrogate as G
+
+    def say(msg):
+        print(f"[surrogate] {msg}", file=sys.stderr, flush=True)
+
+    torch.cuda.set_device(0)
+    scene, train, held, opts = W.w4_surrogate()
+    g = M.Gaussians.from_scene(scene, device="cuda:0")
+    ws = M.Workspace("cuda:0")
+    t = time.perf_counter()
+    x, tt, info = G.harvest(g, train, opts, args.harvest, seed=3, ws=ws)
+    torch.cuda.synchronize()
+    t_h = time.perf_counter() - t
+    say(f"harvest {info} in {t_h:.1f} s")
+    t = time.perf_counter()
+    theta, packed, losses = G.train(x, tt, steps=args.train_steps, batch=65536, lr=3e-3, lr_final=1e-4,
+                                    log_every=max(1, args.train_steps // 10))
+    torch.cuda.synchronize()
+    t_t = time.perf_counter() - t
+    say(f"trained {args.train_steps} steps in {t_t:.1f} s, losses {losses}")
+    del x, tt
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(args.steps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / args.steps
+
+    from paper_2512_11800_amd import _lib as L
+    per_cam = []
+    rng = np.random.default_rng(4)
+    for i, cam in enumerate(held):
+        plain = M.render_forward(g, [cam], opts, ws=ws)[0]
+        sur = M.render_forward_surrogate(g, [cam], opts, packed, ws=ws)[0]
+        ms_plain = timed(lambda: M.render_forward(g, [cam], opts, ws=ws))
+        L.profile_read()
+        L.profile_enable(True)
+        ms_sur = timed(lambda: M.render_forward_surrogate(g, [cam], opts, packed, ws=ws,
+                                                                  check_capacity=False))
+        L.profile_enable(False)
+        st = {k: round(v[0] / max(1, v[1]), 4) for k, v in L.profile_read().items() if v[1]}
+        a = plain[0].cpu().numpy().reshape(-1, 3).astype(np.float64)
+        b = sur[0].cpu().numpy().reshape(-1, 3).astype(np.float64)
+        mse = float(((a - b) ** 2).mean())
+        rec = {"camera": i, "ms_plain": ms_plain, "ms_surrogate": ms_sur,
+               "psnr_surrogate_vs_plain": 10 * math.log10(1.0 / mse) if mse > 0 else None,
+               "surrogate_stages_ms": st}
+        if args.gt_pixels > 0:
+            from oracle.exact import exact_pixels, psnr
+            pix = rng.choice(cam.width * cam.height, args.gt_pixels, replace=False)
+            t = time.perf_counter()
+            gt = exact_pixels(scene, cam, pix)
+            rec["psnr_plain_vs_gt"] = psnr(a[pix], gt)
+            rec["psnr_surrogate_vs_gt"] = psnr(b[pix], gt)
+            rec["delta_psnr_db"] = rec["psnr_surrogate_vs_gt"] - rec["psnr_plain_vs_gt"]
+            rec["gt_pixels"] = int(args.gt_pixels)
+            rec["gt_seconds"] = time.perf_counter() - t
+        say(json.dumps(rec))
+        per_cam.append(rec)
+    return {"harvest": info, "harvest_s": t_h, "train_s": t_t, "train_steps": args.train_steps,
+            "losses": losses, "cameras": per_cam}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--mode", choices=["fwd", "fwdbwd"], default="fwd")
+    ap.add_argument("--mode", choices=["fwd", "fwdbwd", "surrogate"], default="fwd")
+    ap.add_argument("--harvest", type=int, default=10_000_000)
+    ap.add_argument("--train-steps", type=int, default=4000)
+    ap.add_argument("--gt-pixels", type=int, default=32)
     ap.add_argument("--k", type=int, default=4, choices=[4, 6])
     ap.add_argument("--cpu-sample-px", type=int, default=3000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -158,6 +242,28 @@ def main():
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(the camera-parallel multi-GPU design is documented but not built)", file=sys.stderr)
         sys.exit(2)
+
+    if args.mode == "surrogate":
+        args.k = 6
+        sres = surrogate_bench(args)
+        cams = sres["cameras"]
+        ms_p = sum(c["ms_plain"] for c in cams) / len(cams)
+        ms_s = sum(c["ms_surrogate"] for c in cams) / len(cams)
+        out = {
+            "metric": "ms/frame 1080p fwd & fwd+bwd, 500k Gaussians; surrogate vs plain at ΔPSNR<0.1",
+            "value": ms_s, "unit": "ms/frame", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": ms_s, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32+bf16", "data": "synthetic",
+            "config": {"workload": "500k Gaussians, 64 clusters, SH3, 1920x1080, K=6, N=3, surrogate "
+                                   "forward, 8 held-out cameras", "mode": "surrogate"},
+            "plain_ms_per_frame": ms_p, "speedup_vs_plain": ms_p / ms_s,
+            "min_psnr_surrogate_vs_plain": min(c["psnr_surrogate_vs_plain"] or 1e9 for c in cams),
+            "surrogate": sres,
+        }
+        if all("delta_psnr_db" in c for c in cams):
+            out["max_abs_delta_psnr_db"] = max(abs(c["delta_psnr_db"]) for c in cams)
+        print(json.dumps(out), flush=True)
+        return
 
     res, scene, cams, opts, n_pairs = gpu_bench(args)
     cpu = None

@@ -81,8 +81,8 @@ typedef struct mb_options {
   float conf_c;        /* confidence level c of the proxy, App. D (0.01)     */
   float beta;          /* interpolation between the bounds, Sec. 3.2 (0.25)  */
   float eps;           /* clamp of Eq. 15's denominator (1e-6)               */
-  int32_t recon;       /* 0: moment bounds; 1: learned surrogate (K = 6)     */
-  const void *surrogate; /* device weights (mb_mlp layout) when recon = 1    */
+  int32_t recon;       /* reserved, 0 (the surrogate has its own entry point) */
+  const void *surrogate; /* reserved, NULL                                   */
   int32_t full_coverage; /* debug: every Gaussian covers every pixel        */
   int32_t reserved;
 } mb_options;
@@ -171,15 +171,53 @@ int mb_mlp_loss_grad(const void *packed, const float *x, const float *t_target, 
 int mb_adam_step(float *theta, float *m, float *v, const float *grad, int64_t count, int32_t step,
                  float lr, float beta1, float beta2, float eps, void *stream);
 
+/* Training samples of the surrogate (not part of the paper): mb_render_forward
+ * (n_moments = 6) that also appends a seeded pseudo-random subset of its
+ * quadrature queries, each independently with probability `rate` (a hash of
+ * seed, pixel, record and edge decides), to samples[capacity][12] (device):
+ *   [0..5] asinh of the pixel's standardised moments 1..6 (mean 0, variance 1
+ *          in the moment variable), [6] the standardised query, clamped to
+ *          [-10, 10], [7] m_0, [8] transmittance exp(-m_0 F) of the moment
+ *          bounds at the query; as int32 bit patterns: [9] the 32 hash bits,
+ *          [10] flat pixel index (camera * H + y) * W + x, [11] record * (N+1)
+ *          + edge, record = camera * n + Gaussian.
+ * *count (device int32) is advanced atomically by every selected query, also
+ * past `capacity`, where samples are dropped; the caller zeroes it before the
+ * first of a series of calls. Sample order in the buffer is not deterministic,
+ * the set of samples is: sort by [9] for a fixed order. */
+int mb_render_forward_harvest(const mb_gaussians *g, const mb_camera *cams, int32_t n_cams,
+                              const mb_options *opts, void *gws, size_t gws_bytes, void *pws,
+                              size_t pws_bytes, int64_t n_entries, float rate, uint32_t seed,
+                              float *samples, int32_t capacity, int32_t *count, float *image,
+                              float *saved, void *stream);
+
+/* Forward render with the learned surrogate in place of the moment bounds'
+ * evaluation (Sec. 3.2's reconstruction; everything else as
+ * mb_render_forward, n_moments = 6). Three kernels: passes 0-1 and a list of
+ * the quadrature queries; the MLP (mlp_packed from mb_mlp_pack) on that list;
+ * the quadrature of Eq. 7 and Eq. 15 from its outputs.
+ *  qws  device, mb_query_workspace_bytes(n_cams, width, height,
+ *       query_capacity) bytes. Its first 8 bytes receive the number of
+ *       queries the frame needed (uint64). If that exceeds query_capacity the
+ *       image is incomplete: call again with a larger capacity.
+ *  saved as in mb_render_forward; [7] carries the covering count only. */
+size_t mb_query_workspace_bytes(int32_t n_cams, int32_t width, int32_t height,
+                                int64_t query_capacity);
+int mb_render_forward_surrogate(const mb_gaussians *g, const mb_camera *cams, int32_t n_cams,
+                                const mb_options *opts, void *gws, size_t gws_bytes, void *pws,
+                                size_t pws_bytes, int64_t n_entries, const void *mlp_packed,
+                                void *qws, size_t qws_bytes, int64_t query_capacity,
+                                float *image, float *saved, void *stream);
+
 /* Stage timing. While enabled, every entry point records HIP events around
  * each of its stages on its stream (a small per-process overhead).
  * mb_profile_read waits for the recorded events, writes up to `max` stage
  * totals in milliseconds to ms[] and launch counts to calls[] (both host,
  * may be NULL), clears the record and returns the number of stages
  * (MB_STAGE_COUNT). Stages, in order: preprocess, scan, emit, sort, lists,
- * render_forward, render_backward, gradients, mlp. Not thread safe with
- * concurrent renders. */
-#define MB_STAGE_COUNT 9
+ * render_forward, render_backward, gradients, mlp, render_consume (the
+ * surrogate's quadrature). Not thread safe with concurrent renders. */
+#define MB_STAGE_COUNT 10
 void mb_profile_enable(int32_t on);
 int32_t mb_profile_read(double *ms, int64_t *calls, int32_t max);
 

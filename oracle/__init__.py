@@ -20,6 +20,10 @@ Each function follows the passage of the paper cited in its docstring:
                     App. B) and opacity rescaling (Eq. 15).
 * ``render``     -- the forward pass over a set of pixels and its gradient by
                     float64 autograd.
+* ``exact``      -- the volume rendering equation (Eqs. 2-3) without the
+                    moment approximation: the ground truth for image quality.
+* ``surrogate``  -- float64 reference of the learned surrogate (not in the
+                    paper) and the inputs it takes.
 
 Where the paper is silent or garbled the oracle takes one reading; each one
 is listed in the repository's design notes and named where it is used.

@@ -50,6 +50,8 @@ class PixelResult:
     pair_slot: torch.Tensor
     pair_gid: torch.Tensor
     pair_q: torch.Tensor
+    pair_y: torch.Tensor     # [pairs, N+1] moment variable at the quadrature edges
+    pair_tau: torch.Tensor   # [pairs, N+1] reconstructed optical depth there
 
 
 def _standardised_basis(slot, mu, sigma, omega, t_near, n_pix):
@@ -73,9 +75,12 @@ def _standardised_basis(slot, mu, sigma, omega, t_near, n_pix):
 
 
 def render_pixels(scene_t, scene, cam, opts, px: torch.Tensor, py: torch.Tensor,
-                  proxy=None, margin_tol: float = 2e-3, orient_eps: float = 0.0) -> PixelResult:
+                  proxy=None, margin_tol: float = 2e-3, orient_eps: float = 0.0,
+                  tau_model=None) -> PixelResult:
     """Render the listed pixels (all pairs of each listed pixel are formed, so
-    every listed pixel is complete)."""
+    every listed pixel is complete). ``tau_model(mom_q, y)`` replaces the
+    reconstruction of Sec. 3.2 when given (optical depth at queries y [Q] of
+    pixels with moments mom_q [Q, K+1]), e.g. by a learned surrogate."""
     n_pix = px.shape[0]
     k_mom = opts.n_moments
     n_half = k_mom // 2
@@ -101,6 +106,8 @@ def render_pixels(scene_t, scene, cam, opts, px: torch.Tensor, py: torch.Tensor,
     mom_q = mom[slot].repeat_interleave(n_edge, dim=0)
 
     def tau_at(y):
+        if tau_model is not None:
+            return tau_model(mom_q, y.reshape(-1)).reshape(y.shape)
         tau, _, _ = bound_tau(mom_q, y.reshape(-1), n_half, opts.beta)
         return tau.reshape(y.shape)
 
@@ -108,15 +115,17 @@ def render_pixels(scene_t, scene, cam, opts, px: torch.Tensor, py: torch.Tensor,
         return (warp(t, t_near) - centre[slot][:, None]) / scale[slot][:, None]
 
     if slot.shape[0] > 0:
-        q, _, _ = particle_quadrature(mu, sigma, omega, tau_at, t_near, opts.kappa,
-                                      opts.n_intervals, warp_y)
+        q, tau_e, t_e = particle_quadrature(mu, sigma, omega, tau_at, t_near, opts.kappa,
+                                            opts.n_intervals, warp_y)
+        y_e = warp_y(t_e)
     else:
         q = torch.zeros(0, dtype=DT)
+        tau_e = y_e = torch.zeros(0, n_edge, dtype=DT)
     s_rgb = torch.zeros(n_pix, 3, dtype=DT).index_add(0, slot, q[:, None] * rgb_all[gid])
     o = torch.zeros(n_pix, dtype=DT).index_add(0, slot, q)
     image = rescale(mom[:, 0], s_rgb, o, opts.eps, cam.background)
     return PixelResult(image, s_rgb, o, mom, centre, scale, amb, int(slot.shape[0]),
-                       slot, gid, q)
+                       slot, gid, q, y_e, tau_e)
 
 
 def _pixel_chunks(cam, px, py, max_pixels):
@@ -125,7 +134,8 @@ def _pixel_chunks(cam, px, py, max_pixels):
 
 
 def render_image(scene, cam, opts, pixels: Optional[np.ndarray] = None,
-                 max_pixels: int = 4096, margin_tol: float = 2e-3, orient_eps: float = 0.0):
+                 max_pixels: int = 4096, margin_tol: float = 2e-3, orient_eps: float = 0.0,
+                 tau_model=None):
     """Forward render of ``pixels`` (flat indices y * W + x; default: the
     whole image). Returns a dict of numpy arrays: image [P,3], s_rgb [P,3],
     opacity [P], moments [P,K+1], ambiguous [P] (a coverage decision within
@@ -143,7 +153,7 @@ def render_image(scene, cam, opts, pixels: Optional[np.ndarray] = None,
     with torch.no_grad():
         for _, px, py in _pixel_chunks(cam, px_all, py_all, max_pixels):
             r = render_pixels(scene_t, scene, cam, opts, px, py, proxy=proxy,
-                              margin_tol=margin_tol, orient_eps=orient_eps)
+                              margin_tol=margin_tol, orient_eps=orient_eps, tau_model=tau_model)
             outs["image"].append(r.image)
             outs["s_rgb"].append(r.s_rgb)
             outs["opacity"].append(r.opacity)

@@ -12,6 +12,15 @@ the rounding points of the bf16 kernels: weights (W1, W2, w3) and inputs
 (split into a bf16 pair hi + lo), the hidden activation H1, and the
 back-propagated dZ2 and dZ1 before they enter the matrix products.
 Parameter order: W1[64][7], b1[64], W2[64][64] (out, in), b2[64], w3[64], b3.
+
+Inputs of the network at a query y of a pixel (``features``, ``query``): the
+pixel's normalised moments b_1..b_6 in standardised form (the moments of the
+measure after the increasing affine map y -> (y - mean) / std), each passed
+through asinh, and the query mapped the same way, clamped to [-10, 10]. The
+bounds of Sec. 3.2 are covariant under such maps (a reading stated with the
+oracle's pixel basis), so the normalised optical depth at the query is a
+function of these seven numbers alone; ``exact_model`` is that function and
+pins the feature map (a render through it reproduces the plain render).
 """
 from __future__ import annotations
 
@@ -118,3 +127,73 @@ def adam(theta, m, v, grad, step, lr, b1=0.9, b2=0.999, eps=1e-8):
     mh = m / (1 - b1 ** step)
     vh = v / (1 - b2 ** step)
     return theta - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+MAX_Z = 10.0
+
+
+def features(mom):
+    """mom [P, 7] moments m_0..m_6 of a pixel in any increasing affine moment
+    variable. Returns (feat [P, 6] = asinh of the standardised moments 1..6,
+    mean [P], std [P]) of the normalised measure in that variable."""
+    mom = np.asarray(mom, np.float64)
+    b = mom / mom[:, :1]
+    mean = b[:, 1]
+    var = b[:, 2] - mean * mean
+    std = np.sqrt(np.where(var > 0, var, 1.0))
+    central = np.zeros((mom.shape[0], 7))
+    for k in range(7):
+        # E[(y - mean)^k] by the binomial theorem
+        central[:, k] = sum(comb(k, j) * b[:, j] * (-mean) ** (k - j) for j in range(k + 1))
+    std_mom = central[:, 1:] / std[:, None] ** np.arange(1, 7)[None, :]
+    return np.arcsinh(std_mom), mean, std
+
+
+def comb(k, j):
+    from math import comb as _c
+    return _c(k, j)
+
+
+def query(y, mean, std, max_z: float = MAX_Z):
+    """The query y in the standardised variable, clamped to [-max_z, max_z]."""
+    return np.clip((np.asarray(y, np.float64) - mean) / std, -max_z, max_z)
+
+
+def network_inputs(mom_q, y, max_z: float = MAX_Z):
+    """Rows (6 features, query, m_0) for queries y [Q] of pixels with moments
+    mom_q [Q, 7] (one row of moments per query)."""
+    feat, mean, std = features(mom_q)
+    z = query(y, mean, std, max_z)
+    return np.concatenate([feat, z[:, None], np.asarray(mom_q, np.float64)[:, :1]], axis=1)
+
+
+def tau_model(theta, bf16_mode: bool = True):
+    """Optical depth m_0 F(inputs) of the network with parameters theta, in
+    the (mom_q, y) -> tau form of the oracle renderer's reconstruction hook."""
+    import torch
+
+    def model(mom_q, y):
+        m = mom_q.detach().numpy() if hasattr(mom_q, "detach") else np.asarray(mom_q)
+        yy = y.detach().numpy() if hasattr(y, "detach") else np.asarray(y)
+        x = network_inputs(m, yy)
+        f, _ = forward(theta, x, bf16_mode)
+        return torch.as_tensor(m[:, 0] * f, dtype=torch.float64)
+    return model
+
+
+def exact_model(beta: float, max_z: float = MAX_Z):
+    """The target the network learns: the bound interpolation of Sec. 3.2
+    evaluated from the network inputs alone (standardised moments recovered
+    by sinh, m_0 = 1, query as given), times m_0. With max_z = inf it is the
+    reconstruction itself, written in the network's inputs."""
+    import torch
+    from .bounds import bound_tau
+
+    def model(mom_q, y):
+        m = mom_q.detach().numpy() if hasattr(mom_q, "detach") else np.asarray(mom_q)
+        yy = y.detach().numpy() if hasattr(y, "detach") else np.asarray(y)
+        x = network_inputs(m, yy, max_z)
+        b = np.concatenate([np.ones((x.shape[0], 1)), np.sinh(x[:, :6])], axis=1)
+        tau, _, _ = bound_tau(torch.as_tensor(b), torch.as_tensor(x[:, 6]), 3, beta)
+        return torch.as_tensor(m[:, 0]) * tau
+    return model

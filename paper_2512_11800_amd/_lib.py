@@ -19,9 +19,9 @@ MB_ERR_WORKSPACE = -3
 MB_ERR_HIP = -4
 MB_MAX_CAMERAS = 16
 MB_SAVED_FLOATS_PER_PIXEL = 8
-MB_STAGE_COUNT = 9
+MB_STAGE_COUNT = 10
 STAGES = ("preprocess", "scan", "emit", "sort", "lists", "render_forward", "render_backward",
-          "gradients", "mlp")
+          "gradients", "mlp", "render_consume")
 
 
 class MbGaussians(ctypes.Structure):
@@ -79,6 +79,15 @@ SIGNATURES = [
                                      POINTER(MbOptions), c_void_p, c_size_t, c_void_p, c_size_t,
                                      c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                      c_void_p, c_void_p, c_void_p]),
+    ("mb_render_forward_harvest", c_int32, [POINTER(MbGaussians), POINTER(MbCamera), c_int32,
+                                            POINTER(MbOptions), c_void_p, c_size_t, c_void_p,
+                                            c_size_t, c_int64, c_float, ctypes.c_uint32, c_void_p,
+                                            c_int32, c_void_p, c_void_p, c_void_p, c_void_p]),
+    ("mb_query_workspace_bytes", c_size_t, [c_int32, c_int32, c_int32, c_int64]),
+    ("mb_render_forward_surrogate", c_int32, [POINTER(MbGaussians), POINTER(MbCamera), c_int32,
+                                              POINTER(MbOptions), c_void_p, c_size_t, c_void_p,
+                                              c_size_t, c_int64, c_void_p, c_void_p, c_size_t,
+                                              c_int64, c_void_p, c_void_p, c_void_p]),
 ]
 
 

@@ -17,7 +17,7 @@ namespace {
 // ---------------------------------------------------------------------------
 // Stage timing with HIP events on the caller's stream (mb_profile_*).
 // ---------------------------------------------------------------------------
-enum Stage { S_PREPROCESS = 0, S_SCAN, S_EMIT, S_SORT, S_LISTS, S_RENDER_FWD, S_RENDER_BWD, S_GRADS, S_MLP };
+enum Stage { S_PREPROCESS = 0, S_SCAN, S_EMIT, S_SORT, S_LISTS, S_RENDER_FWD, S_RENDER_BWD, S_GRADS, S_MLP, S_CONSUME };
 
 struct Profiler {
   std::mutex mu;
@@ -221,6 +221,90 @@ int key_bits(int64_t n_keys) {
   return b;
 }
 
+// emit, sort and per-tile lists of the forward entry points
+int build_lists(const mb_gaussians* g, const GaussWs& w, const PairWs& p, int n_cams, int tx, int ty,
+                int full_coverage, int64_t n_entries, hipStream_t s) {
+  int n_keys = tx * ty * n_cams;
+  EmitArgs ea;
+  ea.rec = w.rec; ea.tbox = w.tbox; ea.offsets = w.offsets; ea.counts = w.counts;
+  ea.n = g->n; ea.n_cams = n_cams; ea.tiles_x = tx; ea.tiles_y = ty; ea.full_coverage = full_coverage;
+  ea.keys = p.keys_a; ea.vals = p.vals_a; ea.entry_rec = p.entry_rec;
+  hipError_t e;
+  {
+    StageTimer t(S_EMIT, s);
+    e = launch_emit(ea, s);
+  }
+  if (e != hipSuccess) return hip_fail(e, "emit");
+  {
+    StageTimer t(S_SORT, s);
+    e = launch_radix_sort(p.keys_a, p.vals_a, p.keys_b, p.vals_b, n_entries, key_bits(n_keys), p.radix_tmp, s);
+  }
+  if (e != hipSuccess) return hip_fail(e, "sort");
+  {
+    StageTimer t(S_LISTS, s);
+    e = launch_finish_lists(p.keys_a, p.vals_a, p.entry_rec, n_entries, p.sorted_rec, p.inv, p.ranges, n_keys, s);
+  }
+  if (e != hipSuccess) return hip_fail(e, "lists");
+  return MB_OK;
+}
+
+struct FwdSetup {
+  GaussWs w;
+  PairWs p;
+  CamSet cs;
+  RenderArgs ra;
+  int n_keys;
+};
+
+// argument and workspace checks shared by the forward entry points
+int forward_setup(const mb_gaussians* g, const mb_camera* cams, int32_t n_cams, const mb_options* o, void* gws,
+                  size_t gws_bytes, void* pws, size_t pws_bytes, int64_t n_entries, float* image, float* saved,
+                  FwdSetup& f) {
+  int rc = check_common(g, cams, n_cams, o);
+  if (rc) return rc;
+  if (!image || !saved) return fail(MB_ERR_ARG, "null image or saved output");
+  if (n_entries < 0) return fail(MB_ERR_ARG, "negative n_entries");
+  f.w = carve_gauss(gws, g->n, n_cams);
+  if (!gws || gws_bytes < f.w.bytes)
+    return fail(MB_ERR_WORKSPACE, "Gaussian workspace needs %zu bytes, got %zu", f.w.bytes, gws_bytes);
+  int tx = tiles_of(cams[0].width), ty = tiles_of(cams[0].height);
+  f.n_keys = tx * ty * n_cams;
+  f.p = carve_pairs(pws, n_entries, f.n_keys);
+  if (!pws || pws_bytes < f.p.bytes)
+    return fail(MB_ERR_WORKSPACE, "pair workspace needs %zu bytes, got %zu", f.p.bytes, pws_bytes);
+  f.cs = make_cams(cams, n_cams);
+  RenderArgs& ra = f.ra;
+  memset(&ra, 0, sizeof(ra));
+  ra.rec = f.w.rec; ra.sorted_rec = f.p.sorted_rec; ra.ranges = f.p.ranges;
+  ra.image = image; ra.saved = saved;
+  ra.tiles_x = tx; ra.tiles_y = ty; ra.n_cams = n_cams; ra.full_coverage = o->full_coverage;
+  ra.kappa = o->kappa; ra.beta = o->beta; ra.eps = o->eps;
+  fill_quantiles(o, ra.xq, ra.eq);
+  return MB_OK;
+}
+
+struct QueryWs {
+  unsigned long long* count;
+  float* pixfeat;
+  long long* pix_qbase;
+  float *q_z, *q_f;
+  int* q_pix;
+  size_t bytes;
+};
+
+QueryWs carve_queries(void* p, int64_t n_pix, int64_t q_cap) {
+  Carver c(p);
+  QueryWs w;
+  w.count = c.take<unsigned long long>(1);
+  w.pixfeat = c.take<float>((size_t)n_pix * kPixFeat);
+  w.pix_qbase = c.take<long long>((size_t)n_pix);
+  w.q_z = c.take<float>((size_t)q_cap);
+  w.q_pix = c.take<int>((size_t)q_cap);
+  w.q_f = c.take<float>((size_t)q_cap);
+  w.bytes = c.off;
+  return w;
+}
+
 }  // namespace
 
 extern "C" {
@@ -342,54 +426,95 @@ int mb_prepare(const mb_gaussians* g, const mb_camera* cams, int32_t n_cams, con
 int mb_render_forward(const mb_gaussians* g, const mb_camera* cams, int32_t n_cams, const mb_options* o, void* gws,
                       size_t gws_bytes, void* pws, size_t pws_bytes, int64_t n_entries, float* image, float* saved,
                       void* stream) {
-  int rc = check_common(g, cams, n_cams, o);
+  FwdSetup f;
+  int rc = forward_setup(g, cams, n_cams, o, gws, gws_bytes, pws, pws_bytes, n_entries, image, saved, f);
   if (rc) return rc;
-  if (!image || !saved) return fail(MB_ERR_ARG, "null image or saved output");
-  if (n_entries < 0) return fail(MB_ERR_ARG, "negative n_entries");
-  GaussWs w = carve_gauss(gws, g->n, n_cams);
-  if (!gws || gws_bytes < w.bytes)
-    return fail(MB_ERR_WORKSPACE, "Gaussian workspace needs %zu bytes, got %zu", w.bytes, gws_bytes);
-  int tx = tiles_of(cams[0].width), ty = tiles_of(cams[0].height);
-  int n_keys = tx * ty * n_cams;
-  PairWs p = carve_pairs(pws, n_entries, n_keys);
-  if (!pws || pws_bytes < p.bytes)
-    return fail(MB_ERR_WORKSPACE, "pair workspace needs %zu bytes, got %zu", p.bytes, pws_bytes);
   hipStream_t s = (hipStream_t)stream;
-  CamSet cs = make_cams(cams, n_cams);
-
-  EmitArgs ea;
-  ea.rec = w.rec; ea.tbox = w.tbox; ea.offsets = w.offsets; ea.counts = w.counts;
-  ea.n = g->n; ea.n_cams = n_cams; ea.tiles_x = tx; ea.tiles_y = ty; ea.full_coverage = o->full_coverage;
-  ea.keys = p.keys_a; ea.vals = p.vals_a; ea.entry_rec = p.entry_rec;
+  rc = build_lists(g, f.w, f.p, n_cams, f.ra.tiles_x, f.ra.tiles_y, o->full_coverage, n_entries, s);
+  if (rc) return rc;
   hipError_t e;
   {
-    StageTimer t(S_EMIT, s);
-    e = launch_emit(ea, s);
-  }
-  if (e != hipSuccess) return hip_fail(e, "emit");
-  {
-    StageTimer t(S_SORT, s);
-    e = launch_radix_sort(p.keys_a, p.vals_a, p.keys_b, p.vals_b, n_entries, key_bits(n_keys), p.radix_tmp, s);
-  }
-  if (e != hipSuccess) return hip_fail(e, "sort");
-  {
-    StageTimer t(S_LISTS, s);
-    e = launch_finish_lists(p.keys_a, p.vals_a, p.entry_rec, n_entries, p.sorted_rec, p.inv, p.ranges, n_keys, s);
-  }
-  if (e != hipSuccess) return hip_fail(e, "lists");
-
-  RenderArgs ra;
-  memset(&ra, 0, sizeof(ra));
-  ra.rec = w.rec; ra.sorted_rec = p.sorted_rec; ra.ranges = p.ranges;
-  ra.image = image; ra.saved = saved;
-  ra.tiles_x = tx; ra.tiles_y = ty; ra.n_cams = n_cams; ra.full_coverage = o->full_coverage;
-  ra.kappa = o->kappa; ra.beta = o->beta; ra.eps = o->eps;
-  fill_quantiles(o, ra.xq, ra.eq);
-  {
     StageTimer t(S_RENDER_FWD, s);
-    e = launch_render_forward(ra, cs, o->n_moments, o->n_intervals, s);
+    e = launch_render_forward(f.ra, f.cs, o->n_moments, o->n_intervals, s);
   }
   if (e != hipSuccess) return hip_fail(e, "render_forward");
+  return MB_OK;
+}
+
+int mb_render_forward_harvest(const mb_gaussians* g, const mb_camera* cams, int32_t n_cams, const mb_options* o,
+                              void* gws, size_t gws_bytes, void* pws, size_t pws_bytes, int64_t n_entries,
+                              float rate, uint32_t seed, float* samples, int32_t capacity, int32_t* count,
+                              float* image, float* saved, void* stream) {
+  FwdSetup f;
+  int rc = forward_setup(g, cams, n_cams, o, gws, gws_bytes, pws, pws_bytes, n_entries, image, saved, f);
+  if (rc) return rc;
+  if (o->n_moments != 6) return fail(MB_ERR_ARG, "the surrogate's samples need n_moments = 6");
+  if (!(rate >= 0.f && rate <= 1.f)) return fail(MB_ERR_ARG, "harvest rate must lie in [0, 1]");
+  if (capacity < 0 || !count || (capacity > 0 && !samples)) return fail(MB_ERR_ARG, "bad sample buffer");
+  hipStream_t s = (hipStream_t)stream;
+  rc = build_lists(g, f.w, f.p, n_cams, f.ra.tiles_x, f.ra.tiles_y, o->full_coverage, n_entries, s);
+  if (rc) return rc;
+  f.ra.harvest = samples;
+  f.ra.harvest_count = count;
+  f.ra.harvest_cap = capacity;
+  f.ra.harvest_rate = rate;
+  f.ra.seed = seed;
+  hipError_t e;
+  {
+    StageTimer t(S_RENDER_FWD, s);
+    e = launch_render_forward(f.ra, f.cs, o->n_moments, o->n_intervals, s, kModeHarvest);
+  }
+  if (e != hipSuccess) return hip_fail(e, "render_forward_harvest");
+  return MB_OK;
+}
+
+size_t mb_query_workspace_bytes(int32_t n_cams, int32_t width, int32_t height, int64_t query_capacity) {
+  if (n_cams < 1 || width <= 0 || height <= 0 || query_capacity < 0) return 0;
+  return carve_queries(nullptr, (int64_t)n_cams * width * height, query_capacity).bytes;
+}
+
+int mb_render_forward_surrogate(const mb_gaussians* g, const mb_camera* cams, int32_t n_cams, const mb_options* o,
+                                void* gws, size_t gws_bytes, void* pws, size_t pws_bytes, int64_t n_entries,
+                                const void* mlp_packed, void* qws, size_t qws_bytes, int64_t query_capacity,
+                                float* image, float* saved, void* stream) {
+  FwdSetup f;
+  int rc = forward_setup(g, cams, n_cams, o, gws, gws_bytes, pws, pws_bytes, n_entries, image, saved, f);
+  if (rc) return rc;
+  if (o->n_moments != 6) return fail(MB_ERR_ARG, "the surrogate takes n_moments = 6");
+  if (!mlp_packed) return fail(MB_ERR_ARG, "null surrogate weights");
+  if (query_capacity < 0) return fail(MB_ERR_ARG, "negative query capacity");
+  int64_t n_pix = (int64_t)n_cams * cams[0].width * cams[0].height;
+  QueryWs q = carve_queries(qws, n_pix, query_capacity);
+  if (!qws || qws_bytes < q.bytes)
+    return fail(MB_ERR_WORKSPACE, "query workspace needs %zu bytes, got %zu", q.bytes, qws_bytes);
+  hipStream_t s = (hipStream_t)stream;
+  rc = build_lists(g, f.w, f.p, n_cams, f.ra.tiles_x, f.ra.tiles_y, o->full_coverage, n_entries, s);
+  if (rc) return rc;
+  RenderArgs& ra = f.ra;
+  ra.pixfeat = q.pixfeat;
+  ra.pix_qbase = q.pix_qbase;
+  ra.q_count = q.count;
+  ra.q_cap = query_capacity;
+  ra.q_z = q.q_z;
+  ra.q_pix = q.q_pix;
+  ra.q_f = q.q_f;
+  hipError_t e = hipMemsetAsync(q.count, 0, sizeof(unsigned long long), s);
+  if (e != hipSuccess) return hip_fail(e, "query counter reset");
+  {
+    StageTimer t(S_RENDER_FWD, s);
+    e = launch_render_forward(ra, f.cs, o->n_moments, o->n_intervals, s, kModeEmit);
+  }
+  if (e != hipSuccess) return hip_fail(e, "render_forward (surrogate queries)");
+  {
+    StageTimer t(S_MLP, s);
+    e = launch_mlp_forward_gather(mlp_packed, q.pixfeat, n_pix, q.q_pix, q.q_z, q.count, query_capacity, q.q_f, s);
+  }
+  if (e != hipSuccess) return hip_fail(e, "surrogate inference");
+  {
+    StageTimer t(S_CONSUME, s);
+    e = launch_render_consume(ra, f.cs, o->n_intervals, s);
+  }
+  if (e != hipSuccess) return hip_fail(e, "render_forward (surrogate quadrature)");
   return MB_OK;
 }
 

@@ -27,6 +27,11 @@ constexpr float kPi = 3.14159265358979323846f;
 constexpr float kSqrtHalfPi = 1.2533141373155003f;  // sqrt(pi/2)
 constexpr float kInvSqrt2 = 0.7071067811865476f;
 constexpr double kMinDepth = 1e-20;  // optical depth below which a pixel is empty
+// surrogate: per-pixel record (6 features, m0, basis centre, basis scale,
+// covering count) and harvested training sample (6 features, query, m0,
+// transmittance, selection hash bits, pixel index, record * (N+1) + edge)
+constexpr int kPixFeat = 10;
+constexpr int kHarvestStride = 12;
 
 // Render record fields (float index inside the 24-float record).
 enum RecField {

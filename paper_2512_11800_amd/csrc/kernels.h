@@ -60,9 +60,25 @@ struct RenderArgs {
   float kappa, beta, eps;
   float xq[8];    // standard-normal edge quantiles
   float eq[8];    // exp(-kappa^2 xq^2 / 2)
+  // surrogate query list (emit / consume variants)
+  float* pixfeat;                 // [C,H,W,kPixFeat] per-pixel features, m0, basis, count
+  long long* pix_qbase;           // [C,H,W] first query of the pixel, -1 if none
+  unsigned long long* q_count;    // queries requested (may exceed q_cap)
+  long long q_cap;
+  float* q_z;                     // [q_cap] standardised query
+  int* q_pix;                     // [q_cap] flat pixel index
+  const float* q_f;               // [q_cap] surrogate output F
+  // training-sample harvest (harvest variant)
+  float* harvest;                 // [harvest_cap, kHarvestStride]
+  int* harvest_count;
+  int harvest_cap;
+  float harvest_rate;
+  uint32_t seed;
 };
+enum RenderMode { kModePlain = 0, kModeHarvest = 1, kModeEmit = 2 };
 hipError_t launch_render_forward(const RenderArgs& a, const CamSet& cams, int n_moments,
-                                 int n_intervals, hipStream_t s);
+                                 int n_intervals, hipStream_t s, int mode = kModePlain);
+hipError_t launch_render_consume(const RenderArgs& a, const CamSet& cams, int n_intervals, hipStream_t s);
 
 hipError_t launch_render_backward(const RenderArgs& r, const float* saved, const float* grad_image,
                                   const int* sorted_k, float* partials, const CamSet& cams, int n_moments,
@@ -84,6 +100,11 @@ size_t mlp_packed_bytes();
 size_t mlp_workspace_bytes(int64_t n);
 hipError_t launch_mlp_pack(const float* theta, void* packed, hipStream_t s);
 hipError_t launch_mlp_forward(const void* packed, const float* x, int64_t n, float* f, hipStream_t s);
+// surrogate inputs gathered from the render's query list: features of pixel
+// q_pix[i] (of n_pix) and query q_z[i] for i < min(*q_count, q_cap)
+hipError_t launch_mlp_forward_gather(const void* packed, const float* pixfeat, int64_t n_pix, const int* q_pix,
+                                     const float* q_z, const unsigned long long* q_count, int64_t q_cap, float* f,
+                                     hipStream_t s);
 hipError_t launch_mlp_loss_grad(const void* packed, const float* x, const float* t, int64_t n, float* grad,
                                 float* loss, float* ws, hipStream_t s);
 hipError_t launch_adam(float* th, float* m, float* v, const float* g, int64_t count, int step, float lr, float b1,

@@ -132,12 +132,9 @@ struct TrainLds {
   float dout[64];
 };
 
+// stage the wave's 64 input vectors (v: this lane's kIn inputs) as bf16 pairs
 template <class L>
-__device__ __forceinline__ void load_inputs(L& w, const float* x, int64_t q, bool valid, int lane, float& m0) {
-  float v[8];
-#pragma unroll
-  for (int k = 0; k < 8; ++k) v[k] = valid ? x[q * 8 + k] : 0.f;
-  m0 = v[7];
+__device__ __forceinline__ void stage_inputs(L& w, const float* v, int lane) {
   uint16_t hi[kIn], lo[kIn];
 #pragma unroll
   for (int k = 0; k < kIn; ++k) {
@@ -153,6 +150,15 @@ __device__ __forceinline__ void load_inputs(L& w, const float* x, int64_t q, boo
   if constexpr (sizeof(L) == sizeof(TrainLds))
 #pragma unroll
     for (int k = kXStride; k < 32; ++k) w.xt[k][lane] = 0;
+}
+
+template <class L>
+__device__ __forceinline__ void load_inputs(L& w, const float* x, int64_t q, bool valid, int lane, float& m0) {
+  float v[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) v[k] = valid ? x[q * 8 + k] : 0.f;
+  m0 = v[7];
+  stage_inputs(w, v, lane);
 }
 
 // layers 1-3 for the wave's 64 queries; returns the output pre-activation of
@@ -245,6 +251,47 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const MlpPacked* gp, const 
     bool valid = q < n;
     float m0;
     load_inputs(w, x, q, valid, lane, m0);
+    __syncthreads();
+    f32x16 z1[2][2], z2[2][2];
+    float out = mlp_forward_wave(w, P, lane, z1, z2);
+    if (valid) f_out[q] = sigmoid(out);
+  }
+}
+
+// The same network on the render's query list: the inputs of query i are the
+// six features of pixel q_pix[i] and the standardised query q_z[i]. The
+// number of queries is read on the device (the render pass appends them).
+__global__ __launch_bounds__(256) void k_mlp_forward_gather(const MlpPacked* gp, const float* pixfeat, const int* q_pix,
+                                                            const float* q_z, const unsigned long long* q_count,
+                                                            int64_t q_cap, int64_t n_pix, float* f_out) {
+  __shared__ MlpPacked P;
+  __shared__ FwdLds ws[4];
+  const unsigned long long cnt = *q_count;
+  const int64_t n = cnt < (unsigned long long)q_cap ? (int64_t)cnt : q_cap;
+  if (n == 0) return;
+  {
+    const float4* src = reinterpret_cast<const float4*>(gp);
+    float4* dst = reinterpret_cast<float4*>(&P);
+    for (int i = threadIdx.x; i < (int)(sizeof(MlpPacked) / 16); i += blockDim.x) dst[i] = src[i];
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  FwdLds& w = ws[wave];
+  const int64_t chunks = (n + 63) / 64;
+  const int64_t per_block = ((chunks + gridDim.x - 1) / gridDim.x + 3) / 4 * 4;
+  for (int64_t it = 0; it < per_block; it += 4) {
+    int64_t q = ((int64_t)blockIdx.x * per_block + it + wave) * 64 + lane;
+    bool valid = q < n;
+    float v[kIn];
+    // slots of a list that overflowed may hold no query: keep their pixel
+    // index inside the image (their outputs are never read)
+    int64_t p = valid ? (int64_t)q_pix[q] : 0;
+    p = (p >= 0 && p < n_pix) ? p : 0;
+    const float* pf = pixfeat + (size_t)p * kPixFeat;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) v[k] = valid ? pf[k] : 0.f;
+    v[6] = valid ? q_z[q] : 0.f;
+    stage_inputs(w, v, lane);
     __syncthreads();
     f32x16 z1[2][2], z2[2][2];
     float out = mlp_forward_wave(w, P, lane, z1, z2);
@@ -460,6 +507,15 @@ size_t mlp_workspace_bytes(int64_t n) { return (size_t)mlp_grid(n, kTrainWaves) 
 
 hipError_t launch_mlp_pack(const float* theta, void* packed, hipStream_t s) {
   hipLaunchKernelGGL(k_mlp_pack, dim3(1), dim3(256), 0, s, theta, (MlpPacked*)packed);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_forward_gather(const void* packed, const float* pixfeat, int64_t n_pix, const int* q_pix,
+                                     const float* q_z, const unsigned long long* q_count, int64_t q_cap, float* f,
+                                     hipStream_t s) {
+  if (q_cap <= 0 || n_pix <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mlp_forward_gather, dim3(mlp_grid(q_cap, 4)), dim3(256), 0, s, (const MlpPacked*)packed,
+                     pixfeat, q_pix, q_z, q_count, q_cap, n_pix, f);
   return hipGetLastError();
 }
 

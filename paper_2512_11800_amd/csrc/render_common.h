@@ -87,32 +87,52 @@ __device__ __forceinline__ float phi_fn(float x) {
   return fabsf(x) < 1e-4f ? 1.f - x * (0.5f - x * (1.f / 6.f)) : -expm1f(-x) / x;
 }
 
-// Quadrature of Eq. 7 for one Gaussian against the pixel's bounds; returns q.
-template <int NH, int NQ>
-__device__ __forceinline__ float particle_quadrature(const RayG& g, const PixelBasis& pb, const LInv<NH>& L,
-                                                     float m0, float tn, const RenderArgs& a) {
-  float tau[NQ], off[NQ], sj[NQ];
+// Interval edges of one Gaussian's quadrature (App. B sample spacing): edge
+// offsets, the clamp to the near bound, the moment variable y at each edge
+// and the particle density sigma_i there.
+template <int NQ>
+struct QEdges {
+  float off[NQ], y[NQ], sj[NQ], tau[NQ];
   bool cl[NQ];
+};
+
+template <int NQ>
+__device__ __forceinline__ void quad_edges(const RayG& g, const PixelBasis& pb, float tn, const RenderArgs& a,
+                                           QEdges<NQ>& e) {
   float dtc = g.mu - pb.tc;
 #pragma unroll
   for (int j = 0; j < NQ; ++j) {
-    off[j] = a.kappa * g.sig * a.xq[j];
-    float t = g.mu + off[j];
-    cl[j] = t < tn;
-    float dt = cl[j] ? (tn - pb.tc) : (dtc + off[j]);
-    t = cl[j] ? tn : t;
-    float y = warp_y(pb, t, dt);
-    tau[j] = m0 * bound_F<NH>(L, y, a.beta);
+    e.off[j] = a.kappa * g.sig * a.xq[j];
+    float t = g.mu + e.off[j];
+    e.cl[j] = t < tn;
+    float dt = e.cl[j] ? (tn - pb.tc) : (dtc + e.off[j]);
+    t = e.cl[j] ? tn : t;
+    e.y[j] = warp_y(pb, t, dt);
     float r = (t - g.mu) * fast_rcp(g.sig);
-    sj[j] = g.omega * (cl[j] ? __expf(-0.5f * r * r) : a.eq[j]);
+    e.sj[j] = g.omega * (e.cl[j] ? __expf(-0.5f * r * r) : a.eq[j]);
   }
+}
+
+// Eq. 7 sum over the intervals, given the optical depth at every edge
+template <int NQ>
+__device__ __forceinline__ float quad_sum(const RayG& g, float tn, const QEdges<NQ>& e) {
   float q = 0.f;
 #pragma unroll
   for (int j = 0; j + 1 < NQ; ++j) {
-    float delta = cl[j + 1] ? 0.f : (cl[j] ? (g.mu + off[j + 1] - tn) : (off[j + 1] - off[j]));
-    q += __expf(-tau[j]) * delta * phi_fn(tau[j + 1] - tau[j]) * sj[j];
+    float delta = e.cl[j + 1] ? 0.f : (e.cl[j] ? (g.mu + e.off[j + 1] - tn) : (e.off[j + 1] - e.off[j]));
+    q += __expf(-e.tau[j]) * delta * phi_fn(e.tau[j + 1] - e.tau[j]) * e.sj[j];
   }
   return q;
+}
+
+// Quadrature of Eq. 7 for one Gaussian against the pixel's moment bounds.
+template <int NH, int NQ>
+__device__ __forceinline__ float particle_quadrature(const RayG& g, const PixelBasis& pb, const LInv<NH>& L,
+                                                     float m0, float tn, const RenderArgs& a, QEdges<NQ>& e) {
+  quad_edges<NQ>(g, pb, tn, a, e);
+#pragma unroll
+  for (int j = 0; j < NQ; ++j) e.tau[j] = m0 * bound_F<NH>(L, e.y[j], a.beta);
+  return quad_sum<NQ>(g, tn, e);
 }
 
 }  // namespace mb

@@ -8,14 +8,80 @@
 //           (Quadrature pass), accumulating sum q_i (r, g, b, 1),
 //   epilogue  Eq. 15 rescaling (Rescale pass).
 // A wave skips a Gaussian when none of its 64 pixels is covered (ballot).
+//
+// Variants (MODE):
+//   kModePlain    the path above;
+//   kModeHarvest  the same, also writing a seeded pseudo-random subset of its
+//                 queries as training samples of the learned surrogate
+//                 (features, query, m_0 and the transmittance of the bounds);
+//   kModeEmit     passes 0-1, then the surrogate's query list in place of the
+//                 bound evaluation; k_render_consume completes the quadrature
+//                 from the surrogate's outputs.
 #include "render_common.h"
 
 namespace mb {
 
-template <int K, int NQ>
+// Surrogate features of a pixel: the moments of its normalised measure in
+// standardised form (mean 0, variance 1 in the moment variable), passed
+// through asinh, and the map (y - mu) / sig of the moment variable onto the
+// standardised one. The moment bounds are covariant under increasing affine
+// maps of the variable, so F at a query depends on these alone.
+__device__ __forceinline__ void surrogate_features(const double* acc, float* feat, float& mu, float& sig) {
+  double b[7];
+  b[0] = 1.0;
+#pragma unroll
+  for (int k = 1; k <= 6; ++k) b[k] = acc[k] / acc[0];
+  const double m = b[1];
+  const double var = b[2] - m * m;
+  const double s = var > 0.0 ? sqrt(var) : 1.0;
+  const double is = 1.0 / s;
+  double c[7];  // central moments E[(y - m)^k]
+  c[0] = 1.0;
+#pragma unroll
+  for (int k = 1; k <= 6; ++k) {
+    // sum_j C(k, j) b_j (-m)^(k - j), with binomials built by the recurrence
+    double acc_k = 0.0, binom = 1.0, pw = 1.0;
+#pragma unroll
+    for (int j = k; j >= 0; --j) {
+      acc_k += binom * b[j] * pw;
+      binom = binom * (double)j / (double)(k - j + 1);
+      pw *= -m;
+    }
+    c[k] = acc_k;
+  }
+  double sk = 1.0;
+#pragma unroll
+  for (int k = 1; k <= 6; ++k) {
+    sk *= is;
+    feat[k - 1] = (float)asinh(c[k] * sk);
+  }
+  mu = (float)m;
+  sig = (float)s;
+}
+
+// 32-bit integer hash for the harvest's sample selection
+__device__ __forceinline__ uint32_t mix_hash(uint32_t a, uint32_t b, uint32_t c) {
+  uint32_t h = a * 0x9E3779B1u ^ (b + 0x7F4A7C15u) * 0x85EBCA77u ^ (c + 0x165667B1u) * 0xC2B2AE3Du;
+  h ^= h >> 16;
+  h *= 0x7FEB352Du;
+  h ^= h >> 15;
+  h *= 0x846CA68Bu;
+  h ^= h >> 16;
+  return h;
+}
+
+constexpr float kMaxZ = 10.f;  // clamp of the standardised query
+
+__device__ __forceinline__ float std_query(float y, float mu, float sig) {
+  return fminf(fmaxf((y - mu) / sig, -kMaxZ), kMaxZ);
+}
+
+template <int K, int NQ, int MODE>
 __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
   constexpr int NH = K / 2;
   __shared__ Stage st;
+  __shared__ long long s_base;
+  __shared__ int s_scan[4];
   const int tiles_per_cam = a.tiles_x * a.tiles_y;
   const int n_keys = tiles_per_cam * a.n_cams;
   const int key = remap_xcd(blockIdx.x, gridDim.x);
@@ -33,6 +99,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
   const float lam = sqrtf(1.f + rx * rx + ry * ry);
   const float tn = c.tn;
   const int2 rg = a.ranges[key];
+  const size_t pix = ((size_t)ci * c.height + (inside ? py : 0)) * c.width + (inside ? px : 0);
 
   // ---- pass 0: the pixel's moment variable ---------------------------------
   float wsum = 0.f, mean = 0.f, m2 = 0.f;
@@ -70,6 +137,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
   double acc[K + 1];
 #pragma unroll
   for (int k = 0; k <= K; ++k) acc[k] = 0.0;
+  int n_cov = 0;
   for (int b = rg.x; b < rg.y; b += kBlock) {
     int nb = min(kBlock, rg.y - b);
     __syncthreads();
@@ -83,6 +151,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
         RayG g = ray_params(st, j, dx, dy, lam);
         float m[K + 1];
         particle_moments<K>(g, pb, tn, m);
+        ++n_cov;
 #pragma unroll
         for (int k = 0; k <= K; ++k) acc[k] += (double)m[k];
       }
@@ -97,7 +166,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
   const bool live = acc[0] > kMinDepth;
   LInv<NH> L;
   bool fallback = false;
-  if (live) {
+  if (live && MODE != kModeEmit) {
     double bn[K + 1];
     bn[0] = 1.0;
 #pragma unroll
@@ -108,9 +177,62 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
     for (int i = 0; i < (NH + 1) * (NH + 2) / 2; ++i) L.l[i] = 0.f;
   }
 
-  // ---- pass 2: quadrature ---------------------------------------------------
+  float feat[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  float smu = 0.f, ssig = 1.f;
+  if constexpr (MODE != kModePlain) {
+    static_assert(K == 6, "the surrogate takes six moments");
+    if (live) surrogate_features(acc, feat, smu, ssig);
+  }
+
+  // ---- surrogate query list: this tile's range, pixel by pixel --------------
+  long long qbase = -1;
+  if constexpr (MODE == kModeEmit) {
+    const int nq = (inside && live) ? n_cov * NQ : 0;
+    int inc = nq;  // inclusive scan over the wave, then over the 4 waves
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      int t = __shfl_up(inc, d, 64);
+      if (lane >= d) inc += t;
+    }
+    if (lane == 63) s_scan[wave] = inc;
+    __syncthreads();
+    int off = inc - nq, tot = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      off += w < wave ? s_scan[w] : 0;
+      tot += s_scan[w];
+    }
+    if (tid == 0) s_base = tot > 0 ? (long long)atomicAdd(a.q_count, (unsigned long long)tot) : 0;
+    __syncthreads();
+    const long long base = s_base;
+    // past the capacity the tile's pixels get no queries; the counter still
+    // reports the full request so the caller can size the list and retry.
+    // A reservation that straddles the capacity fills its part below it with
+    // a harmless query (pixel 0), so every slot below min(count, capacity)
+    // names a pixel of the image.
+    if (base + tot <= a.q_cap) {
+      if (inside && live) qbase = base + off;
+    } else {
+      for (long long i = base + tid; i < a.q_cap; i += kBlock) {
+        a.q_z[i] = 0.f;
+        a.q_pix[i] = 0;
+      }
+    }
+    if (inside) {
+      float* pf = a.pixfeat + pix * kPixFeat;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) pf[k] = feat[k];
+      pf[6] = m0;
+      pf[7] = tc;
+      pf[8] = sd;
+      pf[9] = (float)n_cov;
+      a.pix_qbase[pix] = qbase;
+    }
+  }
+
+  // ---- pass 2: quadrature (or the surrogate's query list) -------------------
   float sr = 0.f, sg = 0.f, sb = 0.f, so = 0.f;
-  int n_cov = 0;
+  int i_pair = 0;
   for (int b = rg.x; b < rg.y; b += kBlock) {
     int nb = min(kBlock, rg.y - b);
     __syncthreads();
@@ -122,23 +244,57 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
       if (__ballot(cov) == 0) continue;
       if (cov) {
         RayG g = ray_params(st, j, dx, dy, lam);
-        float q = particle_quadrature<NH, NQ>(g, pb, L, m0, tn, a);
-        ++n_cov;
-        float4 f5 = st.f[5][j];
-        sr += q * f5.y;
-        sg += q * f5.z;
-        sb += q * f5.w;
-        so += q;
+        QEdges<NQ> e;
+        if constexpr (MODE == kModeEmit) {
+          quad_edges<NQ>(g, pb, tn, a, e);
+          if (qbase >= 0) {
+#pragma unroll
+            for (int k = 0; k < NQ; ++k) {
+              const long long qi = qbase + (long long)i_pair * NQ + k;
+              a.q_z[qi] = std_query(e.y[k], smu, ssig);
+              a.q_pix[qi] = (int)pix;
+            }
+          }
+        } else {
+          float q = particle_quadrature<NH, NQ>(g, pb, L, m0, tn, a, e);
+          if constexpr (MODE == kModeHarvest) {
+            const uint32_t rid = (uint32_t)a.sorted_rec[b + j];
+#pragma unroll
+            for (int k = 0; k < NQ; ++k) {
+              const uint32_t h = mix_hash(a.seed, (uint32_t)pix, rid * NQ + k);
+              if ((float)(h >> 8) * (1.f / 16777216.f) < a.harvest_rate) {
+                const int slot = atomicAdd(a.harvest_count, 1);
+                if (slot < a.harvest_cap) {
+                  float* o = a.harvest + (size_t)slot * kHarvestStride;
+#pragma unroll
+                  for (int f = 0; f < 6; ++f) o[f] = feat[f];
+                  o[6] = std_query(e.y[k], smu, ssig);
+                  o[7] = m0;
+                  o[8] = expf(-e.tau[k]);
+                  o[9] = __uint_as_float(h);
+                  o[10] = __int_as_float((int)pix);
+                  o[11] = __int_as_float((int)(rid * NQ + k));
+                }
+              }
+            }
+          }
+          float4 f5 = st.f[5][j];
+          sr += q * f5.y;
+          sg += q * f5.z;
+          sb += q * f5.w;
+          so += q;
+        }
+        ++i_pair;
       }
     }
   }
+  if constexpr (MODE == kModeEmit) return;
 
   // ---- epilogue: Eq. 15 ------------------------------------------------------
   if (!inside) return;
   float alpha = -expm1f(-m0);
   float tr = expf(-m0);
   float inv_o = 1.f / fmaxf(a.eps, so);
-  size_t pix = ((size_t)ci * c.height + py) * c.width + px;
   float* out = a.image + pix * 3;
   out[0] = alpha * sr * inv_o + tr * c.bg[0];
   out[1] = alpha * sg * inv_o + tr * c.bg[1];
@@ -149,22 +305,108 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
   sv[1] = make_float4(tc, sd, m0, fallback ? -(float)(n_cov + 1) : (float)n_cov);
 }
 
+// Second half of the surrogate forward: Eq. 7 with the optical depth m_0 F
+// from the surrogate's outputs for the queries the emit pass listed, in the
+// same pair order (query index = pixel base + pair * NQ + edge).
+template <int NQ>
+__global__ __launch_bounds__(256) void k_render_consume(RenderArgs a, CamSet cams) {
+  __shared__ Stage st;
+  const int tiles_per_cam = a.tiles_x * a.tiles_y;
+  const int n_keys = tiles_per_cam * a.n_cams;
+  const int key = remap_xcd(blockIdx.x, gridDim.x);
+  if (key >= n_keys) return;
+  const int ci = key / tiles_per_cam;
+  const int tile = key - ci * tiles_per_cam;
+  const int ty = tile / a.tiles_x, tx = tile - ty * a.tiles_x;
+  const CamConst& c = cams.c[ci];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int px = tx * kTile + (wave & 1) * 8 + (lane & 7);
+  const int py = ty * kTile + (wave >> 1) * 8 + (lane >> 3);
+  const bool inside = px < c.width && py < c.height;
+  const float u = (float)px + 0.5f, v = (float)py + 0.5f;
+  const float rx = (u - c.cx) / c.fx, ry = (v - c.cy) / c.fy;
+  const float lam = sqrtf(1.f + rx * rx + ry * ry);
+  const float tn = c.tn;
+  const int2 rg = a.ranges[key];
+  const size_t pix = ((size_t)ci * c.height + (inside ? py : 0)) * c.width + (inside ? px : 0);
+  const float* pf = a.pixfeat + pix * kPixFeat;
+  const float m0 = inside ? pf[6] : 0.f;
+  const long long qbase = inside ? a.pix_qbase[pix] : -1;
+  const bool active = qbase >= 0;
+  const PixelBasis pb = make_basis(inside ? pf[7] : tn, inside ? pf[8] : 1.f, tn);
+  float sr = 0.f, sg = 0.f, sb = 0.f, so = 0.f;
+  int i_pair = 0;
+  for (int b = rg.x; b < rg.y; b += kBlock) {
+    int nb = min(kBlock, rg.y - b);
+    __syncthreads();
+    load_batch(st, a.rec, a.sorted_rec, b, nb);
+    __syncthreads();
+    for (int j = 0; j < nb; ++j) {
+      float dx, dy;
+      bool cov = covers(st, j, u, v, active, dx, dy);
+      if (__ballot(cov) == 0) continue;
+      if (cov) {
+        RayG g = ray_params(st, j, dx, dy, lam);
+        QEdges<NQ> e;
+        quad_edges<NQ>(g, pb, tn, a, e);
+        const float* fq = a.q_f + qbase + (long long)i_pair * NQ;
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) e.tau[k] = m0 * fq[k];
+        float q = quad_sum<NQ>(g, tn, e);
+        float4 f5 = st.f[5][j];
+        sr += q * f5.y;
+        sg += q * f5.z;
+        sb += q * f5.w;
+        so += q;
+        ++i_pair;
+      }
+    }
+  }
+  if (!inside) return;
+  float alpha = -expm1f(-m0);
+  float tr = expf(-m0);
+  float inv_o = 1.f / fmaxf(a.eps, so);
+  float* out = a.image + pix * 3;
+  out[0] = alpha * sr * inv_o + tr * c.bg[0];
+  out[1] = alpha * sg * inv_o + tr * c.bg[1];
+  out[2] = alpha * sb * inv_o + tr * c.bg[2];
+  float4* sv = reinterpret_cast<float4*>(a.saved + pix * MB_SAVED_FLOATS_PER_PIXEL);
+  sv[0] = make_float4(sr, sg, sb, so);
+  sv[1] = make_float4(pf[7], pf[8], m0, pf[9]);
+}
+
 hipError_t launch_render_forward(const RenderArgs& a, const CamSet& cams, int n_moments, int n_intervals,
-                                 hipStream_t s) {
+                                 hipStream_t s, int mode) {
   int n_keys = a.tiles_x * a.tiles_y * a.n_cams;
   int nblocks = ((n_keys + 7) / 8) * 8;
   dim3 grid(nblocks), block(kBlock);
-#define MB_LAUNCH(KK, NN)                                                           \
-  if (n_moments == KK && n_intervals == NN) {                                       \
-    hipLaunchKernelGGL((k_render_fwd<KK, NN + 1>), grid, block, 0, s, a, cams);     \
+#define MB_LAUNCH(KK, NN, MM)                                                       \
+  if (n_moments == KK && n_intervals == NN && mode == MM) {                         \
+    hipLaunchKernelGGL((k_render_fwd<KK, NN + 1, MM>), grid, block, 0, s, a, cams); \
     return hipGetLastError();                                                       \
   }
-  MB_LAUNCH(4, 3)
-  MB_LAUNCH(6, 3)
-  MB_LAUNCH(4, 5)
-  MB_LAUNCH(6, 5)
+  MB_LAUNCH(4, 3, kModePlain)
+  MB_LAUNCH(6, 3, kModePlain)
+  MB_LAUNCH(4, 5, kModePlain)
+  MB_LAUNCH(6, 5, kModePlain)
+  MB_LAUNCH(6, 3, kModeHarvest)
+  MB_LAUNCH(6, 5, kModeHarvest)
+  MB_LAUNCH(6, 3, kModeEmit)
+  MB_LAUNCH(6, 5, kModeEmit)
 #undef MB_LAUNCH
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_render_consume(const RenderArgs& a, const CamSet& cams, int n_intervals, hipStream_t s) {
+  int n_keys = a.tiles_x * a.tiles_y * a.n_cams;
+  dim3 grid(((n_keys + 7) / 8) * 8), block(kBlock);
+  if (n_intervals == 3)
+    hipLaunchKernelGGL(k_render_consume<4>, grid, block, 0, s, a, cams);
+  else if (n_intervals == 5)
+    hipLaunchKernelGGL(k_render_consume<6>, grid, block, 0, s, a, cams);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
 }
 
 }  // namespace mb

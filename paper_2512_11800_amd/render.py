@@ -68,7 +68,7 @@ def camera_struct(cam) -> L.MbCamera:
     return c
 
 
-def options_struct(opts=None, surrogate: Optional[torch.Tensor] = None) -> L.MbOptions:
+def options_struct(opts=None) -> L.MbOptions:
     o = L.MbOptions()
     L.load().mb_default_options(ctypes.byref(o))
     if opts is not None:
@@ -79,9 +79,6 @@ def options_struct(opts=None, surrogate: Optional[torch.Tensor] = None) -> L.MbO
         o.beta = float(opts.beta)
         o.eps = float(opts.eps)
         o.full_coverage = int(bool(getattr(opts, "full_coverage", False)))
-        o.recon = int(getattr(opts, "recon", 0))
-    if surrogate is not None:
-        o.surrogate = surrogate.data_ptr()
     return o
 
 
@@ -92,6 +89,8 @@ class Workspace:
         self.device = torch.device(device)
         self.gws: Optional[torch.Tensor] = None
         self.pws: Optional[torch.Tensor] = None
+        self.qws: Optional[torch.Tensor] = None
+        self.q_cap: int = 0
 
     def _ensure(self, name: str, nbytes: int) -> torch.Tensor:
         cur = getattr(self, name)
@@ -130,38 +129,103 @@ def project(g: Gaussians, cam, opts=None) -> torch.Tensor:
     return out
 
 
-def render_forward(g: Gaussians, cams: Sequence, opts=None, ws: Optional[Workspace] = None,
-                   surrogate: Optional[torch.Tensor] = None):
+class _Frame:
+    """Arguments of one forward call after mb_prepare (outputs allocated)."""
+
+    def __init__(self, g: Gaussians, cams: Sequence, opts, ws: Optional[Workspace]):
+        lib = L.load()
+        self.cam_arr = _cams(cams)
+        self.n_cams = len(self.cam_arr)
+        self.width, self.height = int(self.cam_arr[0].width), int(self.cam_arr[0].height)
+        self.o = options_struct(opts)
+        self.gs = g.struct()
+        self.ws = ws or Workspace(g.means.device)
+        gws = self.ws._ensure("gws", lib.mb_gauss_workspace_bytes(g.n, self.n_cams))
+        n_entries = ctypes.c_int64(0)
+        L.check(lib.mb_prepare(ctypes.byref(self.gs), self.cam_arr, self.n_cams, ctypes.byref(self.o),
+                               _ptr(gws), gws.numel(), ctypes.byref(n_entries), _stream()))
+        self.n_entries = int(n_entries.value)
+        self.ws._ensure("pws", lib.mb_pair_workspace_bytes(self.n_entries, self.n_cams, self.width,
+                                                           self.height))
+        dev = g.means.device
+        self.image = torch.empty(self.n_cams, self.height, self.width, 3, dtype=torch.float32, device=dev)
+        self.saved = torch.empty(self.n_cams, self.height, self.width, L.MB_SAVED_FLOATS_PER_PIXEL,
+                                 dtype=torch.float32, device=dev)
+
+    def head(self):
+        """The arguments every forward entry point starts with."""
+        ws = self.ws
+        return (ctypes.byref(self.gs), self.cam_arr, self.n_cams, ctypes.byref(self.o), _ptr(ws.gws),
+                ws.gws.numel(), _ptr(ws.pws), ws.pws.numel(), self.n_entries)
+
+    def result(self):
+        return self.image, self.saved, RenderState(self.ws, self.n_entries, self.n_cams, self.width,
+                                                   self.height)
+
+
+def render_forward(g: Gaussians, cams: Sequence, opts=None, ws: Optional[Workspace] = None):
     """mb_prepare + mb_render_forward. Returns (image [C,H,W,3], saved [C,H,W,8], state)."""
+    f = _Frame(g, cams, opts, ws)
+    L.check(L.load().mb_render_forward(*f.head(), _ptr(f.image), _ptr(f.saved), _stream()))
+    return f.result()
+
+
+HARVEST_STRIDE = 12
+
+
+def render_forward_harvest(g: Gaussians, cams: Sequence, opts, rate: float, seed: int,
+                           samples: torch.Tensor, count: torch.Tensor,
+                           ws: Optional[Workspace] = None):
+    """mb_prepare + mb_render_forward_harvest: the plain forward render that
+    also appends training samples of the surrogate to ``samples``
+    [capacity, 12] (device float32) and advances ``count`` (device int32 [1]).
+    Returns (image, saved, state)."""
+    if samples.dtype != torch.float32 or samples.dim() != 2 or samples.shape[1] != HARVEST_STRIDE:
+        raise ValueError("samples must be a float32 [capacity, 12] tensor")
+    if count.dtype != torch.int32 or count.numel() != 1:
+        raise ValueError("count must be a device int32 tensor of one element")
+    f = _Frame(g, cams, opts, ws)
+    L.check(L.load().mb_render_forward_harvest(*f.head(), float(rate), int(seed) & 0xFFFFFFFF,
+                                               _ptr(samples), int(samples.shape[0]), _ptr(count),
+                                               _ptr(f.image), _ptr(f.saved), _stream()))
+    return f.result()
+
+
+def render_forward_surrogate(g: Gaussians, cams: Sequence, opts, mlp_packed: torch.Tensor,
+                             ws: Optional[Workspace] = None, query_capacity: Optional[int] = None,
+                             check_capacity: bool = True):
+    """mb_prepare + mb_render_forward_surrogate (the learned surrogate in place
+    of the moment bounds). The query list lives in ``ws`` and is grown (and
+    the frame rendered again) when a frame needs more queries than it holds;
+    ``check_capacity=False`` skips that readback once ``ws`` is known to be
+    large enough. Returns (image, saved, state)."""
     lib = L.load()
-    cam_arr = _cams(cams)
-    n_cams = len(cam_arr)
-    width, height = int(cam_arr[0].width), int(cam_arr[0].height)
-    o = options_struct(opts, surrogate)
-    gs = g.struct()
-    ws = ws or Workspace(g.means.device)
-    gbytes = lib.mb_gauss_workspace_bytes(g.n, n_cams)
-    gws = ws._ensure("gws", gbytes)
-    n_entries = ctypes.c_int64(0)
-    L.check(lib.mb_prepare(ctypes.byref(gs), cam_arr, n_cams, ctypes.byref(o), _ptr(gws),
-                           gws.numel(), ctypes.byref(n_entries), _stream()))
-    pbytes = lib.mb_pair_workspace_bytes(n_entries.value, n_cams, width, height)
-    pws = ws._ensure("pws", pbytes)
-    image = torch.empty(n_cams, height, width, 3, dtype=torch.float32, device=g.means.device)
-    saved = torch.empty(n_cams, height, width, L.MB_SAVED_FLOATS_PER_PIXEL, dtype=torch.float32,
-                        device=g.means.device)
-    L.check(lib.mb_render_forward(ctypes.byref(gs), cam_arr, n_cams, ctypes.byref(o), _ptr(gws),
-                                  gws.numel(), _ptr(pws), pws.numel(), n_entries.value,
-                                  _ptr(image), _ptr(saved), _stream()))
-    return image, saved, RenderState(ws, int(n_entries.value), n_cams, width, height)
+    f = _Frame(g, cams, opts, ws)
+    ws = f.ws
+    if query_capacity is not None:
+        ws.q_cap = max(ws.q_cap, int(query_capacity))
+    if ws.q_cap == 0:
+        ws.q_cap = 1 << 20
+    while True:
+        need = lib.mb_query_workspace_bytes(f.n_cams, f.width, f.height, ws.q_cap)
+        qws = ws._ensure("qws", need)
+        L.check(lib.mb_render_forward_surrogate(*f.head(), _ptr(mlp_packed), _ptr(qws), qws.numel(),
+                                                ws.q_cap, _ptr(f.image), _ptr(f.saved), _stream()))
+        if not check_capacity:
+            break
+        n_q = int(qws[:8].view(torch.int64).item())
+        if n_q <= ws.q_cap:
+            break
+        ws.q_cap = int(n_q * 1.1) + 1024
+    return f.result()
 
 
 def render_backward(g: Gaussians, cams: Sequence, opts, state: RenderState, saved: torch.Tensor,
-                    grad_image: torch.Tensor, surrogate: Optional[torch.Tensor] = None):
+                    grad_image: torch.Tensor):
     """mb_render_backward. Returns a dict of gradients shaped like the inputs."""
     lib = L.load()
     cam_arr = _cams(cams)
-    o = options_struct(opts, surrogate)
+    o = options_struct(opts)
     grad_image = grad_image.to(torch.float32).contiguous()
     out = {k: torch.empty_like(getattr(g, k)) for k in ("means", "scales", "quats", "densities", "colors")}
     ws = state.ws
@@ -175,25 +239,22 @@ def render_backward(g: Gaussians, cams: Sequence, opts, state: RenderState, save
 
 class _MomentRender(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, means, scales, quats, densities, colors, sh_degree, cams, opts, surrogate):
+    def forward(ctx, means, scales, quats, densities, colors, sh_degree, cams, opts):
         g = Gaussians(means.contiguous(), scales.contiguous(), quats.contiguous(),
                       densities.contiguous(), colors.contiguous(), sh_degree)
-        image, saved, state = render_forward(g, cams, opts, surrogate=surrogate)
-        ctx.g, ctx.cams, ctx.opts, ctx.state, ctx.surrogate = g, cams, opts, state, surrogate
+        image, saved, state = render_forward(g, cams, opts)
+        ctx.g, ctx.cams, ctx.opts, ctx.state = g, cams, opts, state
         ctx.save_for_backward(saved)
         return image
 
     @staticmethod
     def backward(ctx, grad_image):
         (saved,) = ctx.saved_tensors
-        grads = render_backward(ctx.g, ctx.cams, ctx.opts, ctx.state, saved, grad_image,
-                                surrogate=ctx.surrogate)
+        grads = render_backward(ctx.g, ctx.cams, ctx.opts, ctx.state, saved, grad_image)
         return (grads["means"], grads["scales"], grads["quats"], grads["densities"],
-                grads["colors"], None, None, None, None)
+                grads["colors"], None, None, None)
 
 
-def render(means, scales, quats, densities, colors, cams, opts=None, sh_degree: int = -1,
-           surrogate: Optional[torch.Tensor] = None) -> torch.Tensor:
+def render(means, scales, quats, densities, colors, cams, opts=None, sh_degree: int = -1) -> torch.Tensor:
     """Differentiable render [C,H,W,3] of the Gaussians from ``cams``."""
-    return _MomentRender.apply(means, scales, quats, densities, colors, sh_degree, list(cams),
-                               opts, surrogate)
+    return _MomentRender.apply(means, scales, quats, densities, colors, sh_degree, list(cams), opts)

@@ -95,3 +95,49 @@ def train(x: torch.Tensor, t: torch.Tensor, steps: int, batch: int = 65536, lr: 
         if log_every and (step % log_every == 0 or step == steps):
             losses.append((step, float(loss.item())))
     return theta, packed, losses
+
+
+def _pairs_of(saved: torch.Tensor) -> int:
+    """Covering (pixel, Gaussian) pairs of a forward render, from saved[..., 7]
+    (the count n, or -(n + 1) where the Hankel factor took a bias)."""
+    c = saved[..., 7]
+    return int(torch.where(c < 0, -c - 1, c).sum().item())
+
+
+def harvest(g, cams, opts, n_target: int, seed: int = 0, ws=None):
+    """Training samples of the surrogate from the plain forward render of
+    every camera in ``cams`` (one camera per call of
+    mb_render_forward_harvest): about ``n_target`` queries drawn uniformly
+    from all (pixel, covering Gaussian, quadrature edge) queries of the
+    frames. The selection is a hash threshold, so the set is deterministic;
+    the rows are returned in hash order, cut to the n_target smallest hashes.
+    Returns (x [N, 8] = features, query, m_0; t [N] transmittance of the
+    moment bounds; info dict)."""
+    from .render import HARVEST_STRIDE, Workspace, render_forward_harvest
+    cams = list(cams)
+    dev = g.means.device
+    ws = ws or Workspace(dev)
+    nq = opts.n_intervals + 1
+    # size the sampling rate from the first camera's query count
+    probe = torch.empty(1, HARVEST_STRIDE, dtype=torch.float32, device=dev)
+    count = torch.zeros(1, dtype=torch.int32, device=dev)
+    _, saved, _ = render_forward_harvest(g, cams[:1], opts, 0.0, seed, probe, count, ws)
+    est = max(1, _pairs_of(saved) * nq * len(cams))
+    rate = min(1.0, 1.2 * n_target / est)
+    cap = int(1.5 * n_target) + 4096
+    while True:
+        samples = torch.empty(cap, HARVEST_STRIDE, dtype=torch.float32, device=dev)
+        count.zero_()
+        for i, cam in enumerate(cams):
+            render_forward_harvest(g, [cam], opts, rate, (seed * 1000003 + i) & 0xFFFFFFFF,
+                                     samples, count, ws)
+        got = int(count.item())
+        if got <= cap:
+            break
+        cap = int(got * 1.1) + 4096  # keep every selected sample: the set stays deterministic
+    samples = samples[:got]
+    key = samples[:, 9].view(torch.int32).to(torch.int64) & 0xFFFFFFFF
+    order = torch.argsort(key * (1 << 31) + (samples[:, 10].view(torch.int32).to(torch.int64)))
+    samples = samples[order[:n_target]]
+    info = {"rate": rate, "selected": got, "queries_estimate": est, "kept": int(samples.shape[0])}
+    return samples[:, :8].contiguous(), samples[:, 8].contiguous(), info

@@ -640,3 +640,118 @@ def test_bf16_rounding_is_nearest_even():
     assert bf16(1.0 + 2 ** -8) == 1.0          # tie -> even
     assert bf16(1.0 + 3 * 2 ** -8) == 1.0 + 2 ** -6  # tie -> even (up)
     assert bf16(1.0 + 2 ** -8 + 2 ** -12) == 1.0 + 2 ** -7
+
+
+# ---------------------------------------------------------------------------
+# Ground truth of Eqs. 2-3 (oracle.exact) used for image quality.
+# ---------------------------------------------------------------------------
+
+def test_exact_single_gaussian_closed_form():
+    """One Gaussian: int sigma T dt = 1 - T(inf), so L = c (1 - e^-tau) + e^-tau bg."""
+    from oracle.exact import exact_ray
+    mu, sig, om = np.array([3.0]), np.array([0.2]), np.array([4.0])
+    tau = om[0] * sig[0] * math.sqrt(math.pi / 2) * erfc((0.5 - mu[0]) / (math.sqrt(2) * sig[0]))
+    c = np.array([[0.7, 0.2, 0.1]])
+    bg = np.array([0.3, 0.3, 0.9])
+    got = exact_ray(mu, sig, om, c, 0.5, bg)
+    assert np.allclose(got, c[0] * (1 - math.exp(-tau)) + math.exp(-tau) * bg, atol=1e-12)
+    # a Gaussian cut by the near bound
+    got = exact_ray(np.array([0.6]), sig, om, c, 0.5, bg)
+    tau = om[0] * sig[0] * math.sqrt(math.pi / 2) * erfc((0.5 - 0.6) / (math.sqrt(2) * sig[0]))
+    assert np.allclose(got, c[0] * (1 - math.exp(-tau)) + math.exp(-tau) * bg, atol=1e-12)
+
+
+def test_exact_grey_scene_and_front_to_back_limit():
+    """Equal colours: L = c (1 - T(inf)) for any overlap. Far-apart thin
+    Gaussians: front-to-back compositing of their opacities."""
+    from oracle.exact import exact_ray
+    rng = np.random.default_rng(11)
+    mu = rng.uniform(1, 3, 12)
+    sig = rng.uniform(0.01, 0.4, 12)
+    om = rng.lognormal(0, 1, 12)
+    c = np.tile([0.5, 0.25, 1.0], (12, 1))
+    tot = (om * sig * math.sqrt(math.pi / 2) * erfc((0.2 - mu) / (math.sqrt(2) * sig))).sum()
+    got = exact_ray(mu, sig, om, c, 0.2, np.zeros(3))
+    assert np.allclose(got, c[0] * (1 - math.exp(-tot)), rtol=1e-9)
+    mu2, sig2, om2 = np.array([2.0, 5.0]), np.array([0.05, 0.05]), np.array([10.0, 20.0])
+    a = 1 - np.exp(-om2 * sig2 * math.sqrt(2 * math.pi))
+    c2 = np.array([[1.0, 0, 0], [0, 0, 1.0]])
+    got = exact_ray(mu2, sig2, om2, c2, 0.2, np.zeros(3))
+    assert np.allclose(got, c2[0] * a[0] + (1 - a[0]) * c2[1] * a[1], atol=1e-12)
+
+
+def test_exact_pixels_match_ray_marching_of_3d_density():
+    """The whole chain (rays, Eqs. 4-6, SH colour, Eqs. 2-3) against a fine
+    ray marching of the summed 3D density of a tiny multicolour scene."""
+    from oracle.exact import exact_pixels
+    scene = _tiny_scene(3, 5)
+    cam = W.camera_on_axis(2.0, 12, 12)
+    pix = np.arange(0, 144, 7)
+    got = exact_pixels(scene, cam, pix)
+    st = scene_tensors(scene)
+    rot = quat_to_rot(st["quats"]).numpy()
+    precs = [rot[i] @ np.diag(1 / scene.scales[i].astype(float) ** 2) @ rot[i].T for i in range(scene.n)]
+    t = np.linspace(cam.t_near, 6, 200001)
+    for k, p in enumerate(pix):
+        d = oracle.pixel_directions(cam, torch.tensor([p % 12]), torch.tensor([p // 12]))[0].numpy()
+        x = cam.origin + t[:, None] * d
+        sig = np.stack([scene.densities[i] * np.exp(-0.5 * np.einsum(
+            "ti,ij,tj->t", x - scene.means[i], precs[i], x - scene.means[i])) for i in range(scene.n)])
+        tot = sig.sum(0)
+        tau = np.concatenate([[0], np.cumsum(0.5 * (tot[1:] + tot[:-1]) * np.diff(t))])
+        ref = np.trapezoid((np.exp(-tau) * (sig.T @ scene.colors).T).T, t, axis=0)
+        assert np.abs(ref - got[k]).max() < 2e-6, p
+
+
+# ---------------------------------------------------------------------------
+# Inputs of the learned surrogate (oracle.surrogate.features / query).
+# ---------------------------------------------------------------------------
+
+def _normal_raw_moments(m, s, k_max=6):
+    from scipy.stats import norm
+    return np.array([norm(m, s).moment(k) if k else 1.0 for k in range(k_max + 1)])
+
+
+def test_surrogate_features_of_a_normal_measure():
+    """Any normal measure standardises to the moments 0, 1, 0, 3, 0, 15."""
+    from oracle.surrogate import features, query
+    mom = np.stack([2.5 * _normal_raw_moments(1.7, 0.4), 0.1 * _normal_raw_moments(-3.0, 2.0)])
+    feat, mean, std = features(mom)
+    assert np.allclose(feat, np.arcsinh([0, 1, 0, 3, 0, 15])[None, :], atol=1e-9)
+    assert np.allclose(mean, [1.7, -3.0]) and np.allclose(std, [0.4, 2.0])
+    assert np.allclose(query(np.array([1.7 + 0.8, -3.0 - 30]), mean, std), [2.0, -10.0])
+
+
+def test_surrogate_features_invariant_under_affine_variable():
+    """Features and standardised queries of an atomic measure do not change
+    when the moment variable is mapped by y -> a y + c, a > 0."""
+    from oracle.surrogate import features, query
+    rng = np.random.default_rng(12)
+    x = rng.normal(size=5)
+    w = rng.uniform(0.1, 1.0, 5)
+    a, c = 2.7, -1.3
+    m1 = np.array([[(w * x ** k).sum() for k in range(7)]])
+    m2 = np.array([[(w * (a * x + c) ** k).sum() for k in range(7)]])
+    f1, mu1, s1 = features(m1)
+    f2, mu2, s2 = features(m2)
+    assert np.allclose(f1, f2, atol=1e-9)
+    assert np.allclose(query(0.3, mu1, s1), query(a * 0.3 + c, mu2, s2))
+    # direct definition: standardised moments of the atoms
+    z = (x - (w * x).sum() / w.sum())
+    z = z / math.sqrt((w * z * z).sum() / w.sum())
+    assert np.allclose(f1[0], np.arcsinh([(w * z ** k).sum() / w.sum() for k in range(1, 7)]))
+
+
+def test_render_through_the_surrogate_inputs_reproduces_the_plain_render():
+    """The reconstruction written as a function of the network's inputs alone
+    (exact_model, no clamp) renders the same image as the plain path, so the
+    inputs carry everything the bounds use."""
+    from oracle.surrogate import exact_model
+    scene, cams, opts = W.w1_small()
+    opts.n_moments = 6
+    sub = scene.subset(np.arange(400))
+    pix = np.arange(0, 128 * 128, 37)
+    a = oracle.render_image(sub, cams[0], opts, pixels=pix)
+    b = oracle.render_image(sub, cams[0], opts, pixels=pix, tau_model=exact_model(opts.beta, np.inf))
+    assert a["n_pairs"] > 500
+    assert np.abs(a["image"] - b["image"]).max() < 1e-8
