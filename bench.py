@@ -4,9 +4,11 @@
 Workload: 500,000 Gaussians in 64 isotropic clusters (SH degree 3), one
 1920x1080 pinhole camera at distance 10, K=4 power moments, N=3 intervals;
 synthetic, seeded. A step is one frame through the whole path: preprocess,
-tile binning, the fused moment + quadrature render, and (mode fwdbwd, the
-default once the backward pass is present) the adjoint render and gradient
-reduction. Inputs are resident in HBM before timing starts.
+tile binning, the moment + quadrature render and, for forward + backward,
+the adjoint render and the gradient reduction. The default mode times both
+(the value is forward + backward, the forward figure is reported beside it);
+``--mode surrogate`` runs the learned-surrogate comparison at K=6. Inputs are
+resident in HBM before timing starts.
 
 Prints one JSON line (the benchmark contract) with ms/frame, the dominant
 kernel's roofline position (algorithmic FLOPs per launch over its measured
@@ -27,26 +29,37 @@ sys.path.insert(0, ROOT)
 PEAK_FP32_VALU_TFLOPS = 157.3  # MI355X vector FP32 (256 CUs, 2.4 GHz)
 
 
-def flops_per_pair(k_mom: int, n_int: int, backward: bool = False) -> dict:
+def flops_per_pair(k_mom: int, n_int: int) -> dict:
     """Arithmetic operations of the method per (pixel, Gaussian) pair, counted
     from its formulas (each add, multiply, divide, compare and transcendental
-    counts one): the ray-space Gaussian (Eqs. 4-6), the warp linearisation and
-    the moment recurrence (Eqs. 10-12), and per quadrature edge the moment-bound
-    reconstruction (kernel polynomial, roots, Christoffel weights) and the
-    Eq. 7 interval terms. The tally is derived in the design notes."""
+    counts one), for the passes of the forward and backward kernels:
+      ray        the ray-space Gaussian of Eqs. 4-6 from the record (37)
+      warp_lin   the warp's linearisation point, value and slope (12)
+      moments    the recurrence of Eqs. 10-12 (18 + 7 (K - 1) + K + 1)
+      recon      one reconstruction of the bounds at a query: L^-1 v(y),
+                 kernel-polynomial roots, Christoffel weights, interpolation
+                 (73 for K = 4, 169 for K = 6 with its cubic)
+      hermite    the adjoint of one reconstruction: divided differences of the
+                 Hermite interpolant and its monomial form (85 / 165)
+      quadrature ray + (N + 1) (13 + recon) + 9 N + 8 (edges, warp, sigma_i,
+                 the Eq. 7 interval terms)
+    Backward: pass 1 repeats the moments; pass 2 the quadrature plus, per
+    edge, the adjoint and the (K + 1)-term accumulation; pass 3 the quadrature,
+    per edge the adjoint and the depth derivatives, the moment Jacobian in
+    three tangents and the chain to the record coefficients."""
     n = k_mom // 2
-    ray = 37
-    warp_lin = 12
+    ray, warp_lin = 37, 12
     mom = 18 + 7 * (k_mom - 1) + (k_mom + 1)
-    if n == 2:
-        recon = 73
-    else:
-        recon = 169
-    per_edge = 13 + recon
-    quad = ray + (n_int + 1) * per_edge + 9 * n_int + 8
-    fwd = {"moment_pass": ray + warp_lin + mom, "quadrature_pass": quad}
-    fwd["forward"] = fwd["moment_pass"] + fwd["quadrature_pass"]
-    return fwd
+    recon = 73 if n == 2 else 169
+    herm = 85 if n == 2 else 165
+    quad = ray + (n_int + 1) * (13 + recon) + 9 * n_int + 8
+    out = {"moment_pass": ray + warp_lin + mom, "quadrature_pass": quad}
+    out["forward"] = out["moment_pass"] + out["quadrature_pass"]
+    bwd1 = out["moment_pass"]
+    bwd2 = quad + (n_int + 1) * (herm + 3 * (k_mom + 1) + 2) + 6
+    bwd3 = quad + (n_int + 1) * (herm + 10) + 20 * n_int + (40 + 3 * mom) + 60
+    out["backward"] = bwd1 + bwd2 + bwd3
+    return out
 
 
 def _workload(k_mom: int):
@@ -56,6 +69,9 @@ def _workload(k_mom: int):
 
 
 def gpu_bench(args):
+    """Timed frames of the forward path and of forward + backward on the W2
+    scene (inputs resident on the GPU), with stage timings from the library's
+    HIP events."""
     import torch
 
     import paper_2512_11800_amd as M
@@ -65,83 +81,108 @@ def gpu_bench(args):
     scene, cams, opts = _workload(args.k)
     g = M.Gaussians.from_scene(scene, device="cuda:0")
     ws = M.Workspace("cuda:0")
-    backward = args.mode == "fwdbwd"
+    h, w = cams[0].height, cams[0].width
+    grad_img = torch.full((1, h, w, 3), 1.0 / (3 * h * w), device="cuda:0")
 
-    grad_img = None
+    def fwd():
+        return M.render_forward(g, cams, opts, ws=ws)
 
-    def step():
+    def fwdbwd():
         image, saved, st = M.render_forward(g, cams, opts, ws=ws)
-        if backward:
-            M.render_backward(g, cams, opts, st, saved, grad_img)
+        M.render_backward(g, cams, opts, st, saved, grad_img)
         return image, saved, st
 
-    if backward:
-        h, w = cams[0].height, cams[0].width
-        grad_img = torch.full((1, h, w, 3), 1.0 / (3 * h * w), device="cuda:0")
-    for _ in range(args.warmup):
-        image, saved, st = step()
-    torch.cuda.synchronize()
-    n_cov = saved[..., 7].abs().sum().item() - (saved[..., 7] < 0).sum().item()
-    n_pairs = int(round(n_cov))
-    n_fallback = int((saved[..., 7] < 0).sum().item())
+    def timed(step):
+        for _ in range(args.warmup):
+            out = step()
+        torch.cuda.synchronize()
+        L.profile_read()  # clear
+        L.profile_enable(True)
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        wall0 = time.perf_counter()
+        t0.record()
+        for _ in range(args.steps):
+            out = step()
+        t1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - wall0
+        L.profile_enable(False)
+        stages = L.profile_read()
+        return out, t0.elapsed_time(t1) / args.steps, 1e3 * wall / args.steps, stages
 
-    L.profile_read()  # clear
-    L.profile_enable(True)
-    torch.cuda.synchronize()
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    wall0 = time.perf_counter()
-    t0.record()
-    for _ in range(args.steps):
-        step()
-    t1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    L.profile_enable(False)
-    stages = L.profile_read()
-    ms_step = t0.elapsed_time(t1) / args.steps
-
+    modes = {"fwd": [("fwd", fwd)], "fwdbwd": [("fwdbwd", fwdbwd)],
+             "both": [("fwd", fwd), ("fwdbwd", fwdbwd)]}[args.mode]
+    res = {}
+    for name, step in modes:
+        (image, saved, st), ms, wall_ms, stages = timed(step)
+        print(f"[bench] {name}: {ms:.3f} ms/frame", file=sys.stderr, flush=True)
+        res[name] = {"ms_per_step": ms, "wall_ms_per_step": wall_ms,
+                     "stages_ms": {k: round(v[0] / max(1, v[1]), 4) for k, v in stages.items() if v[1]},
+                     "stages_raw": stages}
+    c = saved[..., 7]
+    n_pairs = int(torch.where(c < 0, -c - 1, c).sum().item())
+    n_fallback = int((c < 0).sum().item())
     fl = flops_per_pair(args.k, opts.n_intervals)
-    dom = "render_forward"
-    dom_ms = stages[dom][0] / max(1, stages[dom][1])
-    achieved = fl["forward"] * n_pairs / (dom_ms * 1e-3) / 1e12
-    res = {
-        "ms_per_step": ms_step,
-        "wall_ms_per_step": 1e3 * wall / args.steps,
-        "n_pairs": n_pairs,
-        "n_entries": st.n_entries,
-        "n_fallback_pixels": n_fallback,
-        "stages_ms": {k: round(v[0] / max(1, v[1]), 4) for k, v in stages.items() if v[1]},
-        "roofline": {"bound": "alu", "kernel": "k_render_fwd", "achieved": achieved,
-                     "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_VALU_TFLOPS, "traffic": None,
-                     "flops_per_pair": fl["forward"], "kernel_ms": dom_ms},
-        "pairs_per_s": n_pairs / (dom_ms * 1e-3),
-    }
-    return res, scene, cams, opts, n_pairs
+
+    def roofline(stage, kernel, flops):
+        raw = res[last]["stages_raw"][stage]
+        kms = raw[0] / max(1, raw[1])
+        ach = flops * n_pairs / (kms * 1e-3) / 1e12
+        return {"bound": "alu", "kernel": kernel, "achieved": ach, "peak": PEAK_FP32_VALU_TFLOPS,
+                "unit": "TFLOP/s", "frac": ach / PEAK_FP32_VALU_TFLOPS, "traffic": None,
+                "flops_per_pair": flops, "pairs_per_launch": n_pairs, "kernel_ms": kms}
+
+    last = modes[-1][0]
+    out = {"n_pairs": n_pairs, "n_entries": st.n_entries, "n_fallback_pixels": n_fallback, "modes": res}
+    out["roofline_fwd"] = roofline("render_forward", "k_render_fwd", fl["forward"])
+    if last == "fwdbwd":
+        out["roofline_bwd"] = roofline("render_backward", "k_render_bwd", fl["backward"])
+    for r in res.values():
+        r.pop("stages_raw")
+    return out, scene, cams, opts, n_pairs
 
 
-def cpu_baseline(scene, cams, opts, n_pairs_frame: int, budget_px: int):
-    """The oracle, as it stands, on a bounded sample of the same frame:
-    pixels on a regular stride across the image, scaled to ms/frame by the
+def cpu_baseline(scene, cams, opts, n_pairs_frame: int, budget_px: int, backward: bool):
+    """The oracle, as it stands, on a bounded sample of the same frame: pixels
+    on a regular stride across the image, forward (render_image) and forward +
+    backward (render_backward, float64 autograd), scaled to ms/frame by the
     frame's pair count."""
     import numpy as np
     import torch
 
     import oracle
+    from oracle.proxy import screen_proxy
+    from oracle.render import scene_tensors
     cam = cams[0]
     n_px = cam.width * cam.height
     stride = max(1, n_px // budget_px)
     pix = np.arange(stride // 2, n_px, stride)
+    # the per-frame part (screen proxies of all Gaussians) is timed on its own
+    # and counted once; the per-pair part is scaled by the frame's pairs
+    t = time.perf_counter()
+    screen_proxy(scene_tensors(scene), cam, opts.conf_c)
+    t_proxy = time.perf_counter() - t
     t = time.perf_counter()
     r = oracle.render_image(scene, cam, opts, pixels=pix)
-    dt = time.perf_counter() - t
-    pairs_per_s = r["n_pairs"] / dt
-    return {"value": 1e3 * n_pairs_frame / pairs_per_s, "unit": "ms/frame", "cores": torch.get_num_threads(),
-            "kind": "oracle",
-            "sample": f"{len(pix)} pixels on a stride of {stride} ({r['n_pairs']} pairs, {dt:.1f} s), "
-                      f"extrapolated by pairs/s to the frame's {n_pairs_frame} pairs",
-            "pairs_per_s": pairs_per_s}
+    dt_f = time.perf_counter() - t
+    pairs = r["n_pairs"]
+    scale = n_pairs_frame / pairs
+    out = {"unit": "ms/frame", "cores": torch.get_num_threads(), "kind": "oracle",
+           "fwd_value": 1e3 * (t_proxy + max(dt_f - t_proxy, 0.0) * scale)}
+    desc = (f"{len(pix)} pixels on a stride of {stride} ({pairs} pairs): forward {dt_f:.1f} s "
+            f"of which {t_proxy:.1f} s per-frame proxies")
+    if backward:
+        g = np.full((len(pix), 3), 1.0 / (3 * n_px))
+        t = time.perf_counter()
+        oracle.render_backward(scene, cam, opts, g, pixels=pix)
+        dt_fb = time.perf_counter() - t
+        out["value"] = 1e3 * (t_proxy + max(dt_fb - t_proxy, 0.0) * scale)
+        desc += f", forward+backward {dt_fb:.1f} s"
+    else:
+        out["value"] = out["fwd_value"]
+    out["sample"] = desc + f"; per-pair time scaled to the frame's {n_pairs_frame} pairs"
+    return out
 
 
 def surrogate_bench(args):
@@ -230,12 +271,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--mode", choices=["fwd", "fwdbwd", "surrogate"], default="fwd")
+    ap.add_argument("--mode", choices=["both", "fwd", "fwdbwd", "surrogate"], default="both")
     ap.add_argument("--harvest", type=int, default=10_000_000)
     ap.add_argument("--train-steps", type=int, default=4000)
     ap.add_argument("--gt-pixels", type=int, default=32)
     ap.add_argument("--k", type=int, default=4, choices=[4, 6])
-    ap.add_argument("--cpu-sample-px", type=int, default=3000)
+    ap.add_argument("--cpu-sample-px", type=int, default=12000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -268,16 +309,19 @@ def main():
     res, scene, cams, opts, n_pairs = gpu_bench(args)
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(scene, cams, opts, n_pairs, args.cpu_sample_px)
-    label = "fwd+bwd" if args.mode == "fwdbwd" else "fwd"
+        cpu = cpu_baseline(scene, cams, opts, n_pairs, args.cpu_sample_px, "fwdbwd" in res["modes"])
+    modes = res["modes"]
+    main_mode = "fwdbwd" if "fwdbwd" in modes else "fwd"
+    label = {"fwd": "fwd", "fwdbwd": "fwd+bwd"}[main_mode]
+    dom = res.get("roofline_bwd", res["roofline_fwd"])
     out = {
         "metric": "ms/frame 1080p fwd & fwd+bwd, 500k Gaussians; surrogate vs plain at ΔPSNR<0.1",
-        "value": res["ms_per_step"],
+        "value": modes[main_mode]["ms_per_step"],
         "unit": "ms/frame",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": res["ms_per_step"],
+        "ms_per_step": modes[main_mode]["ms_per_step"],
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
@@ -286,15 +330,19 @@ def main():
         "config": {"workload": f"500k Gaussians, 64 clusters, SH3, 1920x1080, K={args.k}, N=3, {label}",
                    "n_gaussians": scene.n, "width": cams[0].width, "height": cams[0].height,
                    "n_moments": args.k, "n_intervals": opts.n_intervals, "mode": label},
-        "roofline": res["roofline"],
+        "roofline": dom,
         "cpu_baseline": cpu,
-        "pairs_per_s": res["pairs_per_s"],
-        "n_pairs": res["n_pairs"],
-        "n_entries": res["n_entries"],
-        "n_fallback_pixels": res["n_fallback_pixels"],
-        "stages_ms": res["stages_ms"],
-        "wall_ms_per_step": res["wall_ms_per_step"],
     }
+    if "fwd" in modes:
+        out["fwd_ms_per_frame"] = modes["fwd"]["ms_per_step"]
+    if "fwdbwd" in modes:
+        out["fwdbwd_ms_per_frame"] = modes["fwdbwd"]["ms_per_step"]
+    out["roofline_fwd"] = res["roofline_fwd"]
+    out["pairs_per_frame"] = res["n_pairs"]
+    out["n_entries"] = res["n_entries"]
+    out["n_fallback_pixels"] = res["n_fallback_pixels"]
+    out["stages_ms"] = {m: modes[m]["stages_ms"] for m in modes}
+    out["wall_ms_per_step"] = {m: modes[m]["wall_ms_per_step"] for m in modes}
     print(json.dumps(out), flush=True)
 
 

@@ -151,18 +151,27 @@ struct BwdArgs {
   float* partials;          // [E,4,kGradStride]
 };
 
-__device__ __forceinline__ float wave_sum(float v) {
+// inclusive scan of v over the lanes of its segment (segments start at the
+// lanes of `head_mask`); the segment's last lane ends with the segment sum
+__device__ __forceinline__ float segment_scan(float v, int lane, int seg_start) {
 #pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  for (int d = 1; d < 64; d <<= 1) {
+    float t = __shfl_up(v, d, 64);
+    if (lane - d >= seg_start) v += t;
+  }
   return v;
 }
 
 template <int K, int NQ>
 __global__ __launch_bounds__(256) void k_render_bwd(BwdArgs ba, CamSet cams) {
   constexpr int NH = K / 2;
+  constexpr int NL = (NH + 1) * (NH + 2) / 2;
   const RenderArgs& a = ba.r;
   __shared__ Stage st;
   __shared__ int sk[kBlock];
+  __shared__ WaveQueue wq[4];
+  __shared__ __align__(16) float wres[4][(K + 1) * 64];  // per queued pair results
+  __shared__ float carry[4][G_COUNT];                    // partial slot of an entry split over chunks
   const int tiles_per_cam = a.tiles_x * a.tiles_y;
   const int n_keys = tiles_per_cam * a.n_cams;
   const int key = remap_xcd(blockIdx.x, gridDim.x);
@@ -172,8 +181,9 @@ __global__ __launch_bounds__(256) void k_render_bwd(BwdArgs ba, CamSet cams) {
   const int ty = tile / a.tiles_x, tx = tile - ty * a.tiles_x;
   const CamConst& c = cams.c[ci];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int px = tx * kTile + (wave & 1) * 8 + (lane & 7);
-  const int py = ty * kTile + (wave >> 1) * 8 + (lane >> 3);
+  const int x0 = tx * kTile + (wave & 1) * 8, y0 = ty * kTile + (wave >> 1) * 8;
+  const int px = x0 + (lane & 7);
+  const int py = y0 + (lane >> 3);
   const bool inside = px < c.width && py < c.height;
   const float u = (float)px + 0.5f, v = (float)py + 0.5f;
   const float rx = (u - c.cx) / c.fx, ry = (v - c.cy) / c.fy;
@@ -181,6 +191,8 @@ __global__ __launch_bounds__(256) void k_render_bwd(BwdArgs ba, CamSet cams) {
   const float tn = c.tn;
   const int2 rg = a.ranges[key];
   const size_t pix = inside ? ((size_t)ci * c.height + py) * c.width + px : 0;
+  WaveQueue& q = wq[wave];
+  float* res = wres[wave];
 
   float sv[8] = {0.f, 0.f, 0.f, 0.f, tn + 1.f, 1.f, 0.f, 0.f};
   float gi[3] = {0.f, 0.f, 0.f};
@@ -195,26 +207,75 @@ __global__ __launch_bounds__(256) void k_render_bwd(BwdArgs ba, CamSet cams) {
   }
   const PixelBasis pb = make_basis(sv[4], sv[5], tn);
 
+  // per-pixel values of pixel lane p, for a queued pair evaluated on another lane
+  auto basis_of = [&](int p) {
+    PixelBasis r;
+    r.tc = from_lane(pb.tc, p);
+    r.p = from_lane(pb.p, p);
+    r.p15 = from_lane(pb.p15, p);
+    r.amp = from_lane(pb.amp, p);
+    return r;
+  };
+  // the pair at queue position `lane` (entry j, pixel lane p); inactive lanes
+  // (lane >= n) get p = lane so the cross-lane reads stay uniform
+  auto item_of = [&](int n, int& j, int& p) {
+    const bool act = lane < n;
+    const int it = act ? (int)q.item[lane] : lane;
+    j = act ? (it >> 6) : 0;
+    p = it & 63;
+    return act;
+  };
+  auto ray_of = [&](int j, int p, float lamp) {
+    const float dx = (float)(x0 + (p & 7)) + 0.5f - st.f[0][j].x;
+    const float dy = (float)(y0 + (p >> 3)) + 0.5f - st.f[0][j].y;
+    return ray_params(st, j, dx, dy, lamp);
+  };
+
   // ---- pass 1: recompute the moments (identical to the forward pass) -------
   double acc[K + 1];
 #pragma unroll
   for (int k = 0; k <= K; ++k) acc[k] = 0.0;
-  for (int b = rg.x; b < rg.y; b += kBlock) {
-    int nb = min(kBlock, rg.y - b);
-    __syncthreads();
-    load_batch(st, a.rec, a.sorted_rec, b, nb);
-    __syncthreads();
-    for (int j = 0; j < nb; ++j) {
-      float dx, dy;
-      bool cov = covers(st, j, u, v, inside, dx, dy);
-      if (__ballot(cov) == 0) continue;
-      if (cov) {
-        RayG g = ray_params(st, j, dx, dy, lam);
+  {
+    auto flush = [&](int n, uint64_t own) {
+      int j, p;
+      const bool act = item_of(n, j, p);
+      const PixelBasis pp = basis_of(p);
+      const float lamp = from_lane(lam, p);
+      if (act) {
+        RayG g = ray_of(j, p, lamp);
         float m[K + 1];
-        particle_moments<K>(g, pb, tn, m);
+        particle_moments<K>(g, pp, tn, m);
 #pragma unroll
-        for (int k = 0; k <= K; ++k) acc[k] += (double)m[k];
+        for (int k = 0; k <= K; ++k) res[k * 64 + lane] = m[k];
       }
+      __builtin_amdgcn_wave_barrier();
+      while (own) {
+        const int i = __builtin_ctzll(own);
+        own &= own - 1;
+#pragma unroll
+        for (int k = 0; k <= K; ++k) acc[k] += (double)res[k * 64 + i];
+      }
+      __builtin_amdgcn_wave_barrier();
+    };
+    for (int b = rg.x; b < rg.y; b += kBlock) {
+      int nb = min(kBlock, rg.y - b);
+      __syncthreads();
+      load_batch(st, a.rec, a.sorted_rec, b, nb);
+      __syncthreads();
+      QueueCursor qc;
+      queue_reset(qc);
+      for (int j = 0; j < nb; ++j) {
+        float dx, dy;
+        bool cov = covers(st, j, u, v, inside, dx, dy);
+        uint64_t mask = __ballot(cov);
+        if (mask == 0) continue;
+        queue_push(q, qc, mask, cov, j, lane);
+        if (qc.cnt >= 64) {
+          flush(64, qc.own_lo);
+          queue_pop64(q, qc, lane);
+        }
+      }
+      if (qc.cnt > 0) flush(qc.cnt, qc.own_lo);
     }
   }
   const float m0 = (float)acc[0];
@@ -235,7 +296,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(BwdArgs ba, CamSet cams) {
 #pragma unroll
     for (int k = 1; k <= K; ++k) bk[k] = 0.f;
 #pragma unroll
-    for (int i = 0; i < (NH + 1) * (NH + 2) / 2; ++i) L.l[i] = 0.f;
+    for (int i = 0; i < NL; ++i) L.l[i] = 0.f;
   }
 
   // ---- Eq. 15 adjoint, folded into the two stages -------------------------
@@ -252,26 +313,40 @@ __global__ __launch_bounds__(256) void k_render_bwd(BwdArgs ba, CamSet cams) {
   }
 
   const bool active = inside && live;
+  auto linv_of = [&](int p) {
+    LInv<NH> r;
+#pragma unroll
+    for (int i = 0; i < NL; ++i) r.l[i] = from_lane(L.l[i], p);
+    return r;
+  };
+
   // ---- pass 2: adjoint moments ---------------------------------------------
   float dm[K + 1];
 #pragma unroll
   for (int k = 0; k <= K; ++k) dm[k] = 0.f;
-  dm[0] = (inside && live) ? e0 : 0.f;
-  for (int b = rg.x; b < rg.y; b += kBlock) {
-    int nb = min(kBlock, rg.y - b);
-    __syncthreads();
-    load_batch(st, a.rec, a.sorted_rec, b, nb);
-    __syncthreads();
-    for (int j = 0; j < nb; ++j) {
-      float dx, dy;
-      bool cov = covers(st, j, u, v, active, dx, dy);
-      if (__ballot(cov) == 0) continue;
-      if (cov) {
-        RayG g = ray_params(st, j, dx, dy, lam);
+  dm[0] = active ? e0 : 0.f;
+  {
+    auto flush = [&](int n, uint64_t own) {
+      int j, p;
+      const bool act = item_of(n, j, p);
+      const PixelBasis pp = basis_of(p);
+      const LInv<NH> Lp = linv_of(p);
+      const float lamp = from_lane(lam, p), m0p = from_lane(m0, p);
+      const float ga0 = from_lane(ga[0], p), ga1 = from_lane(ga[1], p), ga2 = from_lane(ga[2], p);
+      const float gbp = from_lane(gb, p);
+      float bkp[K + 1];
+      bkp[0] = 1.f;
+#pragma unroll
+      for (int k = 1; k <= K; ++k) bkp[k] = from_lane(bk[k], p);
+      if (act) {
+        RayG g = ray_of(j, p, lamp);
         QuadState<NH, NQ> s;
-        quad_state<NH, NQ>(g, pb, L, m0, tn, a, s);
+        quad_state<NH, NQ>(g, pp, Lp, m0p, tn, a, s);
         float4 f5 = st.f[5][j];
-        float gbar = ga[0] * f5.y + ga[1] * f5.z + ga[2] * f5.w + gb;
+        float gbar = ga0 * f5.y + ga1 * f5.z + ga2 * f5.w + gbp;
+        float d[K + 1];
+#pragma unroll
+        for (int k = 0; k <= K; ++k) d[k] = 0.f;
 #pragma unroll
         for (int e = 0; e < NQ; ++e) {
           float lamk[2 * NH + 1], dl;
@@ -280,49 +355,85 @@ __global__ __launch_bounds__(256) void k_render_bwd(BwdArgs ba, CamSet cams) {
           float lb = 0.f;
 #pragma unroll
           for (int k = 1; k <= K; ++k) {
-            dm[k] += wgt * lamk[k];
-            lb += lamk[k] * bk[k];
+            d[k] += wgt * lamk[k];
+            lb += lamk[k] * bkp[k];
           }
-          dm[0] += wgt * (s.F[e] - lb);
+          d[0] += wgt * (s.F[e] - lb);
+        }
+#pragma unroll
+        for (int k = 0; k <= K; ++k) res[k * 64 + lane] = d[k];
+      }
+      __builtin_amdgcn_wave_barrier();
+      while (own) {
+        const int i = __builtin_ctzll(own);
+        own &= own - 1;
+#pragma unroll
+        for (int k = 0; k <= K; ++k) dm[k] += res[k * 64 + i];
+      }
+      __builtin_amdgcn_wave_barrier();
+    };
+    for (int b = rg.x; b < rg.y; b += kBlock) {
+      int nb = min(kBlock, rg.y - b);
+      __syncthreads();
+      load_batch(st, a.rec, a.sorted_rec, b, nb);
+      __syncthreads();
+      QueueCursor qc;
+      queue_reset(qc);
+      for (int j = 0; j < nb; ++j) {
+        float dx, dy;
+        bool cov = covers(st, j, u, v, active, dx, dy);
+        uint64_t mask = __ballot(cov);
+        if (mask == 0) continue;
+        queue_push(q, qc, mask, cov, j, lane);
+        if (qc.cnt >= 64) {
+          flush(64, qc.own_lo);
+          queue_pop64(q, qc, lane);
         }
       }
+      if (qc.cnt > 0) flush(qc.cnt, qc.own_lo);
     }
   }
 
   // ---- pass 3: per-pair gradients, one reduction per (entry, wave) ---------
-  for (int b = rg.x; b < rg.y; b += kBlock) {
-    int nb = min(kBlock, rg.y - b);
-    __syncthreads();
-    load_batch(st, a.rec, a.sorted_rec, b, nb);
-    if (tid < nb) sk[tid] = ba.sorted_k[b + tid];
-    __syncthreads();
-    for (int j = 0; j < nb; ++j) {
-      float dx, dy;
-      bool cov = covers(st, j, u, v, active, dx, dy);
-      float4* slot = reinterpret_cast<float4*>(ba.partials + ((size_t)sk[j] * 4 + wave) * kGradStride);
-      if (__ballot(cov) == 0) {
-        if (lane == 0) {
+  // Queued pairs of one entry are contiguous; a segmented scan over the lanes
+  // sums each entry's pairs, and the last lane of the segment writes the
+  // entry's slot. An entry split over two evaluations of the queue leaves its
+  // first part in `carry`.
+  {
+    float* cw = carry[wave];
+    int carry_j = -1;
+    auto slot_of = [&](int j) {
+      return reinterpret_cast<float4*>(ba.partials + ((size_t)sk[j] * 4 + wave) * kGradStride);
+    };
+    auto flush = [&](int n, int cont_j) {
+      int j, p;
+      const bool act = item_of(n, j, p);
+      const PixelBasis pp = basis_of(p);
+      const LInv<NH> Lp = linv_of(p);
+      const float lamp = from_lane(lam, p), m0p = from_lane(m0, p);
+      float gap[3] = {from_lane(ga[0], p), from_lane(ga[1], p), from_lane(ga[2], p)};
+      const float gbp = from_lane(gb, p);
+      float dmp[K + 1];
 #pragma unroll
-          for (int f = 0; f < kGradStride / 4; ++f) slot[f] = make_float4(0.f, 0.f, 0.f, 0.f);
-        }
-        continue;
-      }
+      for (int k = 0; k <= K; ++k) dmp[k] = from_lane(dm[k], p);
       float gr[G_COUNT];
 #pragma unroll
       for (int f = 0; f < G_COUNT; ++f) gr[f] = 0.f;
-      if (cov) {
-        RayG g = ray_params(st, j, dx, dy, lam);
+      if (act) {
+        const float dx = (float)(x0 + (p & 7)) + 0.5f - st.f[0][j].x;
+        const float dy = (float)(y0 + (p >> 3)) + 0.5f - st.f[0][j].y;
+        RayG g = ray_params(st, j, dx, dy, lamp);
         QuadState<NH, NQ> s;
-        quad_state<NH, NQ>(g, pb, L, m0, tn, a, s);
+        quad_state<NH, NQ>(g, pp, Lp, m0p, tn, a, s);
         float4 f5 = st.f[5][j];
-        float gbar = ga[0] * f5.y + ga[1] * f5.z + ga[2] * f5.w + gb;
+        float gbar = gap[0] * f5.y + gap[1] * f5.z + gap[2] * f5.w + gbp;
         // dq / d(mu, Sigma, omega) at fixed moments
         float dq0 = 0.f, dq1 = 0.f, dq2 = 0.f;
 #pragma unroll
         for (int e = 0; e < NQ; ++e) {
           float lamk[2 * NH + 1], dl;
           hermite_adjoint<NH>(s.y[e], s.x[e], s.below[e], a.beta, lamk, dl);
-          float dtau_dt = -m0 * s.w0[e] * dl * warp_dy(pb, s.t[e]);
+          float dtau_dt = -m0p * s.w0[e] * dl * warp_dy(pp, s.t[e]);
           float dtdmu = s.cl[e] ? 0.f : 1.f;
           float dtdsig = s.cl[e] ? 0.f : a.kappa * a.xq[e];
           dq0 += s.A[e] * dtau_dt * dtdmu;
@@ -345,7 +456,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(BwdArgs ba, CamSet cams) {
           dq2 += cs * s.sr[e];
         }
         float gm[3];
-        moment_grads<K>(g, pb, tn, dm, gm);
+        moment_grads<K>(g, pp, tn, dmp, gm);
         float gmu = gbar * dq0 + gm[0];
         float gsig = gbar * dq1 + gm[1];
         float gom = gbar * dq2 + gm[2];
@@ -355,7 +466,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(BwdArgs ba, CamSet cams) {
         float x = f4.y * dx * dx + 2.f * f4.z * dx * dy + f4.w * dy * dy;
         float id = fast_rcp(d);
         float ek = __expf(-0.5f * x * id);
-        float gE = gmu * lam * id;
+        float gE = gmu * lamp * id;
         float gD = -gmu * g.mu * id - 0.5f * gsig * g.sig * id + 0.5f * gom * g.omega * x * id * id;
         float gX = -0.5f * gom * g.omega * id;
         gr[G_D0] = gD;
@@ -375,19 +486,71 @@ __global__ __launch_bounds__(256) void k_render_bwd(BwdArgs ba, CamSet cams) {
         gr[G_P0X] = -gdx;
         gr[G_P0Y] = -gdy;
         gr[G_W] = gom * ek;
-        gr[G_CR] = s.q * ga[0];
-        gr[G_CG] = s.q * ga[1];
-        gr[G_CB] = s.q * ga[2];
+        gr[G_CR] = s.q * gap[0];
+        gr[G_CG] = s.q * gap[1];
+        gr[G_CB] = s.q * gap[2];
       }
+      // segments: runs of equal entries (inactive lanes are segments of their own)
+      const int jprev = __shfl_up(j, 1, 64);
+      const bool head = !act || lane == 0 || jprev != j;
+      const uint64_t heads = __ballot(head);
+      const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1);
+      const int seg_start = 63 - __builtin_clzll(heads & upto);
+      const int jnext = __shfl_down(j, 1, 64);
+      const bool last = act && (lane == n - 1 || jnext != j);
 #pragma unroll
-      for (int f = 0; f < G_COUNT; ++f) gr[f] = wave_sum(gr[f]);
-      if (lane == 0) {
-        slot[0] = make_float4(gr[0], gr[1], gr[2], gr[3]);
-        slot[1] = make_float4(gr[4], gr[5], gr[6], gr[7]);
-        slot[2] = make_float4(gr[8], gr[9], gr[10], gr[11]);
-        slot[3] = make_float4(gr[12], gr[13], gr[14], gr[15]);
-        slot[4] = make_float4(gr[16], gr[17], 0.f, 0.f);
+      for (int f = 0; f < G_COUNT; ++f) gr[f] = segment_scan(gr[f], lane, seg_start);
+      if (last) {
+        if (seg_start == 0 && j == carry_j) {
+#pragma unroll
+          for (int f = 0; f < G_COUNT; ++f) gr[f] += cw[f];
+        }
+        if (lane == n - 1 && j == cont_j) {
+#pragma unroll
+          for (int f = 0; f < G_COUNT; ++f) cw[f] = gr[f];
+        } else {
+          float4* slot = slot_of(j);
+          slot[0] = make_float4(gr[0], gr[1], gr[2], gr[3]);
+          slot[1] = make_float4(gr[4], gr[5], gr[6], gr[7]);
+          slot[2] = make_float4(gr[8], gr[9], gr[10], gr[11]);
+          slot[3] = make_float4(gr[12], gr[13], gr[14], gr[15]);
+          slot[4] = make_float4(gr[16], gr[17], 0.f, 0.f);
+        }
       }
+      __builtin_amdgcn_wave_barrier();
+      // the entry continuing into the next evaluation (if any) owns the carry
+      const int jl = __shfl(j, n - 1, 64);
+      carry_j = (jl == cont_j) ? cont_j : -1;
+    };
+    for (int b = rg.x; b < rg.y; b += kBlock) {
+      int nb = min(kBlock, rg.y - b);
+      __syncthreads();
+      load_batch(st, a.rec, a.sorted_rec, b, nb);
+      if (tid < nb) sk[tid] = ba.sorted_k[b + tid];
+      __syncthreads();
+      QueueCursor qc;
+      queue_reset(qc);
+      carry_j = -1;
+      for (int j = 0; j < nb; ++j) {
+        float dx, dy;
+        bool cov = covers(st, j, u, v, active, dx, dy);
+        uint64_t mask = __ballot(cov);
+        if (mask == 0) {
+          if (lane == 0) {
+            float4* slot = slot_of(j);
+#pragma unroll
+            for (int f = 0; f < kGradStride / 4; ++f) slot[f] = make_float4(0.f, 0.f, 0.f, 0.f);
+          }
+          continue;
+        }
+        queue_push(q, qc, mask, cov, j, lane);
+        if (qc.cnt >= 64) {
+          const int cont_j = qc.cnt > 64 ? (int)(q.item[64] >> 6) : -1;
+          flush(64, cont_j);
+          queue_pop64(q, qc, lane);
+        }
+      }
+      if (qc.cnt > 0) flush(qc.cnt, -1);
     }
   }
 }

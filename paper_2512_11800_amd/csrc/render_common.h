@@ -15,6 +15,61 @@ struct RayG {
   float mu, sig, omega;
 };
 
+// ---------------------------------------------------------------------------
+// Per-wave compaction of covering pairs. A wave owns an 8x8 pixel block; while
+// it walks the staged list, the (entry, pixel) pairs that pass the coverage
+// test are appended to a queue in (entry, pixel) order and evaluated 64 at a
+// time, one pair per lane, so the arithmetic runs on full waves whatever the
+// fraction of the block a Gaussian covers. A pair's results go back to the
+// pixel's own lane (the owner), which adds them in queue order: per pixel the
+// summation order is the list order, as without compaction.
+// ---------------------------------------------------------------------------
+struct WaveQueue {
+  uint16_t item[128];  // (entry in the staged batch) << 6 | pixel lane
+};
+
+struct QueueCursor {
+  int cnt;                  // queued pairs (wave-uniform)
+  uint64_t own_lo, own_hi;  // this lane's queue positions [0, 64) and [64, 128)
+};
+
+__device__ __forceinline__ void queue_reset(QueueCursor& qc) {
+  qc.cnt = 0;
+  qc.own_lo = 0;
+  qc.own_hi = 0;
+}
+
+// Append this lane's pair (entry j) if cov; all lanes call it with the same
+// ballot mask. Returns the new count.
+__device__ __forceinline__ void queue_push(WaveQueue& q, QueueCursor& qc, uint64_t mask, bool cov, int j,
+                                           int lane) {
+  if (cov) {
+    int pos = qc.cnt + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+    q.item[pos] = (uint16_t)((j << 6) | lane);
+    if (pos < 64)
+      qc.own_lo |= 1ull << pos;
+    else
+      qc.own_hi |= 1ull << (pos - 64);
+  }
+  qc.cnt += __popcll(mask);
+}
+
+// After evaluating positions [0, 64): move the rest to the front.
+__device__ __forceinline__ void queue_pop64(WaveQueue& q, QueueCursor& qc, int lane) {
+  int rest = qc.cnt - 64;
+  uint16_t it = lane < rest ? q.item[64 + lane] : (uint16_t)0;
+  __builtin_amdgcn_wave_barrier();
+  if (lane < rest) q.item[lane] = it;
+  __builtin_amdgcn_wave_barrier();
+  qc.own_lo = qc.own_hi;
+  qc.own_hi = 0;
+  qc.cnt = rest;
+}
+
+// value of pixel lane p (all lanes must take part)
+__device__ __forceinline__ float from_lane(float v, int p) { return __shfl(v, p, 64); }
+
 __device__ __forceinline__ int remap_xcd(int bid, int nblocks) {
   // blocks are dispatched round-robin over the 8 XCDs; give each XCD a
   // contiguous run of tiles so neighbouring tiles share its L2

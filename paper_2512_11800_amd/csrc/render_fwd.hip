@@ -133,28 +133,67 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
   }
   const PixelBasis pb = make_basis(tc, sd, tn);
 
-  // ---- pass 1: moments ------------------------------------------------------
+  // ---- pass 1: moments (compacted, see WaveQueue) ---------------------------
+  __shared__ WaveQueue wq[4];
+  // per-wave results of the queued pairs: m_0..m_K in pass 1, q (r, g, b, 1) in pass 2
+  __shared__ __align__(16) float wres[4][(K + 1) * 64];
+  WaveQueue& q = wq[wave];
+  const int x0 = tx * kTile + (wave & 1) * 8, y0 = ty * kTile + (wave >> 1) * 8;
   double acc[K + 1];
 #pragma unroll
   for (int k = 0; k <= K; ++k) acc[k] = 0.0;
   int n_cov = 0;
-  for (int b = rg.x; b < rg.y; b += kBlock) {
-    int nb = min(kBlock, rg.y - b);
-    __syncthreads();
-    load_batch(st, a.rec, a.sorted_rec, b, nb);
-    __syncthreads();
-    for (int j = 0; j < nb; ++j) {
-      float dx, dy;
-      bool cov = covers(st, j, u, v, inside, dx, dy);
-      if (__ballot(cov) == 0) continue;
-      if (cov) {
-        RayG g = ray_params(st, j, dx, dy, lam);
+  {
+    float* wm = wres[wave];  // [K + 1][64]
+    auto flush = [&](int n, uint64_t own) {
+      const bool act = lane < n;
+      const int it = act ? (int)q.item[lane] : lane;
+      const int j = act ? (it >> 6) : 0;
+      const int p = it & 63;
+      PixelBasis pp;
+      pp.tc = from_lane(pb.tc, p);
+      pp.p = from_lane(pb.p, p);
+      pp.p15 = from_lane(pb.p15, p);
+      pp.amp = from_lane(pb.amp, p);
+      const float lamp = from_lane(lam, p);
+      if (act) {
+        const float dx = (float)(x0 + (p & 7)) + 0.5f - st.f[0][j].x;
+        const float dy = (float)(y0 + (p >> 3)) + 0.5f - st.f[0][j].y;
+        RayG g = ray_params(st, j, dx, dy, lamp);
         float m[K + 1];
-        particle_moments<K>(g, pb, tn, m);
-        ++n_cov;
+        particle_moments<K>(g, pp, tn, m);
 #pragma unroll
-        for (int k = 0; k <= K; ++k) acc[k] += (double)m[k];
+        for (int k = 0; k <= K; ++k) wm[k * 64 + lane] = m[k];
       }
+      __builtin_amdgcn_wave_barrier();
+      while (own) {
+        const int i = __builtin_ctzll(own);
+        own &= own - 1;
+#pragma unroll
+        for (int k = 0; k <= K; ++k) acc[k] += (double)wm[k * 64 + i];
+      }
+      __builtin_amdgcn_wave_barrier();
+    };
+    for (int b = rg.x; b < rg.y; b += kBlock) {
+      int nb = min(kBlock, rg.y - b);
+      __syncthreads();
+      load_batch(st, a.rec, a.sorted_rec, b, nb);
+      __syncthreads();
+      QueueCursor qc;
+      queue_reset(qc);
+      for (int j = 0; j < nb; ++j) {
+        float dx, dy;
+        bool cov = covers(st, j, u, v, inside, dx, dy);
+        uint64_t mask = __ballot(cov);
+        if (mask == 0) continue;
+        n_cov += cov ? 1 : 0;
+        queue_push(q, qc, mask, cov, j, lane);
+        if (qc.cnt >= 64) {
+          flush(64, qc.own_lo);
+          queue_pop64(q, qc, lane);
+        }
+      }
+      if (qc.cnt > 0) flush(qc.cnt, qc.own_lo);
     }
   }
 
@@ -232,20 +271,20 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
 
   // ---- pass 2: quadrature (or the surrogate's query list) -------------------
   float sr = 0.f, sg = 0.f, sb = 0.f, so = 0.f;
-  int i_pair = 0;
-  for (int b = rg.x; b < rg.y; b += kBlock) {
-    int nb = min(kBlock, rg.y - b);
-    __syncthreads();
-    load_batch(st, a.rec, a.sorted_rec, b, nb);
-    __syncthreads();
-    for (int j = 0; j < nb; ++j) {
-      float dx, dy;
-      bool cov = covers(st, j, u, v, inside && live, dx, dy);
-      if (__ballot(cov) == 0) continue;
-      if (cov) {
-        RayG g = ray_params(st, j, dx, dy, lam);
-        QEdges<NQ> e;
-        if constexpr (MODE == kModeEmit) {
+  if constexpr (MODE == kModeEmit) {
+    int i_pair = 0;
+    for (int b = rg.x; b < rg.y; b += kBlock) {
+      int nb = min(kBlock, rg.y - b);
+      __syncthreads();
+      load_batch(st, a.rec, a.sorted_rec, b, nb);
+      __syncthreads();
+      for (int j = 0; j < nb; ++j) {
+        float dx, dy;
+        bool cov = covers(st, j, u, v, inside && live, dx, dy);
+        if (__ballot(cov) == 0) continue;
+        if (cov) {
+          RayG g = ray_params(st, j, dx, dy, lam);
+          QEdges<NQ> e;
           quad_edges<NQ>(g, pb, tn, a, e);
           if (qbase >= 0) {
 #pragma unroll
@@ -255,40 +294,101 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
               a.q_pix[qi] = (int)pix;
             }
           }
-        } else {
-          float q = particle_quadrature<NH, NQ>(g, pb, L, m0, tn, a, e);
-          if constexpr (MODE == kModeHarvest) {
-            const uint32_t rid = (uint32_t)a.sorted_rec[b + j];
+          ++i_pair;
+        }
+      }
+    }
+    return;
+  } else {
+    float4* cb = reinterpret_cast<float4*>(wres[wave]);  // [64]
+    // evaluate queue positions [0, n) (one per lane), then add the results of
+    // this lane's own positions (bits of `own`) in order
+    auto flush = [&](int n, uint64_t own, int b) {
+      const bool act = lane < n;
+      const int it = act ? (int)q.item[lane] : lane;
+      const int j = act ? (it >> 6) : 0;
+      const int p = it & 63;
+      PixelBasis pp;
+      pp.tc = from_lane(pb.tc, p);
+      pp.p = from_lane(pb.p, p);
+      pp.p15 = from_lane(pb.p15, p);
+      pp.amp = from_lane(pb.amp, p);
+      LInv<NH> Lp;
 #pragma unroll
-            for (int k = 0; k < NQ; ++k) {
-              const uint32_t h = mix_hash(a.seed, (uint32_t)pix, rid * NQ + k);
-              if ((float)(h >> 8) * (1.f / 16777216.f) < a.harvest_rate) {
-                const int slot = atomicAdd(a.harvest_count, 1);
-                if (slot < a.harvest_cap) {
-                  float* o = a.harvest + (size_t)slot * kHarvestStride;
+      for (int i = 0; i < (NH + 1) * (NH + 2) / 2; ++i) Lp.l[i] = from_lane(L.l[i], p);
+      const float m0p = from_lane(m0, p), lamp = from_lane(lam, p);
+      float featp[6], smup = 0.f, ssigp = 1.f;
+      if constexpr (MODE == kModeHarvest) {
 #pragma unroll
-                  for (int f = 0; f < 6; ++f) o[f] = feat[f];
-                  o[6] = std_query(e.y[k], smu, ssig);
-                  o[7] = m0;
-                  o[8] = expf(-e.tau[k]);
-                  o[9] = __uint_as_float(h);
-                  o[10] = __int_as_float((int)pix);
-                  o[11] = __int_as_float((int)(rid * NQ + k));
-                }
+        for (int f = 0; f < 6; ++f) featp[f] = from_lane(feat[f], p);
+        smup = from_lane(smu, p);
+        ssigp = from_lane(ssig, p);
+      }
+      if (act) {
+        const int ppx = x0 + (p & 7), ppy = y0 + (p >> 3);
+        const float dx = (float)ppx + 0.5f - st.f[0][j].x;
+        const float dy = (float)ppy + 0.5f - st.f[0][j].y;
+        RayG g = ray_params(st, j, dx, dy, lamp);
+        QEdges<NQ> e;
+        float qv = particle_quadrature<NH, NQ>(g, pp, Lp, m0p, tn, a, e);
+        if constexpr (MODE == kModeHarvest) {
+          const uint32_t rid = (uint32_t)a.sorted_rec[b + j];
+          const size_t pixp = ((size_t)ci * c.height + ppy) * c.width + ppx;
+#pragma unroll
+          for (int k = 0; k < NQ; ++k) {
+            const uint32_t h = mix_hash(a.seed, (uint32_t)pixp, rid * NQ + k);
+            if ((float)(h >> 8) * (1.f / 16777216.f) < a.harvest_rate) {
+              const int slot = atomicAdd(a.harvest_count, 1);
+              if (slot < a.harvest_cap) {
+                float* o = a.harvest + (size_t)slot * kHarvestStride;
+#pragma unroll
+                for (int f = 0; f < 6; ++f) o[f] = featp[f];
+                o[6] = std_query(e.y[k], smup, ssigp);
+                o[7] = m0p;
+                o[8] = expf(-e.tau[k]);
+                o[9] = __uint_as_float(h);
+                o[10] = __int_as_float((int)pixp);
+                o[11] = __int_as_float((int)(rid * NQ + k));
               }
             }
           }
-          float4 f5 = st.f[5][j];
-          sr += q * f5.y;
-          sg += q * f5.z;
-          sb += q * f5.w;
-          so += q;
         }
-        ++i_pair;
+        float4 f5 = st.f[5][j];
+        cb[lane] = make_float4(qv * f5.y, qv * f5.z, qv * f5.w, qv);
       }
+      __builtin_amdgcn_wave_barrier();
+      while (own) {
+        const int i = __builtin_ctzll(own);
+        own &= own - 1;
+        const float4 c4 = cb[i];
+        sr += c4.x;
+        sg += c4.y;
+        sb += c4.z;
+        so += c4.w;
+      }
+      __builtin_amdgcn_wave_barrier();
+    };
+    for (int b = rg.x; b < rg.y; b += kBlock) {
+      int nb = min(kBlock, rg.y - b);
+      __syncthreads();
+      load_batch(st, a.rec, a.sorted_rec, b, nb);
+      __syncthreads();
+      QueueCursor qc;
+      queue_reset(qc);
+      for (int j = 0; j < nb; ++j) {
+        float dx, dy;
+        bool cov = covers(st, j, u, v, inside && live, dx, dy);
+        uint64_t mask = __ballot(cov);
+        if (mask == 0) continue;
+        queue_push(q, qc, mask, cov, j, lane);
+        if (qc.cnt >= 64) {
+          flush(64, qc.own_lo, b);
+          queue_pop64(q, qc, lane);
+        }
+      }
+      if (qc.cnt > 0) flush(qc.cnt, qc.own_lo, b);
     }
   }
-  if constexpr (MODE == kModeEmit) return;
 
   // ---- epilogue: Eq. 15 ------------------------------------------------------
   if (!inside) return;
