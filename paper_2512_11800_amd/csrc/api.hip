@@ -113,6 +113,7 @@ struct PairWs {
   uint32_t *keys_a, *keys_b;
   int *vals_a, *vals_b, *entry_rec, *sorted_rec, *inv, *radix_tmp;
   int2* ranges;
+  int *order, *order_tmp;
   float* partials;
   size_t bytes;
 };
@@ -129,6 +130,8 @@ PairWs carve_pairs(void* p, int64_t e, int n_keys) {
   w.inv = c.take<int>((size_t)e);
   w.radix_tmp = c.take<int>(radix_tmp_ints(e));
   w.ranges = c.take<int2>((size_t)n_keys);
+  w.order = c.take<int>((size_t)n_keys);
+  w.order_tmp = c.take<int>(order_tmp_ints(n_keys));
   w.partials = c.take<float>((size_t)e * 4 * kGradStride);  // one slot per (entry, wave)
   w.bytes = c.off;
   return w;
@@ -243,6 +246,7 @@ int build_lists(const mb_gaussians* g, const GaussWs& w, const PairWs& p, int n_
   {
     StageTimer t(S_LISTS, s);
     e = launch_finish_lists(p.keys_a, p.vals_a, p.entry_rec, n_entries, p.sorted_rec, p.inv, p.ranges, n_keys, s);
+    if (e == hipSuccess) e = launch_tile_order(p.ranges, n_keys, p.order, p.order_tmp, s);
   }
   if (e != hipSuccess) return hip_fail(e, "lists");
   return MB_OK;
@@ -275,7 +279,7 @@ int forward_setup(const mb_gaussians* g, const mb_camera* cams, int32_t n_cams, 
   f.cs = make_cams(cams, n_cams);
   RenderArgs& ra = f.ra;
   memset(&ra, 0, sizeof(ra));
-  ra.rec = f.w.rec; ra.sorted_rec = f.p.sorted_rec; ra.ranges = f.p.ranges;
+  ra.rec = f.w.rec; ra.sorted_rec = f.p.sorted_rec; ra.ranges = f.p.ranges; ra.order = f.p.order;
   ra.image = image; ra.saved = saved;
   ra.tiles_x = tx; ra.tiles_y = ty; ra.n_cams = n_cams; ra.full_coverage = o->full_coverage;
   ra.kappa = o->kappa; ra.beta = o->beta; ra.eps = o->eps;
@@ -540,7 +544,7 @@ int mb_render_backward(const mb_gaussians* g, const mb_camera* cams, int32_t n_c
   CamSet cs = make_cams(cams, n_cams);
   RenderArgs ra;
   memset(&ra, 0, sizeof(ra));
-  ra.rec = w.rec; ra.sorted_rec = p.sorted_rec; ra.ranges = p.ranges;
+  ra.rec = w.rec; ra.sorted_rec = p.sorted_rec; ra.ranges = p.ranges; ra.order = p.order;
   ra.tiles_x = tx; ra.tiles_y = ty; ra.n_cams = n_cams; ra.full_coverage = o->full_coverage;
   ra.kappa = o->kappa; ra.beta = o->beta; ra.eps = o->eps;
   fill_quantiles(o, ra.xq, ra.eq);

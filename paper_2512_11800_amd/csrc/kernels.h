@@ -50,10 +50,16 @@ hipError_t launch_finish_lists(const uint32_t* keys, const int* vals, const int*
                                int64_t n, int* sorted_rec, int* inv, int2* ranges,
                                int n_keys, hipStream_t s);
 
+// tile dispatch order (longest list first) into order[n_keys]; tmp holds
+// order_tmp_ints(n_keys) ints
+size_t order_tmp_ints(int n_keys);
+hipError_t launch_tile_order(const int2* ranges, int n_keys, int* order, int* tmp, hipStream_t s);
+
 struct RenderArgs {
   const float4* rec;
   const int* sorted_rec;
   const int2* ranges;
+  const int* order;  // [n_keys] tile of each block
   float* image;   // [C,H,W,3]
   float* saved;   // [C,H,W,8]
   int tiles_x, tiles_y, n_cams, full_coverage;

@@ -174,7 +174,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(BwdArgs ba, CamSet cams) {
   __shared__ float carry[4][G_COUNT];                    // partial slot of an entry split over chunks
   const int tiles_per_cam = a.tiles_x * a.tiles_y;
   const int n_keys = tiles_per_cam * a.n_cams;
-  const int key = remap_xcd(blockIdx.x, gridDim.x);
+  const int key = block_key(a);
   if (key >= n_keys) return;
   const int ci = key / tiles_per_cam;
   const int tile = key - ci * tiles_per_cam;
@@ -560,8 +560,7 @@ hipError_t launch_render_backward(const RenderArgs& r, const float* saved, const
                                   int n_intervals, hipStream_t s) {
   BwdArgs ba{r, saved, grad_image, sorted_k, partials};
   int n_keys = r.tiles_x * r.tiles_y * r.n_cams;
-  int nblocks = ((n_keys + 7) / 8) * 8;
-  dim3 grid(nblocks), block(kBlock);
+  dim3 grid(n_keys), block(kBlock);
 #define MB_LAUNCH(KK, NN)                                                         \
   if (n_moments == KK && n_intervals == NN) {                                     \
     hipLaunchKernelGGL((k_render_bwd<KK, NN + 1>), grid, block, 0, s, ba, cams); \

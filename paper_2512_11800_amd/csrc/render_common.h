@@ -70,12 +70,9 @@ __device__ __forceinline__ void queue_pop64(WaveQueue& q, QueueCursor& qc, int l
 // value of pixel lane p (all lanes must take part)
 __device__ __forceinline__ float from_lane(float v, int p) { return __shfl(v, p, 64); }
 
-__device__ __forceinline__ int remap_xcd(int bid, int nblocks) {
-  // blocks are dispatched round-robin over the 8 XCDs; give each XCD a
-  // contiguous run of tiles so neighbouring tiles share its L2
-  int per = nblocks >> 3;
-  return (bid & 7) * per + (bid >> 3);
-}
+// tile (camera * tiles + tile) of this block: the dispatch order sorts the
+// tiles by list length, longest first
+__device__ __forceinline__ int block_key(const RenderArgs& a) { return a.order[blockIdx.x]; }
 
 __device__ __forceinline__ void load_batch(Stage& st, const float4* rec, const int* sorted_rec, int b, int nb) {
   int tid = threadIdx.x;

@@ -84,7 +84,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
   __shared__ int s_scan[4];
   const int tiles_per_cam = a.tiles_x * a.tiles_y;
   const int n_keys = tiles_per_cam * a.n_cams;
-  const int key = remap_xcd(blockIdx.x, gridDim.x);
+  const int key = block_key(a);
   if (key >= n_keys) return;
   const int ci = key / tiles_per_cam;
   const int tile = key - ci * tiles_per_cam;
@@ -413,7 +413,7 @@ __global__ __launch_bounds__(256) void k_render_consume(RenderArgs a, CamSet cam
   __shared__ Stage st;
   const int tiles_per_cam = a.tiles_x * a.tiles_y;
   const int n_keys = tiles_per_cam * a.n_cams;
-  const int key = remap_xcd(blockIdx.x, gridDim.x);
+  const int key = block_key(a);
   if (key >= n_keys) return;
   const int ci = key / tiles_per_cam;
   const int tile = key - ci * tiles_per_cam;
@@ -478,8 +478,7 @@ __global__ __launch_bounds__(256) void k_render_consume(RenderArgs a, CamSet cam
 hipError_t launch_render_forward(const RenderArgs& a, const CamSet& cams, int n_moments, int n_intervals,
                                  hipStream_t s, int mode) {
   int n_keys = a.tiles_x * a.tiles_y * a.n_cams;
-  int nblocks = ((n_keys + 7) / 8) * 8;
-  dim3 grid(nblocks), block(kBlock);
+  dim3 grid(n_keys), block(kBlock);
 #define MB_LAUNCH(KK, NN, MM)                                                       \
   if (n_moments == KK && n_intervals == NN && mode == MM) {                         \
     hipLaunchKernelGGL((k_render_fwd<KK, NN + 1, MM>), grid, block, 0, s, a, cams); \
@@ -499,7 +498,7 @@ hipError_t launch_render_forward(const RenderArgs& a, const CamSet& cams, int n_
 
 hipError_t launch_render_consume(const RenderArgs& a, const CamSet& cams, int n_intervals, hipStream_t s) {
   int n_keys = a.tiles_x * a.tiles_y * a.n_cams;
-  dim3 grid(((n_keys + 7) / 8) * 8), block(kBlock);
+  dim3 grid(n_keys), block(kBlock);
   if (n_intervals == 3)
     hipLaunchKernelGGL(k_render_consume<4>, grid, block, 0, s, a, cams);
   else if (n_intervals == 5)

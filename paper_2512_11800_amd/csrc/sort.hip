@@ -224,6 +224,33 @@ __global__ __launch_bounds__(256) void k_finish(const uint32_t* keys, const int*
   if (i == n - 1 || keys[i + 1] != key) ranges[key].y = (int)(i + 1);
 }
 
+// Dispatch order of the tiles: longest list first (stable, so ties keep tile
+// order). Heavy tiles start early instead of forming the tail of the launch,
+// and consecutive blocks, which the hardware deals round-robin to the XCDs,
+// spread the heavy tiles over all of them.
+__global__ __launch_bounds__(256) void k_tile_keys(const int2* ranges, int n_keys, uint32_t* keys, int* vals) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_keys) return;
+  int2 r = ranges[i];
+  int len = r.y - r.x;
+  keys[i] = 0xFFFFu - (uint32_t)min(max(len, 0), 0xFFFF);
+  vals[i] = i;
+}
+
+size_t order_tmp_ints(int n_keys) { return 4 * (size_t)n_keys + radix_tmp_ints(n_keys); }
+
+hipError_t launch_tile_order(const int2* ranges, int n_keys, int* order, int* tmp, hipStream_t s) {
+  if (n_keys <= 0) return hipSuccess;
+  uint32_t* ka = reinterpret_cast<uint32_t*>(tmp);
+  uint32_t* kb = ka + n_keys;
+  int* vb = tmp + 2 * (size_t)n_keys;
+  int* rt = tmp + 4 * (size_t)n_keys;
+  hipLaunchKernelGGL(k_tile_keys, dim3((n_keys + 255) / 256), dim3(256), 0, s, ranges, n_keys, ka, order);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_radix_sort(ka, order, kb, vb, n_keys, 16, rt, s);
+}
+
 hipError_t launch_finish_lists(const uint32_t* keys, const int* vals, const int* entry_rec, int64_t n,
                                int* sorted_rec, int* inv, int2* ranges, int n_keys, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_ranges, dim3((n_keys + 255) / 256), dim3(256), 0, s, ranges, n_keys);
