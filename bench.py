@@ -266,12 +266,33 @@ def surrogate_bench(args):
             "losses": losses, "cameras": per_cam}
 
 
+def copy_calibration(args):
+    """A plain device-to-device copy of a known size (1 GiB read, 1 GiB
+    written), the reference that scales the FETCH_SIZE / WRITE_SIZE counters
+    of a profiled run to bytes."""
+    import torch
+    n = 1 << 28
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(args.steps):
+        dst.copy_(src)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / args.steps
+    print(json.dumps({"mode": "copy", "bytes_read": 4 * n, "bytes_written": 4 * n, "ms_per_copy": ms,
+                      "GB_per_s": 8 * n / (ms * 1e-3) / 1e9}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--mode", choices=["both", "fwd", "fwdbwd", "surrogate"], default="both")
+    ap.add_argument("--mode", choices=["both", "fwd", "fwdbwd", "surrogate", "copy"], default="both")
     ap.add_argument("--harvest", type=int, default=10_000_000)
     ap.add_argument("--train-steps", type=int, default=4000)
     ap.add_argument("--gt-pixels", type=int, default=32)
@@ -284,6 +305,9 @@ def main():
               "(the camera-parallel multi-GPU design is documented but not built)", file=sys.stderr)
         sys.exit(2)
 
+    if args.mode == "copy":
+        copy_calibration(args)
+        return
     if args.mode == "surrogate":
         args.k = 6
         sres = surrogate_bench(args)
