@@ -114,6 +114,7 @@ struct PairWs {
   int *vals_a, *vals_b, *entry_rec, *sorted_rec, *inv, *radix_tmp;
   int2* ranges;
   int *order, *order_tmp;
+  uint64_t* masks;
   float* partials;
   size_t bytes;
 };
@@ -132,6 +133,7 @@ PairWs carve_pairs(void* p, int64_t e, int n_keys) {
   w.ranges = c.take<int2>((size_t)n_keys);
   w.order = c.take<int>((size_t)n_keys);
   w.order_tmp = c.take<int>(order_tmp_ints(n_keys));
+  w.masks = c.take<uint64_t>((size_t)e * 4);
   w.partials = c.take<float>((size_t)e * 4 * kGradStride);  // one slot per (entry, wave)
   w.bytes = c.off;
   return w;
@@ -280,6 +282,7 @@ int forward_setup(const mb_gaussians* g, const mb_camera* cams, int32_t n_cams, 
   RenderArgs& ra = f.ra;
   memset(&ra, 0, sizeof(ra));
   ra.rec = f.w.rec; ra.sorted_rec = f.p.sorted_rec; ra.ranges = f.p.ranges; ra.order = f.p.order;
+  ra.masks = f.p.masks;
   ra.image = image; ra.saved = saved;
   ra.tiles_x = tx; ra.tiles_y = ty; ra.n_cams = n_cams; ra.full_coverage = o->full_coverage;
   ra.kappa = o->kappa; ra.beta = o->beta; ra.eps = o->eps;
@@ -545,6 +548,7 @@ int mb_render_backward(const mb_gaussians* g, const mb_camera* cams, int32_t n_c
   RenderArgs ra;
   memset(&ra, 0, sizeof(ra));
   ra.rec = w.rec; ra.sorted_rec = p.sorted_rec; ra.ranges = p.ranges; ra.order = p.order;
+  ra.masks = p.masks;
   ra.tiles_x = tx; ra.tiles_y = ty; ra.n_cams = n_cams; ra.full_coverage = o->full_coverage;
   ra.kappa = o->kappa; ra.beta = o->beta; ra.eps = o->eps;
   fill_quantiles(o, ra.xq, ra.eq);

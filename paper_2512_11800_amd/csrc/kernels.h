@@ -60,6 +60,7 @@ struct RenderArgs {
   const int* sorted_rec;
   const int2* ranges;
   const int* order;  // [n_keys] tile of each block
+  uint64_t* masks;   // [E,4] coverage of list entry (sorted position) by the pixels of wave w
   float* image;   // [C,H,W,3]
   float* saved;   // [C,H,W,8]
   int tiles_x, tiles_y, n_cams, full_coverage;

@@ -66,12 +66,16 @@ __host__ __device__ inline float bf16_float(uint16_t b) {
 }
 
 __device__ __forceinline__ float gelu_d(float x, float& d) {
-  // tanh form: 0.5 x (1 + tanh(c (x + a x^3)))
+  // tanh form 0.5 x (1 + tanh(u)), u = c (x + a x^3), evaluated as x s with
+  // s = 1 / (1 + exp(-2u)) (the same function: 0.5 (1 + tanh u) = s):
+  // one exp2 and one reciprocal, no tanh
   const float c = 0.7978845608028654f, a = 0.044715f;
-  float u = c * (x + a * x * x * x);
-  float t = 1.f - 2.f * fast_rcp(1.f + __expf(2.f * u));
-  d = 0.5f * (1.f + t) + 0.5f * x * (1.f - t * t) * c * (1.f + 3.f * a * x * x);
-  return 0.5f * x * (1.f + t);
+  const float k = -2.f * c * 1.4426950408889634f;  // -2 c log2(e)
+  const float x2 = x * x;
+  const float e = __builtin_amdgcn_exp2f(k * x * (1.f + a * x2));
+  const float sg = fast_rcp(1.f + e);
+  d = sg + 2.f * c * x * sg * (1.f - sg) * (1.f + 3.f * a * x2);
+  return x * sg;
 }
 __device__ __forceinline__ float gelu(float x) {
   float d;

@@ -5,12 +5,15 @@
 //            in: a = g (1 - e^-m0) / max(eps, O), b = dL/dO, e0 = dL/dm0;
 //   pass 2   Adjoint-Moment stage: dm = e0 e_0 + sum_i (a . c_i + b) dq_i/dm,
 //            through the quadrature (Eq. 7) and the adjoint of the moment
-//            bounds at every interval edge;
-//   pass 3   Gradient stage: per pair (a . c_i + b) dq_i/dtheta_i + dm . dm_i/dtheta_i
-//            for theta = (mu, Sigma, omega), chained to the record
-//            coefficients, summed over the wave's 64 pixels and written to
-//            one slot per (list entry, wave); a per-Gaussian kernel then sums
-//            the slots (one reduction, no atomics, deterministic).
+//            bounds at every interval edge; the same evaluation also gives
+//            the part of the Gradient stage that does not depend on dm,
+//            (a . c_i + b) dq_i/dtheta_i for theta = (mu, Sigma, omega) and the
+//            colour term, chained to the record coefficients;
+//   pass 3   the rest of the Gradient stage, dm . dm_i/dtheta_i.
+// Per-pair gradients are summed over the wave's pixels into one slot per
+// (list entry, wave) (pass 2 writes it, pass 3 adds to it); a per-Gaussian
+// kernel then sums the slots: one reduction, no atomics, deterministic.
+// The passes walk the coverage masks the forward pass stored.
 #include "render_common.h"
 
 namespace mb {
@@ -151,8 +154,39 @@ struct BwdArgs {
   float* partials;          // [E,4,kGradStride]
 };
 
-// inclusive scan of v over the lanes of its segment (segments start at the
-// lanes of `head_mask`); the segment's last lane ends with the segment sum
+// (mu, Sigma, omega) gradients of one pair -> gradients of its record
+// coefficients (the inverse of ray_params); linear in (gmu, gsig, gom)
+__device__ __forceinline__ void chain_record(float gmu, float gsig, float gom, const RayG& g, float lamp, float dx,
+                                             float dy, const float4& f2, const float4& f3, const float4& f4,
+                                             float* gr) {
+  float d = f2.x + 2.f * (f2.y * dx + f2.z * dy) + f2.w * dx * dx + 2.f * f3.x * dx * dy + f3.y * dy * dy;
+  float x = f4.y * dx * dx + 2.f * f4.z * dx * dy + f4.w * dy * dy;
+  float id = fast_rcp(d);
+  float ek = __expf(-0.5f * x * id);
+  float gE = gmu * lamp * id;
+  float gD = -gmu * g.mu * id - 0.5f * gsig * g.sig * id + 0.5f * gom * g.omega * x * id * id;
+  float gX = -0.5f * gom * g.omega * id;
+  gr[G_D0] = gD;
+  gr[G_D1X] = 2.f * gD * dx;
+  gr[G_D1Y] = 2.f * gD * dy;
+  gr[G_D2XX] = gD * dx * dx;
+  gr[G_D2XY] = 2.f * gD * dx * dy;
+  gr[G_D2YY] = gD * dy * dy;
+  gr[G_E0] = gE;
+  gr[G_EX] = gE * dx;
+  gr[G_EY] = gE * dy;
+  gr[G_XXX] = gX * dx * dx;
+  gr[G_XXY] = 2.f * gX * dx * dy;
+  gr[G_XYY] = gX * dy * dy;
+  float gdx = 2.f * gD * (f2.y + f2.w * dx + f3.x * dy) + gE * f3.w + 2.f * gX * (f4.y * dx + f4.z * dy);
+  float gdy = 2.f * gD * (f2.z + f3.x * dx + f3.y * dy) + gE * f4.x + 2.f * gX * (f4.z * dx + f4.w * dy);
+  gr[G_P0X] = -gdx;
+  gr[G_P0Y] = -gdy;
+  gr[G_W] = gom * ek;
+}
+
+// inclusive scan of v over the lanes of its segment; the segment's last lane
+// ends with the segment sum
 __device__ __forceinline__ float segment_scan(float v, int lane, int seg_start) {
 #pragma unroll
   for (int d = 1; d < 64; d <<= 1) {
@@ -162,8 +196,56 @@ __device__ __forceinline__ float segment_scan(float v, int lane, int seg_start) 
   return v;
 }
 
+// Per-entry sums of the gradients gr[] of the evaluated queue positions
+// [0, n): queued pairs of one entry are contiguous, a segmented scan over the
+// lanes sums each entry's pairs and the segment's last lane writes (ADD =
+// false) or adds to (ADD = true) the entry's slot. An entry that continues
+// past position n - 1 (cont_j) leaves its partial sum in `carry`.
+template <bool ADD>
+__device__ __forceinline__ void reduce_to_slots(float* gr, bool act, int j, int n, int lane, int cont_j, int& carry_j,
+                                                float* carry, float* partials, const int* sk, int wave) {
+  const int jprev = __shfl_up(j, 1, 64);
+  const bool head = !act || lane == 0 || jprev != j;
+  const uint64_t heads = __ballot(head);
+  const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1);
+  const int seg_start = 63 - __builtin_clzll(heads & upto);
+  const int jnext = __shfl_down(j, 1, 64);
+  const bool last = act && (lane == n - 1 || jnext != j);
+#pragma unroll
+  for (int f = 0; f < G_COUNT; ++f) gr[f] = segment_scan(gr[f], lane, seg_start);
+  if (last) {
+    if (seg_start == 0 && j == carry_j) {
+#pragma unroll
+      for (int f = 0; f < G_COUNT; ++f) gr[f] += carry[f];
+    }
+    if (lane == n - 1 && j == cont_j) {
+#pragma unroll
+      for (int f = 0; f < G_COUNT; ++f) carry[f] = gr[f];
+    } else {
+      float4* slot = reinterpret_cast<float4*>(partials + ((size_t)sk[j] * 4 + wave) * kGradStride);
+      if constexpr (ADD) {
+        float4 s0 = slot[0], s1 = slot[1], s2 = slot[2], s3 = slot[3], s4 = slot[4];
+        gr[0] += s0.x; gr[1] += s0.y; gr[2] += s0.z; gr[3] += s0.w;
+        gr[4] += s1.x; gr[5] += s1.y; gr[6] += s1.z; gr[7] += s1.w;
+        gr[8] += s2.x; gr[9] += s2.y; gr[10] += s2.z; gr[11] += s2.w;
+        gr[12] += s3.x; gr[13] += s3.y; gr[14] += s3.z; gr[15] += s3.w;
+        gr[16] += s4.x; gr[17] += s4.y;
+      }
+      slot[0] = make_float4(gr[0], gr[1], gr[2], gr[3]);
+      slot[1] = make_float4(gr[4], gr[5], gr[6], gr[7]);
+      slot[2] = make_float4(gr[8], gr[9], gr[10], gr[11]);
+      slot[3] = make_float4(gr[12], gr[13], gr[14], gr[15]);
+      slot[4] = make_float4(gr[16], gr[17], 0.f, 0.f);
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+  // the entry continuing into the next evaluation (if any) owns the carry
+  const int jl = __shfl(j, n - 1, 64);
+  carry_j = (jl == cont_j) ? cont_j : -1;
+}
+
 template <int K, int NQ>
-__global__ __launch_bounds__(256) void k_render_bwd(BwdArgs ba, CamSet cams) {
+__global__ __launch_bounds__(256, (K == 4 && NQ == 4) ? 3 : 2) void k_render_bwd(BwdArgs ba, CamSet cams) {
   constexpr int NH = K / 2;
   constexpr int NL = (NH + 1) * (NH + 2) / 2;
   const RenderArgs& a = ba.r;
@@ -171,7 +253,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(BwdArgs ba, CamSet cams) {
   __shared__ int sk[kBlock];
   __shared__ WaveQueue wq[4];
   __shared__ __align__(16) float wres[4][(K + 1) * 64];  // per queued pair results
-  __shared__ float carry[4][G_COUNT];                    // partial slot of an entry split over chunks
+  __shared__ float carry[4][G_COUNT];                    // partial slot of an entry split over evaluations
   const int tiles_per_cam = a.tiles_x * a.tiles_y;
   const int n_keys = tiles_per_cam * a.n_cams;
   const int key = block_key(a);
@@ -207,8 +289,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(BwdArgs ba, CamSet cams) {
   }
   const PixelBasis pb = make_basis(sv[4], sv[5], tn);
 
-  // per-pixel values of pixel lane p, for a queued pair evaluated on another lane
-  auto basis_of = [&](int p) {
+  auto basis_of = [&](int p) __attribute__((always_inline)) {
     PixelBasis r;
     r.tc = from_lane(pb.tc, p);
     r.p = from_lane(pb.p, p);
@@ -218,17 +299,22 @@ __global__ __launch_bounds__(256) void k_render_bwd(BwdArgs ba, CamSet cams) {
   };
   // the pair at queue position `lane` (entry j, pixel lane p); inactive lanes
   // (lane >= n) get p = lane so the cross-lane reads stay uniform
-  auto item_of = [&](int n, int& j, int& p) {
+  auto item_of = [&](int n, int& j, int& p) __attribute__((always_inline)) {
     const bool act = lane < n;
     const int it = act ? (int)q.item[lane] : lane;
     j = act ? (it >> 6) : 0;
     p = it & 63;
     return act;
   };
-  auto ray_of = [&](int j, int p, float lamp) {
-    const float dx = (float)(x0 + (p & 7)) + 0.5f - st.f[0][j].x;
-    const float dy = (float)(y0 + (p >> 3)) + 0.5f - st.f[0][j].y;
-    return ray_params(st, j, dx, dy, lamp);
+  auto offsets_of = [&](int j, int p, float& dx, float& dy) __attribute__((always_inline)) {
+    dx = (float)(x0 + (p & 7)) + 0.5f - st.f[0][j].x;
+    dy = (float)(y0 + (p >> 3)) + 0.5f - st.f[0][j].y;
+  };
+  auto stage = [&](int b, int nb, bool keys) __attribute__((always_inline)) {
+    __syncthreads();
+    load_batch(st, a.rec, a.sorted_rec, b, nb);
+    if (keys && tid < nb) sk[tid] = ba.sorted_k[b + tid];
+    __syncthreads();
   };
 
   // ---- pass 1: recompute the moments (identical to the forward pass) -------
@@ -236,13 +322,15 @@ __global__ __launch_bounds__(256) void k_render_bwd(BwdArgs ba, CamSet cams) {
 #pragma unroll
   for (int k = 0; k <= K; ++k) acc[k] = 0.0;
   {
-    auto flush = [&](int n, uint64_t own) {
+    auto flush = [&](int n, uint64_t own) __attribute__((always_inline)) {
       int j, p;
       const bool act = item_of(n, j, p);
       const PixelBasis pp = basis_of(p);
       const float lamp = from_lane(lam, p);
       if (act) {
-        RayG g = ray_of(j, p, lamp);
+        float dx, dy;
+        offsets_of(j, p, dx, dy);
+        RayG g = ray_params(st, j, dx, dy, lamp);
         float m[K + 1];
         particle_moments<K>(g, pp, tn, m);
 #pragma unroll
@@ -259,22 +347,15 @@ __global__ __launch_bounds__(256) void k_render_bwd(BwdArgs ba, CamSet cams) {
     };
     for (int b = rg.x; b < rg.y; b += kBlock) {
       int nb = min(kBlock, rg.y - b);
-      __syncthreads();
-      load_batch(st, a.rec, a.sorted_rec, b, nb);
-      __syncthreads();
+      stage(b, nb, false);
       QueueCursor qc;
       queue_reset(qc);
-      for (int j = 0; j < nb; ++j) {
-        float dx, dy;
-        bool cov = covers(st, j, u, v, inside, dx, dy);
-        uint64_t mask = __ballot(cov);
-        if (mask == 0) continue;
-        queue_push(q, qc, mask, cov, j, lane);
-        if (qc.cnt >= 64) {
-          flush(64, qc.own_lo);
-          queue_pop64(q, qc, lane);
-        }
-      }
+      queue_from_masks(q, qc, a.masks, b, nb, wave, lane, ~0ull,
+                       [&]() __attribute__((always_inline)) {
+                         flush(64, qc.own_lo);
+                         queue_pop64(q, qc, lane);
+                       },
+                       [](int) {});
       if (qc.cnt > 0) flush(qc.cnt, qc.own_lo);
     }
   }
@@ -313,40 +394,51 @@ __global__ __launch_bounds__(256) void k_render_bwd(BwdArgs ba, CamSet cams) {
   }
 
   const bool active = inside && live;
-  auto linv_of = [&](int p) {
-    LInv<NH> r;
+  const uint64_t active_mask = __ballot(active);
+  float* cw = carry[wave];
+  auto zero_slot = [&](int j) __attribute__((always_inline)) {
+    float4* slot = reinterpret_cast<float4*>(ba.partials + ((size_t)sk[j] * 4 + wave) * kGradStride);
 #pragma unroll
-    for (int i = 0; i < NL; ++i) r.l[i] = from_lane(L.l[i], p);
-    return r;
+    for (int f = 0; f < kGradStride / 4; ++f) slot[f] = make_float4(0.f, 0.f, 0.f, 0.f);
   };
 
-  // ---- pass 2: adjoint moments ---------------------------------------------
+  // ---- pass 2: adjoint moments, and the dm-independent gradients -----------
   float dm[K + 1];
 #pragma unroll
   for (int k = 0; k <= K; ++k) dm[k] = 0.f;
   dm[0] = active ? e0 : 0.f;
   {
-    auto flush = [&](int n, uint64_t own) {
+    int carry_j = -1;
+    auto flush = [&](int n, uint64_t own, int cont_j) __attribute__((always_inline)) {
       int j, p;
       const bool act = item_of(n, j, p);
       const PixelBasis pp = basis_of(p);
-      const LInv<NH> Lp = linv_of(p);
+      LInv<NH> Lp;
+#pragma unroll
+      for (int i = 0; i < NL; ++i) Lp.l[i] = from_lane(L.l[i], p);
       const float lamp = from_lane(lam, p), m0p = from_lane(m0, p);
-      const float ga0 = from_lane(ga[0], p), ga1 = from_lane(ga[1], p), ga2 = from_lane(ga[2], p);
+      float gap[3] = {from_lane(ga[0], p), from_lane(ga[1], p), from_lane(ga[2], p)};
       const float gbp = from_lane(gb, p);
       float bkp[K + 1];
       bkp[0] = 1.f;
 #pragma unroll
       for (int k = 1; k <= K; ++k) bkp[k] = from_lane(bk[k], p);
+      float gr[G_COUNT];
+#pragma unroll
+      for (int f = 0; f < G_COUNT; ++f) gr[f] = 0.f;
       if (act) {
-        RayG g = ray_of(j, p, lamp);
+        float dx, dy;
+        offsets_of(j, p, dx, dy);
+        RayG g = ray_params(st, j, dx, dy, lamp);
         QuadState<NH, NQ> s;
         quad_state<NH, NQ>(g, pp, Lp, m0p, tn, a, s);
         float4 f5 = st.f[5][j];
-        float gbar = ga0 * f5.y + ga1 * f5.z + ga2 * f5.w + gbp;
+        float gbar = gap[0] * f5.y + gap[1] * f5.z + gap[2] * f5.w + gbp;
         float d[K + 1];
 #pragma unroll
         for (int k = 0; k <= K; ++k) d[k] = 0.f;
+        // dq / d(mu, Sigma, omega) at fixed moments
+        float dq0 = 0.f, dq1 = 0.f, dq2 = 0.f;
 #pragma unroll
         for (int e = 0; e < NQ; ++e) {
           float lamk[2 * NH + 1], dl;
@@ -359,80 +451,6 @@ __global__ __launch_bounds__(256) void k_render_bwd(BwdArgs ba, CamSet cams) {
             lb += lamk[k] * bkp[k];
           }
           d[0] += wgt * (s.F[e] - lb);
-        }
-#pragma unroll
-        for (int k = 0; k <= K; ++k) res[k * 64 + lane] = d[k];
-      }
-      __builtin_amdgcn_wave_barrier();
-      while (own) {
-        const int i = __builtin_ctzll(own);
-        own &= own - 1;
-#pragma unroll
-        for (int k = 0; k <= K; ++k) dm[k] += res[k * 64 + i];
-      }
-      __builtin_amdgcn_wave_barrier();
-    };
-    for (int b = rg.x; b < rg.y; b += kBlock) {
-      int nb = min(kBlock, rg.y - b);
-      __syncthreads();
-      load_batch(st, a.rec, a.sorted_rec, b, nb);
-      __syncthreads();
-      QueueCursor qc;
-      queue_reset(qc);
-      for (int j = 0; j < nb; ++j) {
-        float dx, dy;
-        bool cov = covers(st, j, u, v, active, dx, dy);
-        uint64_t mask = __ballot(cov);
-        if (mask == 0) continue;
-        queue_push(q, qc, mask, cov, j, lane);
-        if (qc.cnt >= 64) {
-          flush(64, qc.own_lo);
-          queue_pop64(q, qc, lane);
-        }
-      }
-      if (qc.cnt > 0) flush(qc.cnt, qc.own_lo);
-    }
-  }
-
-  // ---- pass 3: per-pair gradients, one reduction per (entry, wave) ---------
-  // Queued pairs of one entry are contiguous; a segmented scan over the lanes
-  // sums each entry's pairs, and the last lane of the segment writes the
-  // entry's slot. An entry split over two evaluations of the queue leaves its
-  // first part in `carry`.
-  {
-    float* cw = carry[wave];
-    int carry_j = -1;
-    auto slot_of = [&](int j) {
-      return reinterpret_cast<float4*>(ba.partials + ((size_t)sk[j] * 4 + wave) * kGradStride);
-    };
-    auto flush = [&](int n, int cont_j) {
-      int j, p;
-      const bool act = item_of(n, j, p);
-      const PixelBasis pp = basis_of(p);
-      const LInv<NH> Lp = linv_of(p);
-      const float lamp = from_lane(lam, p), m0p = from_lane(m0, p);
-      float gap[3] = {from_lane(ga[0], p), from_lane(ga[1], p), from_lane(ga[2], p)};
-      const float gbp = from_lane(gb, p);
-      float dmp[K + 1];
-#pragma unroll
-      for (int k = 0; k <= K; ++k) dmp[k] = from_lane(dm[k], p);
-      float gr[G_COUNT];
-#pragma unroll
-      for (int f = 0; f < G_COUNT; ++f) gr[f] = 0.f;
-      if (act) {
-        const float dx = (float)(x0 + (p & 7)) + 0.5f - st.f[0][j].x;
-        const float dy = (float)(y0 + (p >> 3)) + 0.5f - st.f[0][j].y;
-        RayG g = ray_params(st, j, dx, dy, lamp);
-        QuadState<NH, NQ> s;
-        quad_state<NH, NQ>(g, pp, Lp, m0p, tn, a, s);
-        float4 f5 = st.f[5][j];
-        float gbar = gap[0] * f5.y + gap[1] * f5.z + gap[2] * f5.w + gbp;
-        // dq / d(mu, Sigma, omega) at fixed moments
-        float dq0 = 0.f, dq1 = 0.f, dq2 = 0.f;
-#pragma unroll
-        for (int e = 0; e < NQ; ++e) {
-          float lamk[2 * NH + 1], dl;
-          hermite_adjoint<NH>(s.y[e], s.x[e], s.below[e], a.beta, lamk, dl);
           float dtau_dt = -m0p * s.w0[e] * dl * warp_dy(pp, s.t[e]);
           float dtdmu = s.cl[e] ? 0.f : 1.f;
           float dtdsig = s.cl[e] ? 0.f : a.kappa * a.xq[e];
@@ -455,101 +473,76 @@ __global__ __launch_bounds__(256) void k_render_bwd(BwdArgs ba, CamSet cams) {
           }
           dq2 += cs * s.sr[e];
         }
-        float gm[3];
-        moment_grads<K>(g, pp, tn, dmp, gm);
-        float gmu = gbar * dq0 + gm[0];
-        float gsig = gbar * dq1 + gm[1];
-        float gom = gbar * dq2 + gm[2];
-        // (mu, Sigma, omega) -> record coefficients (see ray_params)
-        float4 f2 = st.f[2][j], f3 = st.f[3][j], f4 = st.f[4][j];
-        float d = f2.x + 2.f * (f2.y * dx + f2.z * dy) + f2.w * dx * dx + 2.f * f3.x * dx * dy + f3.y * dy * dy;
-        float x = f4.y * dx * dx + 2.f * f4.z * dx * dy + f4.w * dy * dy;
-        float id = fast_rcp(d);
-        float ek = __expf(-0.5f * x * id);
-        float gE = gmu * lamp * id;
-        float gD = -gmu * g.mu * id - 0.5f * gsig * g.sig * id + 0.5f * gom * g.omega * x * id * id;
-        float gX = -0.5f * gom * g.omega * id;
-        gr[G_D0] = gD;
-        gr[G_D1X] = 2.f * gD * dx;
-        gr[G_D1Y] = 2.f * gD * dy;
-        gr[G_D2XX] = gD * dx * dx;
-        gr[G_D2XY] = 2.f * gD * dx * dy;
-        gr[G_D2YY] = gD * dy * dy;
-        gr[G_E0] = gE;
-        gr[G_EX] = gE * dx;
-        gr[G_EY] = gE * dy;
-        gr[G_XXX] = gX * dx * dx;
-        gr[G_XXY] = 2.f * gX * dx * dy;
-        gr[G_XYY] = gX * dy * dy;
-        float gdx = 2.f * gD * (f2.y + f2.w * dx + f3.x * dy) + gE * f3.w + 2.f * gX * (f4.y * dx + f4.z * dy);
-        float gdy = 2.f * gD * (f2.z + f3.x * dx + f3.y * dy) + gE * f4.x + 2.f * gX * (f4.z * dx + f4.w * dy);
-        gr[G_P0X] = -gdx;
-        gr[G_P0Y] = -gdy;
-        gr[G_W] = gom * ek;
+#pragma unroll
+        for (int k = 0; k <= K; ++k) res[k * 64 + lane] = d[k];
+        chain_record(gbar * dq0, gbar * dq1, gbar * dq2, g, lamp, dx, dy, st.f[2][j], st.f[3][j], st.f[4][j], gr);
         gr[G_CR] = s.q * gap[0];
         gr[G_CG] = s.q * gap[1];
         gr[G_CB] = s.q * gap[2];
       }
-      // segments: runs of equal entries (inactive lanes are segments of their own)
-      const int jprev = __shfl_up(j, 1, 64);
-      const bool head = !act || lane == 0 || jprev != j;
-      const uint64_t heads = __ballot(head);
-      const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1);
-      const int seg_start = 63 - __builtin_clzll(heads & upto);
-      const int jnext = __shfl_down(j, 1, 64);
-      const bool last = act && (lane == n - 1 || jnext != j);
-#pragma unroll
-      for (int f = 0; f < G_COUNT; ++f) gr[f] = segment_scan(gr[f], lane, seg_start);
-      if (last) {
-        if (seg_start == 0 && j == carry_j) {
-#pragma unroll
-          for (int f = 0; f < G_COUNT; ++f) gr[f] += cw[f];
-        }
-        if (lane == n - 1 && j == cont_j) {
-#pragma unroll
-          for (int f = 0; f < G_COUNT; ++f) cw[f] = gr[f];
-        } else {
-          float4* slot = slot_of(j);
-          slot[0] = make_float4(gr[0], gr[1], gr[2], gr[3]);
-          slot[1] = make_float4(gr[4], gr[5], gr[6], gr[7]);
-          slot[2] = make_float4(gr[8], gr[9], gr[10], gr[11]);
-          slot[3] = make_float4(gr[12], gr[13], gr[14], gr[15]);
-          slot[4] = make_float4(gr[16], gr[17], 0.f, 0.f);
-        }
-      }
       __builtin_amdgcn_wave_barrier();
-      // the entry continuing into the next evaluation (if any) owns the carry
-      const int jl = __shfl(j, n - 1, 64);
-      carry_j = (jl == cont_j) ? cont_j : -1;
+      while (own) {
+        const int i = __builtin_ctzll(own);
+        own &= own - 1;
+#pragma unroll
+        for (int k = 0; k <= K; ++k) dm[k] += res[k * 64 + i];
+      }
+      reduce_to_slots<false>(gr, act, j, n, lane, cont_j, carry_j, cw, ba.partials, sk, wave);
     };
     for (int b = rg.x; b < rg.y; b += kBlock) {
       int nb = min(kBlock, rg.y - b);
-      __syncthreads();
-      load_batch(st, a.rec, a.sorted_rec, b, nb);
-      if (tid < nb) sk[tid] = ba.sorted_k[b + tid];
-      __syncthreads();
+      stage(b, nb, true);
       QueueCursor qc;
       queue_reset(qc);
       carry_j = -1;
-      for (int j = 0; j < nb; ++j) {
-        float dx, dy;
-        bool cov = covers(st, j, u, v, active, dx, dy);
-        uint64_t mask = __ballot(cov);
-        if (mask == 0) {
-          if (lane == 0) {
-            float4* slot = slot_of(j);
+      queue_from_masks(q, qc, a.masks, b, nb, wave, lane, active_mask,
+                       [&]() __attribute__((always_inline)) {
+                         const int cont_j = qc.cnt > 64 ? (int)(q.item[64] >> 6) : -1;
+                         flush(64, qc.own_lo, cont_j);
+                         queue_pop64(q, qc, lane);
+                       },
+                       zero_slot);
+      if (qc.cnt > 0) flush(qc.cnt, qc.own_lo, -1);
+    }
+  }
+
+  // ---- pass 3: the moment part of the Gradient stage ------------------------
+  {
+    int carry_j = -1;
+    auto flush = [&](int n, int cont_j) __attribute__((always_inline)) {
+      int j, p;
+      const bool act = item_of(n, j, p);
+      const PixelBasis pp = basis_of(p);
+      const float lamp = from_lane(lam, p);
+      float dmp[K + 1];
 #pragma unroll
-            for (int f = 0; f < kGradStride / 4; ++f) slot[f] = make_float4(0.f, 0.f, 0.f, 0.f);
-          }
-          continue;
-        }
-        queue_push(q, qc, mask, cov, j, lane);
-        if (qc.cnt >= 64) {
-          const int cont_j = qc.cnt > 64 ? (int)(q.item[64] >> 6) : -1;
-          flush(64, cont_j);
-          queue_pop64(q, qc, lane);
-        }
+      for (int k = 0; k <= K; ++k) dmp[k] = from_lane(dm[k], p);
+      float gr[G_COUNT];
+#pragma unroll
+      for (int f = 0; f < G_COUNT; ++f) gr[f] = 0.f;
+      if (act) {
+        float dx, dy;
+        offsets_of(j, p, dx, dy);
+        RayG g = ray_params(st, j, dx, dy, lamp);
+        float gm[3];
+        moment_grads<K>(g, pp, tn, dmp, gm);
+        chain_record(gm[0], gm[1], gm[2], g, lamp, dx, dy, st.f[2][j], st.f[3][j], st.f[4][j], gr);
       }
+      reduce_to_slots<true>(gr, act, j, n, lane, cont_j, carry_j, cw, ba.partials, sk, wave);
+    };
+    for (int b = rg.x; b < rg.y; b += kBlock) {
+      int nb = min(kBlock, rg.y - b);
+      stage(b, nb, true);
+      QueueCursor qc;
+      queue_reset(qc);
+      carry_j = -1;
+      queue_from_masks(q, qc, a.masks, b, nb, wave, lane, active_mask,
+                       [&]() __attribute__((always_inline)) {
+                         const int cont_j = qc.cnt > 64 ? (int)(q.item[64] >> 6) : -1;
+                         flush(64, cont_j);
+                         queue_pop64(q, qc, lane);
+                       },
+                       [](int) {});
       if (qc.cnt > 0) flush(qc.cnt, -1);
     }
   }

@@ -67,6 +67,30 @@ __device__ __forceinline__ void queue_pop64(WaveQueue& q, QueueCursor& qc, int l
   qc.cnt = rest;
 }
 
+// Queue the pairs of the staged batch [b, b + nb) from the stored coverage
+// masks of this wave (restricted to the lanes of `keep`), skipping empty
+// entries 64 at a time. on_full() evaluates and pops 64 queued pairs;
+// on_empty(j) is called by the lane that loaded entry j's mask when it is
+// empty (after the restriction).
+template <class Full, class Empty>
+__device__ __forceinline__ void queue_from_masks(WaveQueue& q, QueueCursor& qc, const uint64_t* masks, int b, int nb,
+                                                 int wave, int lane, uint64_t keep, Full&& on_full,
+                                                 Empty&& on_empty) {
+  for (int j0 = 0; j0 < nb; j0 += 64) {
+    const bool in = j0 + lane < nb;
+    const uint64_t mk = in ? (masks[(size_t)(b + j0 + lane) * 4 + wave] & keep) : 0ull;
+    if (in && mk == 0) on_empty(j0 + lane);
+    uint64_t nz = __ballot(mk != 0);
+    while (nz) {
+      const int l = __builtin_ctzll(nz);
+      nz &= nz - 1;
+      const uint64_t m = __shfl(mk, l, 64);
+      queue_push(q, qc, m, (m >> lane) & 1ull, j0 + l, lane);
+      if (qc.cnt >= 64) on_full();
+    }
+  }
+}
+
 // value of pixel lane p (all lanes must take part)
 __device__ __forceinline__ float from_lane(float v, int p) { return __shfl(v, p, 64); }
 

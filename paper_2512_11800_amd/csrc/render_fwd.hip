@@ -7,7 +7,9 @@
 //   pass 2  per-Gaussian quadrature, Eq. 7 / App. B, against the bounds
 //           (Quadrature pass), accumulating sum q_i (r, g, b, 1),
 //   epilogue  Eq. 15 rescaling (Rescale pass).
-// A wave skips a Gaussian when none of its 64 pixels is covered (ballot).
+// Pass 0 tests coverage and stores, per list entry and wave, the 64-bit mask
+// of covered pixels; the later passes (and the backward kernel) walk the
+// masks instead. Covering pairs are evaluated compacted (see WaveQueue).
 //
 // Variants (MODE):
 //   kModePlain    the path above;
@@ -101,76 +103,53 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
   const int2 rg = a.ranges[key];
   const size_t pix = ((size_t)ci * c.height + (inside ? py : 0)) * c.width + (inside ? px : 0);
 
-  // ---- pass 0: the pixel's moment variable ---------------------------------
-  float wsum = 0.f, mean = 0.f, m2 = 0.f;
-  for (int b = rg.x; b < rg.y; b += kBlock) {
-    int nb = min(kBlock, rg.y - b);
-    __syncthreads();
-    load_batch(st, a.rec, a.sorted_rec, b, nb);
-    __syncthreads();
-    for (int j = 0; j < nb; ++j) {
-      float dx, dy;
-      bool cov = covers(st, j, u, v, inside, dx, dy);
-      if (__ballot(cov) == 0) continue;
-      if (cov) {
-        RayG g = ray_params(st, j, dx, dy, lam);
-        float wgt = g.omega * g.sig;
-        if (wgt > 0.f) {
-          wsum += wgt;
-          float d = g.mu - mean;
-          mean += d * wgt / wsum;
-          m2 += wgt * (d * (g.mu - mean) + g.sig * g.sig);
-        }
-      }
-    }
-  }
-  float tc = fmaxf(mean, tn);
-  float sd = wsum > 0.f ? sqrtf(fmaxf(m2 / wsum, 0.f)) : 1.f;
-  {
-    float q = 1.f + 0.8f * tc, xn = 1.f + 0.8f * tn;
-    float gp = 1.2f * xn * sqrtf(xn) / (q * q * sqrtf(q));  // g_hat'(tc)
-    sd = fmaxf(sd * gp, 1e-30f);
-  }
-  const PixelBasis pb = make_basis(tc, sd, tn);
-
-  // ---- pass 1: moments (compacted, see WaveQueue) ---------------------------
   __shared__ WaveQueue wq[4];
-  // per-wave results of the queued pairs: m_0..m_K in pass 1, q (r, g, b, 1) in pass 2
+  // per-wave results of the queued pairs: 3 or K + 1 floats per pair in passes
+  // 0 and 1, q (r, g, b, 1) in pass 2
   __shared__ __align__(16) float wres[4][(K + 1) * 64];
   WaveQueue& q = wq[wave];
+  float* res = wres[wave];
   const int x0 = tx * kTile + (wave & 1) * 8, y0 = ty * kTile + (wave >> 1) * 8;
-  double acc[K + 1];
-#pragma unroll
-  for (int k = 0; k <= K; ++k) acc[k] = 0.0;
+  // the pair at queue position `lane` (entry j, pixel lane p); inactive lanes
+  // (lane >= n) get p = lane so the cross-lane reads stay uniform
+  auto item_of = [&](int n, int& j, int& p) __attribute__((always_inline)) {
+    const bool act = lane < n;
+    const int it = act ? (int)q.item[lane] : lane;
+    j = act ? (it >> 6) : 0;
+    p = it & 63;
+    return act;
+  };
+  auto ray_of = [&](int j, int p, float lamp) __attribute__((always_inline)) {
+    const float dx = (float)(x0 + (p & 7)) + 0.5f - st.f[0][j].x;
+    const float dy = (float)(y0 + (p >> 3)) + 0.5f - st.f[0][j].y;
+    return ray_params(st, j, dx, dy, lamp);
+  };
+
+  // ---- pass 0: coverage masks and the pixel's moment variable --------------
+  float wsum = 0.f, mean = 0.f, m2 = 0.f;
   int n_cov = 0;
   {
-    float* wm = wres[wave];  // [K + 1][64]
-    auto flush = [&](int n, uint64_t own) {
-      const bool act = lane < n;
-      const int it = act ? (int)q.item[lane] : lane;
-      const int j = act ? (it >> 6) : 0;
-      const int p = it & 63;
-      PixelBasis pp;
-      pp.tc = from_lane(pb.tc, p);
-      pp.p = from_lane(pb.p, p);
-      pp.p15 = from_lane(pb.p15, p);
-      pp.amp = from_lane(pb.amp, p);
+    auto flush = [&](int n, uint64_t own) __attribute__((always_inline)) {
+      int j, p;
+      const bool act = item_of(n, j, p);
       const float lamp = from_lane(lam, p);
       if (act) {
-        const float dx = (float)(x0 + (p & 7)) + 0.5f - st.f[0][j].x;
-        const float dy = (float)(y0 + (p >> 3)) + 0.5f - st.f[0][j].y;
-        RayG g = ray_params(st, j, dx, dy, lamp);
-        float m[K + 1];
-        particle_moments<K>(g, pp, tn, m);
-#pragma unroll
-        for (int k = 0; k <= K; ++k) wm[k * 64 + lane] = m[k];
+        RayG g = ray_of(j, p, lamp);
+        res[lane] = g.omega * g.sig;
+        res[64 + lane] = g.mu;
+        res[128 + lane] = g.sig;
       }
       __builtin_amdgcn_wave_barrier();
       while (own) {
         const int i = __builtin_ctzll(own);
         own &= own - 1;
-#pragma unroll
-        for (int k = 0; k <= K; ++k) acc[k] += (double)wm[k * 64 + i];
+        const float wgt = res[i], mu = res[64 + i], sg = res[128 + i];
+        if (wgt > 0.f) {
+          wsum += wgt;
+          float d = mu - mean;
+          mean += d * wgt / wsum;
+          m2 += wgt * (d * (mu - mean) + sg * sg);
+        }
       }
       __builtin_amdgcn_wave_barrier();
     };
@@ -185,6 +164,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
         float dx, dy;
         bool cov = covers(st, j, u, v, inside, dx, dy);
         uint64_t mask = __ballot(cov);
+        if (lane == 0) a.masks[(size_t)(b + j) * 4 + wave] = mask;
         if (mask == 0) continue;
         n_cov += cov ? 1 : 0;
         queue_push(q, qc, mask, cov, j, lane);
@@ -193,6 +173,61 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
           queue_pop64(q, qc, lane);
         }
       }
+      if (qc.cnt > 0) flush(qc.cnt, qc.own_lo);
+    }
+  }
+  float tc = fmaxf(mean, tn);
+  float sd = wsum > 0.f ? sqrtf(fmaxf(m2 / wsum, 0.f)) : 1.f;
+  {
+    float qq = 1.f + 0.8f * tc, xn = 1.f + 0.8f * tn;
+    float gp = 1.2f * xn * sqrtf(xn) / (qq * qq * sqrtf(qq));  // g_hat'(tc)
+    sd = fmaxf(sd * gp, 1e-30f);
+  }
+  const PixelBasis pb = make_basis(tc, sd, tn);
+
+  // ---- pass 1: moments ------------------------------------------------------
+  double acc[K + 1];
+#pragma unroll
+  for (int k = 0; k <= K; ++k) acc[k] = 0.0;
+  {
+    auto flush = [&](int n, uint64_t own) __attribute__((always_inline)) {
+      int j, p;
+      const bool act = item_of(n, j, p);
+      PixelBasis pp;
+      pp.tc = from_lane(pb.tc, p);
+      pp.p = from_lane(pb.p, p);
+      pp.p15 = from_lane(pb.p15, p);
+      pp.amp = from_lane(pb.amp, p);
+      const float lamp = from_lane(lam, p);
+      if (act) {
+        RayG g = ray_of(j, p, lamp);
+        float m[K + 1];
+        particle_moments<K>(g, pp, tn, m);
+#pragma unroll
+        for (int k = 0; k <= K; ++k) res[k * 64 + lane] = m[k];
+      }
+      __builtin_amdgcn_wave_barrier();
+      while (own) {
+        const int i = __builtin_ctzll(own);
+        own &= own - 1;
+#pragma unroll
+        for (int k = 0; k <= K; ++k) acc[k] += (double)res[k * 64 + i];
+      }
+      __builtin_amdgcn_wave_barrier();
+    };
+    for (int b = rg.x; b < rg.y; b += kBlock) {
+      int nb = min(kBlock, rg.y - b);
+      __syncthreads();
+      load_batch(st, a.rec, a.sorted_rec, b, nb);
+      __syncthreads();
+      QueueCursor qc;
+      queue_reset(qc);
+      queue_from_masks(q, qc, a.masks, b, nb, wave, lane, ~0ull,
+                       [&]() __attribute__((always_inline)) {
+                         flush(64, qc.own_lo);
+                         queue_pop64(q, qc, lane);
+                       },
+                       [](int) {});
       if (qc.cnt > 0) flush(qc.cnt, qc.own_lo);
     }
   }
@@ -300,10 +335,11 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
     }
     return;
   } else {
-    float4* cb = reinterpret_cast<float4*>(wres[wave]);  // [64]
+    float4* cb = reinterpret_cast<float4*>(res);  // [64]
+    const uint64_t live_mask = __ballot(inside && live);
     // evaluate queue positions [0, n) (one per lane), then add the results of
     // this lane's own positions (bits of `own`) in order
-    auto flush = [&](int n, uint64_t own, int b) {
+    auto flush = [&](int n, uint64_t own, int b) __attribute__((always_inline)) {
       const bool act = lane < n;
       const int it = act ? (int)q.item[lane] : lane;
       const int j = act ? (it >> 6) : 0;
@@ -375,17 +411,12 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
       __syncthreads();
       QueueCursor qc;
       queue_reset(qc);
-      for (int j = 0; j < nb; ++j) {
-        float dx, dy;
-        bool cov = covers(st, j, u, v, inside && live, dx, dy);
-        uint64_t mask = __ballot(cov);
-        if (mask == 0) continue;
-        queue_push(q, qc, mask, cov, j, lane);
-        if (qc.cnt >= 64) {
-          flush(64, qc.own_lo, b);
-          queue_pop64(q, qc, lane);
-        }
-      }
+      queue_from_masks(q, qc, a.masks, b, nb, wave, lane, live_mask,
+                       [&]() __attribute__((always_inline)) {
+                         flush(64, qc.own_lo, b);
+                         queue_pop64(q, qc, lane);
+                       },
+                       [](int) {});
       if (qc.cnt > 0) flush(qc.cnt, qc.own_lo, b);
     }
   }
