@@ -65,6 +65,7 @@ struct CamSet {
 
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float fast_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
 // erfc with an exact shortcut: for b < -3.9, erfc(b) = 2 - erfc(-b) with
 // erfc(-b) < 4e-8, below half an ulp of 2, so the float result is 2 exactly.
@@ -234,7 +235,7 @@ __device__ __forceinline__ PixelBasis make_basis(float tc, float s, float tn) {
 // y at depth t, given dt = t - tc computed by the caller without cancellation
 __device__ __forceinline__ float warp_y(const PixelBasis& b, float t, float dt) {
   float q = 1.f + 0.8f * t;
-  float sq = sqrtf(q);
+  float sq = fast_sqrt(q);
   float q15 = q * sq;
   float num = (q + b.p) * q + b.p * b.p;
   float den = (q15 + b.p15) * (b.p15 * q15);
@@ -244,8 +245,8 @@ __device__ __forceinline__ float warp_y(const PixelBasis& b, float t, float dt) 
 // dy/dt at depth t: 1.5 amp q^-2.5
 __device__ __forceinline__ float warp_dy(const PixelBasis& b, float t) {
   float q = 1.f + 0.8f * t;
-  float sq = sqrtf(q);
-  return 1.5f * b.amp / (q * q * sq);
+  float sq = fast_sqrt(q);
+  return 1.5f * b.amp * fast_rcp(q * q * sq);
 }
 
 }  // namespace mb

@@ -89,7 +89,22 @@ __device__ __forceinline__ bool tile_box(float mx, float my, const Rect& r, int 
   return true;
 }
 
+// DEG: SH degree (-1 for plain RGB). The block's SH coefficients are first
+// copied to LDS with coalesced loads (a Gaussian's 48 floats are contiguous,
+// so per-thread reads would touch 64 cache lines per instruction), one padded
+// row per Gaussian against bank conflicts.
+template <int DEG>
 __global__ __launch_bounds__(256) void k_preprocess(PrepArgs a, CamSet cams) {
+  constexpr int kPer = DEG < 0 ? 3 : (DEG + 1) * (DEG + 1) * 3;
+  constexpr int kRow = kPer | 1;
+  __shared__ float shc[256 * kRow];
+  {
+    const int g0 = blockIdx.x * blockDim.x;
+    const int cnt = min(256, a.n - g0) * kPer;
+    const float* src = a.colors + (size_t)g0 * kPer;
+    for (int i = threadIdx.x; i < cnt; i += 256) shc[(i / kPer) * kRow + i % kPer] = src[i];
+    __syncthreads();
+  }
   int g = blockIdx.x * blockDim.x + threadIdx.x;
   int ci = blockIdx.y;
   if (g >= a.n) return;
@@ -154,18 +169,19 @@ __global__ __launch_bounds__(256) void k_preprocess(PrepArgs a, CamSet cams) {
 
   // --- emission colour: RGB or SH at the per-Gaussian view direction ------
   float rgb[3];
-  if (a.sh_degree < 0) {
-    rgb[0] = a.colors[3 * g]; rgb[1] = a.colors[3 * g + 1]; rgb[2] = a.colors[3 * g + 2];
+  const float* f = shc + threadIdx.x * kRow;
+  if constexpr (DEG < 0) {
+    rgb[0] = f[0]; rgb[1] = f[1]; rgb[2] = f[2];
   } else {
+    constexpr int nb = (DEG + 1) * (DEG + 1);
     float dx = mean[0] - c.o[0], dy = mean[1] - c.o[1], dz = mean[2] - c.o[2];
     float inv = rsqrtf(dx * dx + dy * dy + dz * dz);
     float basis[16];
-    sh_basis(dx * inv, dy * inv, dz * inv, a.sh_degree, basis);
-    int nb = (a.sh_degree + 1) * (a.sh_degree + 1);
-    const float* f = a.colors + (size_t)g * nb * 3;
+    sh_basis(dx * inv, dy * inv, dz * inv, DEG, basis);
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
       float v = 0.5f;
+#pragma unroll
       for (int k = 0; k < nb; ++k) v += basis[k] * f[3 * k + ch];
       rgb[ch] = fmaxf(v, 0.f);
     }
@@ -182,7 +198,14 @@ __global__ __launch_bounds__(256) void k_preprocess(PrepArgs a, CamSet cams) {
 hipError_t launch_preprocess(const PrepArgs& a, const CamSet& cams, hipStream_t s) {
   if (a.n == 0) return hipSuccess;
   dim3 grid((a.n + 255) / 256, cams.n_cams);
-  hipLaunchKernelGGL(k_preprocess, grid, dim3(256), 0, s, a, cams);
+  switch (a.sh_degree) {
+    case -1: hipLaunchKernelGGL(k_preprocess<-1>, grid, dim3(256), 0, s, a, cams); break;
+    case 0: hipLaunchKernelGGL(k_preprocess<0>, grid, dim3(256), 0, s, a, cams); break;
+    case 1: hipLaunchKernelGGL(k_preprocess<1>, grid, dim3(256), 0, s, a, cams); break;
+    case 2: hipLaunchKernelGGL(k_preprocess<2>, grid, dim3(256), 0, s, a, cams); break;
+    case 3: hipLaunchKernelGGL(k_preprocess<3>, grid, dim3(256), 0, s, a, cams); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -65,7 +65,7 @@ __device__ __forceinline__ void linv_t_apply(const LInv<NH>& L, const float* z, 
 // Real roots of c0 + c1 x + c2 x^2 (stable form).
 __device__ __forceinline__ void roots2(const float* c, float* x) {
   float disc = fmaxf(c[1] * c[1] - 4.f * c[2] * c[0], 0.f);
-  float sq = sqrtf(disc);
+  float sq = fast_sqrt(disc);
   float q = -0.5f * (c[1] + copysignf(sq, c[1]));
   x[0] = q * fast_rcp(c[2]);
   x[1] = c[0] * fast_rcp(q);
@@ -75,7 +75,7 @@ __device__ __forceinline__ float cubic_newton(const float* c, float x, int iters
   for (int it = 0; it < iters; ++it) {
     float p = ((c[3] * x + c[2]) * x + c[1]) * x + c[0];
     float dp = (3.f * c[3] * x + 2.f * c[2]) * x + c[1];
-    float st = p / dp;
+    float st = p * fast_rcp(dp);
     x = (dp != 0.f && isfinite(st)) ? x - st : x;
   }
   return x;
@@ -96,15 +96,15 @@ __device__ __forceinline__ void roots3(const float* c, float* x) {
     x[2] = copysignf(1e30f, -c[2] * c[3]);
     return;
   }
-  float inv = 1.f / c[3];
+  float inv = fast_rcp(c[3]);
   float a = c[2] * inv, b = c[1] * inv, cc = c[0] * inv;
   float a3 = a * (1.f / 3.f);
   float q = a3 * a3 - b * (1.f / 3.f);
   float r = a3 * a3 * a3 - 0.5f * a3 * b + 0.5f * cc;
   q = fmaxf(q, 0.f);
-  float sq = sqrtf(q);
+  float sq = fast_sqrt(q);
   float den = q * sq;
-  float arg = den > 0.f ? fminf(fmaxf(r / den, -1.f), 1.f) : 0.f;
+  float arg = den > 0.f ? fminf(fmaxf(r * fast_rcp(den), -1.f), 1.f) : 0.f;
   float th = acosf(arg) * (1.f / 3.f);
   const float two_pi_3 = 2.0943951023931953f;
   float big = 0.f;
@@ -115,7 +115,7 @@ __device__ __forceinline__ void roots3(const float* c, float* x) {
   }
   big = cubic_newton(c, big, 2);
   // p(x) = (x - big)(A x^2 + B x + C), matched from the constant term up
-  float ib = 1.f / big;
+  float ib = fast_rcp(big);
   float cq = -c[0] * ib;
   float bq = (cq - c[1]) * ib;
   float aq = (bq - c[2]) * ib;
@@ -209,7 +209,7 @@ __device__ __forceinline__ void hermite_adjoint(float y, const float* xs, const 
 #pragma unroll
     for (int a = 0; a + order < NN; ++a) {
       float dz = z[a + order] - z[a];
-      f[a] = dz != 0.f ? (f[a + 1] - f[a]) / dz : 0.f;  // equal nodes: zero slope
+      f[a] = dz != 0.f ? (f[a + 1] - f[a]) * fast_rcp(dz) : 0.f;  // equal nodes: zero slope
     }
     coef[order] = f[0];
   }

@@ -29,10 +29,23 @@ struct QuadState {
   float q;
 };
 
+// phi'(x) = (e^-x - phi(x)) / x: the derivative of phi's series for |x| < 1/2
+// (terms up to x^7), the direct form beyond
 __device__ __forceinline__ float dphi_fn(float x) {
-  // d/dx (1 - e^-x)/x = (e^-x - phi(x)) / x
-  if (fabsf(x) < 1e-3f) return -0.5f + x * (1.f / 3.f - x * 0.125f);
-  return (expf(-x) + expm1f(-x) / x) / x;
+  // coefficients (-1)^k k / (k+1)!, k = 1..8
+  float s = 8.f / 362880.f;
+  s = fmaf(s, -x, 7.f / 40320.f);
+  s = fmaf(s, -x, 6.f / 5040.f);
+  s = fmaf(s, -x, 5.f / 720.f);
+  s = fmaf(s, -x, 4.f / 120.f);
+  s = fmaf(s, -x, 3.f / 24.f);
+  s = fmaf(s, -x, 2.f / 6.f);
+  s = fmaf(s, -x, 0.5f);
+  s = -s;
+  const float e = __expf(-x);
+  const float r = fast_rcp(x);
+  float d = (e - (1.f - e) * r) * r;
+  return fabsf(x) < 0.5f ? s : d;
 }
 
 template <int NH, int NQ>
@@ -468,8 +481,9 @@ __global__ __launch_bounds__(256, (K == 4 && NQ == 4) ? 3 : 2) void k_render_bwd
           if (s.cl[e]) {
             float r = (s.t[e] - g.mu) * fast_rcp(g.sig);
             float sj = g.omega * s.sr[e];
-            dq0 += cs * sj * r / g.sig;
-            dq1 += cs * sj * r * r / g.sig;
+            const float isg = fast_rcp(g.sig);
+            dq0 += cs * sj * r * isg;
+            dq1 += cs * sj * r * r * isg;
           }
           dq2 += cs * s.sr[e];
         }

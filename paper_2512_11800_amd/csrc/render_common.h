@@ -158,9 +158,21 @@ __device__ __forceinline__ void particle_moments(const RayG& g, const PixelBasis
   }
 }
 
+// phi(x) = (1 - e^-x) / x: its Taylor series up to x^8 for |x| < 1/2
+// (truncation below 1e-8 relative), the direct form beyond (no cancellation
+// there: 1 - e^-x > 0.39)
 __device__ __forceinline__ float phi_fn(float x) {
-  // (1 - e^-x) / x, continued by its series near 0
-  return fabsf(x) < 1e-4f ? 1.f - x * (0.5f - x * (1.f / 6.f)) : -expm1f(-x) / x;
+  float s = 1.f / 362880.f;
+  s = fmaf(s, -x, 1.f / 40320.f);
+  s = fmaf(s, -x, 1.f / 5040.f);
+  s = fmaf(s, -x, 1.f / 720.f);
+  s = fmaf(s, -x, 1.f / 120.f);
+  s = fmaf(s, -x, 1.f / 24.f);
+  s = fmaf(s, -x, 1.f / 6.f);
+  s = fmaf(s, -x, 0.5f);
+  s = fmaf(s, -x, 1.f);
+  float d = (1.f - __expf(-x)) * fast_rcp(x);
+  return fabsf(x) < 0.5f ? s : d;
 }
 
 // Interval edges of one Gaussian's quadrature (App. B sample spacing): edge

@@ -147,7 +147,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
         if (wgt > 0.f) {
           wsum += wgt;
           float d = mu - mean;
-          mean += d * wgt / wsum;
+          mean += d * wgt / wsum;  // IEEE division: weights can be denormal
           m2 += wgt * (d * (mu - mean) + sg * sg);
         }
       }
