@@ -62,8 +62,12 @@ def flops_per_pair(k_mom: int, n_int: int) -> dict:
     return out
 
 
-def _workload(k_mom: int):
+def _workload(k_mom: int, name: str = "w2"):
     import workloads as W
+    if name == "w5":
+        scene, cams, opts = W.w5_large()
+        opts.n_moments = k_mom
+        return scene, cams, opts
     scene, cams, opts = W.w2_clusters(n_moments=k_mom)
     return scene, cams, opts
 
@@ -78,11 +82,11 @@ def gpu_bench(args):
     from paper_2512_11800_amd import _lib as L
 
     torch.cuda.set_device(0)
-    scene, cams, opts = _workload(args.k)
+    scene, cams, opts = _workload(args.k, args.workload)
     g = M.Gaussians.from_scene(scene, device="cuda:0")
     ws = M.Workspace("cuda:0")
-    h, w = cams[0].height, cams[0].width
-    grad_img = torch.full((1, h, w, 3), 1.0 / (3 * h * w), device="cuda:0")
+    h, w, nc = cams[0].height, cams[0].width, len(cams)
+    grad_img = torch.full((nc, h, w, 3), 1.0 / (3 * h * w * nc), device="cuda:0")
 
     def fwd():
         return M.render_forward(g, cams, opts, ws=ws)
@@ -297,6 +301,9 @@ def main():
     ap.add_argument("--train-steps", type=int, default=4000)
     ap.add_argument("--gt-pixels", type=int, default=32)
     ap.add_argument("--k", type=int, default=4, choices=[4, 6])
+    ap.add_argument("--workload", choices=["w2", "w5"], default="w2",
+                    help="w2: 500k Gaussians, one 1080p camera (the metric's workload); "
+                         "w5: 3M Gaussians, 8 cameras at 3840x2160 in one launch sequence")
     ap.add_argument("--cpu-sample-px", type=int, default=12000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -332,7 +339,7 @@ def main():
 
     res, scene, cams, opts, n_pairs = gpu_bench(args)
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload == "w2":
         cpu = cpu_baseline(scene, cams, opts, n_pairs, args.cpu_sample_px, "fwdbwd" in res["modes"])
     modes = res["modes"]
     main_mode = "fwdbwd" if "fwdbwd" in modes else "fwd"
@@ -351,9 +358,13 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"500k Gaussians, 64 clusters, SH3, 1920x1080, K={args.k}, N=3, {label}",
-                   "n_gaussians": scene.n, "width": cams[0].width, "height": cams[0].height,
-                   "n_moments": args.k, "n_intervals": opts.n_intervals, "mode": label},
+        "config": {"workload": (f"500k Gaussians, 64 clusters, SH3, 1920x1080, K={args.k}, N=3, {label}"
+                                if args.workload == "w2" else
+                                f"3M Gaussians, 256 clusters, SH3, 8 cameras 3840x2160 in one launch "
+                                f"sequence, K={args.k}, N=3, {label}"),
+                   "n_gaussians": scene.n, "n_cameras": len(cams), "width": cams[0].width,
+                   "height": cams[0].height, "n_moments": args.k, "n_intervals": opts.n_intervals,
+                   "mode": label},
         "roofline": dom,
         "cpu_baseline": cpu,
     }

@@ -131,7 +131,7 @@ PairWs carve_pairs(void* p, int64_t e, int n_keys) {
   w.inv = c.take<int>((size_t)e);
   w.radix_tmp = c.take<int>(radix_tmp_ints(e));
   w.ranges = c.take<int2>((size_t)n_keys);
-  w.order = c.take<int>((size_t)n_keys);
+  w.order = c.take<int>((size_t)render_blocks(n_keys));
   w.order_tmp = c.take<int>(order_tmp_ints(n_keys));
   w.masks = c.take<uint64_t>((size_t)e * 4);
   w.partials = c.take<float>((size_t)e * 4 * kGradStride);  // one slot per (entry, wave)
@@ -228,7 +228,7 @@ int key_bits(int64_t n_keys) {
 
 // emit, sort and per-tile lists of the forward entry points
 int build_lists(const mb_gaussians* g, const GaussWs& w, const PairWs& p, int n_cams, int tx, int ty,
-                int full_coverage, int64_t n_entries, hipStream_t s) {
+                int full_coverage, int64_t n_entries, hipStream_t s, bool split_heavy = true) {
   int n_keys = tx * ty * n_cams;
   EmitArgs ea;
   ea.rec = w.rec; ea.tbox = w.tbox; ea.offsets = w.offsets; ea.counts = w.counts;
@@ -248,7 +248,8 @@ int build_lists(const mb_gaussians* g, const GaussWs& w, const PairWs& p, int n_
   {
     StageTimer t(S_LISTS, s);
     e = launch_finish_lists(p.keys_a, p.vals_a, p.entry_rec, n_entries, p.sorted_rec, p.inv, p.ranges, n_keys, s);
-    if (e == hipSuccess) e = launch_tile_order(p.ranges, n_keys, p.order, p.order_tmp, s);
+    if (e == hipSuccess)
+      e = launch_tile_order(p.ranges, n_keys, split_heavy ? kSplitEntries : 0x7FFFFFFF, p.order, p.order_tmp, s);
   }
   if (e != hipSuccess) return hip_fail(e, "lists");
   return MB_OK;
@@ -459,7 +460,7 @@ int mb_render_forward_harvest(const mb_gaussians* g, const mb_camera* cams, int3
   if (!(rate >= 0.f && rate <= 1.f)) return fail(MB_ERR_ARG, "harvest rate must lie in [0, 1]");
   if (capacity < 0 || !count || (capacity > 0 && !samples)) return fail(MB_ERR_ARG, "bad sample buffer");
   hipStream_t s = (hipStream_t)stream;
-  rc = build_lists(g, f.w, f.p, n_cams, f.ra.tiles_x, f.ra.tiles_y, o->full_coverage, n_entries, s);
+  rc = build_lists(g, f.w, f.p, n_cams, f.ra.tiles_x, f.ra.tiles_y, o->full_coverage, n_entries, s, false);
   if (rc) return rc;
   f.ra.harvest = samples;
   f.ra.harvest_count = count;
@@ -495,7 +496,7 @@ int mb_render_forward_surrogate(const mb_gaussians* g, const mb_camera* cams, in
   if (!qws || qws_bytes < q.bytes)
     return fail(MB_ERR_WORKSPACE, "query workspace needs %zu bytes, got %zu", q.bytes, qws_bytes);
   hipStream_t s = (hipStream_t)stream;
-  rc = build_lists(g, f.w, f.p, n_cams, f.ra.tiles_x, f.ra.tiles_y, o->full_coverage, n_entries, s);
+  rc = build_lists(g, f.w, f.p, n_cams, f.ra.tiles_x, f.ra.tiles_y, o->full_coverage, n_entries, s, false);
   if (rc) return rc;
   RenderArgs& ra = f.ra;
   ra.pixfeat = q.pixfeat;

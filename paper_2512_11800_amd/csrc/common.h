@@ -31,6 +31,13 @@ constexpr double kMinDepth = 1e-20;  // optical depth below which a pixel is emp
 // covering count) and harvested training sample (6 features, query, m0,
 // transmittance, selection hash bits, pixel index, record * (N+1) + edge)
 constexpr int kPixFeat = 10;
+// Heavy tiles (more list entries than kSplitEntries) are rendered by four
+// workgroups, one per 8x8 quadrant, whose four waves share the quadrant's
+// pixels and take every fourth list entry. The decision depends on the tile's
+// own list only, so a camera renders the same alone or in a batch. The grid
+// has room for every tile to split; unused blocks exit at once.
+constexpr int kSplitEntries = 512;
+__host__ __device__ inline int render_blocks(int n_keys) { return 4 * n_keys; }
 constexpr int kHarvestStride = 12;
 
 // Render record fields (float index inside the 24-float record).

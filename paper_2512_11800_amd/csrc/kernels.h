@@ -50,16 +50,17 @@ hipError_t launch_finish_lists(const uint32_t* keys, const int* vals, const int*
                                int64_t n, int* sorted_rec, int* inv, int2* ranges,
                                int n_keys, hipStream_t s);
 
-// tile dispatch order (longest list first) into order[n_keys]; tmp holds
-// order_tmp_ints(n_keys) ints
+// block list of the render kernels (render_blocks(n_keys) entries): tiles by
+// decreasing list length, tiles longer than `split` entries as four quadrant
+// blocks; tmp holds order_tmp_ints(n_keys) ints
 size_t order_tmp_ints(int n_keys);
-hipError_t launch_tile_order(const int2* ranges, int n_keys, int* order, int* tmp, hipStream_t s);
+hipError_t launch_tile_order(const int2* ranges, int n_keys, int split, int* blocks, int* tmp, hipStream_t s);
 
 struct RenderArgs {
   const float4* rec;
   const int* sorted_rec;
   const int2* ranges;
-  const int* order;  // [n_keys] tile of each block
+  const int* order;  // [render_blocks(n_keys)] block list (see launch_tile_order)
   uint64_t* masks;   // [E,4] coverage of list entry (sorted position) by the pixels of wave w
   float* image;   // [C,H,W,3]
   float* saved;   // [C,H,W,8]

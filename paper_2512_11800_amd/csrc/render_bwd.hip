@@ -269,14 +269,20 @@ __global__ __launch_bounds__(256, (K == 4 && NQ == 4) ? 3 : 2) void k_render_bwd
   __shared__ float carry[4][G_COUNT];                    // partial slot of an entry split over evaluations
   const int tiles_per_cam = a.tiles_x * a.tiles_y;
   const int n_keys = tiles_per_cam * a.n_cams;
-  const int key = block_key(a);
+  const BlockWork bw = block_work(a);
+  const int key = bw.key;
   if (key >= n_keys) return;
   const int ci = key / tiles_per_cam;
   const int tile = key - ci * tiles_per_cam;
   const int ty = tile / a.tiles_x, tx = tile - ty * a.tiles_x;
   const CamConst& c = cams.c[ci];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int x0 = tx * kTile + (wave & 1) * 8, y0 = ty * kTile + (wave >> 1) * 8;
+  // as in the forward pass: a split block's waves share one quadrant and
+  // take every fourth list entry; slots and masks are per (entry, quadrant)
+  const bool split = bw.quad >= 0;
+  const int quad = split ? bw.quad : wave;
+  const int own4 = split ? wave : -1;
+  const int x0 = tx * kTile + (quad & 1) * 8, y0 = ty * kTile + (quad >> 1) * 8;
   const int px = x0 + (lane & 7);
   const int py = y0 + (lane >> 3);
   const bool inside = px < c.width && py < c.height;
@@ -363,13 +369,27 @@ __global__ __launch_bounds__(256, (K == 4 && NQ == 4) ? 3 : 2) void k_render_bwd
       stage(b, nb, false);
       QueueCursor qc;
       queue_reset(qc);
-      queue_from_masks(q, qc, a.masks, b, nb, wave, lane, ~0ull,
+      queue_from_masks(q, qc, a.masks, b, nb, quad, own4, lane, ~0ull,
                        [&]() __attribute__((always_inline)) {
                          flush(64, qc.own_lo);
                          queue_pop64(q, qc, lane);
                        },
                        [](int) {});
       if (qc.cnt > 0) flush(qc.cnt, qc.own_lo);
+    }
+  }
+  if (split) {
+    double* xd = reinterpret_cast<double*>(&st);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k <= K; ++k) xd[(wave * (K + 1) + k) * 64 + lane] = acc[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k <= K; ++k) {
+      double t = 0.0;
+#pragma unroll
+      for (int w = 0; w < 4; ++w) t += xd[(w * (K + 1) + k) * 64 + lane];
+      acc[k] = t;
     }
   }
   const float m0 = (float)acc[0];
@@ -410,7 +430,7 @@ __global__ __launch_bounds__(256, (K == 4 && NQ == 4) ? 3 : 2) void k_render_bwd
   const uint64_t active_mask = __ballot(active);
   float* cw = carry[wave];
   auto zero_slot = [&](int j) __attribute__((always_inline)) {
-    float4* slot = reinterpret_cast<float4*>(ba.partials + ((size_t)sk[j] * 4 + wave) * kGradStride);
+    float4* slot = reinterpret_cast<float4*>(ba.partials + ((size_t)sk[j] * 4 + quad) * kGradStride);
 #pragma unroll
     for (int f = 0; f < kGradStride / 4; ++f) slot[f] = make_float4(0.f, 0.f, 0.f, 0.f);
   };
@@ -419,7 +439,7 @@ __global__ __launch_bounds__(256, (K == 4 && NQ == 4) ? 3 : 2) void k_render_bwd
   float dm[K + 1];
 #pragma unroll
   for (int k = 0; k <= K; ++k) dm[k] = 0.f;
-  dm[0] = active ? e0 : 0.f;
+  dm[0] = (active && own4 <= 0) ? e0 : 0.f;  // a split block adds e0 once (wave 0)
   {
     int carry_j = -1;
     auto flush = [&](int n, uint64_t own, int cont_j) __attribute__((always_inline)) {
@@ -501,7 +521,7 @@ __global__ __launch_bounds__(256, (K == 4 && NQ == 4) ? 3 : 2) void k_render_bwd
 #pragma unroll
         for (int k = 0; k <= K; ++k) dm[k] += res[k * 64 + i];
       }
-      reduce_to_slots<false>(gr, act, j, n, lane, cont_j, carry_j, cw, ba.partials, sk, wave);
+      reduce_to_slots<false>(gr, act, j, n, lane, cont_j, carry_j, cw, ba.partials, sk, quad);
     };
     for (int b = rg.x; b < rg.y; b += kBlock) {
       int nb = min(kBlock, rg.y - b);
@@ -509,7 +529,7 @@ __global__ __launch_bounds__(256, (K == 4 && NQ == 4) ? 3 : 2) void k_render_bwd
       QueueCursor qc;
       queue_reset(qc);
       carry_j = -1;
-      queue_from_masks(q, qc, a.masks, b, nb, wave, lane, active_mask,
+      queue_from_masks(q, qc, a.masks, b, nb, quad, own4, lane, active_mask,
                        [&]() __attribute__((always_inline)) {
                          const int cont_j = qc.cnt > 64 ? (int)(q.item[64] >> 6) : -1;
                          flush(64, qc.own_lo, cont_j);
@@ -517,6 +537,21 @@ __global__ __launch_bounds__(256, (K == 4 && NQ == 4) ? 3 : 2) void k_render_bwd
                        },
                        zero_slot);
       if (qc.cnt > 0) flush(qc.cnt, qc.own_lo, -1);
+    }
+  }
+
+  if (split) {
+    float* xf = reinterpret_cast<float*>(&st);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k <= K; ++k) xf[(wave * (K + 1) + k) * 64 + lane] = dm[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k <= K; ++k) {
+      float t = 0.f;
+#pragma unroll
+      for (int w = 0; w < 4; ++w) t += xf[(w * (K + 1) + k) * 64 + lane];
+      dm[k] = t;
     }
   }
 
@@ -542,7 +577,7 @@ __global__ __launch_bounds__(256, (K == 4 && NQ == 4) ? 3 : 2) void k_render_bwd
         moment_grads<K>(g, pp, tn, dmp, gm);
         chain_record(gm[0], gm[1], gm[2], g, lamp, dx, dy, st.f[2][j], st.f[3][j], st.f[4][j], gr);
       }
-      reduce_to_slots<true>(gr, act, j, n, lane, cont_j, carry_j, cw, ba.partials, sk, wave);
+      reduce_to_slots<true>(gr, act, j, n, lane, cont_j, carry_j, cw, ba.partials, sk, quad);
     };
     for (int b = rg.x; b < rg.y; b += kBlock) {
       int nb = min(kBlock, rg.y - b);
@@ -550,7 +585,7 @@ __global__ __launch_bounds__(256, (K == 4 && NQ == 4) ? 3 : 2) void k_render_bwd
       QueueCursor qc;
       queue_reset(qc);
       carry_j = -1;
-      queue_from_masks(q, qc, a.masks, b, nb, wave, lane, active_mask,
+      queue_from_masks(q, qc, a.masks, b, nb, quad, own4, lane, active_mask,
                        [&]() __attribute__((always_inline)) {
                          const int cont_j = qc.cnt > 64 ? (int)(q.item[64] >> 6) : -1;
                          flush(64, cont_j);
@@ -567,7 +602,7 @@ hipError_t launch_render_backward(const RenderArgs& r, const float* saved, const
                                   int n_intervals, hipStream_t s) {
   BwdArgs ba{r, saved, grad_image, sorted_k, partials};
   int n_keys = r.tiles_x * r.tiles_y * r.n_cams;
-  dim3 grid(n_keys), block(kBlock);
+  dim3 grid(render_blocks(n_keys)), block(kBlock);
 #define MB_LAUNCH(KK, NN)                                                         \
   if (n_moments == KK && n_intervals == NN) {                                     \
     hipLaunchKernelGGL((k_render_bwd<KK, NN + 1>), grid, block, 0, s, ba, cams); \

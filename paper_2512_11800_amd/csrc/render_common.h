@@ -72,13 +72,15 @@ __device__ __forceinline__ void queue_pop64(WaveQueue& q, QueueCursor& qc, int l
 // entries 64 at a time. on_full() evaluates and pops 64 queued pairs;
 // on_empty(j) is called by the lane that loaded entry j's mask when it is
 // empty (after the restriction).
+// In a split block (see BlockWork) a wave takes only the entries j with
+// j % 4 == its wave index (`own4` >= 0); otherwise every entry (`own4` < 0).
 template <class Full, class Empty>
 __device__ __forceinline__ void queue_from_masks(WaveQueue& q, QueueCursor& qc, const uint64_t* masks, int b, int nb,
-                                                 int wave, int lane, uint64_t keep, Full&& on_full,
+                                                 int quad, int own4, int lane, uint64_t keep, Full&& on_full,
                                                  Empty&& on_empty) {
   for (int j0 = 0; j0 < nb; j0 += 64) {
-    const bool in = j0 + lane < nb;
-    const uint64_t mk = in ? (masks[(size_t)(b + j0 + lane) * 4 + wave] & keep) : 0ull;
+    const bool in = j0 + lane < nb && (own4 < 0 || ((j0 + lane) & 3) == own4);
+    const uint64_t mk = in ? (masks[(size_t)(b + j0 + lane) * 4 + quad] & keep) : 0ull;
     if (in && mk == 0) on_empty(j0 + lane);
     uint64_t nz = __ballot(mk != 0);
     while (nz) {
@@ -94,9 +96,26 @@ __device__ __forceinline__ void queue_from_masks(WaveQueue& q, QueueCursor& qc, 
 // value of pixel lane p (all lanes must take part)
 __device__ __forceinline__ float from_lane(float v, int p) { return __shfl(v, p, 64); }
 
-// tile (camera * tiles + tile) of this block: the dispatch order sorts the
-// tiles by list length, longest first
-__device__ __forceinline__ int block_key(const RenderArgs& a) { return a.order[blockIdx.x]; }
+// Work of a render block (see launch_tile_order): tile key (camera * tiles +
+// tile; n_keys for an empty block) and, for a block of a split tile, the
+// quadrant its four waves share (quad = -1: the whole tile, one quadrant per
+// wave).
+struct BlockWork {
+  int key, quad;
+};
+__device__ __forceinline__ BlockWork block_work(const RenderArgs& a) {
+  const int code = a.order[blockIdx.x];
+  BlockWork w;
+  if (code >= 0) {
+    w.key = code;
+    w.quad = -1;
+  } else {
+    const int v = -code - 1;
+    w.key = v >> 2;
+    w.quad = v & 3;
+  }
+  return w;
+}
 
 __device__ __forceinline__ void load_batch(Stage& st, const float4* rec, const int* sorted_rec, int b, int nb) {
   int tid = threadIdx.x;

@@ -86,15 +86,21 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
   __shared__ int s_scan[4];
   const int tiles_per_cam = a.tiles_x * a.tiles_y;
   const int n_keys = tiles_per_cam * a.n_cams;
-  const int key = block_key(a);
+  const BlockWork bw = block_work(a);
+  const int key = bw.key;
   if (key >= n_keys) return;
   const int ci = key / tiles_per_cam;
   const int tile = key - ci * tiles_per_cam;
   const int ty = tile / a.tiles_x, tx = tile - ty * a.tiles_x;
   const CamConst& c = cams.c[ci];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int px = tx * kTile + (wave & 1) * 8 + (lane & 7);
-  const int py = ty * kTile + (wave >> 1) * 8 + (lane >> 3);
+  // the wave's 8x8 pixel block; in a split block all four waves share one
+  // and each takes every fourth list entry (own4)
+  const bool split = bw.quad >= 0;
+  const int quad = split ? bw.quad : wave;
+  const int own4 = split ? wave : -1;
+  const int px = tx * kTile + (quad & 1) * 8 + (lane & 7);
+  const int py = ty * kTile + (quad >> 1) * 8 + (lane >> 3);
   const bool inside = px < c.width && py < c.height;
   const float u = (float)px + 0.5f, v = (float)py + 0.5f;
   const float rx = (u - c.cx) / c.fx, ry = (v - c.cy) / c.fy;
@@ -109,7 +115,11 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
   __shared__ __align__(16) float wres[4][(K + 1) * 64];
   WaveQueue& q = wq[wave];
   float* res = wres[wave];
-  const int x0 = tx * kTile + (wave & 1) * 8, y0 = ty * kTile + (wave >> 1) * 8;
+  const int x0 = tx * kTile + (quad & 1) * 8, y0 = ty * kTile + (quad >> 1) * 8;
+  // partial per-pixel sums of a split block's four waves, combined in wave
+  // order through the (then idle) staging buffer; every wave ends with the
+  // same totals
+  float* xch = reinterpret_cast<float*>(&st);
   // the pair at queue position `lane` (entry j, pixel lane p); inactive lanes
   // (lane >= n) get p = lane so the cross-lane reads stay uniform
   auto item_of = [&](int n, int& j, int& p) __attribute__((always_inline)) {
@@ -160,11 +170,11 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
       __syncthreads();
       QueueCursor qc;
       queue_reset(qc);
-      for (int j = 0; j < nb; ++j) {
+      for (int j = split ? wave : 0; j < nb; j += split ? 4 : 1) {
         float dx, dy;
         bool cov = covers(st, j, u, v, inside, dx, dy);
         uint64_t mask = __ballot(cov);
-        if (lane == 0) a.masks[(size_t)(b + j) * 4 + wave] = mask;
+        if (lane == 0) a.masks[(size_t)(b + j) * 4 + quad] = mask;
         if (mask == 0) continue;
         n_cov += cov ? 1 : 0;
         queue_push(q, qc, mask, cov, j, lane);
@@ -174,6 +184,32 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
         }
       }
       if (qc.cnt > 0) flush(qc.cnt, qc.own_lo);
+    }
+  }
+  if (split) {
+    // combine the four (weight, mean, M2) states in wave order (Chan et al.)
+    __syncthreads();
+    xch[(wave * 4 + 0) * 64 + lane] = wsum;
+    xch[(wave * 4 + 1) * 64 + lane] = mean;
+    xch[(wave * 4 + 2) * 64 + lane] = m2;
+    xch[(wave * 4 + 3) * 64 + lane] = __int_as_float(n_cov);
+    __syncthreads();
+    wsum = 0.f;
+    mean = 0.f;
+    m2 = 0.f;
+    n_cov = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      const float wb = xch[(w * 4 + 0) * 64 + lane], mb = xch[(w * 4 + 1) * 64 + lane];
+      const float m2b = xch[(w * 4 + 2) * 64 + lane];
+      n_cov += __float_as_int(xch[(w * 4 + 3) * 64 + lane]);
+      if (wb > 0.f) {
+        const float wn = wsum + wb;
+        const float d = mb - mean;
+        m2 += m2b + d * d * (wsum * wb / wn);
+        mean += d * (wb / wn);
+        wsum = wn;
+      }
     }
   }
   float tc = fmaxf(mean, tn);
@@ -222,13 +258,28 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
       __syncthreads();
       QueueCursor qc;
       queue_reset(qc);
-      queue_from_masks(q, qc, a.masks, b, nb, wave, lane, ~0ull,
+      queue_from_masks(q, qc, a.masks, b, nb, quad, own4, lane, ~0ull,
                        [&]() __attribute__((always_inline)) {
                          flush(64, qc.own_lo);
                          queue_pop64(q, qc, lane);
                        },
                        [](int) {});
       if (qc.cnt > 0) flush(qc.cnt, qc.own_lo);
+    }
+  }
+
+  if (split) {
+    double* xd = reinterpret_cast<double*>(&st);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k <= K; ++k) xd[(wave * (K + 1) + k) * 64 + lane] = acc[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k <= K; ++k) {
+      double t = 0.0;
+#pragma unroll
+      for (int w = 0; w < 4; ++w) t += xd[(w * (K + 1) + k) * 64 + lane];
+      acc[k] = t;
     }
   }
 
@@ -411,7 +462,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
       __syncthreads();
       QueueCursor qc;
       queue_reset(qc);
-      queue_from_masks(q, qc, a.masks, b, nb, wave, lane, live_mask,
+      queue_from_masks(q, qc, a.masks, b, nb, quad, own4, lane, live_mask,
                        [&]() __attribute__((always_inline)) {
                          flush(64, qc.own_lo, b);
                          queue_pop64(q, qc, lane);
@@ -419,6 +470,24 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
                        [](int) {});
       if (qc.cnt > 0) flush(qc.cnt, qc.own_lo, b);
     }
+  }
+
+  if (split) {
+    __syncthreads();
+    xch[(wave * 4 + 0) * 64 + lane] = sr;
+    xch[(wave * 4 + 1) * 64 + lane] = sg;
+    xch[(wave * 4 + 2) * 64 + lane] = sb;
+    xch[(wave * 4 + 3) * 64 + lane] = so;
+    __syncthreads();
+    sr = sg = sb = so = 0.f;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      sr += xch[(w * 4 + 0) * 64 + lane];
+      sg += xch[(w * 4 + 1) * 64 + lane];
+      sb += xch[(w * 4 + 2) * 64 + lane];
+      so += xch[(w * 4 + 3) * 64 + lane];
+    }
+    if (wave != 0) return;
   }
 
   // ---- epilogue: Eq. 15 ------------------------------------------------------
@@ -444,7 +513,7 @@ __global__ __launch_bounds__(256) void k_render_consume(RenderArgs a, CamSet cam
   __shared__ Stage st;
   const int tiles_per_cam = a.tiles_x * a.tiles_y;
   const int n_keys = tiles_per_cam * a.n_cams;
-  const int key = block_key(a);
+  const int key = block_work(a).key;  // the surrogate path splits no tile
   if (key >= n_keys) return;
   const int ci = key / tiles_per_cam;
   const int tile = key - ci * tiles_per_cam;
@@ -509,7 +578,7 @@ __global__ __launch_bounds__(256) void k_render_consume(RenderArgs a, CamSet cam
 hipError_t launch_render_forward(const RenderArgs& a, const CamSet& cams, int n_moments, int n_intervals,
                                  hipStream_t s, int mode) {
   int n_keys = a.tiles_x * a.tiles_y * a.n_cams;
-  dim3 grid(n_keys), block(kBlock);
+  dim3 grid(render_blocks(n_keys)), block(kBlock);
 #define MB_LAUNCH(KK, NN, MM)                                                       \
   if (n_moments == KK && n_intervals == NN && mode == MM) {                         \
     hipLaunchKernelGGL((k_render_fwd<KK, NN + 1, MM>), grid, block, 0, s, a, cams); \
@@ -529,7 +598,7 @@ hipError_t launch_render_forward(const RenderArgs& a, const CamSet& cams, int n_
 
 hipError_t launch_render_consume(const RenderArgs& a, const CamSet& cams, int n_intervals, hipStream_t s) {
   int n_keys = a.tiles_x * a.tiles_y * a.n_cams;
-  dim3 grid(n_keys), block(kBlock);
+  dim3 grid(render_blocks(n_keys)), block(kBlock);
   if (n_intervals == 3)
     hipLaunchKernelGGL(k_render_consume<4>, grid, block, 0, s, a, cams);
   else if (n_intervals == 5)

@@ -237,18 +237,52 @@ __global__ __launch_bounds__(256) void k_tile_keys(const int2* ranges, int n_key
   vals[i] = i;
 }
 
+// Block list of the render kernels from the sorted tiles: the first ns tiles
+// (list longer than `split`) get four blocks each,
+// coded -(4 key + quadrant) - 1, then one block per remaining tile (its key),
+// then blocks coded n_keys that exit at once (the grid is render_blocks()).
+__global__ __launch_bounds__(256) void k_block_list(const uint32_t* sorted_keys, const int* order, int n_keys,
+                                                   int split, int* blocks) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int total = render_blocks(n_keys);
+  if (t >= total) return;
+  // ns = number of leading tiles whose list is longer than `split`
+  int lo = 0, hi = n_keys;
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    int len = 0xFFFF - (int)sorted_keys[mid];
+    if (len > split) lo = mid + 1; else hi = mid;
+  }
+  const int ns = lo;
+  if (t < n_keys) {
+    if (t < ns) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) blocks[4 * t + q] = -(4 * order[t] + q) - 1;
+    } else {
+      blocks[3 * ns + t] = order[t];
+    }
+  } else if (t >= n_keys + 3 * ns) {
+    blocks[t] = n_keys;
+  }
+}
+
 size_t order_tmp_ints(int n_keys) { return 4 * (size_t)n_keys + radix_tmp_ints(n_keys); }
 
-hipError_t launch_tile_order(const int2* ranges, int n_keys, int* order, int* tmp, hipStream_t s) {
+hipError_t launch_tile_order(const int2* ranges, int n_keys, int split, int* blocks, int* tmp, hipStream_t s) {
   if (n_keys <= 0) return hipSuccess;
   uint32_t* ka = reinterpret_cast<uint32_t*>(tmp);
   uint32_t* kb = ka + n_keys;
-  int* vb = tmp + 2 * (size_t)n_keys;
+  int* va = tmp + 2 * (size_t)n_keys;
+  int* vb = tmp + 3 * (size_t)n_keys;
   int* rt = tmp + 4 * (size_t)n_keys;
-  hipLaunchKernelGGL(k_tile_keys, dim3((n_keys + 255) / 256), dim3(256), 0, s, ranges, n_keys, ka, order);
+  hipLaunchKernelGGL(k_tile_keys, dim3((n_keys + 255) / 256), dim3(256), 0, s, ranges, n_keys, ka, va);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  return launch_radix_sort(ka, order, kb, vb, n_keys, 16, rt, s);
+  e = launch_radix_sort(ka, va, kb, vb, n_keys, 16, rt, s);
+  if (e != hipSuccess) return e;
+  int total = render_blocks(n_keys);
+  hipLaunchKernelGGL(k_block_list, dim3((total + 255) / 256), dim3(256), 0, s, ka, va, n_keys, split, blocks);
+  return hipGetLastError();
 }
 
 hipError_t launch_finish_lists(const uint32_t* keys, const int* vals, const int* entry_rec, int64_t n,
