@@ -63,3 +63,24 @@ def rescale(m0, s_rgb, o, eps: float, background):
     alpha = -torch.expm1(-m0)
     return alpha[:, None] * s_rgb / torch.clamp_min(o, eps)[:, None] \
         + torch.exp(-m0)[:, None] * bg
+
+
+def interval_depth(mu, sigma, omega, t):
+    """Optical depth of each particle alone over its quadrature intervals
+    [t_j, t_{j+1}] (App. E, regularisation): the integral of
+    omega exp(-(s - mu)^2 / (2 Sigma^2)) over the interval, in closed form
+    omega Sigma sqrt(pi/2) (erf(b_{j+1}) - erf(b_j)), b = (t - mu) / (sqrt2 Sigma).
+    t: [P, N+1] edges; returns [P, N]."""
+    b = (t - mu[:, None]) / (np.sqrt(2.0) * sigma[:, None])
+    e = torch.special.erf(b)
+    return (omega * sigma * np.sqrt(np.pi / 2.0))[:, None] * (e[:, 1:] - e[:, :-1])
+
+
+def consistency_penalty(mu, sigma, omega, tau, t):
+    """P_i = sum_j max(0, tau_ij - (tau(t_{j+1}) - tau(t_j)))^2 over the
+    quadrature intervals (App. E, regularisation; Sec. 3.4): the reconstructed
+    optical depth gained over an interval may not fall below that of any one
+    particle alone. tau, t: [P, N+1] at the edges; returns [P]."""
+    tij = interval_depth(mu, sigma, omega, t)
+    r = torch.clamp_min(tij - (tau[:, 1:] - tau[:, :-1]), 0.0)
+    return (r * r).sum(-1)

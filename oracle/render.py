@@ -22,7 +22,7 @@ from .bounds import bound_tau
 from .geometry import DT, camera_matrices, pixel_directions, quat_to_rot, ray_gaussian, sh_rgb
 from .moments import particle_moments, warp
 from .proxy import covering_pairs, screen_proxy
-from .quadrature import particle_quadrature, rescale
+from .quadrature import consistency_penalty, particle_quadrature, rescale
 
 PARAMS = ("means", "scales", "quats", "densities", "colors")
 
@@ -52,6 +52,7 @@ class PixelResult:
     pair_q: torch.Tensor
     pair_y: torch.Tensor     # [pairs, N+1] moment variable at the quadrature edges
     pair_tau: torch.Tensor   # [pairs, N+1] reconstructed optical depth there
+    penalty: torch.Tensor    # [P] consistency penalty sum_i P_i (App. E)
 
 
 def _standardised_basis(slot, mu, sigma, omega, t_near, n_pix):
@@ -118,14 +119,17 @@ def render_pixels(scene_t, scene, cam, opts, px: torch.Tensor, py: torch.Tensor,
         q, tau_e, t_e = particle_quadrature(mu, sigma, omega, tau_at, t_near, opts.kappa,
                                             opts.n_intervals, warp_y)
         y_e = warp_y(t_e)
+        pen_pair = consistency_penalty(mu, sigma, omega, tau_e, t_e)
     else:
         q = torch.zeros(0, dtype=DT)
+        pen_pair = torch.zeros(0, dtype=DT)
         tau_e = y_e = torch.zeros(0, n_edge, dtype=DT)
+    penalty = torch.zeros(n_pix, dtype=DT).index_add(0, slot, pen_pair)
     s_rgb = torch.zeros(n_pix, 3, dtype=DT).index_add(0, slot, q[:, None] * rgb_all[gid])
     o = torch.zeros(n_pix, dtype=DT).index_add(0, slot, q)
     image = rescale(mom[:, 0], s_rgb, o, opts.eps, cam.background)
     return PixelResult(image, s_rgb, o, mom, centre, scale, amb, int(slot.shape[0]),
-                       slot, gid, q, y_e, tau_e)
+                       slot, gid, q, y_e, tau_e, penalty)
 
 
 def _pixel_chunks(cam, px, py, max_pixels):
@@ -138,9 +142,9 @@ def render_image(scene, cam, opts, pixels: Optional[np.ndarray] = None,
                  tau_model=None):
     """Forward render of ``pixels`` (flat indices y * W + x; default: the
     whole image). Returns a dict of numpy arrays: image [P,3], s_rgb [P,3],
-    opacity [P], moments [P,K+1], ambiguous [P] (a coverage decision within
-    ``margin_tol`` pixels of a rectangle edge, widened for nearly circular
-    proxies by ``orient_eps``), n_pairs."""
+    opacity [P], moments [P,K+1], penalty [P] (consistency penalty), ambiguous
+    [P] (a coverage decision within ``margin_tol`` pixels of a rectangle edge,
+    widened for nearly circular proxies by ``orient_eps``), n_pairs."""
     scene_t = scene_tensors(scene)
     proxy = screen_proxy(scene_t, cam, opts.conf_c)
     if pixels is None:
@@ -148,7 +152,7 @@ def render_image(scene, cam, opts, pixels: Optional[np.ndarray] = None,
     pix = torch.as_tensor(np.asarray(pixels), dtype=torch.long)
     px_all, py_all = pix % cam.width, pix // cam.width
     outs = {k: [] for k in ("image", "s_rgb", "opacity", "moments", "centre",
-                            "scale", "ambiguous")}
+                            "scale", "ambiguous", "penalty")}
     n_pairs = 0
     with torch.no_grad():
         for _, px, py in _pixel_chunks(cam, px_all, py_all, max_pixels):
@@ -161,6 +165,7 @@ def render_image(scene, cam, opts, pixels: Optional[np.ndarray] = None,
             outs["centre"].append(r.centre)
             outs["scale"].append(r.scale)
             outs["ambiguous"].append(r.ambiguous)
+            outs["penalty"].append(r.penalty)
             n_pairs += r.n_pairs
     res = {k: torch.cat(v).numpy() for k, v in outs.items()}
     res["n_pairs"] = n_pairs
@@ -168,8 +173,10 @@ def render_image(scene, cam, opts, pixels: Optional[np.ndarray] = None,
 
 
 def render_backward(scene, cam, opts, grad_image: np.ndarray,
-                    pixels: Optional[np.ndarray] = None, max_pixels: int = 2048):
-    """Gradient of sum(grad_image * image) with respect to the scene
+                    pixels: Optional[np.ndarray] = None, max_pixels: int = 2048,
+                    grad_penalty: Optional[np.ndarray] = None):
+    """Gradient of sum(grad_image * image) (+ sum(grad_penalty * penalty) when
+    given: the per-pixel consistency penalty of App. E) with respect to the scene
     parameters (means, scales, quats, densities, colors), by float64 autograd
     of the forward pass.  Coverage sets and each pixel's moment variable are
     held fixed (the proxy is not differentiated, and the bounds do not depend
@@ -181,11 +188,14 @@ def render_backward(scene, cam, opts, grad_image: np.ndarray,
     pix = torch.as_tensor(np.asarray(pixels), dtype=torch.long)
     px_all, py_all = pix % cam.width, pix // cam.width
     g_img = torch.as_tensor(np.asarray(grad_image), dtype=DT).reshape(-1, 3)
+    g_pen = None if grad_penalty is None else torch.as_tensor(np.asarray(grad_penalty), dtype=DT).reshape(-1)
     grads = {k: torch.zeros_like(v) for k, v in scene_t.items()}
     image = []
     for s, px, py in _pixel_chunks(cam, px_all, py_all, max_pixels):
         r = render_pixels(scene_t, scene, cam, opts, px, py, proxy=proxy)
         loss = (r.image * g_img[s:s + px.shape[0]]).sum()
+        if g_pen is not None:
+            loss = loss + (r.penalty * g_pen[s:s + px.shape[0]]).sum()
         gs = torch.autograd.grad(loss, [scene_t[k] for k in PARAMS], allow_unused=True)
         for k, g in zip(PARAMS, gs):
             if g is not None:

@@ -755,3 +755,78 @@ def test_render_through_the_surrogate_inputs_reproduces_the_plain_render():
     b = oracle.render_image(sub, cams[0], opts, pixels=pix, tau_model=exact_model(opts.beta, np.inf))
     assert a["n_pairs"] > 500
     assert np.abs(a["image"] - b["image"]).max() < 1e-8
+
+
+# ---------------------------------------------------------------------------
+# Consistency penalty (App. E, regularisation).
+# ---------------------------------------------------------------------------
+
+def test_interval_depth_is_the_integral_of_the_particle_density():
+    from oracle.quadrature import interval_depth
+    rng = np.random.default_rng(21)
+    mu, sig, om = rng.uniform(1, 3, 6), rng.uniform(0.05, 0.5, 6), rng.lognormal(0, 1, 6)
+    t = np.sort(rng.uniform(0.2, 4, (6, 4)), axis=1)
+    got = interval_depth(_t(mu), _t(sig), _t(om), _t(t)).numpy()
+    for i in range(6):
+        f = lambda s: om[i] * math.exp(-0.5 * ((s - mu[i]) / sig[i]) ** 2)
+        for j in range(3):
+            ref = integrate.quad(f, t[i, j], t[i, j + 1], epsabs=1e-14, epsrel=1e-12)[0]
+            assert got[i, j] == pytest.approx(ref, rel=1e-10, abs=1e-14)
+
+
+def test_penalty_vanishes_for_the_exact_optical_depth_and_is_the_square_sum_for_none():
+    """With the exact optical depth of all particles on the ray, the gain over
+    any interval is at least one particle's own depth there: P_i = 0. With a
+    reconstruction that predicts no depth, P_i = sum_j tau_ij^2."""
+    from oracle.quadrature import consistency_penalty, interval_depth
+    rng = np.random.default_rng(22)
+    n, tn = 7, 0.2
+    mu, sig, om = rng.uniform(0.5, 3, n), rng.uniform(0.05, 0.6, n), rng.lognormal(0, 1, n)
+    x = np.array([-1.15, -0.32, 0.32, 1.15])
+    t = np.maximum(mu[:, None] + 3 * sig[:, None] * x[None, :], tn)
+
+    def depth_all(tt):  # exact optical depth of the whole ray from t_n to tt
+        return sum(om[k] * sig[k] * math.sqrt(math.pi / 2)
+                   * (math.erf((tt - mu[k]) / (math.sqrt(2) * sig[k]))
+                      - math.erf((tn - mu[k]) / (math.sqrt(2) * sig[k]))) for k in range(n))
+
+    tau = np.array([[depth_all(v) for v in row] for row in t])
+    p = consistency_penalty(_t(mu), _t(sig), _t(om), _t(tau), _t(t)).numpy()
+    assert np.all(np.abs(p) < 1e-24)
+    p0 = consistency_penalty(_t(mu), _t(sig), _t(om), _t(np.zeros_like(t)), _t(t)).numpy()
+    tij = interval_depth(_t(mu), _t(sig), _t(om), _t(t)).numpy()
+    assert np.allclose(p0, (tij ** 2).sum(1), rtol=1e-14)
+
+
+def test_penalty_gradients_vs_central_differences():
+    """Oracle autograd of a loss with a penalty term against central differences."""
+    scene = _tiny_scene(5, 4)
+    cam = W.camera_on_axis(2.0, 8, 8)
+    opts = W.Options(n_moments=4, full_coverage=True)
+    rng = np.random.default_rng(7)
+    g_img = rng.normal(size=(64, 3))
+    g_pen = rng.uniform(0.5, 1.5, 64)
+    grads = oracle.render_backward(scene, cam, opts, g_img, grad_penalty=g_pen)
+    r0 = oracle.render_image(scene, cam, opts)
+    assert r0["penalty"].max() > 1e-6  # the penalty is active on this scene
+
+    base = {k: np.asarray(getattr(scene, k), np.float64) for k in oracle.render.PARAMS}
+
+    def loss64(params):
+        sc = W.Scene(params["means"], params["scales"], params["quats"], params["densities"],
+                     params["colors"], scene.sh_degree)
+        r = oracle.render_image(sc, cam, opts)
+        return float((r["image"] * g_img).sum() + (r["penalty"] * g_pen).sum())
+
+    for name in ("means", "scales", "quats", "densities"):
+        arr = base[name]
+        for _ in range(3):
+            idx = tuple(rng.integers(0, s) for s in arr.shape)
+            h = 1e-6 * max(1.0, abs(arr[idx]))
+            p = {k: v.copy() for k, v in base.items()}
+            p[name][idx] += h
+            lp = loss64(p)
+            p[name][idx] -= 2 * h
+            lm = loss64(p)
+            fd = (lp - lm) / (2 * h)
+            assert grads[name][idx] == pytest.approx(fd, rel=1e-5, abs=1e-8), name
