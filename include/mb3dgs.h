@@ -119,31 +119,38 @@ int mb_prepare(const mb_gaussians *g, const mb_camera *cams, int32_t n_cams,
 
 /* Forward render (Sec. 3.2-3.3, Eqs. 7, 10-12, 15) after mb_prepare with the
  * same arguments. pws must hold mb_pair_workspace_bytes(n_entries, ...).
- *  image [C,H,W,3]  device, written: the rescaled radiance of Eq. 15
- *  saved [C,H,W,8]  device, written: per-pixel state for the backward pass:
- *                   [0..2] sum_i q_i rgb_i, [3] O = sum_i q_i, [4] depth of the
- *                   moment-variable origin, [5] its warp scale, [6] m_0,
- *                   [7] number of covering Gaussians n, or -(n + 1) when the
- *                   pixel's Hankel matrix was not numerically positive
- *                   definite and a diagonal bias was added. */
+ *  image   [C,H,W,3] device, written: the rescaled radiance of Eq. 15
+ *  saved   [C,H,W,8] device, written: per-pixel state for the backward pass:
+ *                    [0..2] sum_i q_i rgb_i, [3] O = sum_i q_i, [4] depth of the
+ *                    moment-variable origin, [5] its warp scale, [6] m_0,
+ *                    [7] number of covering Gaussians n, or -(n + 1) when the
+ *                    pixel's Hankel matrix was not numerically positive
+ *                    definite and a diagonal bias was added.
+ *  penalty [C,H,W] device or NULL: the consistency penalty of App. E per
+ *                    pixel, sum over covering Gaussians i of
+ *                    P_i = sum_j max(0, tau_ij - (tau(t_{j+1}) - tau(t_j)))^2
+ *                    over the quadrature intervals (tau_ij: particle i's own
+ *                    optical depth over the interval). */
 int mb_render_forward(const mb_gaussians *g, const mb_camera *cams, int32_t n_cams,
                       const mb_options *opts, void *gws, size_t gws_bytes, void *pws,
                       size_t pws_bytes, int64_t n_entries, float *image, float *saved,
-                      void *stream);
+                      float *penalty, void *stream);
 
 /* Backward pass (Sec. 3.3, Eq. 22, App. D adjoint rendering) after
  * mb_render_forward with the same arguments and workspaces. Per-pixel moments
  * are recomputed, not stored.
- *  saved       [C,H,W,8] device, from mb_render_forward
- *  grad_image  [C,H,W,3] device, dL/dimage
+ *  saved         [C,H,W,8] device, from mb_render_forward
+ *  grad_image    [C,H,W,3] device, dL/dimage
+ *  grad_penalty  [C,H,W] device, dL/dpenalty, or NULL (no penalty term)
  *  g_means [n,3], g_scales [n,3], g_quats [n,4], g_densities [n],
  *  g_colors (same shape as colors): device, overwritten with dL/dparameter
  *  summed over all cameras. Culled Gaussians receive zero. */
 int mb_render_backward(const mb_gaussians *g, const mb_camera *cams, int32_t n_cams,
                        const mb_options *opts, void *gws, size_t gws_bytes, void *pws,
                        size_t pws_bytes, int64_t n_entries, const float *saved,
-                       const float *grad_image, float *g_means, float *g_scales,
-                       float *g_quats, float *g_densities, float *g_colors, void *stream);
+                       const float *grad_image, const float *grad_penalty, float *g_means,
+                       float *g_scales, float *g_quats, float *g_densities, float *g_colors,
+                       void *stream);
 
 /* ------------------------------------------------------------------------
  * Learned surrogate of the moment -> optical-depth reconstruction (not part of

@@ -209,14 +209,15 @@ double normal_quantile(double u) {
   return x;
 }
 
-void fill_quantiles(const mb_options* o, float* xq, float* eq) {
+void fill_quantiles(const mb_options* o, float* xq, float* eq, float* ecq) {
   int nq = o->n_intervals + 1;
-  for (int j = 0; j < 8; ++j) { xq[j] = 0.f; eq[j] = 0.f; }
+  for (int j = 0; j < 8; ++j) { xq[j] = 0.f; eq[j] = 0.f; ecq[j] = 0.f; }
   for (int j = 0; j < nq; ++j) {
-    // midpoint reading of "uniformly spaced samples on [0, 1]"
+    // midpoint reading of the uniformly spaced samples of App. B
     double x = normal_quantile((j + 0.5) / nq);
     xq[j] = (float)x;
     eq[j] = (float)std::exp(-0.5 * (double)o->kappa * o->kappa * x * x);
+    ecq[j] = (float)std::erfc((double)o->kappa * x / std::sqrt(2.0));
   }
 }
 
@@ -287,7 +288,7 @@ int forward_setup(const mb_gaussians* g, const mb_camera* cams, int32_t n_cams, 
   ra.image = image; ra.saved = saved;
   ra.tiles_x = tx; ra.tiles_y = ty; ra.n_cams = n_cams; ra.full_coverage = o->full_coverage;
   ra.kappa = o->kappa; ra.beta = o->beta; ra.eps = o->eps;
-  fill_quantiles(o, ra.xq, ra.eq);
+  fill_quantiles(o, ra.xq, ra.eq, ra.ecq);
   return MB_OK;
 }
 
@@ -433,10 +434,11 @@ int mb_prepare(const mb_gaussians* g, const mb_camera* cams, int32_t n_cams, con
 
 int mb_render_forward(const mb_gaussians* g, const mb_camera* cams, int32_t n_cams, const mb_options* o, void* gws,
                       size_t gws_bytes, void* pws, size_t pws_bytes, int64_t n_entries, float* image, float* saved,
-                      void* stream) {
+                      float* penalty, void* stream) {
   FwdSetup f;
   int rc = forward_setup(g, cams, n_cams, o, gws, gws_bytes, pws, pws_bytes, n_entries, image, saved, f);
   if (rc) return rc;
+  f.ra.penalty = penalty;
   hipStream_t s = (hipStream_t)stream;
   rc = build_lists(g, f.w, f.p, n_cams, f.ra.tiles_x, f.ra.tiles_y, o->full_coverage, n_entries, s);
   if (rc) return rc;
@@ -528,8 +530,8 @@ int mb_render_forward_surrogate(const mb_gaussians* g, const mb_camera* cams, in
 
 int mb_render_backward(const mb_gaussians* g, const mb_camera* cams, int32_t n_cams, const mb_options* o, void* gws,
                        size_t gws_bytes, void* pws, size_t pws_bytes, int64_t n_entries, const float* saved,
-                       const float* grad_image, float* g_means, float* g_scales, float* g_quats,
-                       float* g_densities, float* g_colors, void* stream) {
+                       const float* grad_image, const float* grad_penalty, float* g_means, float* g_scales,
+                       float* g_quats, float* g_densities, float* g_colors, void* stream) {
   int rc = check_common(g, cams, n_cams, o);
   if (rc) return rc;
   if (!saved || !grad_image) return fail(MB_ERR_ARG, "null saved state or image gradient");
@@ -552,11 +554,12 @@ int mb_render_backward(const mb_gaussians* g, const mb_camera* cams, int32_t n_c
   ra.masks = p.masks;
   ra.tiles_x = tx; ra.tiles_y = ty; ra.n_cams = n_cams; ra.full_coverage = o->full_coverage;
   ra.kappa = o->kappa; ra.beta = o->beta; ra.eps = o->eps;
-  fill_quantiles(o, ra.xq, ra.eq);
+  fill_quantiles(o, ra.xq, ra.eq, ra.ecq);
   hipError_t e;
   {
     StageTimer t(S_RENDER_BWD, s);
-    e = launch_render_backward(ra, saved, grad_image, p.vals_a, p.partials, cs, o->n_moments, o->n_intervals, s);
+    e = launch_render_backward(ra, saved, grad_image, grad_penalty, p.vals_a, p.partials, cs, o->n_moments,
+                               o->n_intervals, s);
   }
   if (e != hipSuccess) return hip_fail(e, "render_backward");
   GradArgs ga;

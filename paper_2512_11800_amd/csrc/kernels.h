@@ -68,6 +68,8 @@ struct RenderArgs {
   float kappa, beta, eps;
   float xq[8];    // standard-normal edge quantiles
   float eq[8];    // exp(-kappa^2 xq^2 / 2)
+  float ecq[8];   // erfc(kappa xq / sqrt2)
+  float* penalty; // [C,H,W] consistency penalty per pixel, or null
   // surrogate query list (emit / consume variants)
   float* pixfeat;                 // [C,H,W,kPixFeat] per-pixel features, m0, basis, count
   long long* pix_qbase;           // [C,H,W] first query of the pixel, -1 if none
@@ -89,8 +91,8 @@ hipError_t launch_render_forward(const RenderArgs& a, const CamSet& cams, int n_
 hipError_t launch_render_consume(const RenderArgs& a, const CamSet& cams, int n_intervals, hipStream_t s);
 
 hipError_t launch_render_backward(const RenderArgs& r, const float* saved, const float* grad_image,
-                                  const int* sorted_k, float* partials, const CamSet& cams, int n_moments,
-                                  int n_intervals, hipStream_t s);
+                                  const float* grad_penalty, const int* sorted_k, float* partials,
+                                  const CamSet& cams, int n_moments, int n_intervals, hipStream_t s);
 
 struct GradArgs {
   const float *means, *scales, *quats, *dens, *colors;

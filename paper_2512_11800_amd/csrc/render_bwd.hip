@@ -163,6 +163,7 @@ struct BwdArgs {
   RenderArgs r;
   const float* saved;       // [C,H,W,8]
   const float* grad_image;  // [C,H,W,3]
+  const float* grad_penalty;  // [C,H,W] dL/d(consistency penalty), or null
   const int* sorted_k;      // [E] entry index of each sorted list position
   float* partials;          // [E,4,kGradStride]
 };
@@ -306,6 +307,8 @@ __global__ __launch_bounds__(256, (K == 4 && NQ == 4) ? 3 : 2) void k_render_bwd
     gi[1] = ba.grad_image[pix * 3 + 1];
     gi[2] = ba.grad_image[pix * 3 + 2];
   }
+  const bool want_gp = ba.grad_penalty != nullptr;
+  const float gpen = (inside && want_gp) ? ba.grad_penalty[pix] : 0.f;
   const PixelBasis pb = make_basis(sv[4], sv[5], tn);
 
   auto basis_of = [&](int p) __attribute__((always_inline)) {
@@ -452,6 +455,7 @@ __global__ __launch_bounds__(256, (K == 4 && NQ == 4) ? 3 : 2) void k_render_bwd
       const float lamp = from_lane(lam, p), m0p = from_lane(m0, p);
       float gap[3] = {from_lane(ga[0], p), from_lane(ga[1], p), from_lane(ga[2], p)};
       const float gbp = from_lane(gb, p);
+      const float gpp = from_lane(gpen, p);
       float bkp[K + 1];
       bkp[0] = 1.f;
 #pragma unroll
@@ -467,16 +471,46 @@ __global__ __launch_bounds__(256, (K == 4 && NQ == 4) ? 3 : 2) void k_render_bwd
         quad_state<NH, NQ>(g, pp, Lp, m0p, tn, a, s);
         float4 f5 = st.f[5][j];
         float gbar = gap[0] * f5.y + gap[1] * f5.z + gap[2] * f5.w + gbp;
+        // consistency penalty (App. E): dP/dtau at the edges (bq, scaled by the
+        // pixel's dL/dP) and its direct dependence on (mu, Sigma, omega)
+        // through tau_ij = omega Sigma sqrt(pi/2) (erfc(b_j) - erfc(b_{j+1}))
+        float bq[NQ];
+#pragma unroll
+        for (int e = 0; e < NQ; ++e) bq[e] = 0.f;
+        float gmu = 0.f, gsig = 0.f, gom = 0.f;
+        if (want_gp) {
+          bool any_cl = false;
+#pragma unroll
+          for (int e = 0; e < NQ; ++e) any_cl = any_cl || s.cl[e];
+          const float isg = fast_rcp(g.sig);
+          const float bnear = (tn - g.mu) * kInvSqrt2 * isg;
+          const float en = any_cl ? erfc_fast(bnear) : 0.f;
+          const float gn = any_cl ? 1.1283791670955126f * __expf(-bnear * bnear) : 0.f;  // -d erfc / db
+          const float cs = g.omega * g.sig * kSqrtHalfPi;
+#pragma unroll
+          for (int e = 0; e + 1 < NQ; ++e) {
+            const float e0 = s.cl[e] ? en : a.ecq[e], e1 = s.cl[e + 1] ? en : a.ecq[e + 1];
+            const float r = fmaxf(cs * (e0 - e1) - (s.tau[e + 1] - s.tau[e]), 0.f);
+            const float tr = 2.f * r * gpp;
+            bq[e] += tr;
+            bq[e + 1] -= tr;
+            const float ds0 = s.cl[e] ? gn * bnear * isg : 0.f, ds1 = s.cl[e + 1] ? gn * bnear * isg : 0.f;
+            const float dm0 = s.cl[e] ? gn * kInvSqrt2 * isg : 0.f, dm1 = s.cl[e + 1] ? gn * kInvSqrt2 * isg : 0.f;
+            gom += tr * g.sig * kSqrtHalfPi * (e0 - e1);
+            gsig += tr * (g.omega * kSqrtHalfPi * (e0 - e1) + cs * (ds0 - ds1));
+            gmu += tr * cs * (dm0 - dm1);
+          }
+        }
         float d[K + 1];
 #pragma unroll
         for (int k = 0; k <= K; ++k) d[k] = 0.f;
-        // dq / d(mu, Sigma, omega) at fixed moments
-        float dq0 = 0.f, dq1 = 0.f, dq2 = 0.f;
+        // (radiance + penalty) gradient at fixed moments: through tau at the
+        // edges (which move with mu and Sigma) and the Eq. 7 interval terms
 #pragma unroll
         for (int e = 0; e < NQ; ++e) {
           float lamk[2 * NH + 1], dl;
           hermite_adjoint<NH>(s.y[e], s.x[e], s.below[e], a.beta, lamk, dl);
-          float wgt = gbar * s.A[e];
+          float wgt = gbar * s.A[e] + bq[e];
           float lb = 0.f;
 #pragma unroll
           for (int k = 1; k <= K; ++k) {
@@ -487,9 +521,10 @@ __global__ __launch_bounds__(256, (K == 4 && NQ == 4) ? 3 : 2) void k_render_bwd
           float dtau_dt = -m0p * s.w0[e] * dl * warp_dy(pp, s.t[e]);
           float dtdmu = s.cl[e] ? 0.f : 1.f;
           float dtdsig = s.cl[e] ? 0.f : a.kappa * a.xq[e];
-          dq0 += s.A[e] * dtau_dt * dtdmu;
-          dq1 += s.A[e] * dtau_dt * dtdsig;
+          gmu += wgt * dtau_dt * dtdmu;
+          gsig += wgt * dtau_dt * dtdsig;
         }
+        float dq0 = 0.f, dq1 = 0.f, dq2 = 0.f;
 #pragma unroll
         for (int e = 0; e + 1 < NQ; ++e) {
           float cdt = s.T[e] * s.ph[e] * g.omega * s.sr[e];
@@ -507,9 +542,12 @@ __global__ __launch_bounds__(256, (K == 4 && NQ == 4) ? 3 : 2) void k_render_bwd
           }
           dq2 += cs * s.sr[e];
         }
+        gmu += gbar * dq0;
+        gsig += gbar * dq1;
+        gom += gbar * dq2;
 #pragma unroll
         for (int k = 0; k <= K; ++k) res[k * 64 + lane] = d[k];
-        chain_record(gbar * dq0, gbar * dq1, gbar * dq2, g, lamp, dx, dy, st.f[2][j], st.f[3][j], st.f[4][j], gr);
+        chain_record(gmu, gsig, gom, g, lamp, dx, dy, st.f[2][j], st.f[3][j], st.f[4][j], gr);
         gr[G_CR] = s.q * gap[0];
         gr[G_CG] = s.q * gap[1];
         gr[G_CB] = s.q * gap[2];
@@ -598,9 +636,9 @@ __global__ __launch_bounds__(256, (K == 4 && NQ == 4) ? 3 : 2) void k_render_bwd
 }
 
 hipError_t launch_render_backward(const RenderArgs& r, const float* saved, const float* grad_image,
-                                  const int* sorted_k, float* partials, const CamSet& cams, int n_moments,
-                                  int n_intervals, hipStream_t s) {
-  BwdArgs ba{r, saved, grad_image, sorted_k, partials};
+                                  const float* grad_penalty, const int* sorted_k, float* partials,
+                                  const CamSet& cams, int n_moments, int n_intervals, hipStream_t s) {
+  BwdArgs ba{r, saved, grad_image, grad_penalty, sorted_k, partials};
   int n_keys = r.tiles_x * r.tiles_y * r.n_cams;
   dim3 grid(render_blocks(n_keys)), block(kBlock);
 #define MB_LAUNCH(KK, NN)                                                         \

@@ -232,6 +232,30 @@ __device__ __forceinline__ float quad_sum(const RayG& g, float tn, const QEdges<
   return q;
 }
 
+// Consistency penalty of one Gaussian (App. E, regularisation): over each
+// quadrature interval the reconstructed optical depth may not grow by less
+// than the particle's own depth there, tau_ij = omega Sigma sqrt(pi/2)
+// (erfc(b_j) - erfc(b_{j+1})), b = (t - mu) / (sqrt2 Sigma); for an edge left
+// of the near bound b is taken at t_n, otherwise it is kappa x_j / sqrt2.
+// P_i = sum_j max(0, tau_ij - (tau_{j+1} - tau_j))^2.
+template <int NQ>
+__device__ __forceinline__ float pair_penalty(const RayG& g, float tn, const QEdges<NQ>& e, const RenderArgs& a) {
+  bool any_cl = false;
+#pragma unroll
+  for (int j = 0; j < NQ; ++j) any_cl = any_cl || e.cl[j];
+  const float en = any_cl ? erfc_fast((tn - g.mu) * kInvSqrt2 * fast_rcp(g.sig)) : 0.f;
+  const float cs = g.omega * g.sig * kSqrtHalfPi;
+  float pen = 0.f;
+#pragma unroll
+  for (int j = 0; j + 1 < NQ; ++j) {
+    const float e0 = e.cl[j] ? en : a.ecq[j];
+    const float e1 = e.cl[j + 1] ? en : a.ecq[j + 1];
+    const float r = fmaxf(cs * (e0 - e1) - (e.tau[j + 1] - e.tau[j]), 0.f);
+    pen += r * r;
+  }
+  return pen;
+}
+
 // Quadrature of Eq. 7 for one Gaussian against the pixel's moment bounds.
 template <int NH, int NQ>
 __device__ __forceinline__ float particle_quadrature(const RayG& g, const PixelBasis& pb, const LInv<NH>& L,

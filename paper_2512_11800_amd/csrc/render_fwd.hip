@@ -356,7 +356,8 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
   }
 
   // ---- pass 2: quadrature (or the surrogate's query list) -------------------
-  float sr = 0.f, sg = 0.f, sb = 0.f, so = 0.f;
+  float sr = 0.f, sg = 0.f, sb = 0.f, so = 0.f, spen = 0.f;
+  const bool want_pen = a.penalty != nullptr;
   if constexpr (MODE == kModeEmit) {
     int i_pair = 0;
     for (int b = rg.x; b < rg.y; b += kBlock) {
@@ -387,6 +388,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
     return;
   } else {
     float4* cb = reinterpret_cast<float4*>(res);  // [64]
+    float* cpen = res + 256;                       // [64] consistency penalty
     const uint64_t live_mask = __ballot(inside && live);
     // evaluate queue positions [0, n) (one per lane), then add the results of
     // this lane's own positions (bits of `own`) in order
@@ -442,6 +444,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
         }
         float4 f5 = st.f[5][j];
         cb[lane] = make_float4(qv * f5.y, qv * f5.z, qv * f5.w, qv);
+        if (want_pen) cpen[lane] = pair_penalty<NQ>(g, tn, e, a);
       }
       __builtin_amdgcn_wave_barrier();
       while (own) {
@@ -452,6 +455,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
         sg += c4.y;
         sb += c4.z;
         so += c4.w;
+        if (want_pen) spen += cpen[i];
       }
       __builtin_amdgcn_wave_barrier();
     };
@@ -474,18 +478,20 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
 
   if (split) {
     __syncthreads();
-    xch[(wave * 4 + 0) * 64 + lane] = sr;
-    xch[(wave * 4 + 1) * 64 + lane] = sg;
-    xch[(wave * 4 + 2) * 64 + lane] = sb;
-    xch[(wave * 4 + 3) * 64 + lane] = so;
+    xch[(wave * 5 + 0) * 64 + lane] = sr;
+    xch[(wave * 5 + 1) * 64 + lane] = sg;
+    xch[(wave * 5 + 2) * 64 + lane] = sb;
+    xch[(wave * 5 + 3) * 64 + lane] = so;
+    xch[(wave * 5 + 4) * 64 + lane] = spen;
     __syncthreads();
-    sr = sg = sb = so = 0.f;
+    sr = sg = sb = so = spen = 0.f;
 #pragma unroll
     for (int w = 0; w < 4; ++w) {
-      sr += xch[(w * 4 + 0) * 64 + lane];
-      sg += xch[(w * 4 + 1) * 64 + lane];
-      sb += xch[(w * 4 + 2) * 64 + lane];
-      so += xch[(w * 4 + 3) * 64 + lane];
+      sr += xch[(w * 5 + 0) * 64 + lane];
+      sg += xch[(w * 5 + 1) * 64 + lane];
+      sb += xch[(w * 5 + 2) * 64 + lane];
+      so += xch[(w * 5 + 3) * 64 + lane];
+      spen += xch[(w * 5 + 4) * 64 + lane];
     }
     if (wave != 0) return;
   }
@@ -501,6 +507,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
   out[2] = alpha * sb * inv_o + tr * c.bg[2];
   float4* sv = reinterpret_cast<float4*>(a.saved + pix * MB_SAVED_FLOATS_PER_PIXEL);
   sv[0] = make_float4(sr, sg, sb, so);
+  if (want_pen) a.penalty[pix] = spen;
   // covering count; stored as -(count + 1) when the Hankel factor needed a fallback
   sv[1] = make_float4(tc, sd, m0, fallback ? -(float)(n_cov + 1) : (float)n_cov);
 }

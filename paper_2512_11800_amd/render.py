@@ -163,11 +163,16 @@ class _Frame:
                                                    self.height)
 
 
-def render_forward(g: Gaussians, cams: Sequence, opts=None, ws: Optional[Workspace] = None):
-    """mb_prepare + mb_render_forward. Returns (image [C,H,W,3], saved [C,H,W,8], state)."""
+def render_forward(g: Gaussians, cams: Sequence, opts=None, ws: Optional[Workspace] = None,
+                   penalty: bool = False):
+    """mb_prepare + mb_render_forward. Returns (image [C,H,W,3], saved [C,H,W,8],
+    state), and the per-pixel consistency penalty [C,H,W] as a fourth item
+    when ``penalty``."""
     f = _Frame(g, cams, opts, ws)
-    L.check(L.load().mb_render_forward(*f.head(), _ptr(f.image), _ptr(f.saved), _stream()))
-    return f.result()
+    pen = (torch.empty(f.n_cams, f.height, f.width, dtype=torch.float32, device=g.means.device)
+           if penalty else None)
+    L.check(L.load().mb_render_forward(*f.head(), _ptr(f.image), _ptr(f.saved), _ptr(pen), _stream()))
+    return f.result() + ((pen,) if penalty else ())
 
 
 HARVEST_STRIDE = 12
@@ -221,17 +226,21 @@ def render_forward_surrogate(g: Gaussians, cams: Sequence, opts, mlp_packed: tor
 
 
 def render_backward(g: Gaussians, cams: Sequence, opts, state: RenderState, saved: torch.Tensor,
-                    grad_image: torch.Tensor):
-    """mb_render_backward. Returns a dict of gradients shaped like the inputs."""
+                    grad_image: torch.Tensor, grad_penalty: Optional[torch.Tensor] = None):
+    """mb_render_backward. Returns a dict of gradients shaped like the inputs.
+    ``grad_penalty`` [C,H,W] adds the gradient of a loss term on the
+    consistency penalty."""
     lib = L.load()
     cam_arr = _cams(cams)
     o = options_struct(opts)
     grad_image = grad_image.to(torch.float32).contiguous()
+    if grad_penalty is not None:
+        grad_penalty = grad_penalty.to(torch.float32).contiguous()
     out = {k: torch.empty_like(getattr(g, k)) for k in ("means", "scales", "quats", "densities", "colors")}
     ws = state.ws
     L.check(lib.mb_render_backward(ctypes.byref(g.struct()), cam_arr, len(cam_arr), ctypes.byref(o),
                                    _ptr(ws.gws), ws.gws.numel(), _ptr(ws.pws), ws.pws.numel(),
-                                   state.n_entries, _ptr(saved), _ptr(grad_image),
+                                   state.n_entries, _ptr(saved), _ptr(grad_image), _ptr(grad_penalty),
                                    _ptr(out["means"]), _ptr(out["scales"]), _ptr(out["quats"]),
                                    _ptr(out["densities"]), _ptr(out["colors"]), _stream()))
     return out
@@ -239,22 +248,32 @@ def render_backward(g: Gaussians, cams: Sequence, opts, state: RenderState, save
 
 class _MomentRender(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, means, scales, quats, densities, colors, sh_degree, cams, opts):
+    def forward(ctx, means, scales, quats, densities, colors, sh_degree, cams, opts, with_penalty):
         g = Gaussians(means.contiguous(), scales.contiguous(), quats.contiguous(),
                       densities.contiguous(), colors.contiguous(), sh_degree)
-        image, saved, state = render_forward(g, cams, opts)
+        out = render_forward(g, cams, opts, penalty=with_penalty)
+        image, saved, state = out[:3]
         ctx.g, ctx.cams, ctx.opts, ctx.state = g, cams, opts, state
+        ctx.with_penalty = with_penalty
         ctx.save_for_backward(saved)
-        return image
+        return (image, out[3]) if with_penalty else image
 
     @staticmethod
-    def backward(ctx, grad_image):
+    def backward(ctx, grad_image, grad_penalty=None):
         (saved,) = ctx.saved_tensors
-        grads = render_backward(ctx.g, ctx.cams, ctx.opts, ctx.state, saved, grad_image)
+        if grad_image is None:
+            grad_image = torch.zeros(ctx.state.n_cams, ctx.state.height, ctx.state.width, 3,
+                                     dtype=torch.float32, device=saved.device)
+        grads = render_backward(ctx.g, ctx.cams, ctx.opts, ctx.state, saved, grad_image,
+                                grad_penalty if ctx.with_penalty else None)
         return (grads["means"], grads["scales"], grads["quats"], grads["densities"],
-                grads["colors"], None, None, None)
+                grads["colors"], None, None, None, None)
 
 
-def render(means, scales, quats, densities, colors, cams, opts=None, sh_degree: int = -1) -> torch.Tensor:
-    """Differentiable render [C,H,W,3] of the Gaussians from ``cams``."""
-    return _MomentRender.apply(means, scales, quats, densities, colors, sh_degree, list(cams), opts)
+def render(means, scales, quats, densities, colors, cams, opts=None, sh_degree: int = -1,
+           with_penalty: bool = False):
+    """Differentiable render [C,H,W,3] of the Gaussians from ``cams``; with
+    ``with_penalty`` also the per-pixel consistency penalty [C,H,W] (App. E),
+    so a loss can add lambda * mean(penalty)."""
+    return _MomentRender.apply(means, scales, quats, densities, colors, sh_degree, list(cams), opts,
+                               with_penalty)
