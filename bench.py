@@ -62,6 +62,37 @@ def flops_per_pair(k_mom: int, n_int: int) -> dict:
     return out
 
 
+def _kernel_source_sha() -> str:
+    """sha256 over the kernel sources (basename and contents, sorted)."""
+    import glob
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2512_11800_amd", "csrc")
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.h"))):
+        h.update(os.path.basename(p).encode())
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def _measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, calibrated), or None when the kernel sources
+    changed since those counters were taken."""
+    path = os.path.join(ROOT, "profiles", "render_w2_k4_counters.md")
+    if not os.path.exists(path):
+        return None
+    sha, val = None, None
+    with open(path) as f:
+        for line in f:
+            line = line.strip()
+            if line.startswith("source_sha256:"):
+                sha = line.split(":", 1)[1].strip()
+            elif line.startswith(f"traffic_bytes[{kernel}]:"):
+                val = float(line[len(f"traffic_bytes[{kernel}]:"):])
+    return val if sha is not None and sha == _kernel_source_sha() else None
+
+
 def _workload(k_mom: int, name: str = "w2"):
     import workloads as W
     if name == "w5":
@@ -129,19 +160,25 @@ def gpu_bench(args):
     n_fallback = int((c < 0).sum().item())
     fl = flops_per_pair(args.k, opts.n_intervals)
 
-    def roofline(stage, kernel, flops):
+    def roofline(stage, kernel, flops, profiled_name):
         raw = res[last]["stages_raw"][stage]
         kms = raw[0] / max(1, raw[1])
         ach = flops * n_pairs / (kms * 1e-3) / 1e12
+        traffic = None
+        if args.workload == "w2" and args.k == 4:
+            traffic = _measured_traffic(profiled_name)
         return {"bound": "alu", "kernel": kernel, "achieved": ach, "peak": PEAK_FP32_VALU_TFLOPS,
-                "unit": "TFLOP/s", "frac": ach / PEAK_FP32_VALU_TFLOPS, "traffic": None,
+                "unit": "TFLOP/s", "frac": ach / PEAK_FP32_VALU_TFLOPS, "traffic": traffic,
+                "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE)",
                 "flops_per_pair": flops, "pairs_per_launch": n_pairs, "kernel_ms": kms}
 
     last = modes[-1][0]
     out = {"n_pairs": n_pairs, "n_entries": st.n_entries, "n_fallback_pixels": n_fallback, "modes": res}
-    out["roofline_fwd"] = roofline("render_forward", "k_render_fwd", fl["forward"])
+    out["roofline_fwd"] = roofline("render_forward", "k_render_fwd", fl["forward"],
+                                   f"mb::k_render_fwd<{args.k}, {opts.n_intervals + 1}, 0>")
     if last == "fwdbwd":
-        out["roofline_bwd"] = roofline("render_backward", "k_render_bwd", fl["backward"])
+        out["roofline_bwd"] = roofline("render_backward", "k_render_bwd", fl["backward"],
+                                       f"mb::k_render_bwd<{args.k}, {opts.n_intervals + 1}>")
     for r in res.values():
         r.pop("stages_raw")
     return out, scene, cams, opts, n_pairs
