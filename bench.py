@@ -95,6 +95,11 @@ def _measured_traffic(kernel: str):
 
 def _workload(k_mom: int, name: str = "w2"):
     import workloads as W
+    if name == "w3":
+        scene, target, cams, opts = W.w3_train()
+        opts.n_moments = k_mom
+        scene.target = target
+        return scene, cams, opts
     if name == "w5":
         scene, cams, opts = W.w5_large()
         opts.n_moments = k_mom
@@ -122,9 +127,18 @@ def gpu_bench(args):
     def fwd():
         return M.render_forward(g, cams, opts, ws=ws)
 
+    target_img = None
+    if args.workload == "w3":
+        # L1 loss against the render of the perturbed copy (computed once)
+        tg = M.Gaussians.from_scene(scene.target, device="cuda:0")
+        target_img = M.render_forward(tg, cams, opts)[0].clone()
+
     def fwdbwd():
         image, saved, st = M.render_forward(g, cams, opts, ws=ws)
-        M.render_backward(g, cams, opts, st, saved, grad_img)
+        gimg = grad_img
+        if target_img is not None:  # d mean|L - target| / dL
+            gimg = torch.sign(image - target_img) / image.numel()
+        M.render_backward(g, cams, opts, st, saved, gimg)
         return image, saved, st
 
     def timed(step):
@@ -338,8 +352,10 @@ def main():
     ap.add_argument("--train-steps", type=int, default=4000)
     ap.add_argument("--gt-pixels", type=int, default=32)
     ap.add_argument("--k", type=int, default=4, choices=[4, 6])
-    ap.add_argument("--workload", choices=["w2", "w5"], default="w2",
+    ap.add_argument("--workload", choices=["w2", "w3", "w5"], default="w2",
                     help="w2: 500k Gaussians, one 1080p camera (the metric's workload); "
+                         "w3: training step, 1M Gaussians at 1600x1064 with an L1 loss against a "
+                         "render of a perturbed copy; "
                          "w5: 3M Gaussians, 8 cameras at 3840x2160 in one launch sequence")
     ap.add_argument("--cpu-sample-px", type=int, default=12000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -395,10 +411,12 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": (f"500k Gaussians, 64 clusters, SH3, 1920x1080, K={args.k}, N=3, {label}"
-                                if args.workload == "w2" else
-                                f"3M Gaussians, 256 clusters, SH3, 8 cameras 3840x2160 in one launch "
-                                f"sequence, K={args.k}, N=3, {label}"),
+        "config": {"workload": {
+                       "w2": f"500k Gaussians, 64 clusters, SH3, 1920x1080, K={args.k}, N=3, {label}",
+                       "w3": f"training step: 1M Gaussians, 64 clusters, SH3, 1600x1064, L1 loss, "
+                             f"K={args.k}, N=3, {label}",
+                       "w5": f"3M Gaussians, 256 clusters, SH3, 8 cameras 3840x2160 in one launch "
+                             f"sequence, K={args.k}, N=3, {label}"}[args.workload],
                    "n_gaussians": scene.n, "n_cameras": len(cams), "width": cams[0].width,
                    "height": cams[0].height, "n_moments": args.k, "n_intervals": opts.n_intervals,
                    "mode": label},

@@ -216,6 +216,29 @@ int mb_render_forward_surrogate(const mb_gaussians *g, const mb_camera *cams, in
                                 void *qws, size_t qws_bytes, int64_t query_capacity,
                                 float *image, float *saved, void *stream);
 
+/* Backward pass through the surrogate render: the adjoint of
+ * mb_render_forward_surrogate, after it, with the same arguments,
+ * workspaces, weights and query capacity. The MLP is run again on the
+ * forward pass's query list for F and its gradient with respect to the
+ * network inputs (bf16 products, fp32 accumulation); the render adjoint then
+ * follows the optical depth m_0 F back through the standardised moments and
+ * the query (clamped queries pass no gradient to it) to the Gaussians.
+ *  qws    device, mb_query_workspace_bytes_backward(n_cams, width, height,
+ *         query_capacity) bytes (the forward layout is its prefix, so the
+ *         forward call may use the same buffer). Pixels whose queries did not
+ *         fit the capacity in the forward call take no gradient.
+ *  saved, grad_image, g_*: as in mb_render_backward. There is no penalty
+ *  term on this path. */
+size_t mb_query_workspace_bytes_backward(int32_t n_cams, int32_t width, int32_t height,
+                                         int64_t query_capacity);
+int mb_render_backward_surrogate(const mb_gaussians *g, const mb_camera *cams, int32_t n_cams,
+                                 const mb_options *opts, void *gws, size_t gws_bytes, void *pws,
+                                 size_t pws_bytes, int64_t n_entries, const void *mlp_packed,
+                                 void *qws, size_t qws_bytes, int64_t query_capacity,
+                                 const float *saved, const float *grad_image, float *g_means,
+                                 float *g_scales, float *g_quats, float *g_densities,
+                                 float *g_colors, void *stream);
+
 /* Stage timing. While enabled, every entry point records HIP events around
  * each of its stages on its stream (a small per-process overhead).
  * mb_profile_read waits for the recorded events, writes up to `max` stage

@@ -174,13 +174,14 @@ def render_image(scene, cam, opts, pixels: Optional[np.ndarray] = None,
 
 def render_backward(scene, cam, opts, grad_image: np.ndarray,
                     pixels: Optional[np.ndarray] = None, max_pixels: int = 2048,
-                    grad_penalty: Optional[np.ndarray] = None):
+                    grad_penalty: Optional[np.ndarray] = None, tau_model=None):
     """Gradient of sum(grad_image * image) (+ sum(grad_penalty * penalty) when
     given: the per-pixel consistency penalty of App. E) with respect to the scene
     parameters (means, scales, quats, densities, colors), by float64 autograd
     of the forward pass.  Coverage sets and each pixel's moment variable are
     held fixed (the proxy is not differentiated, and the bounds do not depend
-    on the moment variable)."""
+    on the moment variable). ``tau_model`` as in ``render_pixels`` (it must be
+    differentiable in torch)."""
     scene_t = scene_tensors(scene, requires_grad=True)
     proxy = screen_proxy(scene_t, cam, opts.conf_c)
     if pixels is None:
@@ -192,7 +193,7 @@ def render_backward(scene, cam, opts, grad_image: np.ndarray,
     grads = {k: torch.zeros_like(v) for k, v in scene_t.items()}
     image = []
     for s, px, py in _pixel_chunks(cam, px_all, py_all, max_pixels):
-        r = render_pixels(scene_t, scene, cam, opts, px, py, proxy=proxy)
+        r = render_pixels(scene_t, scene, cam, opts, px, py, proxy=proxy, tau_model=tau_model)
         loss = (r.image * g_img[s:s + px.shape[0]]).sum()
         if g_pen is not None:
             loss = loss + (r.penalty * g_pen[s:s + px.shape[0]]).sum()

@@ -121,6 +121,19 @@ def loss_grad(theta, x, t_target, bf16_mode: bool = True):
     return loss, pack(g)
 
 
+def input_grad(theta, x, bf16_mode: bool = True):
+    """F [n] and dF/d(inputs) [n, 7] (6 features, query) by the chain rule
+    through the network; with ``bf16_mode`` the back-propagated dZ2 and dZ1
+    are rounded before their matrix products, as in ``loss_grad``."""
+    f, c = forward(theta, x, bf16_mode)
+    r = bf16 if bf16_mode else (lambda v: np.asarray(v, np.float64))
+    dout = f * (1 - f)
+    dz2 = dout[:, None] * c["w3"][None, :] * gelu_prime(c["z2"])
+    dh1 = r(dz2) @ c["w2"]
+    dz1 = dh1 * gelu_prime(c["z1"])
+    return f, r(dz1) @ c["w1"]
+
+
 def adam(theta, m, v, grad, step, lr, b1=0.9, b2=0.999, eps=1e-8):
     m = b1 * m + (1 - b1) * grad
     v = b2 * v + (1 - b2) * grad * grad
@@ -196,4 +209,86 @@ def exact_model(beta: float, max_z: float = MAX_Z):
         b = np.concatenate([np.ones((x.shape[0], 1)), np.sinh(x[:, :6])], axis=1)
         tau, _, _ = bound_tau(torch.as_tensor(b), torch.as_tensor(x[:, 6]), 3, beta)
         return torch.as_tensor(m[:, 0]) * tau
+    return model
+
+
+# ---------------------------------------------------------------------------
+# Differentiable version (torch float64) for the gradient of a render through
+# the surrogate. The bf16 rounding points of the kernels are kept in the
+# forward values and passed straight through in the derivative (the kernels
+# differentiate the network at its rounded values the same way).
+# ---------------------------------------------------------------------------
+
+def _bf16_t(x):
+    import torch
+    with torch.no_grad():
+        r = torch.as_tensor(bf16(x.detach().numpy()), dtype=torch.float64)
+    return x + (r - x).detach()
+
+
+def forward_torch(theta, x):
+    """F [n] of network inputs x [n, 7] (torch float64, differentiable in x);
+    the same rounding points as `forward` with bf16_mode."""
+    import torch
+    p = {k: torch.as_tensor(v, dtype=torch.float64) for k, v in unpack(theta).items()}
+    hi = _bf16_t(x)  # carries d/dx = 1
+    lo = torch.as_tensor(bf16(x.detach().to(torch.float32).to(torch.float64).numpy() - hi.detach().numpy()),
+                         dtype=torch.float64)
+    xq = hi + lo
+    w1, w2, w3 = (torch.as_tensor(bf16(p[k].numpy()), dtype=torch.float64) for k in ("W1", "W2", "w3"))
+    z1 = xq @ w1.T + p["b1"]
+    t1 = torch.tanh(GELU_C * (z1 + GELU_A * z1 ** 3))
+    h1 = _bf16_t(0.5 * z1 * (1 + t1))
+    z2 = h1 @ w2.T + p["b2"]
+    t2 = torch.tanh(GELU_C * (z2 + GELU_A * z2 ** 3))
+    a2 = 0.5 * z2 * (1 + t2)
+    out = a2 @ w3 + p["b3"][0]
+    return torch.sigmoid(out)
+
+
+def _network_fn(theta, bf16_mode: bool):
+    """F(x) as a torch function of x [n, 7] whose value is ``forward`` and
+    whose derivative is ``input_grad`` (same rounding points)."""
+    import torch
+
+    class _Net(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, x):
+            f, dx = input_grad(theta, x.detach().numpy(), bf16_mode)
+            ctx.save_for_backward(torch.as_tensor(dx, dtype=torch.float64))
+            return torch.as_tensor(f, dtype=torch.float64)
+
+        @staticmethod
+        def backward(ctx, g):
+            (dx,) = ctx.saved_tensors
+            return g[:, None] * dx
+
+    return _Net.apply
+
+
+def tau_model_torch(theta, max_z: float = MAX_Z, network: str = "kernel"):
+    """Differentiable optical depth m_0 F(inputs) through the network: the
+    (mom_q, y) -> tau hook of the oracle renderer, for autograd. ``network``:
+    "kernel" (bf16 rounding points of the kernels, forward and backward),
+    "autograd" (``forward_torch``: rounded values, exact derivative) or
+    "exact" (no rounding anywhere)."""
+    import torch
+    from math import comb as _c
+    if network == "autograd":
+        net = lambda x: forward_torch(theta, x)
+    else:
+        net = _network_fn(theta, network == "kernel")
+
+    def model(mom_q, y):
+        b = mom_q / mom_q[:, :1]
+        mean = b[:, 1]
+        var = b[:, 2] - mean * mean
+        std = torch.sqrt(torch.where(var > 0, var, torch.ones_like(var)))
+        cols = []
+        for k in range(1, 7):
+            ck = sum(_c(k, j) * b[:, j] * (-mean) ** (k - j) for j in range(k + 1))
+            cols.append(torch.asinh(ck / std ** k))
+        z = torch.clamp((y - mean) / std, -max_z, max_z)
+        x = torch.stack(cols + [z], dim=1)
+        return mom_q[:, 0] * net(x)
     return model

@@ -88,6 +88,12 @@ SIGNATURES = [
                                               POINTER(MbOptions), c_void_p, c_size_t, c_void_p,
                                               c_size_t, c_int64, c_void_p, c_void_p, c_size_t,
                                               c_int64, c_void_p, c_void_p, c_void_p]),
+    ("mb_query_workspace_bytes_backward", c_size_t, [c_int32, c_int32, c_int32, c_int64]),
+    ("mb_render_backward_surrogate", c_int32, [POINTER(MbGaussians), POINTER(MbCamera), c_int32,
+                                               POINTER(MbOptions), c_void_p, c_size_t, c_void_p,
+                                               c_size_t, c_int64, c_void_p, c_void_p, c_size_t,
+                                               c_int64, c_void_p, c_void_p, c_void_p, c_void_p,
+                                               c_void_p, c_void_p, c_void_p, c_void_p]),
 ]
 
 

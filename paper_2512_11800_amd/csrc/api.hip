@@ -298,10 +298,13 @@ struct QueryWs {
   long long* pix_qbase;
   float *q_z, *q_f;
   int* q_pix;
+  float* q_g;  // backward only: F and dF/d(inputs) per query, [q][8]
   size_t bytes;
 };
 
-QueryWs carve_queries(void* p, int64_t n_pix, int64_t q_cap) {
+// The forward layout is a prefix of the backward one, so a workspace sized
+// for the backward pass serves both.
+QueryWs carve_queries(void* p, int64_t n_pix, int64_t q_cap, bool grads = false) {
   Carver c(p);
   QueryWs w;
   w.count = c.take<unsigned long long>(1);
@@ -310,6 +313,7 @@ QueryWs carve_queries(void* p, int64_t n_pix, int64_t q_cap) {
   w.q_z = c.take<float>((size_t)q_cap);
   w.q_pix = c.take<int>((size_t)q_cap);
   w.q_f = c.take<float>((size_t)q_cap);
+  w.q_g = grads ? c.take<float>((size_t)q_cap * 8) : nullptr;
   w.bytes = c.off;
   return w;
 }
@@ -483,6 +487,11 @@ size_t mb_query_workspace_bytes(int32_t n_cams, int32_t width, int32_t height, i
   return carve_queries(nullptr, (int64_t)n_cams * width * height, query_capacity).bytes;
 }
 
+size_t mb_query_workspace_bytes_backward(int32_t n_cams, int32_t width, int32_t height, int64_t query_capacity) {
+  if (n_cams < 1 || width <= 0 || height <= 0 || query_capacity < 0) return 0;
+  return carve_queries(nullptr, (int64_t)n_cams * width * height, query_capacity, true).bytes;
+}
+
 int mb_render_forward_surrogate(const mb_gaussians* g, const mb_camera* cams, int32_t n_cams, const mb_options* o,
                                 void* gws, size_t gws_bytes, void* pws, size_t pws_bytes, int64_t n_entries,
                                 const void* mlp_packed, void* qws, size_t qws_bytes, int64_t query_capacity,
@@ -528,25 +537,24 @@ int mb_render_forward_surrogate(const mb_gaussians* g, const mb_camera* cams, in
   return MB_OK;
 }
 
-int mb_render_backward(const mb_gaussians* g, const mb_camera* cams, int32_t n_cams, const mb_options* o, void* gws,
-                       size_t gws_bytes, void* pws, size_t pws_bytes, int64_t n_entries, const float* saved,
-                       const float* grad_image, const float* grad_penalty, float* g_means, float* g_scales,
-                       float* g_quats, float* g_densities, float* g_colors, void* stream) {
-  int rc = check_common(g, cams, n_cams, o);
-  if (rc) return rc;
-  if (!saved || !grad_image) return fail(MB_ERR_ARG, "null saved state or image gradient");
-  if (g->n > 0 && (!g_means || !g_scales || !g_quats || !g_densities || !g_colors))
-    return fail(MB_ERR_ARG, "null gradient output");
-  if (n_entries < 0) return fail(MB_ERR_ARG, "negative n_entries");
+namespace {
+
+// shared by the two backward entry points: checks, the render adjoint
+// (plain, or through the surrogate's query list when q is given), and the
+// per-Gaussian gradient reduction
+int backward_common(const mb_gaussians* g, const mb_camera* cams, int32_t n_cams, const mb_options* o, void* gws,
+                    size_t gws_bytes, void* pws, size_t pws_bytes, int64_t n_entries, const float* saved,
+                    const float* grad_image, const float* grad_penalty, float* g_means, float* g_scales,
+                    float* g_quats, float* g_densities, float* g_colors, hipStream_t s, const void* mlp_packed,
+                    const QueryWs* q, int64_t query_capacity) {
+  int tx = tiles_of(cams[0].width), ty = tiles_of(cams[0].height);
+  int n_keys = tx * ty * n_cams;
   GaussWs w = carve_gauss(gws, g->n, n_cams);
   if (!gws || gws_bytes < w.bytes)
     return fail(MB_ERR_WORKSPACE, "Gaussian workspace needs %zu bytes, got %zu", w.bytes, gws_bytes);
-  int tx = tiles_of(cams[0].width), ty = tiles_of(cams[0].height);
-  int n_keys = tx * ty * n_cams;
   PairWs p = carve_pairs(pws, n_entries, n_keys);
   if (!pws || pws_bytes < p.bytes)
     return fail(MB_ERR_WORKSPACE, "pair workspace needs %zu bytes, got %zu", p.bytes, pws_bytes);
-  hipStream_t s = (hipStream_t)stream;
   CamSet cs = make_cams(cams, n_cams);
   RenderArgs ra;
   memset(&ra, 0, sizeof(ra));
@@ -556,10 +564,25 @@ int mb_render_backward(const mb_gaussians* g, const mb_camera* cams, int32_t n_c
   ra.kappa = o->kappa; ra.beta = o->beta; ra.eps = o->eps;
   fill_quantiles(o, ra.xq, ra.eq, ra.ecq);
   hipError_t e;
+  if (q) {
+    int64_t n_pix = (int64_t)n_cams * cams[0].width * cams[0].height;
+    {
+      StageTimer t(S_MLP, s);
+      e = launch_mlp_input_grad_gather(mlp_packed, q->pixfeat, n_pix, q->q_pix, q->q_z, q->count, query_capacity,
+                                       q->q_g, s);
+    }
+    if (e != hipSuccess) return hip_fail(e, "surrogate input gradients");
+    ra.pixfeat = q->pixfeat;
+    ra.pix_qbase = q->pix_qbase;
+    ra.q_count = q->count;
+    ra.q_cap = query_capacity;
+    ra.q_f = q->q_f;
+    ra.q_g = q->q_g;
+  }
   {
     StageTimer t(S_RENDER_BWD, s);
     e = launch_render_backward(ra, saved, grad_image, grad_penalty, p.vals_a, p.partials, cs, o->n_moments,
-                               o->n_intervals, s);
+                               o->n_intervals, s, q != nullptr);
   }
   if (e != hipSuccess) return hip_fail(e, "render_backward");
   GradArgs ga;
@@ -574,6 +597,52 @@ int mb_render_backward(const mb_gaussians* g, const mb_camera* cams, int32_t n_c
   }
   if (e != hipSuccess) return hip_fail(e, "gradients");
   return MB_OK;
+}
+
+int check_backward_args(const mb_gaussians* g, const mb_camera* cams, int32_t n_cams, const mb_options* o,
+                        int64_t n_entries, const float* saved, const float* grad_image, float* g_means,
+                        float* g_scales, float* g_quats, float* g_densities, float* g_colors) {
+  int rc = check_common(g, cams, n_cams, o);
+  if (rc) return rc;
+  if (!saved || !grad_image) return fail(MB_ERR_ARG, "null saved state or image gradient");
+  if (g->n > 0 && (!g_means || !g_scales || !g_quats || !g_densities || !g_colors))
+    return fail(MB_ERR_ARG, "null gradient output");
+  if (n_entries < 0) return fail(MB_ERR_ARG, "negative n_entries");
+  return MB_OK;
+}
+
+}  // namespace
+
+int mb_render_backward(const mb_gaussians* g, const mb_camera* cams, int32_t n_cams, const mb_options* o, void* gws,
+                       size_t gws_bytes, void* pws, size_t pws_bytes, int64_t n_entries, const float* saved,
+                       const float* grad_image, const float* grad_penalty, float* g_means, float* g_scales,
+                       float* g_quats, float* g_densities, float* g_colors, void* stream) {
+  int rc = check_backward_args(g, cams, n_cams, o, n_entries, saved, grad_image, g_means, g_scales, g_quats,
+                               g_densities, g_colors);
+  if (rc) return rc;
+  return backward_common(g, cams, n_cams, o, gws, gws_bytes, pws, pws_bytes, n_entries, saved, grad_image,
+                         grad_penalty, g_means, g_scales, g_quats, g_densities, g_colors, (hipStream_t)stream,
+                         nullptr, nullptr, 0);
+}
+
+int mb_render_backward_surrogate(const mb_gaussians* g, const mb_camera* cams, int32_t n_cams, const mb_options* o,
+                                 void* gws, size_t gws_bytes, void* pws, size_t pws_bytes, int64_t n_entries,
+                                 const void* mlp_packed, void* qws, size_t qws_bytes, int64_t query_capacity,
+                                 const float* saved, const float* grad_image, float* g_means, float* g_scales,
+                                 float* g_quats, float* g_densities, float* g_colors, void* stream) {
+  int rc = check_backward_args(g, cams, n_cams, o, n_entries, saved, grad_image, g_means, g_scales, g_quats,
+                               g_densities, g_colors);
+  if (rc) return rc;
+  if (o->n_moments != 6) return fail(MB_ERR_ARG, "the surrogate takes n_moments = 6");
+  if (!mlp_packed) return fail(MB_ERR_ARG, "null surrogate weights");
+  if (query_capacity < 0) return fail(MB_ERR_ARG, "negative query capacity");
+  int64_t n_pix = (int64_t)n_cams * cams[0].width * cams[0].height;
+  QueryWs q = carve_queries(qws, n_pix, query_capacity, true);
+  if (!qws || qws_bytes < q.bytes)
+    return fail(MB_ERR_WORKSPACE, "query workspace needs %zu bytes, got %zu", q.bytes, qws_bytes);
+  return backward_common(g, cams, n_cams, o, gws, gws_bytes, pws, pws_bytes, n_entries, saved, grad_image,
+                         nullptr, g_means, g_scales, g_quats, g_densities, g_colors, (hipStream_t)stream,
+                         mlp_packed, &q, query_capacity);
 }
 
 // ---------------------------------------------------------------------------

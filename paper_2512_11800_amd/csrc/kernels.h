@@ -78,6 +78,7 @@ struct RenderArgs {
   float* q_z;                     // [q_cap] standardised query
   int* q_pix;                     // [q_cap] flat pixel index
   const float* q_f;               // [q_cap] surrogate output F
+  const float* q_g;               // [q_cap][8] F and dF/d(inputs) (backward through the surrogate)
   // training-sample harvest (harvest variant)
   float* harvest;                 // [harvest_cap, kHarvestStride]
   int* harvest_count;
@@ -92,7 +93,8 @@ hipError_t launch_render_consume(const RenderArgs& a, const CamSet& cams, int n_
 
 hipError_t launch_render_backward(const RenderArgs& r, const float* saved, const float* grad_image,
                                   const float* grad_penalty, const int* sorted_k, float* partials,
-                                  const CamSet& cams, int n_moments, int n_intervals, hipStream_t s);
+                                  const CamSet& cams, int n_moments, int n_intervals, hipStream_t s,
+                                  bool surrogate = false);
 
 struct GradArgs {
   const float *means, *scales, *quats, *dens, *colors;
@@ -115,6 +117,10 @@ hipError_t launch_mlp_forward(const void* packed, const float* x, int64_t n, flo
 hipError_t launch_mlp_forward_gather(const void* packed, const float* pixfeat, int64_t n_pix, const int* q_pix,
                                      const float* q_z, const unsigned long long* q_count, int64_t q_cap, float* f,
                                      hipStream_t s);
+// F and dF/dinputs [q][8] for the render's query list (backward through the surrogate)
+hipError_t launch_mlp_input_grad_gather(const void* packed, const float* pixfeat, int64_t n_pix, const int* q_pix,
+                                        const float* q_z, const unsigned long long* q_count, int64_t q_cap,
+                                        float* out_g, hipStream_t s);
 hipError_t launch_mlp_loss_grad(const void* packed, const float* x, const float* t, int64_t n, float* grad,
                                 float* loss, float* ws, hipStream_t s);
 hipError_t launch_adam(float* th, float* m, float* v, const float* g, int64_t count, int step, float lr, float b1,

@@ -49,6 +49,7 @@ struct MlpPacked {
   float b1[kH], b2[kH];
   float b3;
   float pad[63];
+  float w1f[kIn][kH];         // bf16-rounded W1 as fp32, [k][n] (input gradient)
 };
 static_assert(sizeof(MlpPacked) % 16 == 0, "packed weights must be 16-byte sized");
 
@@ -112,6 +113,10 @@ __global__ __launch_bounds__(256) void k_mlp_pack(const float* th, MlpPacked* p)
   }
   if (threadIdx.x == 0) p->b3 = th[O_B3];
   for (int i = threadIdx.x; i < 63; i += blockDim.x) p->pad[i] = 0.f;
+  for (int i = threadIdx.x; i < kH * kIn; i += blockDim.x) {
+    int n = i / kIn, k = i % kIn;
+    p->w1f[k][n] = bf16_float(bf16_bits(th[O_W1 + i]));
+  }
 }
 
 // LDS working sets of one wave. The layer-3 row sums reuse the H1 (or dZ2)
@@ -300,6 +305,127 @@ __global__ __launch_bounds__(256) void k_mlp_forward_gather(const MlpPacked* gp,
     f32x16 z1[2][2], z2[2][2];
     float out = mlp_forward_wave(w, P, lane, z1, z2);
     if (valid) f_out[q] = sigmoid(out);
+  }
+}
+
+// F and its gradient dF/dx with respect to the 7 inputs for every query of
+// the render's list (for the backward pass through the surrogate): the
+// forward pass as above, then dZ2 = F (1 - F) w3 GELU'(Z2) (bf16) on the
+// matrix cores against W2, dZ1 = dH1 GELU'(Z1) (bf16, staged by rows) and
+// dx = dZ1 W1 on the vector unit. Two waves per workgroup; the H1 storage is
+// reused for dZ2 and then dZ1. out: [cap][8] = F, dF/dx_0..6.
+struct GradInLds {
+  uint16_t x[64][kXStride];
+  union {
+    uint16_t h1[64][kH + 8];
+    float s[64][33];
+    uint16_t dz[64][kH + 8];
+  };
+  float dout[64];
+};
+
+__global__ __launch_bounds__(128) void k_mlp_input_grad_gather(const MlpPacked* gp, const float* pixfeat,
+                                                               const int* q_pix, const float* q_z,
+                                                               const unsigned long long* q_count, int64_t q_cap,
+                                                               int64_t n_pix, float* out_g) {
+  __shared__ MlpPacked P;
+  __shared__ GradInLds ws[2];
+  const unsigned long long cnt = *q_count;
+  const int64_t n = cnt < (unsigned long long)q_cap ? (int64_t)cnt : q_cap;
+  if (n == 0) return;
+  {
+    const float4* src = reinterpret_cast<const float4*>(gp);
+    float4* dst = reinterpret_cast<float4*>(&P);
+    for (int i = threadIdx.x; i < (int)(sizeof(MlpPacked) / 16); i += blockDim.x) dst[i] = src[i];
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lr = lane & 31, hk = 8 * (lane >> 5);
+  GradInLds& w = ws[wave];
+  const int64_t chunks = (n + 63) / 64;
+  const int64_t per_block = ((chunks + gridDim.x - 1) / gridDim.x + 1) / 2 * 2;
+  for (int64_t it = 0; it < per_block; it += 2) {
+    int64_t q = ((int64_t)blockIdx.x * per_block + it + wave) * 64 + lane;
+    bool valid = q < n;
+    float v[kIn];
+    int64_t p = valid ? (int64_t)q_pix[q] : 0;
+    p = (p >= 0 && p < n_pix) ? p : 0;
+    const float* pf = pixfeat + (size_t)p * kPixFeat;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) v[k] = valid ? pf[k] : 0.f;
+    v[6] = valid ? q_z[q] : 0.f;
+    stage_inputs(w, v, lane);
+    __syncthreads();
+    f32x16 z1[2][2], z2[2][2];
+    float out = mlp_forward_wave(w, P, lane, z1, z2);
+    const float f = sigmoid(out);
+    w.dout[lane] = f * (1.f - f);
+    __syncthreads();
+    // dZ2 = dF/dout w3 GELU'(Z2), bf16, rows [q][n]
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < 2; ++nt) {
+        int n2 = 32 * nt + lr;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          int qq = 32 * mt + c_row(r, lane);
+          float d;
+          gelu_d(z2[mt][nt][r], d);
+          w.dz[qq][n2] = bf16_bits(w.dout[qq] * P.w3[n2] * d);
+        }
+      }
+    __syncthreads();
+    // dH1 = dZ2 W2
+    f32x16 dh1[2][2];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < 2; ++nt) {
+        f32x16 acc = {};
+#pragma unroll
+        for (int kt = 0; kt < 4; ++kt)
+          acc = mfma(lds_bf16x8(&w.dz[32 * mt + lr][16 * kt + hk]), lds_bf16x8(&P.w2t[32 * nt + lr][16 * kt + hk]),
+                     acc);
+        dh1[mt][nt] = acc;
+      }
+    __syncthreads();
+    // dZ1 = dH1 GELU'(Z1), bf16, rows [q][n]
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < 2; ++nt) {
+        int n1 = 32 * nt + lr;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          int qq = 32 * mt + c_row(r, lane);
+          float d;
+          gelu_d(z1[mt][nt][r], d);
+          w.dz[qq][n1] = bf16_bits(dh1[mt][nt][r] * d);
+        }
+      }
+    __syncthreads();
+    // dx_k = sum_n dZ1[q][n] W1[n][k] for this lane's query
+    float g[kIn];
+#pragma unroll
+    for (int k = 0; k < kIn; ++k) g[k] = 0.f;
+#pragma unroll
+    for (int n8 = 0; n8 < kH; n8 += 8) {
+      bf16x8 row = lds_bf16x8(&w.dz[lane][n8]);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const float dzv = (float)row[e];
+#pragma unroll
+        for (int k = 0; k < kIn; ++k) g[k] += dzv * P.w1f[k][n8 + e];
+      }
+    }
+    if (valid) {
+      float* o = out_g + q * 8;
+      o[0] = f;
+#pragma unroll
+      for (int k = 0; k < kIn; ++k) o[1 + k] = g[k];
+    }
+    __syncthreads();
   }
 }
 
@@ -520,6 +646,15 @@ hipError_t launch_mlp_forward_gather(const void* packed, const float* pixfeat, i
   if (q_cap <= 0 || n_pix <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_mlp_forward_gather, dim3(mlp_grid(q_cap, 4)), dim3(256), 0, s, (const MlpPacked*)packed,
                      pixfeat, q_pix, q_z, q_count, q_cap, n_pix, f);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_input_grad_gather(const void* packed, const float* pixfeat, int64_t n_pix, const int* q_pix,
+                                        const float* q_z, const unsigned long long* q_count, int64_t q_cap,
+                                        float* out_g, hipStream_t s) {
+  if (q_cap <= 0 || n_pix <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mlp_input_grad_gather, dim3(mlp_grid(q_cap, 2)), dim3(128), 0, s, (const MlpPacked*)packed,
+                     pixfeat, q_pix, q_z, q_count, q_cap, n_pix, out_g);
   return hipGetLastError();
 }
 

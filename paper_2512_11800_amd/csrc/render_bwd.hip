@@ -48,9 +48,10 @@ __device__ __forceinline__ float dphi_fn(float x) {
   return fabsf(x) < 0.5f ? s : d;
 }
 
+// Edges of one Gaussian's quadrature (App. B) and sigma_i there.
 template <int NH, int NQ>
-__device__ __forceinline__ void quad_state(const RayG& g, const PixelBasis& pb, const LInv<NH>& L, float m0,
-                                           float tn, const RenderArgs& a, QuadState<NH, NQ>& s) {
+__device__ __forceinline__ void quad_geom(const RayG& g, const PixelBasis& pb, float tn, const RenderArgs& a,
+                                          QuadState<NH, NQ>& s) {
   float dtc = g.mu - pb.tc;
 #pragma unroll
   for (int j = 0; j < NQ; ++j) {
@@ -60,12 +61,17 @@ __device__ __forceinline__ void quad_state(const RayG& g, const PixelBasis& pb, 
     float dtj = s.cl[j] ? (tn - pb.tc) : (dtc + s.off[j]);
     s.t[j] = s.cl[j] ? tn : t;
     s.y[j] = warp_y(pb, s.t[j], dtj);
-    s.F[j] = canon_at<NH>(L, s.y[j], a.beta, s.x[j], s.below[j], s.w0[j]);
-    s.tau[j] = m0 * s.F[j];
-    s.T[j] = __expf(-s.tau[j]);
     float r = (s.t[j] - g.mu) * fast_rcp(g.sig);
     s.sr[j] = s.cl[j] ? __expf(-0.5f * r * r) : a.eq[j];
   }
+}
+
+// Given the optical depth s.tau at the edges: the Eq. 7 terms, q, and
+// A[j] = dq / dtau_j.
+template <int NH, int NQ>
+__device__ __forceinline__ void quad_terms(const RayG& g, float tn, QuadState<NH, NQ>& s) {
+#pragma unroll
+  for (int j = 0; j < NQ; ++j) s.T[j] = __expf(-s.tau[j]);
   s.q = 0.f;
 #pragma unroll
   for (int j = 0; j < NQ; ++j) s.A[j] = 0.f;
@@ -80,6 +86,66 @@ __device__ __forceinline__ void quad_state(const RayG& g, const PixelBasis& pb, 
     // dq/dtau_j and dq/dtau_{j+1} of this interval's term
     s.A[j] -= tds * (s.ph[j] + s.dph[j]);
     s.A[j + 1] += tds * s.dph[j];
+  }
+}
+
+template <int NH, int NQ>
+__device__ __forceinline__ void quad_state(const RayG& g, const PixelBasis& pb, const LInv<NH>& L, float m0,
+                                           float tn, const RenderArgs& a, QuadState<NH, NQ>& s) {
+  quad_geom<NH, NQ>(g, pb, tn, a, s);
+#pragma unroll
+  for (int j = 0; j < NQ; ++j) {
+    s.F[j] = canon_at<NH>(L, s.y[j], a.beta, s.x[j], s.below[j], s.w0[j]);
+    s.tau[j] = m0 * s.F[j];
+  }
+  quad_terms<NH, NQ>(g, tn, s);
+}
+
+// Double-precision dual number (one tangent) for the Jacobian of the
+// surrogate's inputs with respect to the pixel's moments.
+struct DualD {
+  double v, d;
+  __device__ DualD(double a = 0.0, double b = 0.0) : v(a), d(b) {}
+};
+__device__ __forceinline__ DualD operator+(DualD a, DualD b) { return DualD(a.v + b.v, a.d + b.d); }
+__device__ __forceinline__ DualD operator-(DualD a, DualD b) { return DualD(a.v - b.v, a.d - b.d); }
+__device__ __forceinline__ DualD operator*(DualD a, DualD b) { return DualD(a.v * b.v, a.d * b.v + a.v * b.d); }
+__device__ __forceinline__ DualD operator/(DualD a, DualD b) {
+  double r = a.v / b.v;
+  return DualD(r, (a.d - r * b.d) / b.v);
+}
+
+// Surrogate inputs as functions of the pixel's moments m_0..m_6, as in the
+// forward pass: asinh of the standardised moments 1..6 of b = m / m_0, and
+// the standardisation (mean mu, standard deviation sig) of the moment variable.
+__device__ __forceinline__ void feat_from_moments(const DualD* m, DualD* feat, DualD& mu, DualD& sig) {
+  DualD b[7];
+  b[0] = DualD(1.0);
+#pragma unroll
+  for (int k = 1; k <= 6; ++k) b[k] = m[k] / m[0];
+  mu = b[1];
+  DualD var = b[2] - mu * mu;
+  if (var.v > 0.0) {
+    const double sq = sqrt(var.v);
+    sig = DualD(sq, 0.5 * var.d / sq);
+  } else {
+    sig = DualD(1.0);
+  }
+  const DualD is = DualD(1.0) / sig;
+  DualD sk(1.0);
+#pragma unroll
+  for (int k = 1; k <= 6; ++k) {
+    DualD c(0.0), pw(1.0);
+    double binom = 1.0;
+#pragma unroll
+    for (int j = k; j >= 0; --j) {
+      c = c + DualD(binom) * b[j] * pw;
+      binom = binom * (double)j / (double)(k - j + 1);
+      pw = pw * (DualD(0.0) - mu);
+    }
+    sk = sk * is;
+    const DualD u = c * sk;
+    feat[k - 1] = DualD(asinh(u.v), u.d / sqrt(1.0 + u.v * u.v));
   }
 }
 
@@ -258,15 +324,20 @@ __device__ __forceinline__ void reduce_to_slots(float* gr, bool act, int j, int 
   carry_j = (jl == cont_j) ? cont_j : -1;
 }
 
-template <int K, int NQ>
+// SUR: the backward pass through the learned surrogate (the forward pass was
+// mb_render_forward_surrogate): the optical depth at every edge is m_0 F with
+// F and dF/d(inputs) from the query list, and the adjoint reaches the moments
+// through the surrogate's inputs instead of the moment bounds.
+template <int K, int NQ, int SUR>
 __global__ __launch_bounds__(256, (K == 4 && NQ == 4) ? 3 : 2) void k_render_bwd(BwdArgs ba, CamSet cams) {
   constexpr int NH = K / 2;
   constexpr int NL = (NH + 1) * (NH + 2) / 2;
+  constexpr int NRES = SUR ? 9 : K + 1;  // results per queued pair
   const RenderArgs& a = ba.r;
   __shared__ Stage st;
   __shared__ int sk[kBlock];
   __shared__ WaveQueue wq[4];
-  __shared__ __align__(16) float wres[4][(K + 1) * 64];  // per queued pair results
+  __shared__ __align__(16) float wres[4][NRES * 64];     // per queued pair results
   __shared__ float carry[4][G_COUNT];                    // partial slot of an entry split over evaluations
   const int tiles_per_cam = a.tiles_x * a.tiles_y;
   const int n_keys = tiles_per_cam * a.n_cams;
@@ -400,7 +471,7 @@ __global__ __launch_bounds__(256, (K == 4 && NQ == 4) ? 3 : 2) void k_render_bwd
   LInv<NH> L;
   float bk[K + 1];
   bk[0] = 1.f;
-  if (live) {
+  if (live && !SUR) {
     double bn[K + 1];
     bn[0] = 1.0;
 #pragma unroll
@@ -442,6 +513,145 @@ __global__ __launch_bounds__(256, (K == 4 && NQ == 4) ? 3 : 2) void k_render_bwd
   float dm[K + 1];
 #pragma unroll
   for (int k = 0; k <= K; ++k) dm[k] = 0.f;
+  if constexpr (SUR) {
+    static_assert(K == 6, "the surrogate takes six moments");
+    // the forward pass's standardisation of the moment variable
+    float smu = 0.f, ssig = 1.f;
+    if (live) {
+      const double mb = acc[1] / acc[0];
+      const double var = acc[2] / acc[0] - mb * mb;
+      smu = (float)mb;
+      ssig = (float)(var > 0.0 ? sqrt(var) : 1.0);
+    }
+    // a pixel the forward pass left without queries (its list overflowed)
+    // rendered as empty there and takes no gradient here
+    const long long qb = active ? a.pix_qbase[pix] : -1;
+    const uint64_t sur_mask = __ballot(qb >= 0);
+    float dm0s = 0.f, dmus = 0.f, dsigs = 0.f, dfeat[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    uint32_t my_rank = 0;
+    int carry_j = -1;
+    auto flush = [&](int n, uint64_t own, int cont_j) __attribute__((always_inline)) {
+      int j, p;
+      const bool act = item_of(n, j, p);
+      const PixelBasis pp = basis_of(p);
+      const float lamp = from_lane(lam, p), m0p = from_lane(m0, p);
+      float gap[3] = {from_lane(ga[0], p), from_lane(ga[1], p), from_lane(ga[2], p)};
+      const float gbp = from_lane(gb, p);
+      const float smup = from_lane(smu, p), ssigp = from_lane(ssig, p);
+      const uint32_t qlo = (uint32_t)__shfl((int)(uint32_t)(qb & 0xffffffffll), p, 64);
+      const uint32_t qhi = (uint32_t)__shfl((int)(uint32_t)((unsigned long long)qb >> 32), p, 64);
+      const long long qbase_p = (long long)(((unsigned long long)qhi << 32) | qlo);
+      float gr[G_COUNT];
+#pragma unroll
+      for (int f = 0; f < G_COUNT; ++f) gr[f] = 0.f;
+      if (act) {
+        const uint32_t rank = q.rank[lane];
+        float dx, dy;
+        offsets_of(j, p, dx, dy);
+        RayG g = ray_params(st, j, dx, dy, lamp);
+        QuadState<NH, NQ> s;
+        quad_geom<NH, NQ>(g, pp, tn, a, s);
+        // F as the forward pass used it; its input gradient beside it
+        const long long qi = qbase_p + (long long)rank * NQ;
+        const float* qg = a.q_g + qi * 8;
+#pragma unroll
+        for (int e = 0; e < NQ; ++e) {
+          s.F[e] = a.q_f[qi + e];
+          s.tau[e] = m0p * s.F[e];
+        }
+        quad_terms<NH, NQ>(g, tn, s);
+        float4 f5 = st.f[5][j];
+        const float gbar = gap[0] * f5.y + gap[1] * f5.z + gap[2] * f5.w + gbp;
+        float c[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        float gmu = 0.f, gsig = 0.f, gom = 0.f;
+        const float isg = fast_rcp(ssigp);
+#pragma unroll
+        for (int e = 0; e < NQ; ++e) {
+          const float* ge = qg + e * 8;
+          const float wgt = gbar * s.A[e];
+          c[0] += wgt * s.F[e];  // tau = m_0 F at fixed inputs
+#pragma unroll
+          for (int k = 0; k < 6; ++k) c[1 + k] += wgt * m0p * ge[1 + k];
+          const float zr = (s.y[e] - smup) / ssigp;
+          const float gz = fabsf(zr) < 10.f ? wgt * m0p * ge[7] * isg : 0.f;  // dL/dy at the edge
+          c[7] -= gz;       // z = (y - mu) / sig
+          c[8] -= gz * zr;
+          const float dydt = warp_dy(pp, s.t[e]);
+          gmu += gz * dydt * (s.cl[e] ? 0.f : 1.f);
+          gsig += gz * dydt * (s.cl[e] ? 0.f : a.kappa * a.xq[e]);
+        }
+        float dq0 = 0.f, dq1 = 0.f, dq2 = 0.f;
+#pragma unroll
+        for (int e = 0; e + 1 < NQ; ++e) {
+          float cdt = s.T[e] * s.ph[e] * g.omega * s.sr[e];
+          float dmu0 = s.cl[e] ? 0.f : 1.f, dmu1 = s.cl[e + 1] ? 0.f : 1.f;
+          float dsg0 = s.cl[e] ? 0.f : a.kappa * a.xq[e], dsg1 = s.cl[e + 1] ? 0.f : a.kappa * a.xq[e + 1];
+          dq0 += cdt * (dmu1 - dmu0);
+          dq1 += cdt * (dsg1 - dsg0);
+          float cs = s.T[e] * s.dt[e] * s.ph[e];
+          if (s.cl[e]) {
+            float r = (s.t[e] - g.mu) * fast_rcp(g.sig);
+            float sj = g.omega * s.sr[e];
+            const float igs = fast_rcp(g.sig);
+            dq0 += cs * sj * r * igs;
+            dq1 += cs * sj * r * r * igs;
+          }
+          dq2 += cs * s.sr[e];
+        }
+        gmu += gbar * dq0;
+        gsig += gbar * dq1;
+        gom += gbar * dq2;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) res[k * 64 + lane] = c[k];
+        chain_record(gmu, gsig, gom, g, lamp, dx, dy, st.f[2][j], st.f[3][j], st.f[4][j], gr);
+        gr[G_CR] = s.q * gap[0];
+        gr[G_CG] = s.q * gap[1];
+        gr[G_CB] = s.q * gap[2];
+      }
+      __builtin_amdgcn_wave_barrier();
+      while (own) {
+        const int i = __builtin_ctzll(own);
+        own &= own - 1;
+        dm0s += res[i];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) dfeat[k] += res[(1 + k) * 64 + i];
+        dmus += res[7 * 64 + i];
+        dsigs += res[8 * 64 + i];
+      }
+      reduce_to_slots<false>(gr, act, j, n, lane, cont_j, carry_j, cw, ba.partials, sk, quad);
+    };
+    for (int b = rg.x; b < rg.y; b += kBlock) {
+      int nb = min(kBlock, rg.y - b);
+      stage(b, nb, true);
+      QueueCursor qc;
+      queue_reset(qc);
+      carry_j = -1;
+      queue_from_masks(q, qc, a.masks, b, nb, quad, own4, lane, sur_mask,
+                       [&]() __attribute__((always_inline)) {
+                         const int cont_j = qc.cnt > 64 ? (int)(q.item[64] >> 6) : -1;
+                         flush(64, qc.own_lo, cont_j);
+                         queue_pop64(q, qc, lane);
+                       },
+                       zero_slot, &my_rank);
+      if (qc.cnt > 0) flush(qc.cnt, qc.own_lo, -1);
+    }
+    // the moment adjoint through the surrogate's inputs (forward-mode Jacobian
+    // of the standardised features in double, one moment at a time)
+    if (active) {
+#pragma unroll 1
+      for (int i = 0; i <= 6; ++i) {
+        DualD md[7], feat[6], mu, sg;
+#pragma unroll
+        for (int k = 0; k <= 6; ++k) md[k] = DualD(acc[k], k == i ? 1.0 : 0.0);
+        feat_from_moments(md, feat, mu, sg);
+        double d = (i == 0 ? (double)dm0s : 0.0) + (double)dmus * mu.d + (double)dsigs * sg.d;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) d += (double)dfeat[k] * feat[k].d;
+        dm[i] = (float)d;
+      }
+      if (own4 <= 0) dm[0] += e0;
+    }
+  } else {
   dm[0] = (active && own4 <= 0) ? e0 : 0.f;  // a split block adds e0 once (wave 0)
   {
     int carry_j = -1;
@@ -578,6 +788,7 @@ __global__ __launch_bounds__(256, (K == 4 && NQ == 4) ? 3 : 2) void k_render_bwd
     }
   }
 
+  }
   if (split) {
     float* xf = reinterpret_cast<float*>(&st);
     __syncthreads();
@@ -637,19 +848,22 @@ __global__ __launch_bounds__(256, (K == 4 && NQ == 4) ? 3 : 2) void k_render_bwd
 
 hipError_t launch_render_backward(const RenderArgs& r, const float* saved, const float* grad_image,
                                   const float* grad_penalty, const int* sorted_k, float* partials,
-                                  const CamSet& cams, int n_moments, int n_intervals, hipStream_t s) {
+                                  const CamSet& cams, int n_moments, int n_intervals, hipStream_t s,
+                                  bool surrogate) {
   BwdArgs ba{r, saved, grad_image, grad_penalty, sorted_k, partials};
   int n_keys = r.tiles_x * r.tiles_y * r.n_cams;
   dim3 grid(render_blocks(n_keys)), block(kBlock);
-#define MB_LAUNCH(KK, NN)                                                         \
-  if (n_moments == KK && n_intervals == NN) {                                     \
-    hipLaunchKernelGGL((k_render_bwd<KK, NN + 1>), grid, block, 0, s, ba, cams); \
-    return hipGetLastError();                                                     \
+#define MB_LAUNCH(KK, NN, SS)                                                          \
+  if (n_moments == KK && n_intervals == NN && (int)surrogate == SS) {                  \
+    hipLaunchKernelGGL((k_render_bwd<KK, NN + 1, SS>), grid, block, 0, s, ba, cams); \
+    return hipGetLastError();                                                          \
   }
-  MB_LAUNCH(4, 3)
-  MB_LAUNCH(6, 3)
-  MB_LAUNCH(4, 5)
-  MB_LAUNCH(6, 5)
+  MB_LAUNCH(4, 3, 0)
+  MB_LAUNCH(6, 3, 0)
+  MB_LAUNCH(4, 5, 0)
+  MB_LAUNCH(6, 5, 0)
+  MB_LAUNCH(6, 3, 1)
+  MB_LAUNCH(6, 5, 1)
 #undef MB_LAUNCH
   return hipErrorInvalidValue;
 }

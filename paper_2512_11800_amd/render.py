@@ -108,6 +108,7 @@ class RenderState:
     n_cams: int
     width: int
     height: int
+    q_cap: int = 0  # query capacity of a surrogate render
 
 
 def _cams(cams: Sequence) -> ctypes.Array:
@@ -198,13 +199,15 @@ def render_forward_harvest(g: Gaussians, cams: Sequence, opts, rate: float, seed
 
 def render_forward_surrogate(g: Gaussians, cams: Sequence, opts, mlp_packed: torch.Tensor,
                              ws: Optional[Workspace] = None, query_capacity: Optional[int] = None,
-                             check_capacity: bool = True):
+                             check_capacity: bool = True, for_backward: bool = False):
     """mb_prepare + mb_render_forward_surrogate (the learned surrogate in place
     of the moment bounds). The query list lives in ``ws`` and is grown (and
     the frame rendered again) when a frame needs more queries than it holds;
     ``check_capacity=False`` skips that readback once ``ws`` is known to be
-    large enough. Returns (image, saved, state)."""
+    large enough. ``for_backward`` sizes the query workspace for
+    render_backward_surrogate. Returns (image, saved, state)."""
     lib = L.load()
+    size_fn = lib.mb_query_workspace_bytes_backward if for_backward else lib.mb_query_workspace_bytes
     f = _Frame(g, cams, opts, ws)
     ws = f.ws
     if query_capacity is not None:
@@ -212,7 +215,7 @@ def render_forward_surrogate(g: Gaussians, cams: Sequence, opts, mlp_packed: tor
     if ws.q_cap == 0:
         ws.q_cap = 1 << 20
     while True:
-        need = lib.mb_query_workspace_bytes(f.n_cams, f.width, f.height, ws.q_cap)
+        need = size_fn(f.n_cams, f.width, f.height, ws.q_cap)
         qws = ws._ensure("qws", need)
         L.check(lib.mb_render_forward_surrogate(*f.head(), _ptr(mlp_packed), _ptr(qws), qws.numel(),
                                                 ws.q_cap, _ptr(f.image), _ptr(f.saved), _stream()))
@@ -222,7 +225,32 @@ def render_forward_surrogate(g: Gaussians, cams: Sequence, opts, mlp_packed: tor
         if n_q <= ws.q_cap:
             break
         ws.q_cap = int(n_q * 1.1) + 1024
-    return f.result()
+    img, saved, state = f.result()
+    state.q_cap = ws.q_cap
+    return img, saved, state
+
+
+def _grad_outputs(g: Gaussians):
+    return {k: torch.empty_like(getattr(g, k)) for k in ("means", "scales", "quats", "densities", "colors")}
+
+
+def render_backward_surrogate(g: Gaussians, cams: Sequence, opts, state: RenderState, saved: torch.Tensor,
+                              grad_image: torch.Tensor, mlp_packed: torch.Tensor):
+    """mb_render_backward_surrogate after render_forward_surrogate(...,
+    for_backward=True) with the same weights. Returns a dict of gradients
+    shaped like the inputs."""
+    lib = L.load()
+    cam_arr = _cams(cams)
+    o = options_struct(opts)
+    grad_image = grad_image.to(torch.float32).contiguous()
+    out = _grad_outputs(g)
+    ws = state.ws
+    L.check(lib.mb_render_backward_surrogate(
+        ctypes.byref(g.struct()), cam_arr, len(cam_arr), ctypes.byref(o), _ptr(ws.gws), ws.gws.numel(),
+        _ptr(ws.pws), ws.pws.numel(), state.n_entries, _ptr(mlp_packed), _ptr(ws.qws), ws.qws.numel(),
+        state.q_cap, _ptr(saved), _ptr(grad_image), _ptr(out["means"]), _ptr(out["scales"]),
+        _ptr(out["quats"]), _ptr(out["densities"]), _ptr(out["colors"]), _stream()))
+    return out
 
 
 def render_backward(g: Gaussians, cams: Sequence, opts, state: RenderState, saved: torch.Tensor,
@@ -236,7 +264,7 @@ def render_backward(g: Gaussians, cams: Sequence, opts, state: RenderState, save
     grad_image = grad_image.to(torch.float32).contiguous()
     if grad_penalty is not None:
         grad_penalty = grad_penalty.to(torch.float32).contiguous()
-    out = {k: torch.empty_like(getattr(g, k)) for k in ("means", "scales", "quats", "densities", "colors")}
+    out = _grad_outputs(g)
     ws = state.ws
     L.check(lib.mb_render_backward(ctypes.byref(g.struct()), cam_arr, len(cam_arr), ctypes.byref(o),
                                    _ptr(ws.gws), ws.gws.numel(), _ptr(ws.pws), ws.pws.numel(),
@@ -277,3 +305,31 @@ def render(means, scales, quats, densities, colors, cams, opts=None, sh_degree: 
     so a loss can add lambda * mean(penalty)."""
     return _MomentRender.apply(means, scales, quats, densities, colors, sh_degree, list(cams), opts,
                                with_penalty)
+
+
+class _SurrogateRender(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, means, scales, quats, densities, colors, sh_degree, cams, opts, mlp_packed, ws):
+        g = Gaussians(means.contiguous(), scales.contiguous(), quats.contiguous(),
+                      densities.contiguous(), colors.contiguous(), sh_degree)
+        image, saved, state = render_forward_surrogate(g, cams, opts, mlp_packed, ws=ws, for_backward=True)
+        ctx.g, ctx.cams, ctx.opts, ctx.state, ctx.packed = g, cams, opts, state, mlp_packed
+        ctx.save_for_backward(saved)
+        return image
+
+    @staticmethod
+    def backward(ctx, grad_image):
+        (saved,) = ctx.saved_tensors
+        grads = render_backward_surrogate(ctx.g, ctx.cams, ctx.opts, ctx.state, saved, grad_image, ctx.packed)
+        return (grads["means"], grads["scales"], grads["quats"], grads["densities"],
+                grads["colors"], None, None, None, None, None)
+
+
+def render_surrogate(means, scales, quats, densities, colors, cams, mlp_packed: torch.Tensor, opts=None,
+                     sh_degree: int = -1, ws: Optional[Workspace] = None):
+    """Differentiable render [C,H,W,3] through the learned surrogate (weights
+    ``mlp_packed`` from surrogate.mlp_pack, held fixed: they are trained from
+    harvested samples, not through the image). ``ws`` keeps the query list
+    between the forward and backward calls; a fresh one is made when None."""
+    return _SurrogateRender.apply(means, scales, quats, densities, colors, sh_degree, list(cams), opts,
+                                  mlp_packed, ws or Workspace(means.device))

@@ -634,6 +634,78 @@ def test_surrogate_reference_vs_torch_autograd():
     assert np.allclose(th.grad.numpy(), g, rtol=1e-9, atol=1e-14)
 
 
+def test_surrogate_input_gradient_vs_finite_differences():
+    """dF/d(inputs) without rounding against central differences of F."""
+    from oracle import surrogate as S
+    theta = S.init_params(9)
+    x, _ = _mlp_batch(30, 10)
+    f, dx = S.input_grad(theta, x, bf16_mode=False)
+    assert np.array_equal(f, S.forward(theta, x, bf16_mode=False)[0])
+    h = 1e-6
+    for k in range(7):
+        xp = x.copy(); xp[:, k] += h
+        xm = x.copy(); xm[:, k] -= h
+        fd = (S.forward(theta, xp, False)[0] - S.forward(theta, xm, False)[0]) / (2 * h)
+        assert np.allclose(dx[:, k], fd, rtol=1e-6, atol=1e-10)
+
+
+def test_surrogate_input_gradient_rounding_points():
+    """With the kernels' rounding points: F is the bf16 forward value, and the
+    gradient is the exact one up to the bf16 rounding of dZ2 and dZ1 (unit
+    roundoff 2^-9 each, accumulated over 64 terms)."""
+    from oracle import surrogate as S
+    theta = S.init_params(11)
+    x, _ = _mlp_batch(200, 12)
+    f, dx = S.input_grad(theta, x, bf16_mode=True)
+    assert np.array_equal(f, S.forward(theta, x, bf16_mode=True)[0])
+    xt = torch.tensor(x[:, :7], requires_grad=True)
+    S.forward_torch(theta, xt).sum().backward()
+    ref = xt.grad.numpy()
+    rel = np.linalg.norm(dx - ref, axis=1) / np.linalg.norm(ref, axis=1)
+    assert np.median(rel) < 3e-3 and rel.max() < 3e-2
+    # and not equal: the rounding points are there
+    assert rel.max() > 0
+
+
+def test_surrogate_tau_model_gradient_vs_finite_differences():
+    """The feature map's derivative: d tau / d(moments, query) of the torch
+    hook (no rounding) against central differences of the numpy model."""
+    from oracle import surrogate as S
+    theta = S.init_params(13)
+    rng = np.random.default_rng(14)
+    n = 12
+    mom = np.empty((n, 7))
+    # moments of small positive measures on [-1, 1] (the renderer's moment
+    # variable is standardised per pixel, so its moments are of this kind)
+    for i in range(n):
+        pts = rng.uniform(-1, 1, 5)
+        w = rng.uniform(0.1, 1, 5)
+        mom[i] = [(w * pts ** k).sum() for k in range(7)]
+    y = rng.uniform(-0.8, 0.8, n)
+    mt = torch.tensor(mom, requires_grad=True)
+    yt = torch.tensor(y, requires_grad=True)
+    tau = S.tau_model_torch(theta, network="exact")(mt, yt)
+    ref = S.tau_model(theta, bf16_mode=False)(mom, y).numpy()
+    assert np.allclose(tau.detach().numpy(), ref, rtol=1e-12)
+    gm, gy = torch.autograd.grad(tau.sum(), [mt, yt])
+    model = S.tau_model(theta, False)
+
+    def fd(shift, h):
+        # central differences, Richardson-extrapolated (the feature map is
+        # steep where the measure's variance is small)
+        d = lambda hh: (model(*shift(hh)).numpy() - model(*shift(-hh)).numpy()) / (2 * hh)
+        return (4 * d(h / 2) - d(h)) / 3
+    for k in range(7):
+        def shift(hh, k=k):
+            m = mom.copy()
+            m[:, k] += hh
+            return m, y
+        ref_k = fd(shift, 1e-6 * np.abs(mom[:, k]).max())
+        assert np.allclose(gm[:, k].numpy(), ref_k, rtol=1e-6, atol=1e-7 * np.abs(ref_k).max())
+    ref_y = fd(lambda hh: (mom, y + hh), 1e-6)
+    assert np.allclose(gy.numpy(), ref_y, rtol=1e-6, atol=1e-9)
+
+
 def test_bf16_rounding_is_nearest_even():
     from oracle.surrogate import bf16
     assert bf16(1.0) == 1.0
@@ -817,6 +889,40 @@ def test_penalty_gradients_vs_central_differences():
                      params["colors"], scene.sh_degree)
         r = oracle.render_image(sc, cam, opts)
         return float((r["image"] * g_img).sum() + (r["penalty"] * g_pen).sum())
+
+    for name in ("means", "scales", "quats", "densities"):
+        arr = base[name]
+        for _ in range(3):
+            idx = tuple(rng.integers(0, s) for s in arr.shape)
+            h = 1e-6 * max(1.0, abs(arr[idx]))
+            p = {k: v.copy() for k, v in base.items()}
+            p[name][idx] += h
+            lp = loss64(p)
+            p[name][idx] -= 2 * h
+            lm = loss64(p)
+            fd = (lp - lm) / (2 * h)
+            assert grads[name][idx] == pytest.approx(fd, rel=1e-5, abs=1e-8), name
+
+
+def test_render_gradients_through_the_surrogate_vs_central_differences():
+    """Oracle autograd of a render through the network (no rounding, so the
+    loss is smooth) against central differences of the same render."""
+    from oracle import surrogate as S
+    scene = _tiny_scene(5, 4)
+    cam = W.camera_on_axis(2.0, 8, 8)
+    opts = W.Options(n_moments=6, full_coverage=True)
+    theta = S.init_params(17)
+    rng = np.random.default_rng(8)
+    g_img = rng.normal(size=(64, 3))
+    grads = oracle.render_backward(scene, cam, opts, g_img,
+                                   tau_model=S.tau_model_torch(theta, network="exact"))
+    base = {k: np.asarray(getattr(scene, k), np.float64) for k in oracle.render.PARAMS}
+    model = S.tau_model(theta, bf16_mode=False)
+
+    def loss64(params):
+        sc = W.Scene(params["means"], params["scales"], params["quats"], params["densities"],
+                     params["colors"], scene.sh_degree)
+        return float((oracle.render_image(sc, cam, opts, tau_model=model)["image"] * g_img).sum())
 
     for name in ("means", "scales", "quats", "densities"):
         arr = base[name]
