@@ -299,10 +299,25 @@ def surrogate_bench(args):
                                                                   check_capacity=False))
         L.profile_enable(False)
         st = {k: round(v[0] / max(1, v[1]), 4) for k, v in L.profile_read().items() if v[1]}
+        # forward + backward of the two paths (the surrogate's weights fixed)
+        gi = torch.full_like(plain, 1.0 / plain.numel())
+
+        def plain_fb():
+            _, sv, rs = M.render_forward(g, [cam], opts, ws=ws)
+            M.render_backward(g, [cam], opts, rs, sv, gi)
+
+        def sur_fb(check=False):
+            _, sv, rs = M.render_forward_surrogate(g, [cam], opts, packed, ws=ws, check_capacity=check,
+                                                   for_backward=True)
+            M.render_backward_surrogate(g, [cam], opts, rs, sv, gi, packed)
+        sur_fb(True)  # sizes the query workspace for the backward pass
+        ms_plain_fb = timed(plain_fb)
+        ms_sur_fb = timed(sur_fb)
         a = plain[0].cpu().numpy().reshape(-1, 3).astype(np.float64)
         b = sur[0].cpu().numpy().reshape(-1, 3).astype(np.float64)
         mse = float(((a - b) ** 2).mean())
         rec = {"camera": i, "ms_plain": ms_plain, "ms_surrogate": ms_sur,
+               "ms_plain_fwd_bwd": ms_plain_fb, "ms_surrogate_fwd_bwd": ms_sur_fb,
                "psnr_surrogate_vs_plain": 10 * math.log10(1.0 / mse) if mse > 0 else None,
                "surrogate_stages_ms": st}
         if args.gt_pixels > 0:

@@ -181,8 +181,10 @@ def test_surrogate_backward_matches_oracle(n_intervals):
     """Gradients of a render through the (untrained) network: GPU adjoint
     against oracle float64 autograd through the same network with the kernels'
     rounding points (inputs, weights, H1, dZ2, dZ1 in bf16). Ambiguous pixels
-    take no upstream gradient. Residual differences come from float32 against
-    float64 sums deciding a bf16 rounding differently on a few queries."""
+    take no upstream gradient. Bar: 1e-3 relative per parameter group, as for
+    the plain path; the residual (measured ~1e-5) comes from float32 against
+    float64 sums, which can also decide a bf16 rounding differently on a few
+    queries."""
     import paper_2512_11800_amd as M
     from paper_2512_11800_amd import surrogate as G
     scene, cams, opts = _w1_k6(400)
@@ -211,7 +213,7 @@ def test_surrogate_backward_matches_oracle(n_intervals):
         r = float(np.linalg.norm(gpu[k] - ref[k]) / max(np.linalg.norm(ref[k]), 1e-30))
         log(f"[surrogate grad N={n_intervals}] {k}: rel_err={r:.3e} |ref|={np.linalg.norm(ref[k]):.3e}")
         worst = max(worst, r)
-    assert worst <= 1e-2
+    assert worst <= 1e-3
     # the surrogate's adjoint differs from the plain path's
     img_p, saved_p, st_p = M.render_forward(g, [cam], opts)
     plain = M.render_backward(g, [cam], opts, st_p, saved_p, gi)
