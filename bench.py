@@ -43,22 +43,28 @@ def flops_per_pair(k_mom: int, n_int: int) -> dict:
                  Hermite interpolant and its monomial form (85 / 165)
       quadrature ray + (N + 1) (13 + recon) + 9 N + 8 (edges, warp, sigma_i,
                  the Eq. 7 interval terms)
-    Backward: pass 1 repeats the moments; pass 2 the quadrature plus, per
-    edge, the adjoint and the (K + 1)-term accumulation; pass 3 the quadrature,
-    per edge the adjoint and the depth derivatives, the moment Jacobian in
-    three tangents and the chain to the record coefficients."""
+      chain      (mu, Sigma, omega) adjoint to the record's coefficients,
+                 offsets and weight (70)
+    Forward: the moment pass and the quadrature pass. Backward (it starts
+    from the per-pixel moment sums the forward pass stored): pass 2 repeats
+    the quadrature and adds, per edge, the bound's adjoint, its K + 1 moment
+    terms and the depth derivatives (4 K + 20), per interval the derivatives
+    of the Eq. 7 term (20), and per pair the chain and colour terms (90);
+    pass 3 the ray, the moment Jacobian in three tangents (40 + 3 moments)
+    and the chain."""
     n = k_mom // 2
-    ray, warp_lin = 37, 12
+    ray, warp_lin, chain = 37, 12, 70
     mom = 18 + 7 * (k_mom - 1) + (k_mom + 1)
     recon = 73 if n == 2 else 169
     herm = 85 if n == 2 else 165
     quad = ray + (n_int + 1) * (13 + recon) + 9 * n_int + 8
     out = {"moment_pass": ray + warp_lin + mom, "quadrature_pass": quad}
     out["forward"] = out["moment_pass"] + out["quadrature_pass"]
-    bwd1 = out["moment_pass"]
-    bwd2 = quad + (n_int + 1) * (herm + 3 * (k_mom + 1) + 2) + 6
-    bwd3 = quad + (n_int + 1) * (herm + 10) + 20 * n_int + (40 + 3 * mom) + 60
-    out["backward"] = bwd1 + bwd2 + bwd3
+    bwd2 = quad + (n_int + 1) * (herm + 4 * k_mom + 20) + 20 * n_int + 90
+    bwd3 = ray + warp_lin + (40 + 3 * mom) + chain
+    out["adjoint_pass"] = bwd2
+    out["gradient_pass"] = bwd3
+    out["backward"] = bwd2 + bwd3
     return out
 
 

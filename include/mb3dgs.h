@@ -93,7 +93,9 @@ int32_t mb_version(void);
 
 /* Workspace sizes. The Gaussian workspace holds per-(camera, Gaussian)
  * records and tile counts; the pair workspace holds the per-tile lists for
- * n_entries (camera, tile, Gaussian) entries and the backward partials.
+ * n_entries (camera, tile, Gaussian) entries, the backward partials, and each
+ * pixel's moment sums (7 doubles per pixel), which the forward pass leaves
+ * for the backward pass.
  * Both are caller-allocated device memory, 256-byte aligned. */
 size_t mb_gauss_workspace_bytes(int32_t n, int32_t n_cams);
 size_t mb_pair_workspace_bytes(int64_t n_entries, int32_t n_cams, int32_t width,
@@ -137,8 +139,10 @@ int mb_render_forward(const mb_gaussians *g, const mb_camera *cams, int32_t n_ca
                       float *penalty, void *stream);
 
 /* Backward pass (Sec. 3.3, Eq. 22, App. D adjoint rendering) after
- * mb_render_forward with the same arguments and workspaces. Per-pixel moments
- * are recomputed, not stored.
+ * mb_render_forward with the same arguments and workspaces. The per-pixel
+ * moment sums come from the pair workspace, where the forward pass left them;
+ * nothing per (pixel, Gaussian) pair is stored, the pairs' terms are
+ * recomputed.
  *  saved         [C,H,W,8] device, from mb_render_forward
  *  grad_image    [C,H,W,3] device, dL/dimage
  *  grad_penalty  [C,H,W] device, dL/dpenalty, or NULL (no penalty term)

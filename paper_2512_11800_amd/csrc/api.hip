@@ -116,10 +116,11 @@ struct PairWs {
   int *order, *order_tmp;
   uint64_t* masks;
   float* partials;
+  double* pix_mom;
   size_t bytes;
 };
 
-PairWs carve_pairs(void* p, int64_t e, int n_keys) {
+PairWs carve_pairs(void* p, int64_t e, int n_keys, int64_t n_pix) {
   Carver c(p);
   PairWs w;
   w.keys_a = c.take<uint32_t>((size_t)e);
@@ -135,6 +136,7 @@ PairWs carve_pairs(void* p, int64_t e, int n_keys) {
   w.order_tmp = c.take<int>(order_tmp_ints(n_keys));
   w.masks = c.take<uint64_t>((size_t)e * 4);
   w.partials = c.take<float>((size_t)e * 4 * kGradStride);  // one slot per (entry, wave)
+  w.pix_mom = c.take<double>((size_t)n_pix * (kMaxMoments + 1));
   w.bytes = c.off;
   return w;
 }
@@ -277,7 +279,7 @@ int forward_setup(const mb_gaussians* g, const mb_camera* cams, int32_t n_cams, 
     return fail(MB_ERR_WORKSPACE, "Gaussian workspace needs %zu bytes, got %zu", f.w.bytes, gws_bytes);
   int tx = tiles_of(cams[0].width), ty = tiles_of(cams[0].height);
   f.n_keys = tx * ty * n_cams;
-  f.p = carve_pairs(pws, n_entries, f.n_keys);
+  f.p = carve_pairs(pws, n_entries, f.n_keys, (int64_t)n_cams * cams[0].width * cams[0].height);
   if (!pws || pws_bytes < f.p.bytes)
     return fail(MB_ERR_WORKSPACE, "pair workspace needs %zu bytes, got %zu", f.p.bytes, pws_bytes);
   f.cs = make_cams(cams, n_cams);
@@ -285,6 +287,8 @@ int forward_setup(const mb_gaussians* g, const mb_camera* cams, int32_t n_cams, 
   memset(&ra, 0, sizeof(ra));
   ra.rec = f.w.rec; ra.sorted_rec = f.p.sorted_rec; ra.ranges = f.p.ranges; ra.order = f.p.order;
   ra.masks = f.p.masks;
+  ra.pix_mom = f.p.pix_mom;
+  ra.n_pix = (long long)n_cams * cams[0].width * cams[0].height;
   ra.image = image; ra.saved = saved;
   ra.tiles_x = tx; ra.tiles_y = ty; ra.n_cams = n_cams; ra.full_coverage = o->full_coverage;
   ra.kappa = o->kappa; ra.beta = o->beta; ra.eps = o->eps;
@@ -376,7 +380,7 @@ size_t mb_gauss_workspace_bytes(int32_t n, int32_t n_cams) {
 size_t mb_pair_workspace_bytes(int64_t n_entries, int32_t n_cams, int32_t width, int32_t height) {
   if (n_entries < 0 || n_cams < 1 || width <= 0 || height <= 0) return 0;
   int n_keys = tiles_of(width) * tiles_of(height) * n_cams;
-  return carve_pairs(nullptr, n_entries, n_keys).bytes;
+  return carve_pairs(nullptr, n_entries, n_keys, (int64_t)n_cams * width * height).bytes;
 }
 
 int mb_project(const mb_gaussians* g, const mb_camera* cam, const mb_options* o, float* proxy, void* stream) {
@@ -552,7 +556,7 @@ int backward_common(const mb_gaussians* g, const mb_camera* cams, int32_t n_cams
   GaussWs w = carve_gauss(gws, g->n, n_cams);
   if (!gws || gws_bytes < w.bytes)
     return fail(MB_ERR_WORKSPACE, "Gaussian workspace needs %zu bytes, got %zu", w.bytes, gws_bytes);
-  PairWs p = carve_pairs(pws, n_entries, n_keys);
+  PairWs p = carve_pairs(pws, n_entries, n_keys, (int64_t)n_cams * cams[0].width * cams[0].height);
   if (!pws || pws_bytes < p.bytes)
     return fail(MB_ERR_WORKSPACE, "pair workspace needs %zu bytes, got %zu", p.bytes, pws_bytes);
   CamSet cs = make_cams(cams, n_cams);
@@ -560,6 +564,8 @@ int backward_common(const mb_gaussians* g, const mb_camera* cams, int32_t n_cams
   memset(&ra, 0, sizeof(ra));
   ra.rec = w.rec; ra.sorted_rec = p.sorted_rec; ra.ranges = p.ranges; ra.order = p.order;
   ra.masks = p.masks;
+  ra.pix_mom = p.pix_mom;
+  ra.n_pix = (long long)n_cams * cams[0].width * cams[0].height;
   ra.tiles_x = tx; ra.tiles_y = ty; ra.n_cams = n_cams; ra.full_coverage = o->full_coverage;
   ra.kappa = o->kappa; ra.beta = o->beta; ra.eps = o->eps;
   fill_quantiles(o, ra.xq, ra.eq, ra.ecq);

@@ -70,6 +70,8 @@ struct RenderArgs {
   float eq[8];    // exp(-kappa^2 xq^2 / 2)
   float ecq[8];   // erfc(kappa xq / sqrt2)
   float* penalty; // [C,H,W] consistency penalty per pixel, or null
+  double* pix_mom; // [kMaxMoments + 1][C*H*W] per-pixel moment sums, written by the forward pass
+  long long n_pix; // C*H*W
   // surrogate query list (emit / consume variants)
   float* pixfeat;                 // [C,H,W,kPixFeat] per-pixel features, m0, basis, count
   long long* pix_qbase;           // [C,H,W] first query of the pixel, -1 if none

@@ -149,80 +149,70 @@ __device__ __forceinline__ void feat_from_moments(const DualD* m, DualD* feat, D
   }
 }
 
-// sum_k dm[k] * d m_k / d(mu, Sigma, omega) for the moments of Eqs. 10-12
+// sum_k dm[k] * d m_k / d(mu, Sigma, omega) for the moments of Eqs. 10-12,
+// by reverse-mode differentiation of their recurrence: the moments forward
+// (kept in registers), then one adjoint sweep back through the recurrence to
+// the shared terms G, G', bn, E, erfc, and from those to (mu, Sigma, omega).
 template <int K>
 __device__ __forceinline__ void moment_grads(const RayG& g, const PixelBasis& pb, float tn, const float* dmv,
                                              float* out) {
   const float c = kSqrtHalfPi;
-  float mus = fmaxf(g.mu, tn);
-  float ys = warp_y(pb, mus, mus - pb.tc);
-  float yp = warp_dy(pb, mus);
-  float G = ys + yp * (g.mu - mus), Gp = yp;
-  float dG[3] = {Gp, 0.f, 0.f};
-  float q = 1.f + 0.8f * g.mu;
-  float d2 = g.mu > tn ? -3.f * pb.amp / (q * q * q * sqrtf(q)) : 0.f;  // y''(mu)
-  float dGp[3] = {d2, 0.f, 0.f};
-  float is = fast_rcp(g.sig);
-  float bn = (tn - g.mu) * kInvSqrt2 * is;
-  float dbn[3] = {-kInvSqrt2 * is, -bn * is, 0.f};
-  float E = __expf(-bn * bn);
-  float ec = erfc_fast(bn);
-  const float two_rsqrt_pi = 1.1283791670955126f;
-  float m0 = g.omega * g.sig * c * ec;
-  float s2 = g.sig * g.sig;
-  float bnd = Gp * g.omega * s2 * E;
-  float dm0[3], dE[3], dbnd[3];
+  const float mus = fmaxf(g.mu, tn);
+  const float ys = warp_y(pb, mus, mus - pb.tc);
+  const float Gp = warp_dy(pb, mus);
+  const float G = ys + Gp * (g.mu - mus);
+  const float q = 1.f + 0.8f * g.mu;
+  const float d2 = g.mu > tn ? -3.f * pb.amp / (q * q * q * sqrtf(q)) : 0.f;  // y''(mu)
+  const float is = fast_rcp(g.sig);
+  const float bn = (tn - g.mu) * kInvSqrt2 * is;
+  const float E = __expf(-bn * bn);
+  const float ec = erfc_fast(bn);
+  const float s2 = g.sig * g.sig;
+  const float tm = tn - g.mu;
+  // primal: m_0, m_1 and m_k = G m_{k-1} + (k-1) v2 m_{k-2} + bnd un^(k-1)
+  float m[K + 1], up[K];
+  m[0] = g.omega * g.sig * c * ec;
+  const float bnd = Gp * g.omega * s2 * E;
+  m[1] = G * m[0] + bnd;
+  const float un = G + Gp * tm;
+  const float v2 = Gp * Gp * s2;
+  up[0] = 1.f;
 #pragma unroll
-  for (int v = 0; v < 3; ++v) {
-    dE[v] = -2.f * bn * E * dbn[v];
-    float dec = -two_rsqrt_pi * E * dbn[v];
-    dm0[v] = c * g.omega * g.sig * dec;
+  for (int k = 1; k < K; ++k) up[k] = up[k - 1] * un;
+#pragma unroll
+  for (int k = 2; k <= K; ++k) m[k] = G * m[k - 1] + (float)(k - 1) * v2 * m[k - 2] + bnd * up[k - 1];
+  // adjoint sweep
+  float a[K + 1];
+#pragma unroll
+  for (int k = 0; k <= K; ++k) a[k] = dmv[k];
+  float gG = 0.f, gv2 = 0.f, gbnd = 0.f, gun = 0.f;
+#pragma unroll
+  for (int k = K; k >= 2; --k) {
+    const float km = (float)(k - 1);
+    gG += a[k] * m[k - 1];
+    a[k - 1] += a[k] * G;
+    gv2 += a[k] * km * m[k - 2];
+    a[k - 2] += a[k] * km * v2;
+    gbnd += a[k] * up[k - 1];
+    gun += a[k] * km * up[k - 2];
   }
-  dm0[1] += c * g.omega * ec;
-  dm0[2] += c * g.sig * ec;
-  float ds2[3] = {0.f, 2.f * g.sig, 0.f};
-  float dom[3] = {0.f, 0.f, 1.f};
-#pragma unroll
-  for (int v = 0; v < 3; ++v)
-    dbnd[v] = dGp[v] * g.omega * s2 * E + Gp * dom[v] * s2 * E + Gp * g.omega * ds2[v] * E +
-              Gp * g.omega * s2 * dE[v];
-  float m1 = G * m0 + bnd;
-  float dm1[3];
-#pragma unroll
-  for (int v = 0; v < 3; ++v) {
-    dm1[v] = dG[v] * m0 + G * dm0[v] + dbnd[v];
-    out[v] = dmv[0] * dm0[v] + dmv[1] * dm1[v];
-  }
-  float un = G + Gp * (tn - g.mu);
-  float dun[3];
-#pragma unroll
-  for (int v = 0; v < 3; ++v) dun[v] = dG[v] + dGp[v] * (tn - g.mu) - (v == 0 ? Gp : 0.f);
-  float v2 = Gp * Gp * s2;
-  float dv2[3];
-#pragma unroll
-  for (int v = 0; v < 3; ++v) dv2[v] = 2.f * Gp * dGp[v] * s2 + Gp * Gp * ds2[v];
-  float unp = un, dunp[3] = {dun[0], dun[1], dun[2]};
-  float pm2 = m0, pm1 = m1, dpm2[3] = {dm0[0], dm0[1], dm0[2]}, dpm1[3] = {dm1[0], dm1[1], dm1[2]};
-#pragma unroll
-  for (int k = 2; k <= K; ++k) {
-    float km = (float)(k - 1);
-    float mk = G * pm1 + km * v2 * pm2 + bnd * unp;
-    float dmk[3];
-#pragma unroll
-    for (int v = 0; v < 3; ++v) {
-      dmk[v] = dG[v] * pm1 + G * dpm1[v] + km * (dv2[v] * pm2 + v2 * dpm2[v]) + dbnd[v] * unp + bnd * dunp[v];
-      out[v] += dmv[k] * dmk[v];
-    }
-#pragma unroll
-    for (int v = 0; v < 3; ++v) {
-      dunp[v] = dunp[v] * un + unp * dun[v];
-      dpm2[v] = dpm1[v];
-      dpm1[v] = dmk[v];
-    }
-    unp *= un;
-    pm2 = pm1;
-    pm1 = mk;
-  }
+  gun *= bnd;
+  gG += a[1] * m[0] + gun;
+  a[0] += a[1] * G;
+  gbnd += a[1];
+  float gGp = gun * tm + gv2 * 2.f * Gp * s2 + gbnd * g.omega * s2 * E;
+  float gmu = -gun * Gp;
+  const float gs2 = gv2 * Gp * Gp + gbnd * Gp * g.omega * E;
+  const float gE = gbnd * Gp * g.omega * s2;
+  float gom = gbnd * Gp * s2 * E + a[0] * g.sig * c * ec;
+  float gsig = a[0] * g.omega * c * ec + gs2 * 2.f * g.sig;
+  const float gec = a[0] * g.omega * g.sig * c;
+  const float gbn = -2.f * E * (gE * bn + gec * 0.5641895835477563f);  // d erfc/db = -2 E / sqrt(pi)
+  gmu += -gbn * kInvSqrt2 * is + gG * Gp + gGp * d2;
+  gsig += -gbn * bn * is;
+  out[0] = gmu;
+  out[1] = gsig;
+  out[2] = gom;
 }
 
 struct BwdArgs {
@@ -265,14 +255,39 @@ __device__ __forceinline__ void chain_record(float gmu, float gsig, float gom, c
   gr[G_W] = gom * ek;
 }
 
-// inclusive scan of v over the lanes of its segment; the segment's last lane
-// ends with the segment sum
-__device__ __forceinline__ float segment_scan(float v, int lane, int seg_start) {
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    float t = __shfl_up(v, d, 64);
-    if (lane - d >= seg_start) v += t;
-  }
+// Segmented inclusive scan over the wave's lanes with DPP moves: four
+// shifts inside each 16-lane row (row_shr 1, 2, 4, 8), then the classic
+// row_bcast 15 (rows 1 and 3) and row_bcast 31 (rows 2 and 3) steps across
+// rows. Each step adds the moved value times a 0/1 mask that keeps the sum
+// inside the lane's segment [seg_start, lane]; the masks depend only on the
+// segment layout, so one set serves every gradient field. The segment's last
+// lane ends with the segment sum.
+struct ScanMasks {
+  float m[6];
+};
+__device__ __forceinline__ ScanMasks scan_masks(int lane, int seg_start) {
+  ScanMasks s;
+  const int row0 = lane & ~15;
+  const int lo = max(seg_start, row0);
+  s.m[0] = lane - 1 >= lo ? 1.f : 0.f;
+  s.m[1] = lane - 2 >= lo ? 1.f : 0.f;
+  s.m[2] = lane - 4 >= lo ? 1.f : 0.f;
+  s.m[3] = lane - 8 >= lo ? 1.f : 0.f;
+  s.m[4] = ((lane >> 4) & 1) && seg_start < row0 ? 1.f : 0.f;  // takes lane 15 or 47
+  s.m[5] = (lane >> 5) && seg_start <= 31 ? 1.f : 0.f;         // takes lane 31
+  return s;
+}
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_move(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, true));
+}
+__device__ __forceinline__ float segment_scan(float v, const ScanMasks& s) {
+  v = fmaf(dpp_move<0x111, 0xf>(v), s.m[0], v);  // row_shr:1
+  v = fmaf(dpp_move<0x112, 0xf>(v), s.m[1], v);  // row_shr:2
+  v = fmaf(dpp_move<0x114, 0xf>(v), s.m[2], v);  // row_shr:4
+  v = fmaf(dpp_move<0x118, 0xf>(v), s.m[3], v);  // row_shr:8
+  v = fmaf(dpp_move<0x142, 0xa>(v), s.m[4], v);  // row_bcast:15
+  v = fmaf(dpp_move<0x143, 0xc>(v), s.m[5], v);  // row_bcast:31
   return v;
 }
 
@@ -291,8 +306,9 @@ __device__ __forceinline__ void reduce_to_slots(float* gr, bool act, int j, int 
   const int seg_start = 63 - __builtin_clzll(heads & upto);
   const int jnext = __shfl_down(j, 1, 64);
   const bool last = act && (lane == n - 1 || jnext != j);
+  const ScanMasks sm = scan_masks(lane, seg_start);
 #pragma unroll
-  for (int f = 0; f < G_COUNT; ++f) gr[f] = segment_scan(gr[f], lane, seg_start);
+  for (int f = 0; f < G_COUNT; ++f) gr[f] = segment_scan(gr[f], sm);
   if (last) {
     if (seg_start == 0 && j == carry_j) {
 #pragma unroll
@@ -337,6 +353,7 @@ __global__ __launch_bounds__(256, (K == 4 && NQ == 4) ? 3 : 2) void k_render_bwd
   __shared__ Stage st;
   __shared__ int sk[kBlock];
   __shared__ WaveQueue wq[4];
+  __shared__ uint32_t wrank[4][SUR ? 128 : 1];           // pair ranks (surrogate queries)
   __shared__ __align__(16) float wres[4][NRES * 64];     // per queued pair results
   __shared__ float carry[4][G_COUNT];                    // partial slot of an entry split over evaluations
   const int tiles_per_cam = a.tiles_x * a.tiles_y;
@@ -410,62 +427,10 @@ __global__ __launch_bounds__(256, (K == 4 && NQ == 4) ? 3 : 2) void k_render_bwd
     __syncthreads();
   };
 
-  // ---- pass 1: recompute the moments (identical to the forward pass) -------
+  // ---- the pixel's moment sums, as the forward pass left them --------------
   double acc[K + 1];
 #pragma unroll
-  for (int k = 0; k <= K; ++k) acc[k] = 0.0;
-  {
-    auto flush = [&](int n, uint64_t own) __attribute__((always_inline)) {
-      int j, p;
-      const bool act = item_of(n, j, p);
-      const PixelBasis pp = basis_of(p);
-      const float lamp = from_lane(lam, p);
-      if (act) {
-        float dx, dy;
-        offsets_of(j, p, dx, dy);
-        RayG g = ray_params(st, j, dx, dy, lamp);
-        float m[K + 1];
-        particle_moments<K>(g, pp, tn, m);
-#pragma unroll
-        for (int k = 0; k <= K; ++k) res[k * 64 + lane] = m[k];
-      }
-      __builtin_amdgcn_wave_barrier();
-      while (own) {
-        const int i = __builtin_ctzll(own);
-        own &= own - 1;
-#pragma unroll
-        for (int k = 0; k <= K; ++k) acc[k] += (double)res[k * 64 + i];
-      }
-      __builtin_amdgcn_wave_barrier();
-    };
-    for (int b = rg.x; b < rg.y; b += kBlock) {
-      int nb = min(kBlock, rg.y - b);
-      stage(b, nb, false);
-      QueueCursor qc;
-      queue_reset(qc);
-      queue_from_masks(q, qc, a.masks, b, nb, quad, own4, lane, ~0ull,
-                       [&]() __attribute__((always_inline)) {
-                         flush(64, qc.own_lo);
-                         queue_pop64(q, qc, lane);
-                       },
-                       [](int) {});
-      if (qc.cnt > 0) flush(qc.cnt, qc.own_lo);
-    }
-  }
-  if (split) {
-    double* xd = reinterpret_cast<double*>(&st);
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k <= K; ++k) xd[(wave * (K + 1) + k) * 64 + lane] = acc[k];
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k <= K; ++k) {
-      double t = 0.0;
-#pragma unroll
-      for (int w = 0; w < 4; ++w) t += xd[(w * (K + 1) + k) * 64 + lane];
-      acc[k] = t;
-    }
-  }
+  for (int k = 0; k <= K; ++k) acc[k] = inside ? a.pix_mom[(size_t)k * a.n_pix + pix] : 0.0;
   const float m0 = (float)acc[0];
   const bool live = acc[0] > kMinDepth;  // as in the forward pass
   LInv<NH> L;
@@ -528,7 +493,7 @@ __global__ __launch_bounds__(256, (K == 4 && NQ == 4) ? 3 : 2) void k_render_bwd
     const long long qb = active ? a.pix_qbase[pix] : -1;
     const uint64_t sur_mask = __ballot(qb >= 0);
     float dm0s = 0.f, dmus = 0.f, dsigs = 0.f, dfeat[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    uint32_t my_rank = 0;
+    QueueRanks rk{wrank[wave], 0u};
     int carry_j = -1;
     auto flush = [&](int n, uint64_t own, int cont_j) __attribute__((always_inline)) {
       int j, p;
@@ -545,7 +510,7 @@ __global__ __launch_bounds__(256, (K == 4 && NQ == 4) ? 3 : 2) void k_render_bwd
 #pragma unroll
       for (int f = 0; f < G_COUNT; ++f) gr[f] = 0.f;
       if (act) {
-        const uint32_t rank = q.rank[lane];
+        const uint32_t rank = wrank[wave][lane];
         float dx, dy;
         offsets_of(j, p, dx, dy);
         RayG g = ray_params(st, j, dx, dy, lamp);
@@ -630,9 +595,9 @@ __global__ __launch_bounds__(256, (K == 4 && NQ == 4) ? 3 : 2) void k_render_bwd
                        [&]() __attribute__((always_inline)) {
                          const int cont_j = qc.cnt > 64 ? (int)(q.item[64] >> 6) : -1;
                          flush(64, qc.own_lo, cont_j);
-                         queue_pop64(q, qc, lane);
+                         queue_pop64<true>(q, qc, lane, wrank[wave]);
                        },
-                       zero_slot, &my_rank);
+                       zero_slot, &rk);
       if (qc.cnt > 0) flush(qc.cnt, qc.own_lo, -1);
     }
     // the moment adjoint through the surrogate's inputs (forward-mode Jacobian

@@ -26,7 +26,14 @@ struct RayG {
 // ---------------------------------------------------------------------------
 struct WaveQueue {
   uint16_t item[128];  // (entry in the staged batch) << 6 | pixel lane
-  uint32_t rank[128];  // the pair's index among its pixel's covering pairs (when tracked)
+};
+
+// Optional rank tracking beside a queue: q[pos] receives the pair's index
+// among its pixel's covering pairs, counted by the pixel lane's ctr. Kept out
+// of WaveQueue so the kernels that do not need it spend no LDS on it.
+struct QueueRanks {
+  uint32_t* q;  // [128] in LDS, parallel to WaveQueue::item
+  uint32_t ctr;
 };
 
 struct QueueCursor {
@@ -43,12 +50,12 @@ __device__ __forceinline__ void queue_reset(QueueCursor& qc) {
 // Append this lane's pair (entry j) if cov; all lanes call it with the same
 // ballot mask. Returns the new count.
 __device__ __forceinline__ void queue_push(WaveQueue& q, QueueCursor& qc, uint64_t mask, bool cov, int j,
-                                           int lane, uint32_t* rank = nullptr) {
+                                           int lane, QueueRanks* rank = nullptr) {
   if (cov) {
     int pos = qc.cnt + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
     q.item[pos] = (uint16_t)((j << 6) | lane);
-    if (rank) q.rank[pos] = (*rank)++;
+    if (rank) rank->q[pos] = rank->ctr++;
     if (pos < 64)
       qc.own_lo |= 1ull << pos;
     else
@@ -57,15 +64,17 @@ __device__ __forceinline__ void queue_push(WaveQueue& q, QueueCursor& qc, uint64
   qc.cnt += __popcll(mask);
 }
 
-// After evaluating positions [0, 64): move the rest to the front.
-__device__ __forceinline__ void queue_pop64(WaveQueue& q, QueueCursor& qc, int lane) {
+// After evaluating positions [0, 64): move the rest to the front (with their
+// ranks when RANK: only a queue filled with ranks needs them).
+template <bool RANK = false>
+__device__ __forceinline__ void queue_pop64(WaveQueue& q, QueueCursor& qc, int lane, uint32_t* rq = nullptr) {
   int rest = qc.cnt - 64;
   uint16_t it = lane < rest ? q.item[64 + lane] : (uint16_t)0;
-  uint32_t rk = lane < rest ? q.rank[64 + lane] : 0u;
+  uint32_t rk = (RANK && lane < rest) ? rq[64 + lane] : 0u;
   __builtin_amdgcn_wave_barrier();
   if (lane < rest) {
     q.item[lane] = it;
-    q.rank[lane] = rk;
+    if (RANK) rq[lane] = rk;
   }
   __builtin_amdgcn_wave_barrier();
   qc.own_lo = qc.own_hi;
@@ -83,7 +92,7 @@ __device__ __forceinline__ void queue_pop64(WaveQueue& q, QueueCursor& qc, int l
 template <class Full, class Empty>
 __device__ __forceinline__ void queue_from_masks(WaveQueue& q, QueueCursor& qc, const uint64_t* masks, int b, int nb,
                                                  int quad, int own4, int lane, uint64_t keep, Full&& on_full,
-                                                 Empty&& on_empty, uint32_t* rank = nullptr) {
+                                                 Empty&& on_empty, QueueRanks* rank = nullptr) {
   for (int j0 = 0; j0 < nb; j0 += 64) {
     const bool in = j0 + lane < nb && (own4 < 0 || ((j0 + lane) & 3) == own4);
     const uint64_t mk = in ? (masks[(size_t)(b + j0 + lane) * 4 + quad] & keep) : 0ull;

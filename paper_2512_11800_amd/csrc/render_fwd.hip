@@ -282,6 +282,11 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
       acc[k] = t;
     }
   }
+  // the backward pass starts from these sums (one column per moment)
+  if (inside && own4 <= 0) {
+#pragma unroll
+    for (int k = 0; k <= K; ++k) a.pix_mom[(size_t)k * a.n_pix + pix] = acc[k];
+  }
 
   // ---- per-pixel setup ------------------------------------------------------
   const float m0 = (float)acc[0];
