@@ -136,7 +136,10 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
   };
 
   // ---- pass 0: coverage masks and the pixel's moment variable --------------
-  float wsum = 0.f, mean = 0.f, m2 = 0.f;
+  // weighted depth statistics of the covering Gaussians (weight omega Sigma):
+  // sums of w, w mu and w (mu^2 + Sigma^2) in double (weights can be denormal
+  // floats; the variance is a difference of these sums)
+  double sw = 0.0, swm = 0.0, swq = 0.0;
   int n_cov = 0;
   {
     auto flush = [&](int n, uint64_t own) __attribute__((always_inline)) {
@@ -153,13 +156,10 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
       while (own) {
         const int i = __builtin_ctzll(own);
         own &= own - 1;
-        const float wgt = res[i], mu = res[64 + i], sg = res[128 + i];
-        if (wgt > 0.f) {
-          wsum += wgt;
-          float d = mu - mean;
-          mean += d * wgt / wsum;  // IEEE division: weights can be denormal
-          m2 += wgt * (d * (mu - mean) + sg * sg);
-        }
+        const double wgt = (double)res[i], mu = (double)res[64 + i], sg = (double)res[128 + i];
+        sw += wgt;
+        swm = fma(wgt, mu, swm);
+        swq = fma(wgt, fma(mu, mu, sg * sg), swq);
       }
       __builtin_amdgcn_wave_barrier();
     };
@@ -187,33 +187,32 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
     }
   }
   if (split) {
-    // combine the four (weight, mean, M2) states in wave order (Chan et al.)
+    // add the four waves' sums in wave order
+    double* xd = reinterpret_cast<double*>(&st);
     __syncthreads();
-    xch[(wave * 4 + 0) * 64 + lane] = wsum;
-    xch[(wave * 4 + 1) * 64 + lane] = mean;
-    xch[(wave * 4 + 2) * 64 + lane] = m2;
-    xch[(wave * 4 + 3) * 64 + lane] = __int_as_float(n_cov);
+    xd[(wave * 4 + 0) * 64 + lane] = sw;
+    xd[(wave * 4 + 1) * 64 + lane] = swm;
+    xd[(wave * 4 + 2) * 64 + lane] = swq;
+    xd[(wave * 4 + 3) * 64 + lane] = (double)n_cov;
     __syncthreads();
-    wsum = 0.f;
-    mean = 0.f;
-    m2 = 0.f;
+    sw = swm = swq = 0.0;
     n_cov = 0;
 #pragma unroll
     for (int w = 0; w < 4; ++w) {
-      const float wb = xch[(w * 4 + 0) * 64 + lane], mb = xch[(w * 4 + 1) * 64 + lane];
-      const float m2b = xch[(w * 4 + 2) * 64 + lane];
-      n_cov += __float_as_int(xch[(w * 4 + 3) * 64 + lane]);
-      if (wb > 0.f) {
-        const float wn = wsum + wb;
-        const float d = mb - mean;
-        m2 += m2b + d * d * (wsum * wb / wn);
-        mean += d * (wb / wn);
-        wsum = wn;
-      }
+      sw += xd[(w * 4 + 0) * 64 + lane];
+      swm += xd[(w * 4 + 1) * 64 + lane];
+      swq += xd[(w * 4 + 2) * 64 + lane];
+      n_cov += (int)xd[(w * 4 + 3) * 64 + lane];
     }
   }
+  float mean = 0.f, var = 0.f;
+  if (sw > 0.0) {
+    const double md = swm / sw;
+    mean = (float)md;
+    var = (float)fmax(swq / sw - md * md, 0.0);
+  }
   float tc = fmaxf(mean, tn);
-  float sd = wsum > 0.f ? sqrtf(fmaxf(m2 / wsum, 0.f)) : 1.f;
+  float sd = var > 0.f ? sqrtf(var) : 1.f;
   {
     float qq = 1.f + 0.8f * tc, xn = 1.f + 0.8f * tn;
     float gp = 1.2f * xn * sqrtf(xn) / (qq * qq * sqrtf(qq));  // g_hat'(tc)
