@@ -348,7 +348,7 @@ template <int K, int NQ, int SUR>
 __global__ __launch_bounds__(256, (K == 4 && NQ == 4) ? 3 : 2) void k_render_bwd(BwdArgs ba, CamSet cams) {
   constexpr int NH = K / 2;
   constexpr int NL = (NH + 1) * (NH + 2) / 2;
-  constexpr int NRES = SUR ? 9 : K + 1;  // results per queued pair
+  constexpr int NRES = SUR ? 9 : 8;  // results per queued pair ([k][64], or [64][8] in the plain pass 2)
   const RenderArgs& a = ba.r;
   __shared__ Stage st;
   __shared__ int sk[kBlock];
@@ -720,20 +720,26 @@ __global__ __launch_bounds__(256, (K == 4 && NQ == 4) ? 3 : 2) void k_render_bwd
         gmu += gbar * dq0;
         gsig += gbar * dq1;
         gom += gbar * dq2;
+        static_assert(K + 1 <= 8, "eight result slots per pair");
+        float e8[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int k = 0; k <= K; ++k) res[k * 64 + lane] = d[k];
+        for (int k = 0; k <= K; ++k) e8[k] = d[k];
+        float4* r4 = reinterpret_cast<float4*>(res + lane * 8);
+        r4[0] = make_float4(e8[0], e8[1], e8[2], e8[3]);
+        r4[1] = make_float4(e8[4], e8[5], e8[6], e8[7]);
         chain_record(gmu, gsig, gom, g, lamp, dx, dy, st.f[2][j], st.f[3][j], st.f[4][j], gr);
         gr[G_CR] = s.q * gap[0];
         gr[G_CG] = s.q * gap[1];
         gr[G_CB] = s.q * gap[2];
       }
       __builtin_amdgcn_wave_barrier();
-      while (own) {
-        const int i = __builtin_ctzll(own);
-        own &= own - 1;
+      const float4* r4 = reinterpret_cast<const float4*>(res);
+      for_each_own(
+          own, [&](int i) __attribute__((always_inline)) { return make_float2x4(r4[i * 2], r4[i * 2 + 1]); },
+          [&](const Float8& v) __attribute__((always_inline)) {
 #pragma unroll
-        for (int k = 0; k <= K; ++k) dm[k] += res[k * 64 + i];
-      }
+            for (int k = 0; k <= K; ++k) dm[k] += v.f[k];
+          });
       reduce_to_slots<false>(gr, act, j, n, lane, cont_j, carry_j, cw, ba.partials, sk, quad);
     };
     for (int b = rg.x; b < rg.y; b += kBlock) {

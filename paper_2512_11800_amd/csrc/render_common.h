@@ -108,6 +108,31 @@ __device__ __forceinline__ void queue_from_masks(WaveQueue& q, QueueCursor& qc, 
   }
 }
 
+struct Float8 {
+  float f[8];
+};
+__device__ __forceinline__ Float8 make_float2x4(float4 a, float4 b) {
+  return Float8{{a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w}};
+}
+
+// Owner accumulation: calls add(load(i)) for this lane's own queue positions
+// i (bits of `own`) in increasing order, two positions per iteration with
+// both loads issued before either value is consumed.
+template <class Load, class Add>
+__device__ __forceinline__ void for_each_own(uint64_t own, Load&& load, Add&& add) {
+  while (own) {
+    const int i0 = __builtin_ctzll(own);
+    own &= own - 1;
+    const bool two = own != 0;
+    const int i1 = two ? __builtin_ctzll(own) : i0;
+    own &= own - 1;
+    const auto v0 = load(i0);
+    const auto v1 = load(i1);
+    add(v0);
+    if (two) add(v1);
+  }
+}
+
 // value of pixel lane p (all lanes must take part)
 __device__ __forceinline__ float from_lane(float v, int p) { return __shfl(v, p, 64); }
 
