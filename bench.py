@@ -198,7 +198,7 @@ def gpu_bench(args):
                                    f"mb::k_render_fwd<{args.k}, {opts.n_intervals + 1}, 0>")
     if last == "fwdbwd":
         out["roofline_bwd"] = roofline("render_backward", "k_render_bwd", fl["backward"],
-                                       f"mb::k_render_bwd<{args.k}, {opts.n_intervals + 1}>")
+                                       f"mb::k_render_bwd<{args.k}, {opts.n_intervals + 1}, 0>")
     for r in res.values():
         r.pop("stages_raw")
     return out, scene, cams, opts, n_pairs
