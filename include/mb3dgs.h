@@ -75,7 +75,7 @@ typedef struct mb_camera {
 /* Method options. Defaults (mb_default_options) are the paper's printed
  * constants where it gives them. */
 typedef struct mb_options {
-  int32_t n_moments;   /* K power moments beyond m_0: 4 or 6 (K+1 values)   */
+  int32_t n_moments;   /* K power moments beyond m_0: 4, 6 or 8 (K+1 values) */
   int32_t n_intervals; /* N quadrature intervals (N+1 edges): 3 or 5         */
   float kappa;         /* sample spread of the edges, App. B (3)             */
   float conf_c;        /* confidence level c of the proxy, App. D (0.01)     */
@@ -94,7 +94,7 @@ int32_t mb_version(void);
 /* Workspace sizes. The Gaussian workspace holds per-(camera, Gaussian)
  * records and tile counts; the pair workspace holds the per-tile lists for
  * n_entries (camera, tile, Gaussian) entries, the backward partials, and each
- * pixel's moment sums (7 doubles per pixel), which the forward pass leaves
+ * pixel's moment sums (9 doubles per pixel), which the forward pass leaves
  * for the backward pass.
  * Both are caller-allocated device memory, 256-byte aligned. */
 size_t mb_gauss_workspace_bytes(int32_t n, int32_t n_cams);

@@ -159,7 +159,8 @@ int check_common(const mb_gaussians* g, const mb_camera* cams, int n_cams, const
     if (!(c.fx > 0.f) || !(c.fy > 0.f) || !(c.t_near > 0.f))
       return fail(MB_ERR_ARG, "camera %d: focal lengths and t_near must be positive", i);
   }
-  if (o->n_moments != 4 && o->n_moments != 6) return fail(MB_ERR_UNSUPPORTED, "n_moments %d: only 4 and 6", o->n_moments);
+  if (o->n_moments != 4 && o->n_moments != 6 && o->n_moments != 8)
+    return fail(MB_ERR_UNSUPPORTED, "n_moments %d: only 4, 6 and 8", o->n_moments);
   if (o->n_intervals != 3 && o->n_intervals != 5)
     return fail(MB_ERR_UNSUPPORTED, "n_intervals %d: only 3 and 5", o->n_intervals);
   if (!(o->conf_c > 0.f && o->conf_c < 1.f)) return fail(MB_ERR_ARG, "conf_c must be in (0, 1)");

@@ -31,7 +31,7 @@ constexpr double kMinDepth = 1e-20;  // optical depth below which a pixel is emp
 // covering count) and harvested training sample (6 features, query, m0,
 // transmittance, selection hash bits, pixel index, record * (N+1) + edge)
 constexpr int kPixFeat = 10;
-constexpr int kMaxMoments = 6;  // highest moment order K supported
+constexpr int kMaxMoments = 8;  // highest moment order K supported
 // Heavy tiles (more list entries than kSplitEntries) are rendered by four
 // workgroups, one per 8x8 quadrant, whose four waves share the quadrant's
 // pixels and take every fourth list entry. The decision depends on the tile's

@@ -127,15 +127,92 @@ __device__ __forceinline__ void roots3(const float* c, float* x) {
   x[2] = cubic_newton(c, x2[1], 2);
 }
 
-struct Canon3 {  // canonical representation at one query, n <= 3
-  float x[3];
-  float w[3];
+__device__ __forceinline__ float quartic_newton(const float* c, float x, int iters) {
+  for (int it = 0; it < iters; ++it) {
+    float p = (((c[4] * x + c[3]) * x + c[2]) * x + c[1]) * x + c[0];
+    float dp = ((4.f * c[4] * x + 3.f * c[3]) * x + 2.f * c[2]) * x + c[1];
+    float st = p * fast_rcp(dp);
+    x = (dp != 0.f && isfinite(st)) ? x - st : x;
+  }
+  return x;
+}
+
+// Laguerre's iteration on the monic quartic x^4 + a3 x^3 + a2 x^2 + a1 x + a0.
+// Started just outside the roots of a polynomial whose roots are all real,
+// it moves monotonically to the nearest (extreme) root.
+__device__ __forceinline__ float laguerre4(const float* a, float x, int iters) {
+  for (int it = 0; it < iters; ++it) {
+    float p = (((x + a[3]) * x + a[2]) * x + a[1]) * x + a[0];
+    float d1 = ((4.f * x + 3.f * a[3]) * x + 2.f * a[2]) * x + a[1];
+    float d2 = (12.f * x + 6.f * a[3]) * x + 2.f * a[2];
+    float ip = fast_rcp(p);
+    float g = d1 * ip;
+    float h = g * g - d2 * ip;
+    float sq = fast_sqrt(fmaxf(3.f * (4.f * h - g * g), 0.f));
+    float den = g >= 0.f ? g + sq : g - sq;
+    float st = 4.f * fast_rcp(den);
+    x = (p != 0.f && den != 0.f && isfinite(st)) ? x - st : x;
+  }
+  return x;
+}
+
+// Real roots of c0 + c1 x + .. + c4 x^4 (four real roots for a positive
+// definite Hankel matrix). By Samuelson's inequality every root lies within
+// mean +- sqrt(3) sd of the roots (both read off the two leading
+// coefficients); Laguerre's iteration from just outside that interval on
+// either side gives the two extreme roots. The one of larger magnitude is
+// divided out from the low-order end (stable for the dominant root), the
+// cubic left over goes to roots3, and every root gets Newton steps on the
+// full quartic. A vanishing leading coefficient sends one atom to infinity.
+__device__ __forceinline__ void roots4(const float* c, float* x) {
+  float scale = fabsf(c[0]) + fabsf(c[1]) + fabsf(c[2]) + fabsf(c[3]) + fabsf(c[4]);
+  if (!(fabsf(c[4]) > 1e-12f * scale)) {
+    roots3(c, x);
+    x[3] = copysignf(1e30f, -c[3] * c[4]);
+    return;
+  }
+  float inv = fast_rcp(c[4]);
+  float a[4] = {c[0] * inv, c[1] * inv, c[2] * inv, c[3] * inv};
+  float mean = -0.25f * a[3];
+  float var = fmaxf(0.25f * (a[3] * a[3] - 2.f * a[2]) - mean * mean, 0.f);
+  float half = fast_sqrt(3.f * var) * 1.0001f + 1e-6f * (fabsf(mean) + 1.f);
+  float hi = laguerre4(a, mean + half, 4);
+  float lo = laguerre4(a, mean - half, 4);
+  float big = quartic_newton(c, fabsf(hi) >= fabsf(lo) ? hi : lo, 1);
+  // p(x) = (x - big)(A x^3 + B x^2 + C x + D), matched from the constant term up
+  float ib = fast_rcp(big);
+  float d = -c[0] * ib;
+  float cc = (d - c[1]) * ib;
+  float b = (cc - c[2]) * ib;
+  float aa = (b - c[3]) * ib;
+  float qc[4] = {d, cc, b, aa};
+  float x3[3];
+  roots3(qc, x3);
+  x[0] = big;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) x[i + 1] = quartic_newton(c, x3[i], 2);
+}
+
+template <int NH>
+__device__ __forceinline__ void kernel_roots(const float* c, float* x) {
+  static_assert(NH >= 2 && NH <= 4, "two to four atoms besides the query");
+  if constexpr (NH == 2)
+    roots2(c, x);
+  else if constexpr (NH == 3)
+    roots3(c, x);
+  else
+    roots4(c, x);
+}
+
+struct Canon {  // canonical representation at one query, n <= 4
+  float x[4];
+  float w[4];
   float w0;
 };
 
 // Normalised interpolated bound F(y) = sum_{x_i<y} w_i + beta w_0.
 template <int NH>
-__device__ __forceinline__ float bound_F(const LInv<NH>& L, float y, float beta, Canon3* out = nullptr) {
+__device__ __forceinline__ float bound_F(const LInv<NH>& L, float y, float beta, Canon* out = nullptr) {
   float z[NH + 1], c[NH + 1], x[NH];
   linv_apply<NH>(L, y, z);
   float zz = 0.f;
@@ -143,7 +220,7 @@ __device__ __forceinline__ float bound_F(const LInv<NH>& L, float y, float beta,
   for (int i = 0; i <= NH; ++i) zz += z[i] * z[i];
   float w0 = fast_rcp(zz);
   linv_t_apply<NH>(L, z, c);
-  if constexpr (NH == 2) roots2(c, x); else roots3(c, x);
+  kernel_roots<NH>(c, x);
   float lo = 0.f;
 #pragma unroll
   for (int i = 0; i < NH; ++i) {
@@ -169,7 +246,7 @@ __device__ __forceinline__ float canon_at(const LInv<NH>& L, float y, float beta
   for (int i = 0; i <= NH; ++i) zz += z[i] * z[i];
   w0 = fast_rcp(zz);
   linv_t_apply<NH>(L, z, c);
-  if constexpr (NH == 2) roots2(c, x); else roots3(c, x);
+  kernel_roots<NH>(c, x);
   float lo = 0.f;
 #pragma unroll
   for (int i = 0; i < NH; ++i) {

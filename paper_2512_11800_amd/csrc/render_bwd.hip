@@ -348,7 +348,8 @@ template <int K, int NQ, int SUR>
 __global__ __launch_bounds__(256, (K == 4 && NQ == 4) ? 3 : 2) void k_render_bwd(BwdArgs ba, CamSet cams) {
   constexpr int NH = K / 2;
   constexpr int NL = (NH + 1) * (NH + 2) / 2;
-  constexpr int NRES = SUR ? 9 : 8;  // results per queued pair ([k][64], or [64][8] in the plain pass 2)
+  constexpr int RS = (K + 4) / 4 * 4;  // plain pass 2: K + 1 adjoint moments per pair, padded to float4s
+  constexpr int NRES = SUR ? 9 : RS;   // results per queued pair ([k][64], or [64][RS] in the plain pass 2)
   const RenderArgs& a = ba.r;
   __shared__ Stage st;
   __shared__ int sk[kBlock];
@@ -720,13 +721,12 @@ __global__ __launch_bounds__(256, (K == 4 && NQ == 4) ? 3 : 2) void k_render_bwd
         gmu += gbar * dq0;
         gsig += gbar * dq1;
         gom += gbar * dq2;
-        static_assert(K + 1 <= 8, "eight result slots per pair");
-        float e8[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        float e[RS];
 #pragma unroll
-        for (int k = 0; k <= K; ++k) e8[k] = d[k];
-        float4* r4 = reinterpret_cast<float4*>(res + lane * 8);
-        r4[0] = make_float4(e8[0], e8[1], e8[2], e8[3]);
-        r4[1] = make_float4(e8[4], e8[5], e8[6], e8[7]);
+        for (int k = 0; k < RS; ++k) e[k] = k <= K ? d[k] : 0.f;
+        float4* r4 = reinterpret_cast<float4*>(res + lane * RS);
+#pragma unroll
+        for (int q4 = 0; q4 < RS / 4; ++q4) r4[q4] = make_float4(e[4 * q4], e[4 * q4 + 1], e[4 * q4 + 2], e[4 * q4 + 3]);
         chain_record(gmu, gsig, gom, g, lamp, dx, dy, st.f[2][j], st.f[3][j], st.f[4][j], gr);
         gr[G_CR] = s.q * gap[0];
         gr[G_CG] = s.q * gap[1];
@@ -734,11 +734,21 @@ __global__ __launch_bounds__(256, (K == 4 && NQ == 4) ? 3 : 2) void k_render_bwd
       }
       __builtin_amdgcn_wave_barrier();
       const float4* r4 = reinterpret_cast<const float4*>(res);
+      struct Slots {
+        float4 q[RS / 4];
+      };
       for_each_own(
-          own, [&](int i) __attribute__((always_inline)) { return make_float2x4(r4[i * 2], r4[i * 2 + 1]); },
-          [&](const Float8& v) __attribute__((always_inline)) {
+          own,
+          [&](int i) __attribute__((always_inline)) {
+            Slots v;
 #pragma unroll
-            for (int k = 0; k <= K; ++k) dm[k] += v.f[k];
+            for (int q4 = 0; q4 < RS / 4; ++q4) v.q[q4] = r4[i * (RS / 4) + q4];
+            return v;
+          },
+          [&](const Slots& v) __attribute__((always_inline)) {
+            const float* f = reinterpret_cast<const float*>(v.q);
+#pragma unroll
+            for (int k = 0; k <= K; ++k) dm[k] += f[k];
           });
       reduce_to_slots<false>(gr, act, j, n, lane, cont_j, carry_j, cw, ba.partials, sk, quad);
     };
@@ -833,6 +843,8 @@ hipError_t launch_render_backward(const RenderArgs& r, const float* saved, const
   MB_LAUNCH(6, 3, 0)
   MB_LAUNCH(4, 5, 0)
   MB_LAUNCH(6, 5, 0)
+  MB_LAUNCH(8, 3, 0)
+  MB_LAUNCH(8, 5, 0)
   MB_LAUNCH(6, 3, 1)
   MB_LAUNCH(6, 5, 1)
 #undef MB_LAUNCH

@@ -108,13 +108,6 @@ __device__ __forceinline__ void queue_from_masks(WaveQueue& q, QueueCursor& qc, 
   }
 }
 
-struct Float8 {
-  float f[8];
-};
-__device__ __forceinline__ Float8 make_float2x4(float4 a, float4 b) {
-  return Float8{{a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w}};
-}
-
 // Owner accumulation: calls add(load(i)) for this lane's own queue positions
 // i (bits of `own`) in increasing order, two positions per iteration with
 // both loads issued before either value is consumed.

@@ -599,6 +599,8 @@ hipError_t launch_render_forward(const RenderArgs& a, const CamSet& cams, int n_
   MB_LAUNCH(6, 3, kModePlain)
   MB_LAUNCH(4, 5, kModePlain)
   MB_LAUNCH(6, 5, kModePlain)
+  MB_LAUNCH(8, 3, kModePlain)
+  MB_LAUNCH(8, 5, kModePlain)
   MB_LAUNCH(6, 3, kModeHarvest)
   MB_LAUNCH(6, 5, kModeHarvest)
   MB_LAUNCH(6, 3, kModeEmit)

@@ -65,6 +65,19 @@ def test_fd_subset_k6_vs_oracle_autograd():
     assert _check(gpu, ref, "fd-subset K=6", tol=3e-3)
 
 
+def test_fd_subset_k8_vs_oracle_autograd():
+    """Eight moments (the four-atom canonical representation, quartic kernel
+    polynomial)."""
+    scene, cams, opts = W.w3_fd_subset()
+    scene = scene.subset(np.arange(200))
+    opts.n_moments = 8
+    rng = np.random.default_rng(14)
+    g_img = rng.normal(size=(64 * 64, 3))
+    gpu, _ = _gpu_grads(scene, cams, opts, g_img)
+    ref = oracle.render_backward(scene, cams[0], opts, g_img)
+    assert _check(gpu, ref, "fd-subset K=8", tol=3e-3)
+
+
 def test_w1_proxy_coverage_vs_oracle_autograd():
     """The real proxy coverage (W1); upstream gradient zero on ambiguous pixels."""
     scene, cams, opts = W.w1_small()

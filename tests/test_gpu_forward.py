@@ -29,7 +29,7 @@ def test_proxies_match_oracle():
     assert pe2["centre"] < 5e-3 and pe2["half"] < 5e-3 and pe2["orient"] < 1e-5
 
 
-@pytest.mark.parametrize("k_mom", [4, 6])
+@pytest.mark.parametrize("k_mom", [4, 6, 8])
 def test_w1_full_image(k_mom):
     scene, cams, opts = W.w1_small()
     opts.n_moments = k_mom
@@ -65,7 +65,7 @@ def _sample_pixels(scene, cam, n_random=150, n_dense=150, seed=0):
     return np.unique(np.concatenate([rnd, dense]))
 
 
-@pytest.mark.parametrize("k_mom", [4, 6])
+@pytest.mark.parametrize("k_mom", [4, 6, 8])
 def test_w2_full_size_sampled(k_mom):
     """500k Gaussians at 1920x1080, the configuration the benchmark times;
     the oracle computes a sample of pixels one by one."""
@@ -82,7 +82,7 @@ def test_w2_full_size_sampled(k_mom):
     assert mx <= TOL
 
 
-@pytest.mark.parametrize("k_mom", [4, 6])
+@pytest.mark.parametrize("k_mom", [4, 6, 8])
 def test_full_coverage_subset(k_mom):
     """Every Gaussian on every pixel (debug coverage of the gradient checks):
     pixels far from all Gaussians have optical depths near float32 underflow."""
@@ -136,6 +136,9 @@ def test_errors_are_raised_not_crashed():
     import paper_2512_11800_amd as M
     scene, cams, opts = W.w1_small()
     g = M.Gaussians.from_scene(scene)
-    opts.n_moments = 8
+    opts.n_moments = 10
+    with pytest.raises(M.MbError):
+        M.render_forward(g, cams, opts)
+    opts.n_moments = 5
     with pytest.raises(M.MbError):
         M.render_forward(g, cams, opts)

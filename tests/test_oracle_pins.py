@@ -148,7 +148,7 @@ def test_moments_affine_variable_change():
 # Sec. 3.2 reconstruction: canonical representation and bounds.
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("n", [2, 3])
+@pytest.mark.parametrize("n", [2, 3, 4])
 def test_canonical_representation_recovers_atomic_measure(n):
     """A measure with n+1 atoms queried at one of its atoms is its own
     canonical representation (uniqueness), so L and U are its step values."""
@@ -169,7 +169,7 @@ def test_canonical_representation_recovers_atomic_measure(n):
         assert tau.item() == pytest.approx(m0 * (w[:j].sum() + 0.25 * w[j]), abs=1e-9)
 
 
-@pytest.mark.parametrize("n", [2, 3])
+@pytest.mark.parametrize("n", [2, 3, 4])
 def test_bounds_are_sharp_lp_bounds(n):
     """L and U are the smallest and largest mass on (-inf, eta) resp.
     (-inf, eta] over all measures with the given moments; compare with a
@@ -191,7 +191,7 @@ def test_bounds_are_sharp_lp_bounds(n):
         assert lo.item() <= true_cdf + 1e-12 <= up.item() + 2e-12
 
 
-@pytest.mark.parametrize("n", [2, 3])
+@pytest.mark.parametrize("n", [2, 3, 4])
 def test_canonical_nodes_reproduce_all_moments_and_christoffel_weight(n):
     rng = np.random.default_rng(7 + n)
     comps = rng.uniform(-1, 1, 5)
@@ -212,7 +212,7 @@ def test_canonical_nodes_reproduce_all_moments_and_christoffel_weight(n):
 
 def test_tau_monotone_and_bounded():
     rng = np.random.default_rng(3)
-    for n in (2, 3):
+    for n in (2, 3, 4):
         for _ in range(5):
             grid = np.linspace(-3, 3, 2001)
             dens = sum(rng.uniform(0.1, 1) * np.exp(-(grid - rng.uniform(-2, 2)) ** 2
@@ -403,7 +403,7 @@ def _tiny_scene(seed=0, n=6, rgb=None):
                    dens.astype(np.float32), colors.astype(np.float32), -1)
 
 
-@pytest.mark.parametrize("k_mom", [4, 6])
+@pytest.mark.parametrize("k_mom", [4, 6, 8])
 def test_single_colour_scene_renders_exact_opacity(k_mom):
     """S = c O when every Gaussian has colour c, so Eq. 15 gives exactly
     c (1 - e^-m0) + e^-m0 bg, and m0 is the exact optical depth: compare
@@ -565,7 +565,7 @@ def test_linearisation_point():
     assert g.item() == pytest.approx((warp(tn, tn) - c) / s + gp.item() * (mu - tn), rel=1e-14)
 
 
-@pytest.mark.parametrize("n", [2, 3])
+@pytest.mark.parametrize("n", [2, 3, 4])
 def test_bounds_invariant_under_affine_moment_variable(n):
     """The canonical representation maps onto itself under y' = (y - a)/b,
     b > 0, so tau(eta) computed from transformed moments at the transformed
