@@ -38,9 +38,11 @@ def flops_per_pair(k_mom: int, n_int: int) -> dict:
       moments    the recurrence of Eqs. 10-12 (18 + 7 (K - 1) + K + 1)
       recon      one reconstruction of the bounds at a query: L^-1 v(y),
                  kernel-polynomial roots, Christoffel weights, interpolation
-                 (73 for K = 4, 169 for K = 6 with its cubic)
+                 (73 for K = 4, 169 for K = 6 with its cubic, 340 for K = 8
+                 with a quartic counted at the ~80 operations of a closed
+                 form; the kernel's iterative quartic solve spends more)
       hermite    the adjoint of one reconstruction: divided differences of the
-                 Hermite interpolant and its monomial form (85 / 165)
+                 Hermite interpolant and its monomial form (85 / 165 / 232)
       quadrature ray + (N + 1) (13 + recon) + 9 N + 8 (edges, warp, sigma_i,
                  the Eq. 7 interval terms)
       chain      (mu, Sigma, omega) adjoint to the record's coefficients,
@@ -55,8 +57,8 @@ def flops_per_pair(k_mom: int, n_int: int) -> dict:
     n = k_mom // 2
     ray, warp_lin, chain = 37, 12, 70
     mom = 18 + 7 * (k_mom - 1) + (k_mom + 1)
-    recon = 73 if n == 2 else 169
-    herm = 85 if n == 2 else 165
+    recon = {2: 73, 3: 169, 4: 340}[n]
+    herm = {2: 85, 3: 165, 4: 232}[n]
     quad = ray + (n_int + 1) * (13 + recon) + 9 * n_int + 8
     out = {"moment_pass": ray + warp_lin + mom, "quadrature_pass": quad}
     out["forward"] = out["moment_pass"] + out["quadrature_pass"]
@@ -372,7 +374,7 @@ def main():
     ap.add_argument("--harvest", type=int, default=10_000_000)
     ap.add_argument("--train-steps", type=int, default=4000)
     ap.add_argument("--gt-pixels", type=int, default=32)
-    ap.add_argument("--k", type=int, default=4, choices=[4, 6])
+    ap.add_argument("--k", type=int, default=4, choices=[4, 6, 8])
     ap.add_argument("--workload", choices=["w2", "w3", "w5"], default="w2",
                     help="w2: 500k Gaussians, one 1080p camera (the metric's workload); "
                          "w3: training step, 1M Gaussians at 1600x1064 with an L1 loss against a "
