@@ -78,6 +78,20 @@ def test_fd_subset_k8_vs_oracle_autograd():
     assert _check(gpu, ref, "fd-subset K=8", tol=3e-3)
 
 
+@pytest.mark.parametrize("k_mom", [4, 6, 8])
+def test_fd_subset_five_intervals_vs_oracle_autograd(k_mom):
+    """N = 5 quadrature intervals (six edges per Gaussian)."""
+    scene, cams, opts = W.w3_fd_subset()
+    scene = scene.subset(np.arange(200))
+    opts.n_moments = k_mom
+    opts.n_intervals = 5
+    rng = np.random.default_rng(20 + k_mom)
+    g_img = rng.normal(size=(64 * 64, 3))
+    gpu, _ = _gpu_grads(scene, cams, opts, g_img)
+    ref = oracle.render_backward(scene, cams[0], opts, g_img)
+    assert _check(gpu, ref, f"fd-subset K={k_mom} N=5", tol=3e-3)
+
+
 def test_w1_proxy_coverage_vs_oracle_autograd():
     """The real proxy coverage (W1); upstream gradient zero on ambiguous pixels."""
     scene, cams, opts = W.w1_small()

@@ -49,6 +49,20 @@ def test_w1_full_image(k_mom):
     assert m0_err[keep].max() < 1e-4 * max(1.0, ref2["moments"][:, 0].max())
 
 
+@pytest.mark.parametrize("k_mom", [4, 6, 8])
+def test_w1_five_intervals(k_mom):
+    """N = 5 quadrature intervals (six edges per Gaussian)."""
+    scene, cams, opts = W.w1_small()
+    opts.n_moments = k_mom
+    opts.n_intervals = 5
+    img, saved, st = gpu_render(scene, cams, opts)
+    pe = proxy_error(scene, cams[0], opts)
+    tol_m, tol_o = tolerances(pe)
+    ref = oracle.render_image(scene, cams[0], opts, margin_tol=tol_m, orient_eps=tol_o)
+    mx, _ = compare(img[0].reshape(-1, 3), ref, f"W1 K={k_mom} N=5")
+    assert mx <= TOL
+
+
 def _sample_pixels(scene, cam, n_random=150, n_dense=150, seed=0):
     rng = np.random.default_rng(seed)
     rnd = rng.integers(0, cam.width * cam.height, n_random)

@@ -37,7 +37,7 @@ def _check_map(pen, ref, keep, label):
     assert worst <= 1e-4
 
 
-@pytest.mark.parametrize("k_mom", [4, 6])
+@pytest.mark.parametrize("k_mom", [4, 6, 8])
 def test_penalty_map_w1(k_mom):
     scene, cams, opts = W.w1_small()
     opts.n_moments = k_mom
