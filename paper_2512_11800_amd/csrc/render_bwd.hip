@@ -277,19 +277,49 @@ __device__ __forceinline__ ScanMasks scan_masks(int lane, int seg_start) {
   s.m[5] = (lane >> 5) && seg_start <= 31 ? 1.f : 0.f;         // takes lane 31
   return s;
 }
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ float dpp_move(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, true));
+// The scan of all 18 gradient fields in one block of v_fmac_f32 with a DPP
+// source (v += (v moved) * mask; the compiler would emit a separate move for
+// each), step by step over the fields. A DPP read of a VGPR written by a
+// VALU instruction needs two wait states: within the block every read comes
+// 18 instructions after the write it depends on, and the s_nop covers the
+// values written just before the block.
+static_assert(G_COUNT == 18, "the scan block is written for 18 fields");
+#define MB_SCAN_STEP(M, CTRL) \
+  "v_fmac_f32_dpp %0, %0, " M " " CTRL "\n\t" \
+  "v_fmac_f32_dpp %1, %1, " M " " CTRL "\n\t" \
+  "v_fmac_f32_dpp %2, %2, " M " " CTRL "\n\t" \
+  "v_fmac_f32_dpp %3, %3, " M " " CTRL "\n\t" \
+  "v_fmac_f32_dpp %4, %4, " M " " CTRL "\n\t" \
+  "v_fmac_f32_dpp %5, %5, " M " " CTRL "\n\t" \
+  "v_fmac_f32_dpp %6, %6, " M " " CTRL "\n\t" \
+  "v_fmac_f32_dpp %7, %7, " M " " CTRL "\n\t" \
+  "v_fmac_f32_dpp %8, %8, " M " " CTRL "\n\t" \
+  "v_fmac_f32_dpp %9, %9, " M " " CTRL "\n\t" \
+  "v_fmac_f32_dpp %10, %10, " M " " CTRL "\n\t" \
+  "v_fmac_f32_dpp %11, %11, " M " " CTRL "\n\t" \
+  "v_fmac_f32_dpp %12, %12, " M " " CTRL "\n\t" \
+  "v_fmac_f32_dpp %13, %13, " M " " CTRL "\n\t" \
+  "v_fmac_f32_dpp %14, %14, " M " " CTRL "\n\t" \
+  "v_fmac_f32_dpp %15, %15, " M " " CTRL "\n\t" \
+  "v_fmac_f32_dpp %16, %16, " M " " CTRL "\n\t" \
+  "v_fmac_f32_dpp %17, %17, " M " " CTRL "\n\t" \
+
+#define MB_ROW(C) "row_shr:" C " row_mask:0xf bank_mask:0xf bound_ctrl:1"
+__device__ __forceinline__ void segment_scan18(float* g, const ScanMasks& s) {
+  asm("s_nop 1\n\t"
+      MB_SCAN_STEP("%18", MB_ROW("1"))
+      MB_SCAN_STEP("%19", MB_ROW("2"))
+      MB_SCAN_STEP("%20", MB_ROW("4"))
+      MB_SCAN_STEP("%21", MB_ROW("8"))
+      MB_SCAN_STEP("%22", "row_bcast:15 row_mask:0xa bank_mask:0xf bound_ctrl:1")
+      MB_SCAN_STEP("%23", "row_bcast:31 row_mask:0xc bank_mask:0xf bound_ctrl:1")
+      : "+v"(g[0]), "+v"(g[1]), "+v"(g[2]), "+v"(g[3]), "+v"(g[4]), "+v"(g[5]), "+v"(g[6]), "+v"(g[7]),
+        "+v"(g[8]), "+v"(g[9]), "+v"(g[10]), "+v"(g[11]), "+v"(g[12]), "+v"(g[13]), "+v"(g[14]),
+        "+v"(g[15]), "+v"(g[16]), "+v"(g[17])
+      : "v"(s.m[0]), "v"(s.m[1]), "v"(s.m[2]), "v"(s.m[3]), "v"(s.m[4]), "v"(s.m[5]));
 }
-__device__ __forceinline__ float segment_scan(float v, const ScanMasks& s) {
-  v = fmaf(dpp_move<0x111, 0xf>(v), s.m[0], v);  // row_shr:1
-  v = fmaf(dpp_move<0x112, 0xf>(v), s.m[1], v);  // row_shr:2
-  v = fmaf(dpp_move<0x114, 0xf>(v), s.m[2], v);  // row_shr:4
-  v = fmaf(dpp_move<0x118, 0xf>(v), s.m[3], v);  // row_shr:8
-  v = fmaf(dpp_move<0x142, 0xa>(v), s.m[4], v);  // row_bcast:15
-  v = fmaf(dpp_move<0x143, 0xc>(v), s.m[5], v);  // row_bcast:31
-  return v;
-}
+#undef MB_ROW
+#undef MB_SCAN_STEP
 
 // Per-entry sums of the gradients gr[] of the evaluated queue positions
 // [0, n): queued pairs of one entry are contiguous, a segmented scan over the
@@ -306,9 +336,7 @@ __device__ __forceinline__ void reduce_to_slots(float* gr, bool act, int j, int 
   const int seg_start = 63 - __builtin_clzll(heads & upto);
   const int jnext = __shfl_down(j, 1, 64);
   const bool last = act && (lane == n - 1 || jnext != j);
-  const ScanMasks sm = scan_masks(lane, seg_start);
-#pragma unroll
-  for (int f = 0; f < G_COUNT; ++f) gr[f] = segment_scan(gr[f], sm);
+  segment_scan18(gr, scan_masks(lane, seg_start));
   if (last) {
     if (seg_start == 0 && j == carry_j) {
 #pragma unroll
