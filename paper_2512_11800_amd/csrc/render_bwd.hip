@@ -326,9 +326,35 @@ __device__ __forceinline__ void segment_scan18(float* g, const ScanMasks& s) {
 // lanes sums each entry's pairs and the segment's last lane writes (ADD =
 // false) or adds to (ADD = true) the entry's slot. An entry that continues
 // past position n - 1 (cont_j) leaves its partial sum in `carry`.
+// The slot a segment's last lane adds to (pass 3), loaded before the pass's
+// arithmetic so that the load's latency hides behind it; zero elsewhere.
+struct SlotVals {
+  float4 s[5];
+};
+__device__ __forceinline__ bool writes_slot(bool act, int j, int n, int lane, int cont_j) {
+  const int jnext = __shfl_down(j, 1, 64);
+  const bool last = act && (lane == n - 1 || jnext != j);
+  return last && !(lane == n - 1 && j == cont_j);
+}
+__device__ __forceinline__ SlotVals load_slot(bool w, int j, const float* partials, const int* sk, int wave) {
+  SlotVals v;
+  if (w) {
+    const float4* slot = reinterpret_cast<const float4*>(partials + ((size_t)sk[j] * 4 + wave) * kGradStride);
+#pragma unroll
+    for (int f = 0; f < 5; ++f) v.s[f] = slot[f];
+  } else {
+#pragma unroll
+    for (int f = 0; f < 5; ++f) v.s[f] = make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+  return v;
+}
+
+// ADD = true adds the slot's earlier contents, passed in as `prev` (see
+// load_slot); ADD = false overwrites the slot.
 template <bool ADD>
 __device__ __forceinline__ void reduce_to_slots(float* gr, bool act, int j, int n, int lane, int cont_j, int& carry_j,
-                                                float* carry, float* partials, const int* sk, int wave) {
+                                                float* carry, float* partials, const int* sk, int wave,
+                                                const SlotVals* prev = nullptr) {
   const int jprev = __shfl_up(j, 1, 64);
   const bool head = !act || lane == 0 || jprev != j;
   const uint64_t heads = __ballot(head);
@@ -348,12 +374,9 @@ __device__ __forceinline__ void reduce_to_slots(float* gr, bool act, int j, int 
     } else {
       float4* slot = reinterpret_cast<float4*>(partials + ((size_t)sk[j] * 4 + wave) * kGradStride);
       if constexpr (ADD) {
-        float4 s0 = slot[0], s1 = slot[1], s2 = slot[2], s3 = slot[3], s4 = slot[4];
-        gr[0] += s0.x; gr[1] += s0.y; gr[2] += s0.z; gr[3] += s0.w;
-        gr[4] += s1.x; gr[5] += s1.y; gr[6] += s1.z; gr[7] += s1.w;
-        gr[8] += s2.x; gr[9] += s2.y; gr[10] += s2.z; gr[11] += s2.w;
-        gr[12] += s3.x; gr[13] += s3.y; gr[14] += s3.z; gr[15] += s3.w;
-        gr[16] += s4.x; gr[17] += s4.y;
+        const float* pv = reinterpret_cast<const float*>(prev->s);
+#pragma unroll
+        for (int f = 0; f < G_COUNT; ++f) gr[f] += pv[f];
       }
       slot[0] = make_float4(gr[0], gr[1], gr[2], gr[3]);
       slot[1] = make_float4(gr[4], gr[5], gr[6], gr[7]);
@@ -819,6 +842,7 @@ __global__ __launch_bounds__(256, (K == 4 && NQ == 4) ? 3 : 2) void k_render_bwd
     auto flush = [&](int n, int cont_j) __attribute__((always_inline)) {
       int j, p;
       const bool act = item_of(n, j, p);
+      const SlotVals prev = load_slot(writes_slot(act, j, n, lane, cont_j), j, ba.partials, sk, quad);
       const PixelBasis pp = basis_of(p);
       const float lamp = from_lane(lam, p);
       float dmp[K + 1];
@@ -835,7 +859,7 @@ __global__ __launch_bounds__(256, (K == 4 && NQ == 4) ? 3 : 2) void k_render_bwd
         moment_grads<K>(g, pp, tn, dmp, gm);
         chain_record(gm[0], gm[1], gm[2], g, lamp, dx, dy, st.f[2][j], st.f[3][j], st.f[4][j], gr);
       }
-      reduce_to_slots<true>(gr, act, j, n, lane, cont_j, carry_j, cw, ba.partials, sk, quad);
+      reduce_to_slots<true>(gr, act, j, n, lane, cont_j, carry_j, cw, ba.partials, sk, quad, &prev);
     };
     for (int b = rg.x; b < rg.y; b += kBlock) {
       int nb = min(kBlock, rg.y - b);
