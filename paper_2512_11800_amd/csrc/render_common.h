@@ -170,6 +170,27 @@ __device__ __forceinline__ bool covers(const Stage& st, int j, float u, float v,
   return inside && fabsf(c1) <= f1.z && fabsf(c2) <= f1.w;
 }
 
+// Which 8x8 quadrants of the tile at (x0, y0) the axis-aligned box of entry
+// j's rectangle reaches (bit q for quadrant q = 2 row + column). A pixel
+// centre inside the rectangle lies inside the box, whose half extents are
+// |e1x| h1 + |e1y| h2 and |e1y| h1 + |e1x| h2; the margin absorbs the
+// rounding of the per-pixel test, so the bits never miss a covered pixel.
+__device__ __forceinline__ uint8_t quadrants_reached(const Stage& st, int j, int x0, int y0) {
+  const float4 f0 = st.f[0][j], f1 = st.f[1][j];
+  const float cx = f0.x + f0.z, cy = f0.y + f0.w;
+  const float ax = fabsf(f1.x), ay = fabsf(f1.y);
+  const float mx = 0.01f + 1e-5f * fabsf(cx), my = 0.01f + 1e-5f * fabsf(cy);
+  const float ex = ax * f1.z + ay * f1.w + mx, ey = ay * f1.z + ax * f1.w + my;
+  uint8_t bits = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const float lx = (float)(x0 + (q & 1) * 8) + 0.5f, ly = (float)(y0 + (q >> 1) * 8) + 0.5f;
+    const bool hit = cx + ex >= lx && cx - ex <= lx + 7.f && cy + ey >= ly && cy - ey <= ly + 7.f;
+    bits |= hit ? (uint8_t)(1u << q) : (uint8_t)0;
+  }
+  return bits;
+}
+
 // Eqs. 4-6 for the pixel ray in the projected-mean frame (see common.h)
 __device__ __forceinline__ RayG ray_params(const Stage& st, int j, float dx, float dy, float lam) {
   float4 f2 = st.f[2][j], f3 = st.f[3][j], f4 = st.f[4][j];

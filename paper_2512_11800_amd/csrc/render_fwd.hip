@@ -110,6 +110,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
   const size_t pix = ((size_t)ci * c.height + (inside ? py : 0)) * c.width + (inside ? px : 0);
 
   __shared__ WaveQueue wq[4];
+  __shared__ uint8_t reach[kBlock];  // per staged entry: bit q set if its box reaches the tile's quadrant q
   // per-wave results of the queued pairs: 3 or K + 1 floats per pair in passes
   // 0 and 1, q (r, g, b, 1) in pass 2
   __shared__ __align__(16) float wres[4][(K + 1) * 64];
@@ -167,20 +168,34 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
       int nb = min(kBlock, rg.y - b);
       __syncthreads();
       load_batch(st, a.rec, a.sorted_rec, b, nb);
+      // each thread reads back the record it staged itself
+      if (tid < nb) reach[tid] = quadrants_reached(st, tid, tx * kTile, ty * kTile);
       __syncthreads();
       QueueCursor qc;
       queue_reset(qc);
-      for (int j = split ? wave : 0; j < nb; j += split ? 4 : 1) {
-        float dx, dy;
-        bool cov = covers(st, j, u, v, inside, dx, dy);
-        uint64_t mask = __ballot(cov);
-        if (lane == 0) a.masks[(size_t)(b + j) * 4 + quad] = mask;
-        if (mask == 0) continue;
-        n_cov += cov ? 1 : 0;
-        queue_push(q, qc, mask, cov, j, lane);
-        if (qc.cnt >= 64) {
-          flush(64, qc.own_lo);
-          queue_pop64(q, qc, lane);
+      // entries whose rectangle's box misses this wave's 8x8 block cover none
+      // of its pixels: their mask is zero and the per-pixel test is skipped;
+      // the others are tested in list order
+      for (int j0 = 0; j0 < nb; j0 += 64) {
+        const int jl = j0 + lane;
+        const bool mine = jl < nb && (own4 < 0 || (jl & 3) == own4);
+        const bool near = mine && ((reach[mine ? jl : 0] >> quad) & 1);
+        if (mine && !near) a.masks[(size_t)(b + jl) * 4 + quad] = 0ull;
+        uint64_t todo = __ballot(near);
+        while (todo) {
+          const int j = j0 + __builtin_ctzll(todo);
+          todo &= todo - 1;
+          float dx, dy;
+          bool cov = covers(st, j, u, v, inside, dx, dy);
+          uint64_t mask = __ballot(cov);
+          if (lane == 0) a.masks[(size_t)(b + j) * 4 + quad] = mask;
+          if (mask == 0) continue;
+          n_cov += cov ? 1 : 0;
+          queue_push(q, qc, mask, cov, j, lane);
+          if (qc.cnt >= 64) {
+            flush(64, qc.own_lo);
+            queue_pop64(q, qc, lane);
+          }
         }
       }
       if (qc.cnt > 0) flush(qc.cnt, qc.own_lo);
