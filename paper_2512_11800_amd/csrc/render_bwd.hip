@@ -229,12 +229,10 @@ struct BwdArgs {
 __device__ __forceinline__ void chain_record(float gmu, float gsig, float gom, const RayG& g, float lamp, float dx,
                                              float dy, const float4& f2, const float4& f3, const float4& f4,
                                              float* gr) {
-  float d = f2.x + 2.f * (f2.y * dx + f2.z * dy) + f2.w * dx * dx + 2.f * f3.x * dx * dy + f3.y * dy * dy;
-  float x = f4.y * dx * dx + 2.f * f4.z * dx * dy + f4.w * dy * dy;
-  float id = fast_rcp(d);
-  float ek = __expf(-0.5f * x * id);
+  // D, X and the exponential as ray_params evaluated them at this offset
+  const float id = g.id, ek = g.ek;
   float gE = gmu * lamp * id;
-  float gD = -gmu * g.mu * id - 0.5f * gsig * g.sig * id + 0.5f * gom * g.omega * x * id * id;
+  float gD = -gmu * g.mu * id - 0.5f * gsig * g.sig * id + 0.5f * gom * g.omega * g.xid * id;
   float gX = -0.5f * gom * g.omega * id;
   gr[G_D0] = gD;
   gr[G_D1X] = 2.f * gD * dx;
@@ -738,19 +736,17 @@ __global__ __launch_bounds__(256, (K == 4 && NQ == 4) ? 3 : 2) void k_render_bwd
           float lamk[2 * NH + 1], dl;
           hermite_adjoint<NH>(s.y[e], s.x[e], s.below[e], a.beta, lamk, dl);
           float wgt = gbar * s.A[e] + bq[e];
-          float lb = 0.f;
 #pragma unroll
-          for (int k = 1; k <= K; ++k) {
-            d[k] += wgt * lamk[k];
-            lb += lamk[k] * bkp[k];
-          }
-          d[0] += wgt * (s.F[e] - lb);
+          for (int k = 1; k <= K; ++k) d[k] += wgt * lamk[k];
+          d[0] += wgt * s.F[e];  // minus sum_k b_k d[k], taken once after the edges
           float dtau_dt = -m0p * s.w0[e] * dl * warp_dy(pp, s.t[e]);
           float dtdmu = s.cl[e] ? 0.f : 1.f;
           float dtdsig = s.cl[e] ? 0.f : a.kappa * a.xq[e];
           gmu += wgt * dtau_dt * dtdmu;
           gsig += wgt * dtau_dt * dtdsig;
         }
+#pragma unroll
+        for (int k = 1; k <= K; ++k) d[0] -= bkp[k] * d[k];  // the tau = m_0 F(b) chain at b = m / m_0
         float dq0 = 0.f, dq1 = 0.f, dq2 = 0.f;
 #pragma unroll
         for (int e = 0; e + 1 < NQ; ++e) {

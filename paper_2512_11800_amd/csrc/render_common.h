@@ -13,6 +13,7 @@ struct Stage {
 
 struct RayG {
   float mu, sig, omega;
+  float id, xid, ek;  // 1 / D, X / D and exp(-X / 2D) at the pixel offset (for the adjoint)
 };
 
 // ---------------------------------------------------------------------------
@@ -200,9 +201,12 @@ __device__ __forceinline__ RayG ray_params(const Stage& st, int j, float dx, flo
   float x = f4.y * dx * dx + 2.f * f4.z * dx * dy + f4.w * dy * dy;
   float id = fast_rcp(d);
   RayG g;
+  g.id = id;
+  g.xid = x * id;
+  g.ek = __expf(-0.5f * g.xid);
   g.mu = lam * e * id;
   g.sig = lam * fast_rsq(d);
-  g.omega = w * __expf(-0.5f * x * id);
+  g.omega = w * g.ek;
   return g;
 }
 
