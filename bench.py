@@ -452,6 +452,8 @@ def main():
         out["fwdbwd_ms_per_frame"] = modes["fwdbwd"]["ms_per_step"]
     out["roofline_fwd"] = res["roofline_fwd"]
     out["pairs_per_frame"] = res["n_pairs"]
+    # (pixel, Gaussian) evaluations per second of the whole frame (all stages)
+    out["gaussian_pixel_evals_per_s"] = {m: res["n_pairs"] / (modes[m]["ms_per_step"] * 1e-3) for m in modes}
     out["n_entries"] = res["n_entries"]
     out["n_fallback_pixels"] = res["n_fallback_pixels"]
     out["stages_ms"] = {m: modes[m]["stages_ms"] for m in modes}
