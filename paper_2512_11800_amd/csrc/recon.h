@@ -105,12 +105,18 @@ __device__ __forceinline__ void roots3(const float* c, float* x) {
   float sq = fast_sqrt(q);
   float den = q * sq;
   float arg = den > 0.f ? fminf(fmaxf(r * fast_rcp(den), -1.f), 1.f) : 0.f;
-  float th = acosf(arg) * (1.f / 3.f);
+  // the trigonometric roots only seed the Newton steps below, so a short
+  // arccosine (Abramowitz & Stegun 4.4.45, |error| < 7e-5) and the hardware
+  // cosine are accurate enough
+  const float aa = fabsf(arg);
+  float ac = fast_sqrt(1.f - aa) * (1.5707288f + aa * (-0.2121144f + aa * (0.0742610f + aa * -0.0187293f)));
+  ac = arg < 0.f ? 3.14159265358979f - ac : ac;
+  float th = ac * (1.f / 3.f);
   const float two_pi_3 = 2.0943951023931953f;
   float big = 0.f;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    float xk = -2.f * sq * cosf(th + two_pi_3 * (float)k) - a3;
+    float xk = -2.f * sq * __cosf(th + two_pi_3 * (float)k) - a3;
     big = fabsf(xk) > fabsf(big) ? xk : big;
   }
   big = cubic_newton(c, big, 2);
