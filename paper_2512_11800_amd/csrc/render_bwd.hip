@@ -162,7 +162,7 @@ __device__ __forceinline__ void moment_grads(const RayG& g, const PixelBasis& pb
   const float Gp = warp_dy(pb, mus);
   const float G = ys + Gp * (g.mu - mus);
   const float q = 1.f + 0.8f * g.mu;
-  const float d2 = g.mu > tn ? -3.f * pb.amp / (q * q * q * sqrtf(q)) : 0.f;  // y''(mu)
+  const float d2 = g.mu > tn ? -3.f * pb.amp * fast_rcp(q * q * q * fast_sqrt(q)) : 0.f;  // y''(mu)
   const float is = fast_rcp(g.sig);
   const float bn = (tn - g.mu) * kInvSqrt2 * is;
   const float E = __expf(-bn * bn);
@@ -394,7 +394,7 @@ __device__ __forceinline__ void reduce_to_slots(float* gr, bool act, int j, int 
 // F and dF/d(inputs) from the query list, and the adjoint reaches the moments
 // through the surrogate's inputs instead of the moment bounds.
 template <int K, int NQ, int SUR>
-__global__ __launch_bounds__(256, (K == 4 && NQ == 4) ? 3 : 2) void k_render_bwd(BwdArgs ba, CamSet cams) {
+__global__ __launch_bounds__(256, (K <= 6 && NQ == 4 && !SUR) ? 3 : 2) void k_render_bwd(BwdArgs ba, CamSet cams) {
   constexpr int NH = K / 2;
   constexpr int NL = (NH + 1) * (NH + 2) / 2;
   constexpr int RS = (K + 4) / 4 * 4;  // plain pass 2: K + 1 adjoint moments per pair, padded to float4s
