@@ -243,6 +243,50 @@ int mb_render_backward_surrogate(const mb_gaussians *g, const mb_camera *cams, i
                                  float *g_scales, float *g_quats, float *g_densities,
                                  float *g_colors, void *stream);
 
+/* Adaptive density control of the density-based medium (App. E), one thread
+ * per particle. Colours are laid out as in an mb_gaussians set: 3 (SH degree
+ * + 1)^2 floats per particle, or 3 for RGB.
+ *
+ * mb_view_independent_opacity: o_i = 1 - exp(-sqrt(2 pi) w_i min(s_i)), the
+ *   particle's opacity seen along its shortest axis through its centre (the
+ *   pruning criterion). opacity [n] device, written.
+ * mb_density_from_opacity: w_i = -log(1 - o_i) / (sqrt(2 pi) mean(s_i)), the
+ *   appendix's initial peak densities. opacity, scales [n,3] in, densities
+ *   [n] out, all device.
+ * mb_adc_accumulate: grad_acc[i] += |dL/dmean_i| per component and
+ *   grad_count[i] += 1 when that gradient is nonzero (accumulated absolute
+ *   gradient, per view). All device; the caller zeroes them at the start of
+ *   a densification interval.
+ * mb_adc_plan: action[i] = 0 prune (view-independent opacity below
+ *   min_opacity), 2 clone or 3 split (|grad_acc_i| / max(grad_count_i, 1) above
+ *   grad_threshold with some counted view; split if max(s_i) > split_scale),
+ *   else 1 keep; offsets[i] the particle's first output slot (exclusive scan
+ *   of 0/1/2/2 outputs), *n_out (device int32) the size of the new set. ws:
+ *   mb_adc_workspace_bytes(n) bytes. All device.
+ * mb_adc_apply: writes the new set (n_out particles, input order) into the
+ *   output arrays: kept particles once; cloned ones twice at half peak
+ *   density (the two copies add up to the original density); split ones as
+ *   two particles at mean -+ delta s_max e_max with s_max scaled by gamma
+ *   (e_max the axis of the largest scale; gamma = 0.6385502815246582 and
+ *   delta = 0.6128153090966912 as the appendix derives them), everything else
+ *   copied. */
+typedef struct mb_adc_params {
+  float min_opacity;
+  float grad_threshold; /* the appendix uses 1e-4 */
+  float split_scale;
+} mb_adc_params;
+int mb_view_independent_opacity(const mb_gaussians *g, float *opacity, void *stream);
+int mb_density_from_opacity(int32_t n, const float *opacity, const float *scales, float *densities,
+                            void *stream);
+int mb_adc_accumulate(int32_t n, const float *g_means, float *grad_acc, int32_t *grad_count,
+                      void *stream);
+size_t mb_adc_workspace_bytes(int32_t n);
+int mb_adc_plan(const mb_gaussians *g, const float *grad_acc, const int32_t *grad_count,
+                const mb_adc_params *params, int32_t *action, int32_t *offsets, int32_t *n_out,
+                void *ws, size_t ws_bytes, void *stream);
+int mb_adc_apply(const mb_gaussians *g, const int32_t *action, const int32_t *offsets, float *means,
+                 float *scales, float *quats, float *densities, float *colors, void *stream);
+
 /* Stage timing. While enabled, every entry point records HIP events around
  * each of its stages on its stream (a small per-process overhead).
  * mb_profile_read waits for the recorded events, writes up to `max` stage

@@ -42,6 +42,10 @@ class MbOptions(ctypes.Structure):
                 ("surrogate", c_void_p), ("full_coverage", c_int32), ("reserved", c_int32)]
 
 
+class MbAdcParams(ctypes.Structure):
+    _fields_ = [("min_opacity", c_float), ("grad_threshold", c_float), ("split_scale", c_float)]
+
+
 class MbError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"mb3dgs error {code}: {msg}")
@@ -89,6 +93,14 @@ SIGNATURES = [
                                               c_size_t, c_int64, c_void_p, c_void_p, c_size_t,
                                               c_int64, c_void_p, c_void_p, c_void_p]),
     ("mb_query_workspace_bytes_backward", c_size_t, [c_int32, c_int32, c_int32, c_int64]),
+    ("mb_view_independent_opacity", c_int32, [POINTER(MbGaussians), c_void_p, c_void_p]),
+    ("mb_density_from_opacity", c_int32, [c_int32, c_void_p, c_void_p, c_void_p, c_void_p]),
+    ("mb_adc_accumulate", c_int32, [c_int32, c_void_p, c_void_p, c_void_p, c_void_p]),
+    ("mb_adc_workspace_bytes", c_size_t, [c_int32]),
+    ("mb_adc_plan", c_int32, [POINTER(MbGaussians), c_void_p, c_void_p, POINTER(MbAdcParams), c_void_p,
+                              c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    ("mb_adc_apply", c_int32, [POINTER(MbGaussians), c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                               c_void_p, c_void_p, c_void_p]),
     ("mb_render_backward_surrogate", c_int32, [POINTER(MbGaussians), POINTER(MbCamera), c_int32,
                                                POINTER(MbOptions), c_void_p, c_size_t, c_void_p,
                                                c_size_t, c_int64, c_void_p, c_void_p, c_size_t,

@@ -653,6 +653,84 @@ int mb_render_backward_surrogate(const mb_gaussians* g, const mb_camera* cams, i
 }
 
 // ---------------------------------------------------------------------------
+// Adaptive density control (App. E)
+// ---------------------------------------------------------------------------
+namespace {
+int check_gaussians(const mb_gaussians* g) {
+  if (!g) return fail(MB_ERR_ARG, "null gaussians");
+  if (g->n < 0) return fail(MB_ERR_ARG, "negative Gaussian count %d", g->n);
+  if (g->n > 0 && (!g->means || !g->scales || !g->quats || !g->densities || !g->colors))
+    return fail(MB_ERR_ARG, "null Gaussian parameter pointer");
+  if (g->sh_degree < -1 || g->sh_degree > 3) return fail(MB_ERR_UNSUPPORTED, "SH degree %d not in -1..3", g->sh_degree);
+  return MB_OK;
+}
+}  // namespace
+
+int mb_view_independent_opacity(const mb_gaussians* g, float* opacity, void* stream) {
+  int rc = check_gaussians(g);
+  if (rc) return rc;
+  if (g->n > 0 && !opacity) return fail(MB_ERR_ARG, "null opacity output");
+  hipError_t e = launch_vi_opacity(g->n, g->scales, g->densities, opacity, (hipStream_t)stream);
+  return e == hipSuccess ? MB_OK : hip_fail(e, "view_independent_opacity");
+}
+
+int mb_density_from_opacity(int32_t n, const float* opacity, const float* scales, float* densities, void* stream) {
+  if (n < 0) return fail(MB_ERR_ARG, "negative count");
+  if (n > 0 && (!opacity || !scales || !densities)) return fail(MB_ERR_ARG, "null argument");
+  hipError_t e = launch_density_from_opacity(n, opacity, scales, densities, (hipStream_t)stream);
+  return e == hipSuccess ? MB_OK : hip_fail(e, "density_from_opacity");
+}
+
+int mb_adc_accumulate(int32_t n, const float* g_means, float* grad_acc, int32_t* grad_count, void* stream) {
+  if (n < 0) return fail(MB_ERR_ARG, "negative count");
+  if (n > 0 && (!g_means || !grad_acc || !grad_count)) return fail(MB_ERR_ARG, "null argument");
+  hipError_t e = launch_adc_accumulate(n, g_means, grad_acc, grad_count, (hipStream_t)stream);
+  return e == hipSuccess ? MB_OK : hip_fail(e, "adc_accumulate");
+}
+
+size_t mb_adc_workspace_bytes(int32_t n) {
+  if (n < 0) return 0;
+  Carver c(nullptr);
+  c.take<int>((size_t)n);                 // output counts
+  c.take<int>(scan_tmp_ints(n));
+  return c.off;
+}
+
+int mb_adc_plan(const mb_gaussians* g, const float* grad_acc, const int32_t* grad_count, const mb_adc_params* p,
+                int32_t* action, int32_t* offsets, int32_t* n_out, void* ws, size_t ws_bytes, void* stream) {
+  int rc = check_gaussians(g);
+  if (rc) return rc;
+  if (!p || !n_out) return fail(MB_ERR_ARG, "null parameters or count output");
+  if (g->n > 0 && (!grad_acc || !grad_count || !action || !offsets)) return fail(MB_ERR_ARG, "null argument");
+  size_t need = mb_adc_workspace_bytes(g->n);
+  if (!ws || ws_bytes < need) return fail(MB_ERR_WORKSPACE, "ADC workspace needs %zu bytes, got %zu", need, ws_bytes);
+  if ((int64_t)g->n * 2 >= (1ll << 31)) return fail(MB_ERR_ARG, "too many Gaussians");
+  Carver c(ws);
+  int* outs = c.take<int>((size_t)g->n);
+  int* tmp = c.take<int>(scan_tmp_ints(g->n));
+  AdcParams ap{p->min_opacity, p->grad_threshold, p->split_scale};
+  hipError_t e = launch_adc_plan(g->n, g->scales, g->densities, grad_acc, grad_count, ap, action, outs, offsets, tmp,
+                                 n_out, (hipStream_t)stream);
+  return e == hipSuccess ? MB_OK : hip_fail(e, "adc_plan");
+}
+
+int mb_adc_apply(const mb_gaussians* g, const int32_t* action, const int32_t* offsets, float* means, float* scales,
+                 float* quats, float* densities, float* colors, void* stream) {
+  int rc = check_gaussians(g);
+  if (rc) return rc;
+  if (g->n > 0 && (!action || !offsets || !means || !scales || !quats || !densities || !colors))
+    return fail(MB_ERR_ARG, "null argument");
+  AdcApplyArgs a;
+  a.n = g->n;
+  a.color_stride = g->sh_degree < 0 ? 3 : 3 * (g->sh_degree + 1) * (g->sh_degree + 1);
+  a.means = g->means; a.scales = g->scales; a.quats = g->quats; a.dens = g->densities; a.colors = g->colors;
+  a.action = action; a.offsets = offsets;
+  a.out_means = means; a.out_scales = scales; a.out_quats = quats; a.out_dens = densities; a.out_colors = colors;
+  hipError_t e = launch_adc_apply(a, (hipStream_t)stream);
+  return e == hipSuccess ? MB_OK : hip_fail(e, "adc_apply");
+}
+
+// ---------------------------------------------------------------------------
 // Learned surrogate of the reconstruction (MLP, bf16 weights, fp32 accumulation)
 // ---------------------------------------------------------------------------
 int32_t mb_mlp_param_count(void) { return mlp_param_count(); }

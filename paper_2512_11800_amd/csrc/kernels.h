@@ -33,6 +33,27 @@ struct EmitArgs {
 };
 hipError_t launch_emit(const EmitArgs& a, hipStream_t s);
 
+// Adaptive density control (adc.hip).
+enum AdcAction { kAdcPrune = 0, kAdcKeep = 1, kAdcClone = 2, kAdcSplit = 3 };
+constexpr float kSplitGamma = 0.6385502815246582f;  // scale factor of the split axis (App. E)
+constexpr float kSplitDelta = 0.6128153090966912f;  // offset of the split means, in units of that scale
+struct AdcParams {
+  float min_opacity, grad_threshold, split_scale;
+};
+struct AdcApplyArgs {
+  int n, color_stride;
+  const float *means, *scales, *quats, *dens, *colors;
+  const int *action, *offsets;
+  float *out_means, *out_scales, *out_quats, *out_dens, *out_colors;
+};
+hipError_t launch_vi_opacity(int n, const float* scales, const float* dens, float* o, hipStream_t s);
+hipError_t launch_density_from_opacity(int n, const float* o, const float* scales, float* w, hipStream_t s);
+hipError_t launch_adc_accumulate(int n, const float* g, float* acc, int* cnt, hipStream_t s);
+hipError_t launch_adc_plan(int n, const float* scales, const float* dens, const float* acc, const int* cnt,
+                           const AdcParams& p, int* action, int* outs, int* offsets, int* scan_tmp, int* total,
+                           hipStream_t s);
+hipError_t launch_adc_apply(const AdcApplyArgs& a, hipStream_t s);
+
 // exclusive scan of int32 counts (n items) into out (n items), total in *total.
 // tmp must hold scan_tmp_ints(n) ints.
 size_t scan_tmp_ints(int64_t n);

@@ -936,3 +936,108 @@ def test_render_gradients_through_the_surrogate_vs_central_differences():
             lm = loss64(p)
             fd = (lp - lm) / (2 * h)
             assert grads[name][idx] == pytest.approx(fd, rel=1e-5, abs=1e-8), name
+
+
+# ---------------------------------------------------------------------------
+# Adaptive density control (App. E): oracle.adc.
+# ---------------------------------------------------------------------------
+
+def test_split_constants_minimise_the_appendix_objective():
+    """The printed (gamma, delta) sit at the minimum of the appendix's
+    objective: minimising it from several starts lands within 0.01 of them,
+    and their objective value is within 0.2% of the minimum. A plausible
+    misreading (matching the densities without the transmittance) lands far
+    from them."""
+    from scipy import optimize
+    from oracle import adc
+    best = None
+    for c0 in (1.0, 2.0, 3.0):
+        for g0 in (0.5, 0.7, 0.9):
+            r = optimize.minimize(lambda p: adc.split_objective(p[0], p[1]) if 0 < p[1] <= 1 else 1e9,
+                                  [c0, g0], method="Nelder-Mead",
+                                  options=dict(xatol=1e-9, fatol=1e-14, maxiter=4000))
+            best = r if best is None or r.fun < best.fun else best
+    c, g = best.x
+    assert abs(g - adc.SPLIT_GAMMA) < 0.01
+    assert abs(c * (1 - g) - adc.SPLIT_DELTA) < 0.01
+    c_paper = adc.SPLIT_DELTA / (1 - adc.SPLIT_GAMMA)
+    assert adc.split_objective(c_paper, adc.SPLIT_GAMMA) <= best.fun * 1.002
+    # densities alone (no transmittance): a different optimum
+    t = np.linspace(-12, 12, 24001)
+
+    def dens_only(p):
+        d = p[0] * (1 - p[1])
+        r = np.exp(-0.5 * t * t) - np.exp(-(t - d) ** 2 / (2 * p[1] ** 2)) - np.exp(-(t + d) ** 2 / (2 * p[1] ** 2))
+        return float((r * r).sum() * (t[1] - t[0]))
+    r2 = optimize.minimize(dens_only, [1.5, 0.6], method="Nelder-Mead")
+    assert abs(r2.x[1] - adc.SPLIT_GAMMA) > 0.1
+
+
+def test_view_independent_opacity_is_the_opacity_along_the_shortest_axis():
+    """1 - exp(-integral of the 3D density along the line through the centre
+    in the direction of the smallest scale), integrated numerically."""
+    from oracle import adc
+    rng = np.random.default_rng(31)
+    for _ in range(5):
+        s = rng.uniform(0.05, 0.5, 3)
+        q = rng.normal(size=4)
+        w = rng.uniform(0.2, 5.0)
+        mean = rng.normal(size=3)
+        rot = quat_to_rot(torch.tensor(q)).numpy()
+        prec = rot @ np.diag(1 / s ** 2) @ rot.T
+        axis = rot[:, int(np.argmin(s))]
+
+        def dens(t):
+            x = mean + t * axis - mean
+            return w * math.exp(-0.5 * x @ prec @ x)
+        tau = integrate.quad(dens, -20 * s.max(), 20 * s.max(), epsabs=1e-14, epsrel=1e-12, limit=200)[0]
+        assert adc.view_independent_opacity(s[None], np.array([w]))[0] == pytest.approx(1 - math.exp(-tau),
+                                                                                        rel=1e-10)
+
+
+def test_density_from_opacity_inverts_the_opacity_for_equal_scales():
+    from oracle import adc
+    s = np.full((4, 3), 0.2)
+    o = np.array([0.01, 0.1, 0.5, 0.9])
+    w = adc.density_from_opacity(o, s)
+    assert np.allclose(adc.view_independent_opacity(s, w), o, rtol=1e-12)
+
+
+def test_clone_keeps_the_density_field_and_split_follows_the_longest_axis():
+    from oracle import adc
+    rng = np.random.default_rng(5)
+    n = 4
+    means = rng.normal(size=(n, 3))
+    scales = rng.uniform(0.05, 0.4, (n, 3))
+    quats = rng.normal(size=(n, 4))
+    dens = rng.uniform(0.5, 3, n)
+    cols = rng.uniform(0, 1, (n, 3))
+    action = np.array([adc.KEEP, adc.CLONE, adc.SPLIT, adc.PRUNE], np.int32)
+    out = adc.apply(means, scales, quats, dens, cols, action)
+    assert out["means"].shape == (5, 3)
+    rot = quat_to_rot(torch.tensor(quats)).numpy()
+
+    def field(m, s, r, w, x):
+        d = x - m
+        return w * math.exp(-0.5 * d @ (r @ np.diag(1 / s ** 2) @ r.T) @ d)
+    for x in rng.normal(size=(6, 3)) * 0.3 + means[1]:
+        both = sum(field(out["means"][k], out["scales"][k], rot[1], out["densities"][k], x) for k in (1, 2))
+        assert both == pytest.approx(field(means[1], scales[1], rot[1], dens[1], x), rel=1e-12, abs=1e-300)
+    k = int(np.argmax(scales[2]))
+    a = rot[2][:, k]
+    assert np.allclose(out["means"][3] + out["means"][4], 2 * means[2])
+    assert np.allclose(out["means"][4] - out["means"][3], 2 * adc.SPLIT_DELTA * scales[2][k] * a)
+    assert out["scales"][3][k] == pytest.approx(adc.SPLIT_GAMMA * scales[2][k])
+    assert np.allclose(np.delete(out["scales"][3], k), np.delete(scales[2], k))
+
+
+def test_plan_on_hand_built_particles():
+    from oracle import adc
+    scales = np.array([[0.01, 0.02, 0.03], [0.2, 0.2, 0.2], [0.2, 0.2, 0.2], [0.5, 0.2, 0.2], [0.2, 0.2, 0.2]])
+    dens = np.array([0.1, 2.0, 2.0, 2.0, 2.0])   # the first is nearly transparent
+    acc = np.array([[1, 1, 1], [0, 0, 0], [3e-4, 0, 0], [3e-4, 0, 0], [1e-5, 0, 0]], float)
+    cnt = np.array([1, 0, 2, 2, 1])
+    action, off, total = adc.plan(scales, dens, acc, cnt, min_opacity=0.005, grad_threshold=1e-4,
+                                  split_scale=0.3)
+    assert list(action) == [adc.PRUNE, adc.KEEP, adc.CLONE, adc.SPLIT, adc.KEEP]
+    assert list(off) == [0, 0, 1, 3, 5] and total == 6
