@@ -243,6 +243,22 @@ int mb_render_backward_surrogate(const mb_gaussians *g, const mb_camera *cams, i
                                  float *g_scales, float *g_quats, float *g_densities,
                                  float *g_colors, void *stream);
 
+/* D-SSIM term of the training objective (Training and Densification
+ * paragraph: L = (1 - alpha) L1 + alpha L_D-SSIM + lambda L_consistency, alpha
+ * = 0.2, lambda = 0.1), as the 3DGS losses the paper extends define it: per
+ * colour channel, SSIM under an 11 x 11 Gaussian window (sigma 1.5, zero
+ * padding, C1 = 0.01^2, C2 = 0.03^2), averaged over pixels and channels.
+ *  image, target [C,H,W,3] device
+ *  loss          device float, written: 1 - mean SSIM
+ *  grad_image    [C,H,W,3] device or NULL: ACCUMULATED with
+ *                grad_scale * d loss / d image (so an L1 gradient can be
+ *                summed into the same buffer)
+ *  ws            mb_dssim_workspace_bytes(n_cams, width, height) bytes */
+size_t mb_dssim_workspace_bytes(int32_t n_cams, int32_t width, int32_t height);
+int mb_dssim(const float *image, const float *target, int32_t n_cams, int32_t width,
+             int32_t height, float grad_scale, float *loss, float *grad_image, void *ws,
+             size_t ws_bytes, void *stream);
+
 /* Adaptive density control of the density-based medium (App. E), one thread
  * per particle. Colours are laid out as in an mb_gaussians set: 3 (SH degree
  * + 1)^2 floats per particle, or 3 for RGB.

@@ -93,6 +93,9 @@ SIGNATURES = [
                                               c_size_t, c_int64, c_void_p, c_void_p, c_size_t,
                                               c_int64, c_void_p, c_void_p, c_void_p]),
     ("mb_query_workspace_bytes_backward", c_size_t, [c_int32, c_int32, c_int32, c_int64]),
+    ("mb_dssim_workspace_bytes", c_size_t, [c_int32, c_int32, c_int32]),
+    ("mb_dssim", c_int32, [c_void_p, c_void_p, c_int32, c_int32, c_int32, c_float, c_void_p, c_void_p,
+                           c_void_p, c_size_t, c_void_p]),
     ("mb_view_independent_opacity", c_int32, [POINTER(MbGaussians), c_void_p, c_void_p]),
     ("mb_density_from_opacity", c_int32, [c_int32, c_void_p, c_void_p, c_void_p, c_void_p]),
     ("mb_adc_accumulate", c_int32, [c_int32, c_void_p, c_void_p, c_void_p, c_void_p]),

@@ -653,6 +653,48 @@ int mb_render_backward_surrogate(const mb_gaussians* g, const mb_camera* cams, i
 }
 
 // ---------------------------------------------------------------------------
+// D-SSIM term of the training objective
+// ---------------------------------------------------------------------------
+size_t mb_dssim_workspace_bytes(int32_t n_cams, int32_t width, int32_t height) {
+  if (n_cams < 1 || width <= 0 || height <= 0) return 0;
+  Carver c(nullptr);
+  c.take<float>((size_t)n_cams * width * height * 9);
+  c.take<float>((size_t)dssim_blocks(n_cams, width, height));
+  return c.off;
+}
+
+int mb_dssim(const float* image, const float* target, int32_t n_cams, int32_t width, int32_t height,
+             float grad_scale, float* loss, float* grad_image, void* ws, size_t ws_bytes, void* stream) {
+  if (n_cams < 1 || width <= 0 || height <= 0 || width > 16384 || height > 16384)
+    return fail(MB_ERR_ARG, "bad image size");
+  if (!image || !target || !loss) return fail(MB_ERR_ARG, "null image, target or loss");
+  size_t need = mb_dssim_workspace_bytes(n_cams, width, height);
+  if (!ws || ws_bytes < need) return fail(MB_ERR_WORKSPACE, "D-SSIM workspace needs %zu bytes, got %zu", need, ws_bytes);
+  Carver c(ws);
+  SsimArgs a;
+  a.image = image;
+  a.target = target;
+  a.n_cams = n_cams;
+  a.w = width;
+  a.h = height;
+  double gs[11], sum = 0.0;
+  for (int k = 0; k < 11; ++k) {
+    const double x = k - 5;
+    gs[k] = std::exp(-x * x / (2.0 * 1.5 * 1.5));
+    sum += gs[k];
+  }
+  for (int k = 0; k < 11; ++k) a.g[k] = (float)(gs[k] / sum);
+  float* coef = c.take<float>((size_t)n_cams * width * height * 9);
+  a.coef = grad_image ? coef : nullptr;
+  a.partials = c.take<float>((size_t)dssim_blocks(n_cams, width, height));
+  a.loss = loss;
+  a.grad = grad_image;
+  a.grad_scale = grad_scale;
+  hipError_t e = launch_dssim(a, (hipStream_t)stream);
+  return e == hipSuccess ? MB_OK : hip_fail(e, "dssim");
+}
+
+// ---------------------------------------------------------------------------
 // Adaptive density control (App. E)
 // ---------------------------------------------------------------------------
 namespace {

@@ -33,6 +33,20 @@ struct EmitArgs {
 };
 hipError_t launch_emit(const EmitArgs& a, hipStream_t s);
 
+// D-SSIM loss (loss.hip).
+struct SsimArgs {
+  const float *image, *target;  // [C,H,W,3]
+  int n_cams, w, h;
+  float g[11];                  // normalised Gaussian window, sigma 1.5
+  float* coef;                  // [C,H,W,3,3] dS/d(mu_x, E[x^2], E[xy]); null: loss only
+  float* partials;              // [blocks]
+  float* loss;                  // device scalar, 1 - mean SSIM
+  float* grad;                  // [C,H,W,3] accumulated with grad_scale d loss / d image, or null
+  float grad_scale;
+};
+hipError_t launch_dssim(const SsimArgs& a, hipStream_t s);
+int dssim_blocks(int n_cams, int w, int h);
+
 // Adaptive density control (adc.hip).
 enum AdcAction { kAdcPrune = 0, kAdcKeep = 1, kAdcClone = 2, kAdcSplit = 3 };
 constexpr float kSplitGamma = 0.6385502815246582f;  // scale factor of the split axis (App. E)

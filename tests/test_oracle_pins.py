@@ -1041,3 +1041,54 @@ def test_plan_on_hand_built_particles():
                                   split_scale=0.3)
     assert list(action) == [adc.PRUNE, adc.KEEP, adc.CLONE, adc.SPLIT, adc.KEEP]
     assert list(off) == [0, 0, 1, 3, 5] and total == 6
+
+
+# ---------------------------------------------------------------------------
+# The D-SSIM term of the objective: oracle.loss.
+# ---------------------------------------------------------------------------
+
+def test_ssim_against_a_brute_force_window_loop():
+    """Every local statistic summed explicitly over the 11 x 11 window (zero
+    outside the image) on a tiny image, against the separable version and the
+    torch one."""
+    from oracle import loss as Ls
+    rng = np.random.default_rng(3)
+    x = rng.uniform(0, 1, (1, 9, 13, 3))
+    y = np.clip(x + rng.normal(0, 0.1, x.shape), 0, 1)
+    g = Ls.gaussian_window()
+    w2 = np.outer(g, g)
+    h, w = 9, 13
+    ref = np.zeros((h, w, 3))
+    for i in range(h):
+        for j in range(w):
+            acc = np.zeros((5, 3))
+            for di in range(-5, 6):
+                for dj in range(-5, 6):
+                    ii, jj = i + di, j + dj
+                    if 0 <= ii < h and 0 <= jj < w:
+                        a, b = x[0, ii, jj], y[0, ii, jj]
+                        acc += w2[di + 5, dj + 5] * np.stack([a, b, a * a, b * b, a * b])
+            mx, my, ex, ey, exy = acc
+            sx, sy, sxy = ex - mx * mx, ey - my * my, exy - mx * my
+            ref[i, j] = ((2 * mx * my + Ls.C1) * (2 * sxy + Ls.C2)) / ((mx * mx + my * my + Ls.C1) * (sx + sy + Ls.C2))
+    assert np.allclose(Ls.ssim_map(x, y)[0], ref, atol=1e-13)
+    assert Ls.dssim_torch(torch.tensor(x), torch.tensor(y)).item() == pytest.approx(1 - ref.mean(), abs=1e-13)
+
+
+def test_ssim_identity_symmetry_and_gradient():
+    from oracle import loss as Ls
+    rng = np.random.default_rng(4)
+    x = rng.uniform(0, 1, (2, 16, 12, 3))
+    y = rng.uniform(0, 1, x.shape)
+    assert Ls.dssim(x, x) == pytest.approx(0.0, abs=1e-14)
+    assert Ls.dssim(x, y) == pytest.approx(Ls.dssim(y, x), abs=1e-14)
+    xt = torch.tensor(x, requires_grad=True)
+    Ls.dssim_torch(xt, torch.tensor(y)).backward()
+    gx = xt.grad.numpy()
+    for _ in range(6):
+        idx = tuple(int(rng.integers(0, s)) for s in x.shape)
+        h = 1e-6
+        xp = x.copy(); xp[idx] += h
+        xm = x.copy(); xm[idx] -= h
+        fd = (Ls.dssim(xp, y) - Ls.dssim(xm, y)) / (2 * h)
+        assert gx[idx] == pytest.approx(fd, rel=1e-5, abs=1e-12)
