@@ -94,6 +94,8 @@ SIGNATURES = [
                                               c_int64, c_void_p, c_void_p, c_void_p]),
     ("mb_query_workspace_bytes_backward", c_size_t, [c_int32, c_int32, c_int32, c_int64]),
     ("mb_dssim_workspace_bytes", c_size_t, [c_int32, c_int32, c_int32]),
+    ("mb_l1_workspace_bytes", c_size_t, []),
+    ("mb_l1", c_int32, [c_void_p, c_void_p, c_int64, c_float, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
     ("mb_dssim", c_int32, [c_void_p, c_void_p, c_int32, c_int32, c_int32, c_float, c_void_p, c_void_p,
                            c_void_p, c_size_t, c_void_p]),
     ("mb_view_independent_opacity", c_int32, [POINTER(MbGaussians), c_void_p, c_void_p]),

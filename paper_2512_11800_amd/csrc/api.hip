@@ -655,6 +655,18 @@ int mb_render_backward_surrogate(const mb_gaussians* g, const mb_camera* cams, i
 // ---------------------------------------------------------------------------
 // D-SSIM term of the training objective
 // ---------------------------------------------------------------------------
+size_t mb_l1_workspace_bytes(void) { return (size_t)l1_partials() * sizeof(double); }
+
+int mb_l1(const float* image, const float* target, int64_t n, float grad_scale, float* loss, float* grad_image,
+          void* ws, size_t ws_bytes, void* stream) {
+  if (n < 0) return fail(MB_ERR_ARG, "negative count");
+  if (!loss || (n > 0 && (!image || !target))) return fail(MB_ERR_ARG, "null image, target or loss");
+  if (!ws || ws_bytes < mb_l1_workspace_bytes())
+    return fail(MB_ERR_WORKSPACE, "L1 workspace needs %zu bytes, got %zu", mb_l1_workspace_bytes(), ws_bytes);
+  hipError_t e = launch_l1(image, target, n, grad_scale, loss, grad_image, (double*)ws, (hipStream_t)stream);
+  return e == hipSuccess ? MB_OK : hip_fail(e, "l1");
+}
+
 size_t mb_dssim_workspace_bytes(int32_t n_cams, int32_t width, int32_t height) {
   if (n_cams < 1 || width <= 0 || height <= 0) return 0;
   Carver c(nullptr);

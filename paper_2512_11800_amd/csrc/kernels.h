@@ -45,6 +45,9 @@ struct SsimArgs {
   float grad_scale;
 };
 hipError_t launch_dssim(const SsimArgs& a, hipStream_t s);
+int l1_partials();
+hipError_t launch_l1(const float* x, const float* y, int64_t n, float grad_scale, float* loss, float* grad,
+                     double* partials, hipStream_t s);
 int dssim_blocks(int n_cams, int w, int h);
 
 // Adaptive density control (adc.hip).

@@ -158,6 +158,51 @@ hipError_t launch_dssim(const SsimArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+// L1 term: mean |x - y| and grad += scale sign(x - y) / n. Fixed grid, one
+// double partial per block, summed in block order.
+constexpr int kL1Blocks = 1024;
+
+__global__ __launch_bounds__(256) void k_l1(const float* x, const float* y, int64_t n, float gs, float* grad,
+                                            double* partials) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)kL1Blocks * 256) {
+    const float d = x[i] - y[i];
+    s += (double)fabsf(d);
+    if (grad) grad[i] += d > 0.f ? gs : (d < 0.f ? -gs : 0.f);
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_l1_reduce(const double* partials, int64_t n, float* loss) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < kL1Blocks; i += 256) s += partials[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *loss = n > 0 ? (float)(red[0] / (double)n) : 0.f;
+}
+
+int l1_partials() { return kL1Blocks; }
+
+hipError_t launch_l1(const float* x, const float* y, int64_t n, float grad_scale, float* loss, float* grad,
+                     double* partials, hipStream_t s) {
+  const float gs = n > 0 ? grad_scale / (float)n : 0.f;
+  hipLaunchKernelGGL(k_l1, dim3(kL1Blocks), dim3(256), 0, s, x, y, n, gs, grad, partials);
+  hipLaunchKernelGGL(k_l1_reduce, dim3(1), dim3(256), 0, s, partials, n, loss);
+  return hipGetLastError();
+}
+
 int dssim_blocks(int n_cams, int w, int h) {
   return ((w + kSsimTile - 1) / kSsimTile) * ((h + kSsimTile - 1) / kSsimTile) * n_cams;
 }
