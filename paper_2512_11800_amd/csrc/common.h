@@ -75,6 +75,49 @@ __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcp
 __device__ __forceinline__ float fast_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
+// Copy rows [0, nrows) of kPer contiguous floats (nrows <= NT) between global
+// memory and LDS rows of kRow floats with NT threads, coalesced. Each thread
+// issues all its loads before any store: a loop with a runtime bound would
+// wait on every load in turn.
+template <int kPer, int kRow, int NT>
+__device__ __forceinline__ void stage_rows(float* lds, const float* src, int nrows) {
+  const int cnt = nrows * kPer;
+  float v[kPer];
+#pragma unroll
+  for (int it = 0; it < kPer; ++it) {
+    const int i = it * NT + (int)threadIdx.x;
+    v[it] = i < cnt ? src[i] : 0.f;
+  }
+#pragma unroll
+  for (int it = 0; it < kPer; ++it) {
+    const int i = it * NT + (int)threadIdx.x;
+    if (i < cnt) lds[(i / kPer) * kRow + i % kPer] = v[it];
+  }
+}
+template <int kPer, int kRow, int NT>
+__device__ __forceinline__ void unstage_rows(float* dst, const float* lds, int nrows) {
+  const int cnt = nrows * kPer;
+  constexpr int kChunk = 8;  // LDS reads in flight per thread (bounds the registers)
+  // an opaque copy of the thread index: otherwise the compiler hoists every
+  // address of the unrolled loop to the kernel's start, where they stay live
+  int tid = (int)threadIdx.x;
+  asm volatile("" : "+v"(tid));
+#pragma unroll
+  for (int c0 = 0; c0 < kPer; c0 += kChunk) {
+    float v[kChunk];
+#pragma unroll
+    for (int k = 0; k < kChunk; ++k) {
+      const int i = (c0 + k) * NT + tid;
+      v[k] = (c0 + k < kPer && i < cnt) ? lds[(i / kPer) * kRow + i % kPer] : 0.f;
+    }
+#pragma unroll
+    for (int k = 0; k < kChunk; ++k) {
+      const int i = (c0 + k) * NT + tid;
+      if (c0 + k < kPer && i < cnt) dst[i] = v[k];
+    }
+  }
+}
+
 // erfc with an exact shortcut: for b < -3.9, erfc(b) = 2 - erfc(-b) with
 // erfc(-b) < 4e-8, below half an ulp of 2, so the float result is 2 exactly.
 // Most ray Gaussians lie far beyond the near plane (b << 0) and skip erfcf.

@@ -100,9 +100,7 @@ __global__ __launch_bounds__(256) void k_preprocess(PrepArgs a, CamSet cams) {
   __shared__ float shc[256 * kRow];
   {
     const int g0 = blockIdx.x * blockDim.x;
-    const int cnt = min(256, a.n - g0) * kPer;
-    const float* src = a.colors + (size_t)g0 * kPer;
-    for (int i = threadIdx.x; i < cnt; i += 256) shc[(i / kPer) * kRow + i % kPer] = src[i];
+    stage_rows<kPer, kRow, 256>(shc, a.colors + (size_t)g0 * kPer, min(256, a.n - g0));
     __syncthreads();
   }
   int g = blockIdx.x * blockDim.x + threadIdx.x;
