@@ -238,6 +238,8 @@ int build_lists(const mb_gaussians* g, const GaussWs& w, const PairWs& p, int n_
   ea.rec = w.rec; ea.tbox = w.tbox; ea.offsets = w.offsets; ea.counts = w.counts;
   ea.n = g->n; ea.n_cams = n_cams; ea.tiles_x = tx; ea.tiles_y = ty; ea.full_coverage = full_coverage;
   ea.keys = p.keys_a; ea.vals = p.vals_a; ea.entry_rec = p.entry_rec;
+  ea.ranges = g->n > 0 ? p.ranges : nullptr;  // no emit launch without Gaussians
+  ea.n_keys = n_keys;
   hipError_t e;
   {
     StageTimer t(S_EMIT, s);
@@ -251,7 +253,8 @@ int build_lists(const mb_gaussians* g, const GaussWs& w, const PairWs& p, int n_
   if (e != hipSuccess) return hip_fail(e, "sort");
   {
     StageTimer t(S_LISTS, s);
-    e = launch_finish_lists(p.keys_a, p.vals_a, p.entry_rec, n_entries, p.sorted_rec, p.inv, p.ranges, n_keys, s);
+    e = launch_finish_lists(p.keys_a, p.vals_a, p.entry_rec, n_entries, p.sorted_rec, p.inv, p.ranges, n_keys,
+                            ea.ranges != nullptr, s);
     if (e == hipSuccess)
       e = launch_tile_order(p.ranges, n_keys, split_heavy ? kSplitEntries : 0x7FFFFFFF, p.order, p.order_tmp, s);
   }

@@ -30,6 +30,8 @@ struct EmitArgs {
   uint32_t* keys;      // [E] tile key cam * T + tile
   int* vals;           // [E] entry index
   int* entry_rec;      // [E] record index cam * n + g
+  int2* ranges;        // [n_keys] cleared to (0, 0) when not null
+  int n_keys;
 };
 hipError_t launch_emit(const EmitArgs& a, hipStream_t s);
 
@@ -83,14 +85,16 @@ hipError_t launch_radix_sort(uint32_t* keys_a, int* vals_a, uint32_t* keys_b, in
                              int64_t n, int bits, int* tmp, hipStream_t s);
 
 // after the sort: sorted_rec[i] = entry_rec[vals[i]], inv[vals[i]] = i,
-// ranges[key] = [first, last+1) over the sorted keys (ranges zeroed first).
+// ranges[key] = [first, last+1) over the sorted keys (ranges zeroed first,
+// here unless ranges_cleared: the emit kernel clears them when given them).
 hipError_t launch_finish_lists(const uint32_t* keys, const int* vals, const int* entry_rec,
                                int64_t n, int* sorted_rec, int* inv, int2* ranges,
-                               int n_keys, hipStream_t s);
+                               int n_keys, bool ranges_cleared, hipStream_t s);
 
-// block list of the render kernels (render_blocks(n_keys) entries): tiles by
-// decreasing list length, tiles longer than `split` entries as four quadrant
-// blocks; tmp holds order_tmp_ints(n_keys) ints
+// block list of the render kernels (render_blocks(n_keys) entries): tiles
+// longer than `split` entries first, as four quadrant blocks, then the rest,
+// each group by decreasing (quantised) list length; tmp holds
+// order_tmp_ints(n_keys) ints
 size_t order_tmp_ints(int n_keys);
 hipError_t launch_tile_order(const int2* ranges, int n_keys, int split, int* blocks, int* tmp, hipStream_t s);
 

@@ -210,6 +210,11 @@ hipError_t launch_preprocess(const PrepArgs& a, const CamSet& cams, hipStream_t 
 __global__ __launch_bounds__(256) void k_emit(EmitArgs a) {
   int g = blockIdx.x * blockDim.x + threadIdx.x;
   int ci = blockIdx.y;
+  if (a.ranges) {  // empty per-tile ranges, filled in after the sort
+    const int nt = gridDim.x * gridDim.y * blockDim.x;
+    for (int t = (blockIdx.y * gridDim.x + blockIdx.x) * blockDim.x + threadIdx.x; t < a.n_keys; t += nt)
+      a.ranges[t] = make_int2(0, 0);
+  }
   if (g >= a.n) return;
   size_t idx = (size_t)ci * a.n + g;
   int4 box = a.tbox[idx];

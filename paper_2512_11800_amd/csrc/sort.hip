@@ -179,22 +179,29 @@ size_t radix_tmp_ints(int64_t n) {
   return (size_t)(256 * nb) + scan_tmp_ints(256 * nb) + 1;
 }
 
+// one stable pass on digit (key >> shift) & 255
+static hipError_t radix_pass(const uint32_t* kin, const int* vin, uint32_t* kout, int* vout, int64_t n, int shift,
+                             int* tmp, hipStream_t s) {
+  const int64_t nb = (n + kChunk - 1) / kChunk;
+  int* hist = tmp;
+  int* scan_tmp = tmp + 256 * nb;
+  hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(kBlock), 0, s, kin, n, shift, hist, (int)nb);
+  hipError_t e = launch_scan(hist, hist, 256 * nb, scan_tmp, nullptr, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(kBlock), 0, s, kin, vin, kout, vout, n, shift, hist,
+                     (int)nb);
+  return hipGetLastError();
+}
+
 hipError_t launch_radix_sort(uint32_t* keys_a, int* vals_a, uint32_t* keys_b, int* vals_b, int64_t n,
                              int bits, int* tmp, hipStream_t s) {
   if (n <= 1) return hipSuccess;
-  int64_t nb = (n + kChunk - 1) / kChunk;
-  int* hist = tmp;
-  int* scan_tmp = tmp + 256 * nb;
   int passes = (bits + 7) / 8;
   uint32_t *kin = keys_a, *kout = keys_b;
   int *vin = vals_a, *vout = vals_b;
   for (int p = 0; p < passes; ++p) {
-    int shift = 8 * p;
-    hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(kBlock), 0, s, kin, n, shift, hist, (int)nb);
-    hipError_t e = launch_scan(hist, hist, 256 * nb, scan_tmp, nullptr, s);
+    hipError_t e = radix_pass(kin, vin, kout, vout, n, 8 * p, tmp, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(kBlock), 0, s, kin, vin, kout, vout, n,
-                       shift, hist, (int)nb);
     uint32_t* tk = kin; kin = kout; kout = tk;
     int* tv = vin; vin = vout; vout = tv;
   }
@@ -224,34 +231,41 @@ __global__ __launch_bounds__(256) void k_finish(const uint32_t* keys, const int*
   if (i == n - 1 || keys[i + 1] != key) ranges[key].y = (int)(i + 1);
 }
 
-// Dispatch order of the tiles: longest list first (stable, so ties keep tile
-// order). Heavy tiles start early instead of forming the tail of the launch,
-// and consecutive blocks, which the hardware deals round-robin to the XCDs,
-// spread the heavy tiles over all of them.
-__global__ __launch_bounds__(256) void k_tile_keys(const int2* ranges, int n_keys, uint32_t* keys, int* vals) {
+// Dispatch order of the tiles: heavy tiles (list longer than `split`) first,
+// then the rest, each group longest first to a quantised length (one 8-bit
+// radix pass; the sort is stable, so ties keep tile order). Heavy tiles start
+// early instead of forming the tail of the launch, and consecutive blocks,
+// which the hardware deals round-robin to the XCDs, spread them over all of
+// them. Keys below 128 are exactly the heavy tiles.
+__global__ __launch_bounds__(256) void k_tile_keys(const int2* ranges, int n_keys, int split, uint32_t* keys,
+                                                   int* vals) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_keys) return;
   int2 r = ranges[i];
-  int len = r.y - r.x;
-  keys[i] = 0xFFFFu - (uint32_t)min(max(len, 0), 0xFFFF);
+  int len = max(r.y - r.x, 0);
+  uint32_t k;
+  if (len > split)
+    k = 127u - (uint32_t)min((len - split - 1) >> 5, 127);  // 32 entries a step
+  else
+    k = 255u - (uint32_t)min(len >> 2, 127);                 // 4 entries a step
+  keys[i] = k;
   vals[i] = i;
 }
 
-// Block list of the render kernels from the sorted tiles: the first ns tiles
-// (list longer than `split`) get four blocks each,
-// coded -(4 key + quadrant) - 1, then one block per remaining tile (its key),
-// then blocks coded n_keys that exit at once (the grid is render_blocks()).
+// Block list of the render kernels from the ordered tiles: the first ns tiles
+// (the heavy ones) get four blocks each, coded -(4 key + quadrant) - 1, then
+// one block per remaining tile (its key), then blocks coded n_keys that exit
+// at once (the grid is render_blocks()).
 __global__ __launch_bounds__(256) void k_block_list(const uint32_t* sorted_keys, const int* order, int n_keys,
-                                                   int split, int* blocks) {
+                                                   int* blocks) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int total = render_blocks(n_keys);
   if (t >= total) return;
-  // ns = number of leading tiles whose list is longer than `split`
+  // ns = number of leading tiles with a key below 128
   int lo = 0, hi = n_keys;
   while (lo < hi) {
     int mid = (lo + hi) >> 1;
-    int len = 0xFFFF - (int)sorted_keys[mid];
-    if (len > split) lo = mid + 1; else hi = mid;
+    if (sorted_keys[mid] < 128u) lo = mid + 1; else hi = mid;
   }
   const int ns = lo;
   if (t < n_keys) {
@@ -275,19 +289,21 @@ hipError_t launch_tile_order(const int2* ranges, int n_keys, int split, int* blo
   int* va = tmp + 2 * (size_t)n_keys;
   int* vb = tmp + 3 * (size_t)n_keys;
   int* rt = tmp + 4 * (size_t)n_keys;
-  hipLaunchKernelGGL(k_tile_keys, dim3((n_keys + 255) / 256), dim3(256), 0, s, ranges, n_keys, ka, va);
+  hipLaunchKernelGGL(k_tile_keys, dim3((n_keys + 255) / 256), dim3(256), 0, s, ranges, n_keys, split, ka, va);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  e = launch_radix_sort(ka, va, kb, vb, n_keys, 16, rt, s);
+  e = radix_pass(ka, va, kb, vb, n_keys, 0, rt, s);
   if (e != hipSuccess) return e;
   int total = render_blocks(n_keys);
-  hipLaunchKernelGGL(k_block_list, dim3((total + 255) / 256), dim3(256), 0, s, ka, va, n_keys, split, blocks);
+  hipLaunchKernelGGL(k_block_list, dim3((total + 255) / 256), dim3(256), 0, s, kb, vb, n_keys, blocks);
   return hipGetLastError();
 }
 
 hipError_t launch_finish_lists(const uint32_t* keys, const int* vals, const int* entry_rec, int64_t n,
-                               int* sorted_rec, int* inv, int2* ranges, int n_keys, hipStream_t s) {
-  hipLaunchKernelGGL(k_fill_ranges, dim3((n_keys + 255) / 256), dim3(256), 0, s, ranges, n_keys);
+                               int* sorted_rec, int* inv, int2* ranges, int n_keys, bool ranges_cleared,
+                               hipStream_t s) {
+  if (!ranges_cleared)
+    hipLaunchKernelGGL(k_fill_ranges, dim3((n_keys + 255) / 256), dim3(256), 0, s, ranges, n_keys);
   if (n > 0)
     hipLaunchKernelGGL(k_finish, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, keys, vals, entry_rec,
                        n, sorted_rec, inv, ranges);
