@@ -119,7 +119,10 @@ def _workload(k_mom: int, name: str = "w2"):
 def gpu_bench(args):
     """Timed frames of the forward path and of forward + backward on the W2
     scene (inputs resident on the GPU), with stage timings from the library's
-    HIP events."""
+    HIP events. Frames keep the list count on the device (no host round trip
+    inside a frame, the pair workspace sized for 1.25x the first frame's
+    count); every timed frame's count is checked against that capacity
+    afterwards."""
     import torch
 
     import paper_2512_11800_amd as M
@@ -134,7 +137,7 @@ def gpu_bench(args):
     grad_img = torch.full((nc, h, w, 3), 1.0 / (3 * h * w * nc), device="cuda:0")
 
     def fwd():
-        return M.render_forward(g, cams, opts, ws=ws)
+        return M.render_forward(g, cams, opts, ws=ws, on_device=True)
 
     target_img = None
     if args.workload == "w3":
@@ -143,7 +146,7 @@ def gpu_bench(args):
         target_img = M.render_forward(tg, cams, opts)[0].clone()
 
     def fwdbwd():
-        image, saved, st = M.render_forward(g, cams, opts, ws=ws)
+        image, saved, st = M.render_forward(g, cams, opts, ws=ws, on_device=True)
         gimg = grad_img
         if target_img is not None:  # d mean|L - target| / dL, by the library's L1 kernel
             gimg = torch.zeros_like(image)
@@ -175,6 +178,7 @@ def gpu_bench(args):
     res = {}
     for name, step in modes:
         (image, saved, st), ms, wall_ms, stages = timed(step)
+        st.check()  # the frames fitted their workspace (the scene is the same every frame)
         print(f"[bench] {name}: {ms:.3f} ms/frame", file=sys.stderr, flush=True)
         res[name] = {"ms_per_step": ms, "wall_ms_per_step": wall_ms,
                      "stages_ms": {k: round(v[0] / max(1, v[1]), 4) for k, v in stages.items() if v[1]},
@@ -197,7 +201,7 @@ def gpu_bench(args):
                 "flops_per_pair": flops, "pairs_per_launch": n_pairs, "kernel_ms": kms}
 
     last = modes[-1][0]
-    out = {"n_pairs": n_pairs, "n_entries": st.n_entries, "n_fallback_pixels": n_fallback, "modes": res}
+    out = {"n_pairs": n_pairs, "n_entries": st.entry_count(), "n_fallback_pixels": n_fallback, "modes": res}
     out["roofline_fwd"] = roofline("render_forward", "k_render_fwd", fl["forward"],
                                    f"mb::k_render_fwd<{args.k}, {opts.n_intervals + 1}, 0>")
     if last == "fwdbwd":

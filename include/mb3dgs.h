@@ -20,7 +20,8 @@
  *  - The caller owns and allocates every buffer; the library never allocates
  *    or frees device memory and never writes its inputs.
  *  - Every call is enqueued asynchronously on `stream` (a hipStream_t; NULL
- *    is the default stream), except mb_prepare which waits for one count.
+ *    is the default stream), except mb_prepare when it returns the entry
+ *    count and mb_entry_count, which wait for that one count.
  *  - Return value 0 (MB_OK) or a negative MB_ERR_* code; the message of the
  *    last error of the calling thread is available from mb_last_error().
  *    No exception or abort crosses the ABI.
@@ -100,6 +101,19 @@ int32_t mb_version(void);
 size_t mb_gauss_workspace_bytes(int32_t n, int32_t n_cams);
 size_t mb_pair_workspace_bytes(int64_t n_entries, int32_t n_cams, int32_t width,
                                int32_t height);
+/* The largest entry count a pair workspace of pws_bytes holds (the inverse of
+ * mb_pair_workspace_bytes), or -1 when it holds none or an argument is bad. */
+int64_t mb_pair_capacity(size_t pws_bytes, int32_t n_cams, int32_t width, int32_t height);
+
+/* Passed as n_entries to mb_render_forward and mb_render_backward: the entry
+ * count stays on the device, where mb_prepare (called with a NULL count)
+ * left it, and the pair workspace is laid out for its capacity
+ * mb_pair_capacity(pws_bytes, ...). Such a frame needs no host round trip,
+ * so frames can be enqueued back to back. Entries beyond the capacity are
+ * dropped: the render then misses them, and the caller compares
+ * mb_entry_count with the capacity after the fact and renders again with a
+ * larger workspace. The surrogate and harvest entry points take counts only. */
+#define MB_ENTRIES_ON_DEVICE (-1)
 
 /* Screen proxies only (App. D), for inspection: per Gaussian writes
  * proxy[n,8] = (centre_x, centre_y, e1_x, e1_y, half_1, half_2, valid, 0)
@@ -111,16 +125,24 @@ int mb_project(const mb_gaussians *g, const mb_camera *cam, const mb_options *op
 
 /* Stage 1 of a render (Sec. 3.3 culling and proxy): per camera and Gaussian,
  * the screen proxy, the ray-space coefficients and the number of 16x16 tiles
- * its rectangle overlaps. Waits on `stream` once to return the total number
- * of (camera, tile, Gaussian) entries in *n_entries (host pointer). gws must
- * hold mb_gauss_workspace_bytes(g->n, n_cams) bytes. All cameras share one
- * image size. */
+ * its rectangle overlaps. With n_entries (host pointer) not NULL it waits on
+ * `stream` once to return the total number of (camera, tile, Gaussian)
+ * entries there; with NULL the total stays on the device (see
+ * MB_ENTRIES_ON_DEVICE) and nothing waits. gws must hold
+ * mb_gauss_workspace_bytes(g->n, n_cams) bytes. All cameras share one image
+ * size. */
 int mb_prepare(const mb_gaussians *g, const mb_camera *cams, int32_t n_cams,
                const mb_options *opts, void *gws, size_t gws_bytes,
                int64_t *n_entries, void *stream);
 
+/* The entry total of the last mb_prepare on gws (n_gaussians and n_cams as
+ * given to it), read back to the host: waits on `stream`. */
+int mb_entry_count(int32_t n_gaussians, int32_t n_cams, const void *gws, size_t gws_bytes,
+                   int64_t *n_entries, void *stream);
+
 /* Forward render (Sec. 3.2-3.3, Eqs. 7, 10-12, 15) after mb_prepare with the
- * same arguments. pws must hold mb_pair_workspace_bytes(n_entries, ...).
+ * same arguments. n_entries is mb_prepare's count, and pws must then hold
+ * mb_pair_workspace_bytes(n_entries, ...); or it is MB_ENTRIES_ON_DEVICE.
  *  image   [C,H,W,3] device, written: the rescaled radiance of Eq. 15
  *  saved   [C,H,W,8] device, written: per-pixel state for the backward pass:
  *                    [0..2] sum_i q_i rgb_i, [3] O = sum_i q_i, [4] depth of the
@@ -139,7 +161,8 @@ int mb_render_forward(const mb_gaussians *g, const mb_camera *cams, int32_t n_ca
                       float *penalty, void *stream);
 
 /* Backward pass (Sec. 3.3, Eq. 22, App. D adjoint rendering) after
- * mb_render_forward with the same arguments and workspaces. The per-pixel
+ * mb_render_forward with the same arguments and workspaces (n_entries
+ * included: the count, or MB_ENTRIES_ON_DEVICE). The per-pixel
  * moment sums come from the pair workspace, where the forward pass left them;
  * nothing per (pixel, Gaussian) pair is stored, the pairs' terms are
  * recomputed.

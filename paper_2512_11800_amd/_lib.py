@@ -20,6 +20,7 @@ MB_ERR_HIP = -4
 MB_MAX_CAMERAS = 16
 MB_SAVED_FLOATS_PER_PIXEL = 8
 MB_STAGE_COUNT = 10
+MB_ENTRIES_ON_DEVICE = -1
 STAGES = ("preprocess", "scan", "emit", "sort", "lists", "render_forward", "render_backward",
           "gradients", "mlp", "render_consume")
 
@@ -61,6 +62,8 @@ SIGNATURES = [
     ("mb_version", c_int32, []),
     ("mb_gauss_workspace_bytes", c_size_t, [c_int32, c_int32]),
     ("mb_pair_workspace_bytes", c_size_t, [c_int64, c_int32, c_int32, c_int32]),
+    ("mb_pair_capacity", c_int64, [c_size_t, c_int32, c_int32, c_int32]),
+    ("mb_entry_count", c_int32, [c_int32, c_int32, c_void_p, c_size_t, POINTER(c_int64), c_void_p]),
     ("mb_project", c_int32, [POINTER(MbGaussians), POINTER(MbCamera), POINTER(MbOptions),
                              c_void_p, c_void_p]),
     ("mb_prepare", c_int32, [POINTER(MbGaussians), POINTER(MbCamera), c_int32, POINTER(MbOptions),

@@ -143,6 +143,19 @@ PairWs carve_pairs(void* p, int64_t e, int n_keys, int64_t n_pix) {
 
 int tiles_of(int px) { return (px + kTile - 1) / kTile; }
 
+// largest entry count whose pair workspace fits in `bytes` (-1: none)
+int64_t pair_capacity(size_t bytes, int n_cams, int width, int height) {
+  const int n_keys = tiles_of(width) * tiles_of(height) * n_cams;
+  const int64_t n_pix = (int64_t)n_cams * width * height;
+  if (carve_pairs(nullptr, 0, n_keys, n_pix).bytes > bytes) return -1;
+  int64_t lo = 0, hi = INT32_MAX;  // entry indices are int
+  while (lo < hi) {
+    const int64_t mid = lo + (hi - lo + 1) / 2;
+    if (carve_pairs(nullptr, mid, n_keys, n_pix).bytes <= bytes) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
 int check_common(const mb_gaussians* g, const mb_camera* cams, int n_cams, const mb_options* o) {
   if (!g || !cams || !o) return fail(MB_ERR_ARG, "null gaussians, cameras or options");
   if (g->n < 0) return fail(MB_ERR_ARG, "negative Gaussian count %d", g->n);
@@ -231,8 +244,10 @@ int key_bits(int64_t n_keys) {
 }
 
 // emit, sort and per-tile lists of the forward entry points
+// n_entries: the list count, or (with n_dev) the capacity the launches are
+// sized for, the count itself read on the device
 int build_lists(const mb_gaussians* g, const GaussWs& w, const PairWs& p, int n_cams, int tx, int ty,
-                int full_coverage, int64_t n_entries, hipStream_t s, bool split_heavy = true) {
+                int full_coverage, int64_t n_entries, const int* n_dev, hipStream_t s, bool split_heavy = true) {
   int n_keys = tx * ty * n_cams;
   EmitArgs ea;
   ea.rec = w.rec; ea.tbox = w.tbox; ea.offsets = w.offsets; ea.counts = w.counts;
@@ -240,6 +255,7 @@ int build_lists(const mb_gaussians* g, const GaussWs& w, const PairWs& p, int n_
   ea.keys = p.keys_a; ea.vals = p.vals_a; ea.entry_rec = p.entry_rec;
   ea.ranges = g->n > 0 ? p.ranges : nullptr;  // no emit launch without Gaussians
   ea.n_keys = n_keys;
+  ea.cap = n_entries;
   hipError_t e;
   {
     StageTimer t(S_EMIT, s);
@@ -248,13 +264,14 @@ int build_lists(const mb_gaussians* g, const GaussWs& w, const PairWs& p, int n_
   if (e != hipSuccess) return hip_fail(e, "emit");
   {
     StageTimer t(S_SORT, s);
-    e = launch_radix_sort(p.keys_a, p.vals_a, p.keys_b, p.vals_b, n_entries, key_bits(n_keys), p.radix_tmp, s);
+    e = launch_radix_sort(p.keys_a, p.vals_a, p.keys_b, p.vals_b, n_entries, n_dev, key_bits(n_keys), p.radix_tmp,
+                          s);
   }
   if (e != hipSuccess) return hip_fail(e, "sort");
   {
     StageTimer t(S_LISTS, s);
-    e = launch_finish_lists(p.keys_a, p.vals_a, p.entry_rec, n_entries, p.sorted_rec, p.inv, p.ranges, n_keys,
-                            ea.ranges != nullptr, s);
+    e = launch_finish_lists(p.keys_a, p.vals_a, p.entry_rec, n_entries, n_dev, p.sorted_rec, p.inv, p.ranges,
+                            n_keys, ea.ranges != nullptr, s);
     if (e == hipSuccess)
       e = launch_tile_order(p.ranges, n_keys, split_heavy ? kSplitEntries : 0x7FFFFFFF, p.order, p.order_tmp, s);
   }
@@ -268,22 +285,33 @@ struct FwdSetup {
   CamSet cs;
   RenderArgs ra;
   int n_keys;
+  int64_t cap;       // list entries the pair workspace is laid out for
+  const int* n_dev;  // the count on the device (MB_ENTRIES_ON_DEVICE), else null
 };
 
 // argument and workspace checks shared by the forward entry points
 int forward_setup(const mb_gaussians* g, const mb_camera* cams, int32_t n_cams, const mb_options* o, void* gws,
                   size_t gws_bytes, void* pws, size_t pws_bytes, int64_t n_entries, float* image, float* saved,
-                  FwdSetup& f) {
+                  FwdSetup& f, bool device_count_ok = false) {
   int rc = check_common(g, cams, n_cams, o);
   if (rc) return rc;
   if (!image || !saved) return fail(MB_ERR_ARG, "null image or saved output");
-  if (n_entries < 0) return fail(MB_ERR_ARG, "negative n_entries");
+  if (n_entries < 0 && !(device_count_ok && n_entries == MB_ENTRIES_ON_DEVICE))
+    return fail(MB_ERR_ARG, "n_entries %lld is neither a count nor accepted here as MB_ENTRIES_ON_DEVICE",
+                (long long)n_entries);
   f.w = carve_gauss(gws, g->n, n_cams);
   if (!gws || gws_bytes < f.w.bytes)
     return fail(MB_ERR_WORKSPACE, "Gaussian workspace needs %zu bytes, got %zu", f.w.bytes, gws_bytes);
   int tx = tiles_of(cams[0].width), ty = tiles_of(cams[0].height);
   f.n_keys = tx * ty * n_cams;
-  f.p = carve_pairs(pws, n_entries, f.n_keys, (int64_t)n_cams * cams[0].width * cams[0].height);
+  f.n_dev = nullptr;
+  f.cap = n_entries;
+  if (n_entries == MB_ENTRIES_ON_DEVICE) {
+    f.cap = pws ? pair_capacity(pws_bytes, n_cams, cams[0].width, cams[0].height) : -1;
+    if (f.cap < 0) return fail(MB_ERR_WORKSPACE, "pair workspace of %zu bytes holds no list", pws_bytes);
+    f.n_dev = f.w.total;
+  }
+  f.p = carve_pairs(pws, f.cap, f.n_keys, (int64_t)n_cams * cams[0].width * cams[0].height);
   if (!pws || pws_bytes < f.p.bytes)
     return fail(MB_ERR_WORKSPACE, "pair workspace needs %zu bytes, got %zu", f.p.bytes, pws_bytes);
   f.cs = make_cams(cams, n_cams);
@@ -387,6 +415,27 @@ size_t mb_pair_workspace_bytes(int64_t n_entries, int32_t n_cams, int32_t width,
   return carve_pairs(nullptr, n_entries, n_keys, (int64_t)n_cams * width * height).bytes;
 }
 
+int64_t mb_pair_capacity(size_t pws_bytes, int32_t n_cams, int32_t width, int32_t height) {
+  if (n_cams < 1 || width <= 0 || height <= 0) return -1;
+  return pair_capacity(pws_bytes, n_cams, width, height);
+}
+
+int mb_entry_count(int32_t n_gaussians, int32_t n_cams, const void* gws, size_t gws_bytes, int64_t* n_entries,
+                   void* stream) {
+  if (n_gaussians < 0 || n_cams < 1 || !n_entries) return fail(MB_ERR_ARG, "bad arguments");
+  GaussWs w = carve_gauss(const_cast<void*>(gws), n_gaussians, n_cams);
+  if (!gws || gws_bytes < w.bytes)
+    return fail(MB_ERR_WORKSPACE, "Gaussian workspace needs %zu bytes, got %zu", w.bytes, gws_bytes);
+  hipStream_t s = (hipStream_t)stream;
+  int total = 0;
+  hipError_t e = hipMemcpyAsync(&total, w.total, sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "count readback");
+  if (total < 0) return fail(MB_ERR_ARG, "tile entry count overflow");
+  *n_entries = total;
+  return MB_OK;
+}
+
 int mb_project(const mb_gaussians* g, const mb_camera* cam, const mb_options* o, float* proxy, void* stream) {
   int rc = check_common(g, cam, 1, o);
   if (rc) return rc;
@@ -409,7 +458,6 @@ int mb_prepare(const mb_gaussians* g, const mb_camera* cams, int32_t n_cams, con
                size_t gws_bytes, int64_t* n_entries, void* stream) {
   int rc = check_common(g, cams, n_cams, o);
   if (rc) return rc;
-  if (!n_entries) return fail(MB_ERR_ARG, "null n_entries");
   GaussWs w = carve_gauss(gws, g->n, n_cams);
   if (!gws || gws_bytes < w.bytes)
     return fail(MB_ERR_WORKSPACE, "Gaussian workspace needs %zu bytes, got %zu", w.bytes, gws_bytes);
@@ -434,6 +482,7 @@ int mb_prepare(const mb_gaussians* g, const mb_camera* cams, int32_t n_cams, con
     e = launch_scan(w.counts, w.offsets, (int64_t)g->n * n_cams, w.scan_tmp, w.total, s);
   }
   if (e != hipSuccess) return hip_fail(e, "scan");
+  if (!n_entries) return MB_OK;  // the count stays on the device
   int total = 0;
   e = hipMemcpyAsync(&total, w.total, sizeof(int), hipMemcpyDeviceToHost, s);
   if (e != hipSuccess) return hip_fail(e, "count readback");
@@ -448,11 +497,11 @@ int mb_render_forward(const mb_gaussians* g, const mb_camera* cams, int32_t n_ca
                       size_t gws_bytes, void* pws, size_t pws_bytes, int64_t n_entries, float* image, float* saved,
                       float* penalty, void* stream) {
   FwdSetup f;
-  int rc = forward_setup(g, cams, n_cams, o, gws, gws_bytes, pws, pws_bytes, n_entries, image, saved, f);
+  int rc = forward_setup(g, cams, n_cams, o, gws, gws_bytes, pws, pws_bytes, n_entries, image, saved, f, true);
   if (rc) return rc;
   f.ra.penalty = penalty;
   hipStream_t s = (hipStream_t)stream;
-  rc = build_lists(g, f.w, f.p, n_cams, f.ra.tiles_x, f.ra.tiles_y, o->full_coverage, n_entries, s);
+  rc = build_lists(g, f.w, f.p, n_cams, f.ra.tiles_x, f.ra.tiles_y, o->full_coverage, f.cap, f.n_dev, s);
   if (rc) return rc;
   hipError_t e;
   {
@@ -474,7 +523,7 @@ int mb_render_forward_harvest(const mb_gaussians* g, const mb_camera* cams, int3
   if (!(rate >= 0.f && rate <= 1.f)) return fail(MB_ERR_ARG, "harvest rate must lie in [0, 1]");
   if (capacity < 0 || !count || (capacity > 0 && !samples)) return fail(MB_ERR_ARG, "bad sample buffer");
   hipStream_t s = (hipStream_t)stream;
-  rc = build_lists(g, f.w, f.p, n_cams, f.ra.tiles_x, f.ra.tiles_y, o->full_coverage, n_entries, s, false);
+  rc = build_lists(g, f.w, f.p, n_cams, f.ra.tiles_x, f.ra.tiles_y, o->full_coverage, n_entries, nullptr, s, false);
   if (rc) return rc;
   f.ra.harvest = samples;
   f.ra.harvest_count = count;
@@ -515,7 +564,7 @@ int mb_render_forward_surrogate(const mb_gaussians* g, const mb_camera* cams, in
   if (!qws || qws_bytes < q.bytes)
     return fail(MB_ERR_WORKSPACE, "query workspace needs %zu bytes, got %zu", q.bytes, qws_bytes);
   hipStream_t s = (hipStream_t)stream;
-  rc = build_lists(g, f.w, f.p, n_cams, f.ra.tiles_x, f.ra.tiles_y, o->full_coverage, n_entries, s, false);
+  rc = build_lists(g, f.w, f.p, n_cams, f.ra.tiles_x, f.ra.tiles_y, o->full_coverage, n_entries, nullptr, s, false);
   if (rc) return rc;
   RenderArgs& ra = f.ra;
   ra.pixfeat = q.pixfeat;
@@ -560,6 +609,10 @@ int backward_common(const mb_gaussians* g, const mb_camera* cams, int32_t n_cams
   GaussWs w = carve_gauss(gws, g->n, n_cams);
   if (!gws || gws_bytes < w.bytes)
     return fail(MB_ERR_WORKSPACE, "Gaussian workspace needs %zu bytes, got %zu", w.bytes, gws_bytes);
+  if (n_entries == MB_ENTRIES_ON_DEVICE) {  // the layout the forward used with this workspace
+    n_entries = pws ? pair_capacity(pws_bytes, n_cams, cams[0].width, cams[0].height) : -1;
+    if (n_entries < 0) return fail(MB_ERR_WORKSPACE, "pair workspace of %zu bytes holds no list", pws_bytes);
+  }
   PairWs p = carve_pairs(pws, n_entries, n_keys, (int64_t)n_cams * cams[0].width * cams[0].height);
   if (!pws || pws_bytes < p.bytes)
     return fail(MB_ERR_WORKSPACE, "pair workspace needs %zu bytes, got %zu", p.bytes, pws_bytes);
@@ -599,6 +652,7 @@ int backward_common(const mb_gaussians* g, const mb_camera* cams, int32_t n_cams
   ga.means = g->means; ga.scales = g->scales; ga.quats = g->quats; ga.dens = g->densities; ga.colors = g->colors;
   ga.n = g->n; ga.sh_degree = g->sh_degree;
   ga.counts = w.counts; ga.offsets = w.offsets; ga.partials = p.partials;
+  ga.e_cap = n_entries;
   ga.g_means = g_means; ga.g_scales = g_scales; ga.g_quats = g_quats; ga.g_dens = g_densities;
   ga.g_colors = g_colors;
   {
@@ -611,13 +665,16 @@ int backward_common(const mb_gaussians* g, const mb_camera* cams, int32_t n_cams
 
 int check_backward_args(const mb_gaussians* g, const mb_camera* cams, int32_t n_cams, const mb_options* o,
                         int64_t n_entries, const float* saved, const float* grad_image, float* g_means,
-                        float* g_scales, float* g_quats, float* g_densities, float* g_colors) {
+                        float* g_scales, float* g_quats, float* g_densities, float* g_colors,
+                        bool device_count_ok = false) {
   int rc = check_common(g, cams, n_cams, o);
   if (rc) return rc;
   if (!saved || !grad_image) return fail(MB_ERR_ARG, "null saved state or image gradient");
   if (g->n > 0 && (!g_means || !g_scales || !g_quats || !g_densities || !g_colors))
     return fail(MB_ERR_ARG, "null gradient output");
-  if (n_entries < 0) return fail(MB_ERR_ARG, "negative n_entries");
+  if (n_entries < 0 && !(device_count_ok && n_entries == MB_ENTRIES_ON_DEVICE))
+    return fail(MB_ERR_ARG, "n_entries %lld is neither a count nor accepted here as MB_ENTRIES_ON_DEVICE",
+                (long long)n_entries);
   return MB_OK;
 }
 
@@ -628,7 +685,7 @@ int mb_render_backward(const mb_gaussians* g, const mb_camera* cams, int32_t n_c
                        const float* grad_image, const float* grad_penalty, float* g_means, float* g_scales,
                        float* g_quats, float* g_densities, float* g_colors, void* stream) {
   int rc = check_backward_args(g, cams, n_cams, o, n_entries, saved, grad_image, g_means, g_scales, g_quats,
-                               g_densities, g_colors);
+                               g_densities, g_colors, true);
   if (rc) return rc;
   return backward_common(g, cams, n_cams, o, gws, gws_bytes, pws, pws_bytes, n_entries, saved, grad_image,
                          grad_penalty, g_means, g_scales, g_quats, g_densities, g_colors, (hipStream_t)stream,

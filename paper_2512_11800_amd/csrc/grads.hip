@@ -186,7 +186,8 @@ __global__ __launch_bounds__(128) void k_grad_finalize(GradArgs a, CamSet cams) 
       const size_t idx = (size_t)ci * a.n + gl;
       const int cnt = valid ? a.counts[idx] : 0;
       const int off = a.offsets[idx];
-      const int base = __shfl(off, 0), end = __shfl(off + cnt, nw - 1);
+      const int base = __shfl(off, 0);
+      const int end = (int)min((int64_t)__shfl(off + cnt, nw - 1), a.e_cap);  // no slots past the capacity
       float P[G_COUNT];
 #pragma unroll
       for (int f = 0; f < G_COUNT; ++f) P[f] = 0.f;
@@ -202,7 +203,7 @@ __global__ __launch_bounds__(128) void k_grad_finalize(GradArgs a, CamSet cams) 
 #pragma unroll
         for (int f = 0; f < G_COUNT; ++f) rec[lane * kRecRow + f] = r[f];
         __builtin_amdgcn_wave_barrier();
-        const int lo = max(off, w0), hi = min(off + cnt, w0 + 64);
+        const int lo = max(off, w0), hi = min(min(off + cnt, w0 + 64), end);
         for (int j = lo; j < hi; ++j) {
           const float* t = rec + (j - w0) * kRecRow;
 #pragma unroll

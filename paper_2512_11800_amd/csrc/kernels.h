@@ -32,6 +32,7 @@ struct EmitArgs {
   int* entry_rec;      // [E] record index cam * n + g
   int2* ranges;        // [n_keys] cleared to (0, 0) when not null
   int n_keys;
+  int64_t cap;         // entries at or beyond cap are not written (workspace capacity)
 };
 hipError_t launch_emit(const EmitArgs& a, hipStream_t s);
 
@@ -79,16 +80,18 @@ size_t scan_tmp_ints(int64_t n);
 hipError_t launch_scan(const int* in, int* out, int64_t n, int* tmp, int* total, hipStream_t s);
 
 // stable LSD radix sort of (keys, vals) on the low `bits` bits of keys.
-// Buffers *_a hold the input and receive the output; *_b are scratch.
+// Buffers *_a hold the input and receive the output; *_b are scratch. The
+// launch is sized for n items; with n_dev the count is min(*n_dev, n), read
+// on the device.
 size_t radix_tmp_ints(int64_t n);
 hipError_t launch_radix_sort(uint32_t* keys_a, int* vals_a, uint32_t* keys_b, int* vals_b,
-                             int64_t n, int bits, int* tmp, hipStream_t s);
+                             int64_t n, const int* n_dev, int bits, int* tmp, hipStream_t s);
 
 // after the sort: sorted_rec[i] = entry_rec[vals[i]], inv[vals[i]] = i,
 // ranges[key] = [first, last+1) over the sorted keys (ranges zeroed first,
 // here unless ranges_cleared: the emit kernel clears them when given them).
 hipError_t launch_finish_lists(const uint32_t* keys, const int* vals, const int* entry_rec,
-                               int64_t n, int* sorted_rec, int* inv, int2* ranges,
+                               int64_t n, const int* n_dev, int* sorted_rec, int* inv, int2* ranges,
                                int n_keys, bool ranges_cleared, hipStream_t s);
 
 // block list of the render kernels (render_blocks(n_keys) entries): tiles
@@ -145,6 +148,7 @@ struct GradArgs {
   int n, sh_degree;
   const int* counts;     // [C*n]
   const int* offsets;    // [C*n]
+  int64_t e_cap;         // entries with an index at or beyond e_cap have no slots
   const float* partials; // [E,4,kGradStride]
   float *g_means, *g_scales, *g_quats, *g_dens, *g_colors;
 };

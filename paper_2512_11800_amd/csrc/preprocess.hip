@@ -226,6 +226,10 @@ __global__ __launch_bounds__(256) void k_emit(EmitArgs a) {
   int off = a.offsets[idx];
   int count = a.counts[idx];
   uint32_t base_key = (uint32_t)ci * (uint32_t)(a.tiles_x * a.tiles_y);
+  // entries past the workspace capacity are dropped (the caller compares the
+  // count with its capacity and renders again)
+  if (off >= a.cap) return;
+  count = (int)min((int64_t)count, a.cap - off);
   int j = 0;
   for (int ty = box.y; ty <= box.w && j < count; ++ty)
     for (int tx = box.x; tx <= box.z && j < count; ++tx) {

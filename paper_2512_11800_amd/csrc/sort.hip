@@ -110,14 +110,21 @@ hipError_t launch_scan(const int* in, int* out, int64_t n, int* tmp, int* total,
   return hipGetLastError();
 }
 
+// Item count of a launch sized for n_max items: *n_dev when the count lives
+// on the device (clamped to n_max), else n_max.
+__device__ __forceinline__ int64_t items_of(const int* n_dev, int64_t n_max) {
+  return n_dev ? min((int64_t)max(*n_dev, 0), n_max) : n_max;
+}
+
 // ---------------------------------------------------------------------------
 // Radix sort, 8-bit digits. Per pass: block histograms (digit-major), their
 // exclusive scan, then a stable scatter in which every block walks its chunk
 // in index order, 256 items per round, ranking equal digits inside a wave
 // with ballots and across waves through LDS counters.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_radix_hist(const uint32_t* keys, int64_t n, int shift,
-                                                    int* hist, int nblocks) {
+__global__ __launch_bounds__(256) void k_radix_hist(const uint32_t* keys, int64_t n_max, const int* n_dev,
+                                                    int shift, int* hist, int nblocks) {
+  const int64_t n = items_of(n_dev, n_max);
   __shared__ int h[256];
   h[threadIdx.x] = 0;
   __syncthreads();
@@ -132,8 +139,10 @@ __global__ __launch_bounds__(256) void k_radix_hist(const uint32_t* keys, int64_
 }
 
 __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* keys_in, const int* vals_in,
-                                                       uint32_t* keys_out, int* vals_out, int64_t n,
-                                                       int shift, const int* offsets, int nblocks) {
+                                                       uint32_t* keys_out, int* vals_out, int64_t n_max,
+                                                       const int* n_dev, int shift, const int* offsets,
+                                                       int nblocks) {
+  const int64_t n = items_of(n_dev, n_max);
   __shared__ int running[256];
   __shared__ int wave_cnt[4][256];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -180,27 +189,27 @@ size_t radix_tmp_ints(int64_t n) {
 }
 
 // one stable pass on digit (key >> shift) & 255
-static hipError_t radix_pass(const uint32_t* kin, const int* vin, uint32_t* kout, int* vout, int64_t n, int shift,
-                             int* tmp, hipStream_t s) {
+static hipError_t radix_pass(const uint32_t* kin, const int* vin, uint32_t* kout, int* vout, int64_t n,
+                             const int* n_dev, int shift, int* tmp, hipStream_t s) {
   const int64_t nb = (n + kChunk - 1) / kChunk;
   int* hist = tmp;
   int* scan_tmp = tmp + 256 * nb;
-  hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(kBlock), 0, s, kin, n, shift, hist, (int)nb);
+  hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(kBlock), 0, s, kin, n, n_dev, shift, hist, (int)nb);
   hipError_t e = launch_scan(hist, hist, 256 * nb, scan_tmp, nullptr, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(kBlock), 0, s, kin, vin, kout, vout, n, shift, hist,
-                     (int)nb);
+  hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(kBlock), 0, s, kin, vin, kout, vout, n, n_dev, shift,
+                     hist, (int)nb);
   return hipGetLastError();
 }
 
 hipError_t launch_radix_sort(uint32_t* keys_a, int* vals_a, uint32_t* keys_b, int* vals_b, int64_t n,
-                             int bits, int* tmp, hipStream_t s) {
+                             const int* n_dev, int bits, int* tmp, hipStream_t s) {
   if (n <= 1) return hipSuccess;
   int passes = (bits + 7) / 8;
   uint32_t *kin = keys_a, *kout = keys_b;
   int *vin = vals_a, *vout = vals_b;
   for (int p = 0; p < passes; ++p) {
-    hipError_t e = radix_pass(kin, vin, kout, vout, n, 8 * p, tmp, s);
+    hipError_t e = radix_pass(kin, vin, kout, vout, n, n_dev, 8 * p, tmp, s);
     if (e != hipSuccess) return e;
     uint32_t* tk = kin; kin = kout; kout = tk;
     int* tv = vin; vin = vout; vout = tv;
@@ -220,7 +229,9 @@ __global__ __launch_bounds__(256) void k_fill_ranges(int2* ranges, int n_keys) {
 }
 
 __global__ __launch_bounds__(256) void k_finish(const uint32_t* keys, const int* vals, const int* entry_rec,
-                                                int64_t n, int* sorted_rec, int* inv, int2* ranges) {
+                                                int64_t n_max, const int* n_dev, int* sorted_rec, int* inv,
+                                                int2* ranges) {
+  const int64_t n = items_of(n_dev, n_max);
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   int v = vals[i];
@@ -292,7 +303,7 @@ hipError_t launch_tile_order(const int2* ranges, int n_keys, int split, int* blo
   hipLaunchKernelGGL(k_tile_keys, dim3((n_keys + 255) / 256), dim3(256), 0, s, ranges, n_keys, split, ka, va);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  e = radix_pass(ka, va, kb, vb, n_keys, 0, rt, s);
+  e = radix_pass(ka, va, kb, vb, n_keys, nullptr, 0, rt, s);
   if (e != hipSuccess) return e;
   int total = render_blocks(n_keys);
   hipLaunchKernelGGL(k_block_list, dim3((total + 255) / 256), dim3(256), 0, s, kb, vb, n_keys, blocks);
@@ -300,13 +311,13 @@ hipError_t launch_tile_order(const int2* ranges, int n_keys, int split, int* blo
 }
 
 hipError_t launch_finish_lists(const uint32_t* keys, const int* vals, const int* entry_rec, int64_t n,
-                               int* sorted_rec, int* inv, int2* ranges, int n_keys, bool ranges_cleared,
-                               hipStream_t s) {
+                               const int* n_dev, int* sorted_rec, int* inv, int2* ranges, int n_keys,
+                               bool ranges_cleared, hipStream_t s) {
   if (!ranges_cleared)
     hipLaunchKernelGGL(k_fill_ranges, dim3((n_keys + 255) / 256), dim3(256), 0, s, ranges, n_keys);
   if (n > 0)
     hipLaunchKernelGGL(k_finish, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, keys, vals, entry_rec,
-                       n, sorted_rec, inv, ranges);
+                       n, n_dev, sorted_rec, inv, ranges);
   return hipGetLastError();
 }
 

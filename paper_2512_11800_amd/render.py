@@ -91,6 +91,7 @@ class Workspace:
         self.pws: Optional[torch.Tensor] = None
         self.qws: Optional[torch.Tensor] = None
         self.q_cap: int = 0
+        self.capacity: int = 0  # list entries of renders with the count on the device
 
     def _ensure(self, name: str, nbytes: int) -> torch.Tensor:
         cur = getattr(self, name)
@@ -109,6 +110,29 @@ class RenderState:
     width: int
     height: int
     q_cap: int = 0  # query capacity of a surrogate render
+    n_gaussians: int = 0
+
+    def entry_count(self) -> int:
+        """The frame's list-entry total, read back from the device (waits)."""
+        lib = L.load()
+        n = ctypes.c_int64(0)
+        gws = self.ws.gws
+        L.check(lib.mb_entry_count(self.n_gaussians, self.n_cams, _ptr(gws), gws.numel(), ctypes.byref(n),
+                                   _stream()))
+        return int(n.value)
+
+    def check(self):
+        """For a render with the count on the device: raise when the frame had
+        more list entries than its workspace holds (its image then misses
+        them; render again after growing ``ws.capacity``)."""
+        if self.n_entries != L.MB_ENTRIES_ON_DEVICE:
+            return
+        cap = int(L.load().mb_pair_capacity(self.ws.pws.numel(), self.n_cams, self.width, self.height))
+        n = self.entry_count()
+        if n > cap:
+            self.ws.capacity = int(n * 1.25) + 4096
+            raise RuntimeError(f"frame had {n} list entries, workspace holds {cap}; "
+                               f"capacity raised to {self.ws.capacity}, render again")
 
 
 def _cams(cams: Sequence) -> ctypes.Array:
@@ -133,21 +157,30 @@ def project(g: Gaussians, cam, opts=None) -> torch.Tensor:
 class _Frame:
     """Arguments of one forward call after mb_prepare (outputs allocated)."""
 
-    def __init__(self, g: Gaussians, cams: Sequence, opts, ws: Optional[Workspace]):
+    def __init__(self, g: Gaussians, cams: Sequence, opts, ws: Optional[Workspace], on_device: bool = False):
         lib = L.load()
         self.cam_arr = _cams(cams)
         self.n_cams = len(self.cam_arr)
+        self.n_gaussians = g.n
         self.width, self.height = int(self.cam_arr[0].width), int(self.cam_arr[0].height)
         self.o = options_struct(opts)
         self.gs = g.struct()
         self.ws = ws or Workspace(g.means.device)
         gws = self.ws._ensure("gws", lib.mb_gauss_workspace_bytes(g.n, self.n_cams))
-        n_entries = ctypes.c_int64(0)
-        L.check(lib.mb_prepare(ctypes.byref(self.gs), self.cam_arr, self.n_cams, ctypes.byref(self.o),
-                               _ptr(gws), gws.numel(), ctypes.byref(n_entries), _stream()))
-        self.n_entries = int(n_entries.value)
-        self.ws._ensure("pws", lib.mb_pair_workspace_bytes(self.n_entries, self.n_cams, self.width,
-                                                           self.height))
+        head = (ctypes.byref(self.gs), self.cam_arr, self.n_cams, ctypes.byref(self.o), _ptr(gws), gws.numel())
+        if on_device and self.ws.capacity > 0:
+            # the count stays on the device: no wait in this frame
+            L.check(lib.mb_prepare(*head, None, _stream()))
+            self.n_entries = L.MB_ENTRIES_ON_DEVICE
+            need = self.ws.capacity
+        else:
+            n_entries = ctypes.c_int64(0)
+            L.check(lib.mb_prepare(*head, ctypes.byref(n_entries), _stream()))
+            self.n_entries = need = int(n_entries.value)
+            if on_device:  # first frame: size the capacity from its count
+                self.ws.capacity = need = int(need * 1.25) + 4096
+                self.n_entries = L.MB_ENTRIES_ON_DEVICE
+        self.ws._ensure("pws", lib.mb_pair_workspace_bytes(need, self.n_cams, self.width, self.height))
         dev = g.means.device
         self.image = torch.empty(self.n_cams, self.height, self.width, 3, dtype=torch.float32, device=dev)
         self.saved = torch.empty(self.n_cams, self.height, self.width, L.MB_SAVED_FLOATS_PER_PIXEL,
@@ -161,15 +194,18 @@ class _Frame:
 
     def result(self):
         return self.image, self.saved, RenderState(self.ws, self.n_entries, self.n_cams, self.width,
-                                                   self.height)
+                                                   self.height, n_gaussians=self.n_gaussians)
 
 
 def render_forward(g: Gaussians, cams: Sequence, opts=None, ws: Optional[Workspace] = None,
-                   penalty: bool = False):
+                   penalty: bool = False, on_device: bool = False):
     """mb_prepare + mb_render_forward. Returns (image [C,H,W,3], saved [C,H,W,8],
     state), and the per-pixel consistency penalty [C,H,W] as a fourth item
-    when ``penalty``."""
-    f = _Frame(g, cams, opts, ws)
+    when ``penalty``. ``on_device`` keeps the list count on the device
+    (MB_ENTRIES_ON_DEVICE) with the pair workspace sized for ``ws.capacity``
+    (set from the first such frame's count): nothing waits, and
+    ``state.check()`` verifies afterwards that the frame fitted."""
+    f = _Frame(g, cams, opts, ws, on_device)
     pen = (torch.empty(f.n_cams, f.height, f.width, dtype=torch.float32, device=g.means.device)
            if penalty else None)
     L.check(L.load().mb_render_forward(*f.head(), _ptr(f.image), _ptr(f.saved), _ptr(pen), _stream()))
