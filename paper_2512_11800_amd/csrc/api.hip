@@ -111,7 +111,7 @@ GaussWs carve_gauss(void* p, int64_t n, int n_cams) {
 
 struct PairWs {
   uint32_t *keys_a, *keys_b;
-  int *vals_a, *vals_b, *entry_rec, *sorted_rec, *inv, *radix_tmp;
+  int *vals_a, *vals_b, *entry_rec, *sorted_rec, *radix_tmp;
   int2* ranges;
   int *order, *order_tmp;
   uint64_t* masks;
@@ -129,7 +129,6 @@ PairWs carve_pairs(void* p, int64_t e, int n_keys, int64_t n_pix) {
   w.vals_b = c.take<int>((size_t)e);
   w.entry_rec = c.take<int>((size_t)e);
   w.sorted_rec = c.take<int>((size_t)e);
-  w.inv = c.take<int>((size_t)e);
   w.radix_tmp = c.take<int>(radix_tmp_ints(e));
   w.ranges = c.take<int2>((size_t)n_keys);
   w.order = c.take<int>((size_t)render_blocks(n_keys));
@@ -252,7 +251,7 @@ int build_lists(const mb_gaussians* g, const GaussWs& w, const PairWs& p, int n_
   EmitArgs ea;
   ea.rec = w.rec; ea.tbox = w.tbox; ea.offsets = w.offsets; ea.counts = w.counts;
   ea.n = g->n; ea.n_cams = n_cams; ea.tiles_x = tx; ea.tiles_y = ty; ea.full_coverage = full_coverage;
-  ea.keys = p.keys_a; ea.vals = p.vals_a; ea.entry_rec = p.entry_rec;
+  ea.keys = p.keys_a; ea.entry_rec = p.entry_rec;
   ea.ranges = g->n > 0 ? p.ranges : nullptr;  // no emit launch without Gaussians
   ea.n_keys = n_keys;
   ea.cap = n_entries;
@@ -265,13 +264,13 @@ int build_lists(const mb_gaussians* g, const GaussWs& w, const PairWs& p, int n_
   {
     StageTimer t(S_SORT, s);
     e = launch_radix_sort(p.keys_a, p.vals_a, p.keys_b, p.vals_b, n_entries, n_dev, key_bits(n_keys), p.radix_tmp,
-                          s);
+                          s, true);
   }
   if (e != hipSuccess) return hip_fail(e, "sort");
   {
     StageTimer t(S_LISTS, s);
-    e = launch_finish_lists(p.keys_a, p.vals_a, p.entry_rec, n_entries, n_dev, p.sorted_rec, p.inv, p.ranges,
-                            n_keys, ea.ranges != nullptr, s);
+    e = launch_finish_lists(p.keys_a, p.vals_a, p.entry_rec, n_entries, n_dev, p.sorted_rec, p.ranges, n_keys,
+                            ea.ranges != nullptr, s);
     if (e == hipSuccess)
       e = launch_tile_order(p.ranges, n_keys, split_heavy ? kSplitEntries : 0x7FFFFFFF, p.order, p.order_tmp, s);
   }

@@ -27,8 +27,7 @@ struct EmitArgs {
   const int* offsets;  // [C*n] exclusive scan of counts
   const int* counts;   // [C*n] tiles counted by the preprocess kernel
   int n, n_cams, tiles_x, tiles_y, full_coverage;
-  uint32_t* keys;      // [E] tile key cam * T + tile
-  int* vals;           // [E] entry index
+  uint32_t* keys;      // [E] tile key cam * T + tile (the sort's values are the entry indices)
   int* entry_rec;      // [E] record index cam * n + g
   int2* ranges;        // [n_keys] cleared to (0, 0) when not null
   int n_keys;
@@ -82,16 +81,18 @@ hipError_t launch_scan(const int* in, int* out, int64_t n, int* tmp, int* total,
 // stable LSD radix sort of (keys, vals) on the low `bits` bits of keys.
 // Buffers *_a hold the input and receive the output; *_b are scratch. The
 // launch is sized for n items; with n_dev the count is min(*n_dev, n), read
-// on the device.
+// on the device. identity_vals: the input values are 0, 1, 2, ... and vals_a
+// is not read.
 size_t radix_tmp_ints(int64_t n);
 hipError_t launch_radix_sort(uint32_t* keys_a, int* vals_a, uint32_t* keys_b, int* vals_b,
-                             int64_t n, const int* n_dev, int bits, int* tmp, hipStream_t s);
+                             int64_t n, const int* n_dev, int bits, int* tmp, hipStream_t s,
+                             bool identity_vals = false);
 
-// after the sort: sorted_rec[i] = entry_rec[vals[i]], inv[vals[i]] = i,
-// ranges[key] = [first, last+1) over the sorted keys (ranges zeroed first,
-// here unless ranges_cleared: the emit kernel clears them when given them).
+// after the sort: sorted_rec[i] = entry_rec[vals[i]], ranges[key] =
+// [first, last+1) over the sorted keys (ranges zeroed first, here unless
+// ranges_cleared: the emit kernel clears them when given them).
 hipError_t launch_finish_lists(const uint32_t* keys, const int* vals, const int* entry_rec,
-                               int64_t n, const int* n_dev, int* sorted_rec, int* inv, int2* ranges,
+                               int64_t n, const int* n_dev, int* sorted_rec, int2* ranges,
                                int n_keys, bool ranges_cleared, hipStream_t s);
 
 // block list of the render kernels (render_blocks(n_keys) entries): tiles

@@ -236,7 +236,6 @@ __global__ __launch_bounds__(256) void k_emit(EmitArgs a) {
       if (!tile_overlaps(mx, my, r, tx, ty)) continue;
       int e = off + j++;
       a.keys[e] = base_key + (uint32_t)(ty * a.tiles_x + tx);
-      a.vals[e] = e;
       a.entry_rec[e] = (int)idx;
     }
   // never leave a counted slot unwritten; an extra list entry is harmless
@@ -244,7 +243,6 @@ __global__ __launch_bounds__(256) void k_emit(EmitArgs a) {
   for (; j < count; ++j) {
     int e = off + j;
     a.keys[e] = base_key + (uint32_t)(box.y * a.tiles_x + box.x);
-    a.vals[e] = e;
     a.entry_rec[e] = (int)idx;
   }
 }

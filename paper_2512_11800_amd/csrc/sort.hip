@@ -156,7 +156,7 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* keys_in, 
     int64_t i = base + r * kBlock + tid;
     bool valid = i < n;
     uint32_t key = valid ? keys_in[i] : 0u;
-    int val = valid ? vals_in[i] : 0;
+    int val = valid ? (vals_in ? vals_in[i] : (int)i) : 0;  // no vals_in: the identity
     uint32_t d = (key >> shift) & 255u;
     uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -203,21 +203,22 @@ static hipError_t radix_pass(const uint32_t* kin, const int* vin, uint32_t* kout
 }
 
 hipError_t launch_radix_sort(uint32_t* keys_a, int* vals_a, uint32_t* keys_b, int* vals_b, int64_t n,
-                             const int* n_dev, int bits, int* tmp, hipStream_t s) {
-  if (n <= 1) return hipSuccess;
-  int passes = (bits + 7) / 8;
-  uint32_t *kin = keys_a, *kout = keys_b;
-  int *vin = vals_a, *vout = vals_b;
+                             const int* n_dev, int bits, int* tmp, hipStream_t s, bool identity_vals) {
+  const int passes = (bits + 7) / 8;
+  if (n <= 0 || passes <= 0) return hipSuccess;
+  uint32_t* kbuf[2] = {keys_a, keys_b};
+  int* vbuf[2] = {vals_a, vals_b};
+  int cur = 0;  // buffer holding the input of the next pass
   for (int p = 0; p < passes; ++p) {
-    hipError_t e = radix_pass(kin, vin, kout, vout, n, n_dev, 8 * p, tmp, s);
+    const int* vin = (p == 0 && identity_vals) ? nullptr : vbuf[cur];
+    hipError_t e = radix_pass(kbuf[cur], vin, kbuf[cur ^ 1], vbuf[cur ^ 1], n, n_dev, 8 * p, tmp, s);
     if (e != hipSuccess) return e;
-    uint32_t* tk = kin; kin = kout; kout = tk;
-    int* tv = vin; vin = vout; vout = tv;
+    cur ^= 1;
   }
-  if (kin != keys_a) {
-    hipError_t e = hipMemcpyAsync(keys_a, kin, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s);
+  if (cur != 0) {
+    hipError_t e = hipMemcpyAsync(keys_a, keys_b, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return e;
-    e = hipMemcpyAsync(vals_a, vin, n * sizeof(int), hipMemcpyDeviceToDevice, s);
+    e = hipMemcpyAsync(vals_a, vals_b, n * sizeof(int), hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return e;
   }
   return hipGetLastError();
@@ -229,14 +230,12 @@ __global__ __launch_bounds__(256) void k_fill_ranges(int2* ranges, int n_keys) {
 }
 
 __global__ __launch_bounds__(256) void k_finish(const uint32_t* keys, const int* vals, const int* entry_rec,
-                                                int64_t n_max, const int* n_dev, int* sorted_rec, int* inv,
-                                                int2* ranges) {
+                                                int64_t n_max, const int* n_dev, int* sorted_rec, int2* ranges) {
   const int64_t n = items_of(n_dev, n_max);
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   int v = vals[i];
   sorted_rec[i] = entry_rec[v];
-  inv[v] = (int)i;
   uint32_t key = keys[i];
   if (i == 0 || keys[i - 1] != key) ranges[key].x = (int)i;
   if (i == n - 1 || keys[i + 1] != key) ranges[key].y = (int)(i + 1);
@@ -311,13 +310,13 @@ hipError_t launch_tile_order(const int2* ranges, int n_keys, int split, int* blo
 }
 
 hipError_t launch_finish_lists(const uint32_t* keys, const int* vals, const int* entry_rec, int64_t n,
-                               const int* n_dev, int* sorted_rec, int* inv, int2* ranges, int n_keys,
-                               bool ranges_cleared, hipStream_t s) {
+                               const int* n_dev, int* sorted_rec, int2* ranges, int n_keys, bool ranges_cleared,
+                               hipStream_t s) {
   if (!ranges_cleared)
     hipLaunchKernelGGL(k_fill_ranges, dim3((n_keys + 255) / 256), dim3(256), 0, s, ranges, n_keys);
   if (n > 0)
     hipLaunchKernelGGL(k_finish, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, keys, vals, entry_rec,
-                       n, n_dev, sorted_rec, inv, ranges);
+                       n, n_dev, sorted_rec, ranges);
   return hipGetLastError();
 }
 
