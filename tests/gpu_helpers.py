@@ -16,10 +16,19 @@ def log(*args):
     sys.stdout.flush()
 
 
-def gpu_render(scene, cams, opts):
+def gpu_render(scene, cams, opts, on_device=False):
+    """Forward render through the C ABI. on_device: as the benchmark times
+    it, the list count kept on the device (a first frame sizes the capacity,
+    the returned second frame has no host round trip), checked to fit."""
     import paper_2512_11800_amd as M
     g = M.Gaussians.from_scene(scene)
-    img, saved, st = M.render_forward(g, cams, opts)
+    if on_device:
+        ws = M.Workspace()
+        M.render_forward(g, cams, opts, ws=ws, on_device=True)
+        img, saved, st = M.render_forward(g, cams, opts, ws=ws, on_device=True)
+        st.check()
+    else:
+        img, saved, st = M.render_forward(g, cams, opts)
     torch.cuda.synchronize()
     return img.cpu().numpy().astype(np.float64), saved.cpu().numpy().astype(np.float64), st
 

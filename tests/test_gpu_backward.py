@@ -17,12 +17,18 @@ pytestmark = pytest.mark.gpu
 GROUPS = ("means", "scales", "quats", "densities", "colors")
 
 
-def _gpu_grads(scene, cams, opts, grad_img):
+def _gpu_grads(scene, cams, opts, grad_img, on_device=False):
+    """Forward + backward through the C ABI; on_device as the benchmark times
+    it (list count on the device, the second frame of a workspace)."""
     import paper_2512_11800_amd as M
     g = M.Gaussians.from_scene(scene)
-    img, saved, st = M.render_forward(g, cams, opts)
+    ws = M.Workspace()
+    if on_device:
+        M.render_forward(g, cams, opts, ws=ws, on_device=True)
+    img, saved, st = M.render_forward(g, cams, opts, ws=ws, on_device=on_device)
     gi = torch.as_tensor(grad_img, dtype=torch.float32, device="cuda").reshape(img.shape)
     out = M.render_backward(g, cams, opts, st, saved, gi)
+    st.check()
     torch.cuda.synchronize()
     return {k: v.cpu().numpy().astype(np.float64) for k, v in out.items()}, img.cpu().numpy()
 
@@ -108,9 +114,9 @@ def test_w1_proxy_coverage_vs_oracle_autograd():
 
 
 def test_w3_full_size_sampled_gaussians():
-    """1M Gaussians at 1600x1064 (the benchmark's training configuration):
-    gradients of sampled Gaussians, each computed by the oracle from every
-    pixel it covers."""
+    """1M Gaussians at 1600x1064 (the benchmark's training configuration, in
+    its launch configuration): gradients of sampled Gaussians, each computed
+    by the oracle from every pixel it covers."""
     scene, _, cams, opts = W.w3_train()
     cam = cams[0]
     from oracle.proxy import screen_proxy
@@ -138,7 +144,7 @@ def test_w3_full_size_sampled_gaussians():
     vals = rng.normal(size=(len(pix), 3))
     vals[amb] = 0.0
     g_full[pix] = vals
-    gpu, _ = _gpu_grads(scene, cams, opts, g_full)
+    gpu, _ = _gpu_grads(scene, cams, opts, g_full, on_device=True)
     ref = oracle.render_backward(scene, cam, opts, vals, pixels=pix)
     log(f"[w3] sampled {len(sample)} Gaussians over {len(pix)} pixels ({int(amb.sum())} ambiguous)")
     assert _check(gpu, ref, "W3 sampled", idx=sample, tol=2e-3)
