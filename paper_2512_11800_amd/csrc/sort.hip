@@ -96,6 +96,42 @@ __global__ __launch_bounds__(256) void k_scan_down(const int* in, int* out, int6
   }
 }
 
+// Down-sweep that forms its block's offset itself: the sum of the block sums
+// before it (fixed order), for at most kDirectBlocks blocks; block 0 also
+// writes the total. Saves the single-block pass between the two sweeps.
+constexpr int kDirectBlocks = 1024;
+
+__global__ __launch_bounds__(256) void k_scan_down_direct(const int* in, int* out, int64_t n, const int* sums,
+                                                          int nb, int* total) {
+  __shared__ int lds[4];
+  const int upto = total != nullptr && blockIdx.x == 0 ? nb : (int)blockIdx.x;
+  int s = 0;
+  for (int i = threadIdx.x; i < upto; i += kBlock) s += sums[i];
+  int tot;
+  block_exclusive_sum(s, lds, &tot);
+  int before = tot;  // blocks [0, upto)
+  if (blockIdx.x == 0) {
+    if (total != nullptr && threadIdx.x == 0) *total = tot;
+    before = 0;
+  }
+  int64_t base = (int64_t)blockIdx.x * kChunk + threadIdx.x * kItems;
+  int v[kItems];
+  int t = 0;
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    int64_t i = base + k;
+    v[k] = (i < n) ? in[i] : 0;
+    t += v[k];
+  }
+  int off = block_exclusive_sum(t, lds, &tot) + before;
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    int64_t i = base + k;
+    if (i < n) out[i] = off;
+    off += v[k];
+  }
+}
+
 size_t scan_tmp_ints(int64_t n) { return (size_t)((n + kChunk - 1) / kChunk) + 1; }
 
 hipError_t launch_scan(const int* in, int* out, int64_t n, int* tmp, int* total, hipStream_t s) {
@@ -105,8 +141,13 @@ hipError_t launch_scan(const int* in, int* out, int64_t n, int* tmp, int* total,
     return hipSuccess;
   }
   hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kBlock), 0, s, in, n, tmp);
-  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, s, tmp, nb, total);
-  hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kBlock), 0, s, in, out, n, tmp);
+  if (nb <= kDirectBlocks) {
+    hipLaunchKernelGGL(k_scan_down_direct, dim3((unsigned)nb), dim3(kBlock), 0, s, in, out, n, tmp, (int)nb,
+                       total);
+  } else {
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, s, tmp, nb, total);
+    hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kBlock), 0, s, in, out, n, tmp);
+  }
   return hipGetLastError();
 }
 
