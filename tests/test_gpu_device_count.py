@@ -87,3 +87,23 @@ def test_overflow_is_reported_and_stays_in_bounds():
     assert torch.equal(again[0], ref[0]) and torch.equal(again[1], ref[1])
     for k, v in ref[2].items():
         assert torch.equal(again[2][k], v), k
+
+
+@pytest.mark.parametrize("n_keep", [0, 1])
+def test_device_count_empty_and_single(n_keep):
+    """No Gaussians (no emit launch, the capacity's default slack) and one
+    Gaussian: the device-count frame equals the counted one."""
+    import paper_2512_11800_amd as M
+    scene, cams, opts = W.w1_small()
+    scene = scene.subset(np.arange(5, 5 + n_keep))
+    g = M.Gaussians.from_scene(scene)
+    gi = _upstream(cams, 7)
+    ref = _frame(g, cams, opts, M.Workspace(), False, gi)
+    ws = M.Workspace()
+    for _ in range(2):
+        out = _frame(g, cams, opts, ws, True, gi)
+        out[3].check()
+        assert out[3].entry_count() == ref[3].n_entries
+        assert torch.equal(out[0], ref[0]) and torch.equal(out[1], ref[1])
+        for k, v in ref[2].items():
+            assert torch.equal(out[2][k], v), k
