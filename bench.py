@@ -27,6 +27,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_VALU_TFLOPS = 157.3  # MI355X vector FP32 (256 CUs, 2.4 GHz)
+PEAK_HBM_GBPS = 8000.0  # MI355X HBM3E
 
 
 def flops_per_pair(k_mom: int, n_int: int) -> dict:
@@ -160,27 +161,29 @@ def gpu_bench(args):
         torch.cuda.synchronize()
         L.profile_read()  # clear
         L.profile_enable(True)
-        t0 = torch.cuda.Event(enable_timing=True)
-        t1 = torch.cuda.Event(enable_timing=True)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
         wall0 = time.perf_counter()
-        t0.record()
-        for _ in range(args.steps):
+        ev[0].record()
+        for i in range(args.steps):
             out = step()
-        t1.record()
+            ev[i + 1].record()
         torch.cuda.synchronize()
         wall = time.perf_counter() - wall0
         L.profile_enable(False)
         stages = L.profile_read()
-        return out, t0.elapsed_time(t1) / args.steps, 1e3 * wall / args.steps, stages
+        per = sorted(ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps))
+        pct = {q: per[min(len(per) - 1, int(q / 100 * len(per)))] for q in (10, 50, 90)}
+        return out, ev[0].elapsed_time(ev[-1]) / args.steps, 1e3 * wall / args.steps, stages, pct
 
     modes = {"fwd": [("fwd", fwd)], "fwdbwd": [("fwdbwd", fwdbwd)],
              "both": [("fwd", fwd), ("fwdbwd", fwdbwd)]}[args.mode]
     res = {}
     for name, step in modes:
-        (image, saved, st), ms, wall_ms, stages = timed(step)
+        (image, saved, st), ms, wall_ms, stages, pct = timed(step)
         st.check()  # the frames fitted their workspace (the scene is the same every frame)
         print(f"[bench] {name}: {ms:.3f} ms/frame", file=sys.stderr, flush=True)
         res[name] = {"ms_per_step": ms, "wall_ms_per_step": wall_ms,
+                     "step_ms_p10_p50_p90": [round(pct[q], 4) for q in (10, 50, 90)],
                      "stages_ms": {k: round(v[0] / max(1, v[1]), 4) for k, v in stages.items() if v[1]},
                      "stages_raw": stages}
     c = saved[..., 7]
@@ -207,6 +210,16 @@ def gpu_bench(args):
     if last == "fwdbwd":
         out["roofline_bwd"] = roofline("render_backward", "k_render_bwd", fl["backward"],
                                        f"mb::k_render_bwd<{args.k}, {opts.n_intervals + 1}, 0>")
+    # the preprocess against HBM: per (camera, Gaussian) it reads the parameters
+    # (means, scales, quats, density: 44 B, colours 12 (d+1)^2 B) and writes the
+    # 96 B record, the int4 tile box and the tile count (116 B)
+    raw = res[last]["stages_raw"]["preprocess"]
+    pms = raw[0] / max(1, raw[1])
+    per_g = 44 + 12 * (scene.sh_degree + 1) ** 2 + 116 if scene.sh_degree >= 0 else 44 + 12 + 116
+    gbps = per_g * scene.n * len(cams) / (pms * 1e-3) / 1e9
+    out["roofline_preprocess"] = {"bound": "hbm", "kernel": "k_preprocess", "achieved": gbps,
+                                  "peak": PEAK_HBM_GBPS, "unit": "GB/s", "frac": gbps / PEAK_HBM_GBPS,
+                                  "bytes_per_gaussian": per_g, "kernel_ms": pms}
     for r in res.values():
         r.pop("stages_raw")
     return out, scene, cams, opts, n_pairs
@@ -386,12 +399,12 @@ def main():
                          "w3: training step, 1M Gaussians at 1600x1064 with an L1 loss against a "
                          "render of a perturbed copy; "
                          "w5: 3M Gaussians, 8 cameras at 3840x2160 in one launch sequence")
-    ap.add_argument("--cpu-sample-px", type=int, default=12000)
+    ap.add_argument("--cpu-sample-px", type=int, default=30000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the camera-parallel multi-GPU design is documented but not built)", file=sys.stderr)
+        print(f"bench.py: the renderer runs on one GPU; --gpus {args.gpus} is not supported "
+              "(camera-parallel rendering over several GPUs is designed, not implemented)", file=sys.stderr)
         sys.exit(2)
 
     if args.mode == "copy":
@@ -457,6 +470,8 @@ def main():
     if "fwdbwd" in modes:
         out["fwdbwd_ms_per_frame"] = modes["fwdbwd"]["ms_per_step"]
     out["roofline_fwd"] = res["roofline_fwd"]
+    out["roofline_preprocess"] = res["roofline_preprocess"]
+    out["step_ms_p10_p50_p90"] = {m: modes[m]["step_ms_p10_p50_p90"] for m in modes}
     out["pairs_per_frame"] = res["n_pairs"]
     # (pixel, Gaussian) evaluations per second of the whole frame (all stages)
     out["gaussian_pixel_evals_per_s"] = {m: res["n_pairs"] / (modes[m]["ms_per_step"] * 1e-3) for m in modes}
