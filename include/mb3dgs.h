@@ -278,15 +278,17 @@ int mb_render_backward_surrogate(const mb_gaussians *g, const mb_camera *cams, i
  *                summed into the same buffer)
  *  ws            mb_dssim_workspace_bytes(n_cams, width, height) bytes */
 size_t mb_dssim_workspace_bytes(int32_t n_cams, int32_t width, int32_t height);
-/* The L1 term of the same objective: *loss (device) = mean |image - target|
- * over n floats; grad_image (device, or NULL) is ACCUMULATED with
- * grad_scale sign(image - target) / n. ws: mb_l1_workspace_bytes() bytes. */
-size_t mb_l1_workspace_bytes(void);
-int mb_l1(const float *image, const float *target, int64_t n, float grad_scale, float *loss,
-          float *grad_image, void *ws, size_t ws_bytes, void *stream);
 int mb_dssim(const float *image, const float *target, int32_t n_cams, int32_t width,
              int32_t height, float grad_scale, float *loss, float *grad_image, void *ws,
              size_t ws_bytes, void *stream);
+
+/* The L1 term of the objective above: *loss (device) = mean |image - target|
+ * over n floats; grad_image (device, or NULL) is ACCUMULATED with
+ * grad_scale sign(image - target) / n, the sign 0 where they are equal.
+ * ws: mb_l1_workspace_bytes() bytes. */
+size_t mb_l1_workspace_bytes(void);
+int mb_l1(const float *image, const float *target, int64_t n, float grad_scale, float *loss,
+          float *grad_image, void *ws, size_t ws_bytes, void *stream);
 
 /* Adaptive density control of the density-based medium (App. E), one thread
  * per particle. Colours are laid out as in an mb_gaussians set: 3 (SH degree
