@@ -15,7 +15,7 @@ import torch
 
 from . import loss as GL
 from .adc import AdcState
-from .render import Gaussians, render_backward, render_forward
+from .render import Gaussians, Workspace, render_backward, render_forward
 from .surrogate import adam_step
 
 PARAMS = ("means", "scales", "quats", "densities", "colors")
@@ -40,10 +40,15 @@ class Adam:
 
 
 def train_step(g: Gaussians, cams: Sequence, opts, target: torch.Tensor, adam: Adam,
-               adc: Optional[AdcState] = None) -> Dict[str, torch.Tensor]:
+               adc: Optional[AdcState] = None, ws: Optional[Workspace] = None,
+               on_device: bool = False) -> Dict[str, torch.Tensor]:
     """Render, evaluate the objective, back-propagate, update g in place.
-    Returns the loss terms as device scalars."""
-    image, saved, state, pen = render_forward(g, cams, opts, penalty=True)
+    Returns the loss terms as device scalars, and the render state under
+    "state". With ``ws`` and ``on_device`` the step has no host round trip;
+    ``state.check()`` then verifies that the frame fitted the workspace (a
+    workspace sized before a densification step is replaced, or its capacity
+    grows, after it)."""
+    image, saved, state, pen = render_forward(g, cams, opts, ws=ws, penalty=True, on_device=on_device)
     l1, ds, gimg = GL.objective_image_grad(image, target)
     gpen = torch.full_like(pen, GL.LAMBDA / pen.numel())
     cons = GL.l1(pen, torch.zeros_like(pen))  # mean penalty (it is non-negative)
@@ -52,4 +57,4 @@ def train_step(g: Gaussians, cams: Sequence, opts, target: torch.Tensor, adam: A
         adc.accumulate(grads["means"])
     adam.update(g, grads)
     total = (1 - GL.ALPHA) * l1 + GL.ALPHA * ds + GL.LAMBDA * cons
-    return {"l1": l1, "dssim": ds, "consistency": cons, "total": total}
+    return {"l1": l1, "dssim": ds, "consistency": cons, "total": total, "state": state}

@@ -5,7 +5,9 @@ adaptive-density-control step and more training of the new set. Property
 bars: the objective falls by a third and the render's PSNR against the
 target rises (single-view fitting does not pin individual positions, so
 their error is only logged); the densified set has the planned size, renders
-finite, and training it (fresh optimiser state) at least halves its L1."""
+finite, and training it (fresh optimiser state) at least halves its L1. The
+first fit runs its frames with the list count on the device (no host round
+trip per step), each checked to fit its workspace; the second takes counts."""
 import numpy as np
 import pytest
 import torch
@@ -36,8 +38,10 @@ def test_fit_a_perturbed_scene_then_densify():
     adam = T.Adam({"means": 2e-3, "colors": 5e-3})
     state = ADC.AdcState.zeros(g.n)
     first = None
-    for it in range(60):
-        terms = T.train_step(g, cams, opts, target, adam, state)
+    ws = M.Workspace()
+    for it in range(60):  # frames with the list count on the device, checked every step
+        terms = T.train_step(g, cams, opts, target, adam, state, ws=ws, on_device=True)
+        terms["state"].check()
         tot = float(terms["total"])
         first = tot if first is None else first
         if it % 20 == 0:
