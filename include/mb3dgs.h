@@ -334,8 +334,11 @@ int mb_adc_plan(const mb_gaussians *g, const float *grad_acc, const int32_t *gra
 int mb_adc_apply(const mb_gaussians *g, const int32_t *action, const int32_t *offsets, float *means,
                  float *scales, float *quats, float *densities, float *colors, void *stream);
 
-/* Stage timing. While enabled, every entry point records HIP events around
- * each of its stages on its stream (a small per-process overhead).
+/* Stage timing. mb_profile_enable(stages) selects the stages to time: bit s
+ * of `stages` for stage s in the order below, MB_PROFILE_ALL for all, 0 to
+ * stop. Every entry point then records two HIP events around each selected
+ * stage on its stream (each record adds a marker to the stream, a few
+ * microseconds of device time per frame and stage).
  * mb_profile_read waits for the recorded events, writes up to `max` stage
  * totals in milliseconds to ms[] and launch counts to calls[] (both host,
  * may be NULL), clears the record and returns the number of stages
@@ -343,7 +346,8 @@ int mb_adc_apply(const mb_gaussians *g, const int32_t *action, const int32_t *of
  * render_forward, render_backward, gradients, mlp, render_consume (the
  * surrogate's quadrature). Not thread safe with concurrent renders. */
 #define MB_STAGE_COUNT 10
-void mb_profile_enable(int32_t on);
+#define MB_PROFILE_ALL ((1 << MB_STAGE_COUNT) - 1)
+void mb_profile_enable(int32_t stages);
 int32_t mb_profile_read(double *ms, int64_t *calls, int32_t max);
 
 #ifdef __cplusplus

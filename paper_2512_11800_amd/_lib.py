@@ -140,8 +140,15 @@ def check(rc: int):
         raise MbError(rc, msg.decode() if msg else "")
 
 
-def profile_enable(on: bool = True):
-    load().mb_profile_enable(1 if on else 0)
+def profile_enable(on: bool = True, stages=None):
+    """Time every stage (``on``), none, or only the named ``stages``."""
+    if stages is not None:
+        mask = 0
+        for name in stages:
+            mask |= 1 << STAGES.index(name)
+    else:
+        mask = (1 << MB_STAGE_COUNT) - 1 if on else 0
+    load().mb_profile_enable(mask)
 
 
 def profile_read():

@@ -21,7 +21,7 @@ enum Stage { S_PREPROCESS = 0, S_SCAN, S_EMIT, S_SORT, S_LISTS, S_RENDER_FWD, S_
 
 struct Profiler {
   std::mutex mu;
-  bool on = false;
+  uint32_t mask = 0;  // stages being timed (bit s for stage s)
   struct Rec { int stage; hipEvent_t a, b; };
   std::vector<Rec> recs;
   std::vector<hipEvent_t> pool;
@@ -40,7 +40,7 @@ struct StageTimer {
   hipEvent_t a = nullptr, b = nullptr;
   StageTimer(int st, hipStream_t str) : stage(st), s(str) {
     std::lock_guard<std::mutex> lk(g_prof.mu);
-    if (!g_prof.on) return;
+    if (!((g_prof.mask >> stage) & 1u)) return;
     a = g_prof.get();
     b = g_prof.get();
     if (a && b) hipEventRecord(a, s);
@@ -370,9 +370,9 @@ void mb_default_options(mb_options* o) {
 
 const char* mb_last_error(void) { return g_err.c_str(); }
 
-void mb_profile_enable(int32_t on) {
+void mb_profile_enable(int32_t stages) {
   std::lock_guard<std::mutex> lk(g_prof.mu);
-  g_prof.on = on != 0;
+  g_prof.mask = (uint32_t)stages & ((1u << MB_STAGE_COUNT) - 1u);
 }
 
 int32_t mb_profile_read(double* ms, int64_t* calls, int32_t max) {
