@@ -43,13 +43,21 @@ struct StageTimer {
     if (!((g_prof.mask >> stage) & 1u)) return;
     a = g_prof.get();
     b = g_prof.get();
-    if (a && b) hipEventRecord(a, s);
+    if (a && b && hipEventRecord(a, s) == hipSuccess) return;
+    release();  // no timing for this stage
   }
   ~StageTimer() {
     if (!a || !b) return;
-    hipEventRecord(b, s);
+    const bool ok = hipEventRecord(b, s) == hipSuccess;
     std::lock_guard<std::mutex> lk(g_prof.mu);
-    g_prof.recs.push_back({stage, a, b});
+    if (ok) g_prof.recs.push_back({stage, a, b});
+    else release();
+  }
+  // hand the events back to the pool (g_prof.mu held)
+  void release() {
+    if (a) g_prof.pool.push_back(a);
+    if (b) g_prof.pool.push_back(b);
+    a = b = nullptr;
   }
 };
 

@@ -5,6 +5,7 @@ closed forms, numeric integration, textbook cases, linear programming,
 library special functions, invariants, limits and finite differences.
 """
 import math
+import warnings
 
 import numpy as np
 import pytest
@@ -428,8 +429,12 @@ def test_single_colour_scene_renders_exact_opacity(k_mom):
                                                      @ (x - scene.means[i])) for i in range(scene.n))
 
         centres = sorted(float((scene.means[i] - o) @ d) for i in range(scene.n))
-        tau = integrate.quad(dens, cam.t_near, 50, limit=800, epsabs=1e-15, epsrel=1e-12,
-                             points=centres)[0]
+        with warnings.catch_warnings():
+            # quad reports round-off near its tolerance floor; the bar below
+            # (1e-7 relative) is far above it
+            warnings.simplefilter("ignore", integrate.IntegrationWarning)
+            tau = integrate.quad(dens, cam.t_near, 50, limit=800, epsabs=1e-15, epsrel=1e-10,
+                                 points=centres)[0]
         assert r["moments"][pix, 0] == pytest.approx(tau, rel=1e-7, abs=1e-13)
         assert r["opacity"][pix] >= opts.eps
         expect = colour * (1 - math.exp(-tau)) + math.exp(-tau) * np.array(cam.background)
@@ -630,7 +635,7 @@ def test_surrogate_reference_vs_torch_autograd():
     f = torch.sigmoid(a2 @ p["w3"] + p["b3"][0])
     lt = ((torch.exp(-xt[:, 7] * f) - torch.tensor(t)) ** 2).mean()
     lt.backward()
-    assert float(lt) == pytest.approx(loss, rel=1e-12)
+    assert float(lt.detach()) == pytest.approx(loss, rel=1e-12)
     assert np.allclose(th.grad.numpy(), g, rtol=1e-9, atol=1e-14)
 
 
