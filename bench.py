@@ -400,7 +400,7 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--mode", choices=["both", "fwd", "fwdbwd", "surrogate", "copy"], default="both")
     ap.add_argument("--harvest", type=int, default=10_000_000)
     ap.add_argument("--train-steps", type=int, default=4000)
