@@ -15,7 +15,7 @@ from dataclasses import dataclass
 import numpy as np
 import torch
 
-from .geometry import DT, camera_matrices, quat_to_rot
+from .geometry import DT
 
 
 @dataclass
@@ -27,6 +27,31 @@ class Proxy:
     ambiguous: torch.Tensor  # [n] bool: a cull/ellipse decision is within rounding
     kappa: torch.Tensor      # [n]
     quad: torch.Tensor       # [n] mean^T A mean (camera frame)
+    in_frustum: torch.Tensor  # [n] bool: the bounding-sphere cull alone keeps it
+
+
+# Bands of the parity protocol for decisions taken at a threshold. The HIP
+# path takes every per-Gaussian decision (cull, proxy, rectangle) in double
+# precision from the same float32 inputs, so the two sides can differ only by
+# double rounding: relative 1e-12 is thousands of times that.
+CULL_REL = 1e-12
+# Coverage decisions (pixel centre against rectangle edge): the HIP path tests
+# in double against a rectangle computed in double, so |margin| < MARGIN_TOL
+# pixels is ambiguous, and the axes of a near-circle are ambiguous to
+# ORIENT_EPS / (1 - minor^2 / major^2) radians (their conditioning).
+MARGIN_TOL = 1e-9
+ORIENT_EPS = 1e-11
+
+
+def _quat_rot_ld(q: np.ndarray) -> np.ndarray:
+    """Rotation matrices [n,3,3] of quaternions (w, x, y, z), normalised first
+    (the Sec. 3.1 parameterisation), in numpy long double."""
+    q = q / np.sqrt((q * q).sum(-1, keepdims=True))
+    w, x, y, z = q.T
+    r = np.stack([1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y),
+                  2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
+                  2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)], -1)
+    return r.reshape(-1, 3, 3)
 
 
 def screen_proxy(scene_t, cam, conf_c: float) -> Proxy:
@@ -43,37 +68,53 @@ def screen_proxy(scene_t, cam, conf_c: float) -> Proxy:
         m = K^-T A mean,  M = K^-T A K^-1,  W = m m^T - kappa M
         mean2d = -W22^-1 w21,  Sigma2d = (mean2d^T W22 mean2d - w33) W22^-1
     and the rectangle spans sqrt(lambda_k) e_k over the eigenpairs of Sigma2d.
+
+    The paper names the oriented box of the ellipse but not its orientation
+    when the ellipse is (nearly) a circle, where the eigenvectors are
+    ill-conditioned. Reading: the first axis is the major axis at the angle
+    theta = atan2(2 s_xy, s_xx - s_yy) / 2 of Sigma2d = [[s_xx, s_xy],
+    [s_xy, s_yy]], the second axis is it turned by +90 degrees, and an exact
+    circle (s_xy = 0, s_xx = s_yy) takes theta = atan2(0, 0) / 2 = 0.
+
+    The homogeneous conic cancels: m m^T and kappa M agree in their leading
+    digits, so float64 loses about seven of them (3e-7 px on the half lengths
+    of 1080p proxies). The formulas are therefore evaluated as written in
+    numpy long double (64-bit mantissa on x86) from the float32 inputs; the
+    results are returned as float64 tensors. Nothing here is differentiated.
     """
-    r_wc, t_wc, _ = camera_matrices(cam)
-    means, scales, quats, dens = (scene_t[k].detach() for k in
+    LD = np.longdouble
+    w2c = np.asarray(cam.world_to_cam).astype(LD)
+    r_wc, t_wc = w2c[:, :3], w2c[:, 3]
+    means, scales, quats, dens = (scene_t[k].detach().numpy().astype(LD) for k in
                                   ("means", "scales", "quats", "densities"))
+    fx, fy, cx, cy, t_near = (LD(v) for v in (cam.fx, cam.fy, cam.cx, cam.cy, cam.t_near))
     mu_c = means @ r_wc.T + t_wc
-    rot_c = r_wc @ quat_to_rot(quats)
-    a = rot_c @ torch.diag_embed(1.0 / scales ** 2) @ rot_c.transpose(-1, -2)
+    rot_c = r_wc @ _quat_rot_ld(quats)
+    a = (rot_c / (scales ** 2)[:, None, :]) @ np.swapaxes(rot_c, -1, -2)
 
     # --- culling with the bounding sphere -----------------------------------
-    radius = scales.max(dim=-1).values
-    w_img, h_img = cam.width, cam.height
-    normals = torch.tensor([[cam.fx, 0.0, cam.cx], [-cam.fx, 0.0, w_img - cam.cx],
-                            [0.0, cam.fy, cam.cy], [0.0, -cam.fy, h_img - cam.cy]], dtype=DT)
-    normals = normals / normals.norm(dim=-1, keepdim=True)
+    radius = scales.max(axis=-1)
+    w_img, h_img = LD(cam.width), LD(cam.height)
+    normals = np.array([[fx, 0, cx], [-fx, 0, w_img - cx],
+                        [0, fy, cy], [0, -fy, h_img - cy]], dtype=LD)
+    normals = normals / np.sqrt((normals ** 2).sum(-1, keepdims=True))
     side = mu_c @ normals.T + radius[:, None]           # >= 0: not wholly outside
-    near_sphere = mu_c[:, 2] + radius - cam.t_near       # >= 0: not wholly in front of t_n
-    near_centre = mu_c[:, 2] - cam.t_near               # > 0 required
+    near_sphere = mu_c[:, 2] + radius - t_near           # >= 0: not wholly in front of t_n
+    near_centre = mu_c[:, 2] - t_near                   # > 0 required
     in_frustum = (side >= 0).all(-1) & (near_sphere >= 0) & (near_centre > 0)
 
     # --- confidence-interval conic -------------------------------------------
-    u = mu_c / mu_c.norm(dim=-1, keepdim=True)
-    uau = torch.einsum("ni,nij,nj->n", u, a, u)
-    big_c = -math.log(1.0 - conf_c) * torch.sqrt(uau) / math.sqrt(2.0 * math.pi)
-    quad = torch.einsum("ni,nij,nj->n", mu_c, a, mu_c)
-    kappa = 2.0 * (torch.log(big_c) - torch.log(dens)) + quad
-    kinv = torch.tensor([[1.0 / cam.fx, 0.0, -cam.cx / cam.fx],
-                         [0.0, 1.0 / cam.fy, -cam.cy / cam.fy],
-                         [0.0, 0.0, 1.0]], dtype=DT)
-    m = (kinv.T @ (a @ mu_c.unsqueeze(-1))).squeeze(-1)
+    norm_c = np.sqrt((mu_c ** 2).sum(-1))
+    u = mu_c / norm_c[:, None]
+    uau = np.einsum("ni,nij,nj->n", u, a, u)
+    big_c = -np.log1p(-LD(conf_c)) * np.sqrt(uau) / np.sqrt(2 * LD(np.pi))
+    quad = np.einsum("ni,nij,nj->n", mu_c, a, mu_c)
+    with np.errstate(divide="ignore"):
+        kappa = 2 * (np.log(big_c) - np.log(dens)) + quad
+    kinv = np.array([[1 / fx, 0, -cx / fx], [0, 1 / fy, -cy / fy], [0, 0, 1]], dtype=LD)
+    m = (kinv.T @ (a @ mu_c[:, :, None]))[:, :, 0]
     big_m = kinv.T @ a @ kinv
-    w = m.unsqueeze(-1) * m.unsqueeze(-2) - kappa[:, None, None] * big_m
+    w = m[:, :, None] * m[:, None, :] - kappa[:, None, None] * big_m
     w22 = w[:, :2, :2]
     w21 = w[:, :2, 2]
     w33 = w[:, 2, 2]
@@ -81,24 +122,39 @@ def screen_proxy(scene_t, cam, conf_c: float) -> Proxy:
     det22 = w22[:, 0, 0] * w22[:, 1, 1] - w22[:, 0, 1] * w22[:, 1, 0]
     tr22 = w22[:, 0, 0] + w22[:, 1, 1]
     ell_ok = (kappa > 0) & (kappa < quad) & (det22 > 0) & (tr22 < 0)
-    safe = torch.where(ell_ok[:, None, None], w22, -torch.eye(2, dtype=DT).expand_as(w22))
-    w22_inv = torch.linalg.inv(safe)
-    mean2d = -(w22_inv @ w21.unsqueeze(-1)).squeeze(-1)
-    s2 = torch.einsum("ni,nij,nj->n", mean2d, safe, mean2d) - w33
+    d_safe = np.where(ell_ok, det22, 1)
+    w22_inv = np.stack([np.stack([w22[:, 1, 1], -w22[:, 0, 1]], -1),
+                        np.stack([-w22[:, 1, 0], w22[:, 0, 0]], -1)], -2) / d_safe[:, None, None]
+    mean2d = -(w22_inv @ w21[:, :, None])[:, :, 0]
+    s2 = np.einsum("ni,nij,nj->n", mean2d, w22, mean2d) - w33
     ell_ok = ell_ok & (s2 < 0)
     sigma2d = s2[:, None, None] * w22_inv
-    sigma2d = torch.where(ell_ok[:, None, None], sigma2d, torch.eye(2, dtype=DT).expand_as(sigma2d))
-    lam, vec = torch.linalg.eigh(sigma2d)
-    half = torch.sqrt(lam.clamp_min(0.0))
-    axes = vec.transpose(-1, -2)  # rows are eigenvectors
+    sigma2d = np.where(ell_ok[:, None, None], sigma2d, np.eye(2, dtype=LD))
+    sxx, syy, sxy = sigma2d[:, 0, 0], sigma2d[:, 1, 1], sigma2d[:, 0, 1]
+    theta = np.arctan2(2 * sxy, sxx - syy) / 2
+    mid = (sxx + syy) / 2
+    rad = np.sqrt(((sxx - syy) / 2) ** 2 + sxy ** 2)
+    lam_major = mid + rad
+    lam_minor = (sxx * syy - sxy * sxy) / lam_major  # mid - rad without cancellation
+    half = np.sqrt(np.clip(np.stack([lam_major, lam_minor], -1), 0, None))
+    c_t, s_t = np.cos(theta), np.sin(theta)
+    axes = np.stack([np.stack([c_t, s_t], -1), np.stack([-s_t, c_t], -1)], -2)  # rows e_1, e_2
 
     valid = in_frustum & ell_ok
-    # decisions within float32 rounding of their threshold
-    rel = 1e-5
-    amb = ((side.abs() < rel * (mu_c.norm(dim=-1, keepdim=True) + radius[:, None])).any(-1)
-           | (near_centre.abs() < rel * (1 + mu_c.norm(dim=-1)))
-           | ((quad - kappa).abs() < 1e-3) | (kappa.abs() < 1e-3))
-    return Proxy(mean2d, axes, half, valid, amb, kappa, quad)
+    # decisions within double rounding of their threshold (both sides decide
+    # in double or better from the same float32 inputs)
+    scale_side = norm_c[:, None] + radius[:, None]
+    amb = ((np.abs(side) < CULL_REL * scale_side).any(-1)
+           | (np.abs(near_sphere) < CULL_REL * (1 + norm_c + radius))
+           | (np.abs(near_centre) < CULL_REL * (1 + norm_c))
+           | (np.abs(quad - kappa) < CULL_REL * (1 + quad + np.abs(kappa)))
+           | (np.abs(kappa) < CULL_REL * (1 + quad)))
+
+    def t64(x):
+        return torch.from_numpy(np.asarray(x, dtype=np.float64))
+
+    return Proxy(t64(mean2d), t64(axes), t64(half), torch.from_numpy(valid), torch.from_numpy(amb),
+                 t64(kappa), t64(quad), torch.from_numpy(in_frustum))
 
 
 def rect_margin(proxy: Proxy, gidx: torch.Tensor, px: torch.Tensor, py: torch.Tensor):
@@ -117,15 +173,15 @@ def _decision_tol(proxy: Proxy, gidx, px, py, margin_tol, orient_eps):
     if orient_eps <= 0:
         return margin_tol
     h = proxy.half[gidx]
-    ratio = (h[:, 0] / h[:, 1].clamp_min(1e-300)) ** 2
-    dtheta = (orient_eps / (1 - ratio).clamp_min(1e-12)).clamp_max(math.pi)
+    ratio = (h[:, 1] / h[:, 0].clamp_min(1e-300)) ** 2  # minor / major
+    dtheta = (orient_eps / (1 - ratio).clamp_min(1e-300)).clamp_max(math.pi)
     p = torch.stack([px.to(DT) + 0.5, py.to(DT) + 0.5], dim=-1) - proxy.mean2d[gidx]
     return margin_tol + dtheta * p.norm(dim=-1)
 
 
 def covering_pairs(proxy: Proxy, cam, pix_x: torch.Tensor, pix_y: torch.Tensor,
-                   margin_tol: float = 2e-3, full_coverage: bool = False,
-                   chunk: int = 1 << 22, orient_eps: float = 0.0):
+                   margin_tol: float = MARGIN_TOL, full_coverage: bool = False,
+                   chunk: int = 1 << 22, orient_eps: float = ORIENT_EPS):
     """Pairs (pixel slot, Gaussian) with the pixel centre inside the Gaussian's
     rectangle (the proxy the paper rasterises; App. D).
 
@@ -146,8 +202,8 @@ def covering_pairs(proxy: Proxy, cam, pix_x: torch.Tensor, pix_y: torch.Tensor,
     if orient_eps > 0:
         # room for the band of a rotated rectangle around its corners
         h = proxy.half[g_ok]
-        ratio = (h[:, 0] / h[:, 1].clamp_min(1e-300)) ** 2
-        dtheta = (orient_eps / (1 - ratio).clamp_min(1e-12)).clamp_max(math.pi)
+        ratio = (h[:, 1] / h[:, 0].clamp_min(1e-300)) ** 2  # minor / major
+        dtheta = (orient_eps / (1 - ratio).clamp_min(1e-300)).clamp_max(math.pi)
         ext = ext + (dtheta * (h[:, 0] + h[:, 1]))[:, None]
     lo = proxy.mean2d[g_ok] - ext
     hi = proxy.mean2d[g_ok] + ext
@@ -204,7 +260,7 @@ def covering_pairs(proxy: Proxy, cam, pix_x: torch.Tensor, pix_y: torch.Tensor,
     return slot[order], gid[order], ambiguous
 
 
-def _pairs_by_pixel(proxy, g_ok, lo, hi, pix_x, pix_y, margin_tol, n_g, orient_eps=0.0):
+def _pairs_by_pixel(proxy, g_ok, lo, hi, pix_x, pix_y, margin_tol, n_g, orient_eps):
     """Same pairs as ``covering_pairs`` for a short pixel list: each pixel is
     tested against every Gaussian whose dilated box contains its centre."""
     slots, gids, ambiguous = [], [], torch.zeros(pix_x.shape[0], dtype=torch.bool)

@@ -21,7 +21,7 @@ import torch
 from .bounds import bound_tau
 from .geometry import DT, camera_matrices, pixel_directions, quat_to_rot, ray_gaussian, sh_rgb
 from .moments import particle_moments, warp
-from .proxy import covering_pairs, screen_proxy
+from .proxy import MARGIN_TOL, ORIENT_EPS, covering_pairs, screen_proxy
 from .quadrature import consistency_penalty, particle_quadrature, rescale
 
 PARAMS = ("means", "scales", "quats", "densities", "colors")
@@ -76,7 +76,7 @@ def _standardised_basis(slot, mu, sigma, omega, t_near, n_pix):
 
 
 def render_pixels(scene_t, scene, cam, opts, px: torch.Tensor, py: torch.Tensor,
-                  proxy=None, margin_tol: float = 2e-3, orient_eps: float = 0.0,
+                  proxy=None, margin_tol: float = MARGIN_TOL, orient_eps: float = ORIENT_EPS,
                   tau_model=None) -> PixelResult:
     """Render the listed pixels (all pairs of each listed pixel are formed, so
     every listed pixel is complete). ``tau_model(mom_q, y)`` replaces the
@@ -138,7 +138,7 @@ def _pixel_chunks(cam, px, py, max_pixels):
 
 
 def render_image(scene, cam, opts, pixels: Optional[np.ndarray] = None,
-                 max_pixels: int = 4096, margin_tol: float = 2e-3, orient_eps: float = 0.0,
+                 max_pixels: int = 4096, margin_tol: float = MARGIN_TOL, orient_eps: float = ORIENT_EPS,
                  tau_model=None):
     """Forward render of ``pixels`` (flat indices y * W + x; default: the
     whole image). Returns a dict of numpy arrays: image [P,3], s_rgb [P,3],

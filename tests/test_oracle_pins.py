@@ -4,6 +4,7 @@ Each test ties one part of the oracle to something other than itself:
 closed forms, numeric integration, textbook cases, linear programming,
 library special functions, invariants, limits and finite differences.
 """
+import dataclasses
 import math
 import warnings
 
@@ -363,6 +364,114 @@ def test_proxy_covers_the_opacity_level_set():
         total += int(opaque.sum())
     assert total > 100
     assert bad <= 0.02 * total
+
+
+def _fibonacci_sphere(n):
+    k = np.arange(n) + 0.5
+    z = 1 - 2 * k / n
+    phi = math.pi * (1 + math.sqrt(5)) * k
+    rxy = np.sqrt(1 - z * z)
+    return np.stack([rxy * np.cos(phi), rxy * np.sin(phi), z], -1)
+
+
+def _off_centre_rotated_camera():
+    cam = W.camera_look_at((2.0, -1.0, -6.0), (0.3, 0.2, 0.0), (0.1, 1.0, 0.2), 320, 200)
+    return dataclasses.replace(cam, cx=0.3 * cam.width, cy=0.62 * cam.height)
+
+
+def test_bounding_sphere_cull_against_sampled_sphere():
+    """Sec. 3.3 culls with the bounding sphere (mean, max s): keep a Gaussian
+    iff some point of that sphere projects into the image in front of t_n
+    (tested away from the frustum's edges, where the plane test is exact),
+    and, reading R14, the centre itself lies beyond t_n. Spheres straddle,
+    touch and miss each of the four side planes and the near plane of a
+    rotated camera with an off-centre principal point."""
+    cam = _off_centre_rotated_camera()
+    r_wc = cam.world_to_cam[:, :3].astype(np.float64)
+    t_wc = cam.world_to_cam[:, 3].astype(np.float64)
+    fx, fy, cx, cy, wd, ht, tn = cam.fx, cam.fy, cam.cx, cam.cy, cam.width, cam.height, cam.t_near
+    z0, rad = 4.0, 0.1
+    # a point in the middle of each side face (camera frame) and the face's
+    # inward unit normal, built from the image borders u = 0, u = W, v = 0, v = H
+    mid_u, mid_v = (wd / 2 - cx) / fx, (ht / 2 - cy) / fy
+    faces = [(np.array([-cx / fx, mid_v, 1.0]) * z0, np.array([fx, 0.0, cx])),
+             (np.array([(wd - cx) / fx, mid_v, 1.0]) * z0, np.array([-fx, 0.0, wd - cx])),
+             (np.array([mid_u, -cy / fy, 1.0]) * z0, np.array([0.0, fy, cy])),
+             (np.array([mid_u, (ht - cy) / fy, 1.0]) * z0, np.array([0.0, -fy, ht - cy]))]
+    centres = []
+    for p0, n in faces:
+        n = n / np.linalg.norm(n)
+        for d in (-1.5, -1.03, -0.97, -0.5, 0.5):
+            centres.append(p0 + d * rad * n)
+    for d in (-1.5, -1.03, -0.97, -0.5, 0.5, 1.5):
+        centres.append(np.array([mid_u * tn, mid_v * tn, tn]) + np.array([0.0, 0.0, d * rad]))
+    centres = np.array(centres)
+    sphere = _fibonacci_sphere(40000)
+    expected = []
+    for c in centres:
+        pts = c + rad * sphere
+        z = pts[:, 2]
+        with np.errstate(divide="ignore", invalid="ignore"):
+            u = fx * pts[:, 0] / z + cx
+            v = fy * pts[:, 1] / z + cy
+        seen = (z > tn) & (u >= 0) & (u <= wd) & (v >= 0) & (v <= ht)
+        expected.append(bool(seen.any()) and c[2] > tn)
+    means = (centres - t_wc) @ r_wc  # world = R^T (camera - t)
+    n = len(centres)
+    rng = np.random.default_rng(3)
+    scene = W.Scene(means.astype(np.float32),
+                    np.tile(np.array([[rad, rad / 2, rad / 3]], np.float32), (n, 1)),
+                    rng.normal(size=(n, 4)).astype(np.float32), np.ones(n, np.float32),
+                    np.ones((n, 3), np.float32), -1)
+    got = screen_proxy(scene_tensors(scene), cam, 0.01).in_frustum.numpy()
+    assert sum(expected) not in (0, n)
+    assert got.tolist() == expected
+
+
+def test_pixel_rays_of_a_rotated_camera_pass_through_projected_points():
+    """Sec. 3.3 maps pixel p to the ray direction normalize(K^-1 p) in camera
+    space: the ray through the projection of a world point under K [R | t]
+    (here at a continuous pixel position) passes through that point."""
+    cam = _off_centre_rotated_camera()
+    # an exactly orthonormal (float64) rotation: the float32 one is orthonormal
+    # only to 3e-8, which would hide nothing but blur the bound below
+    u_, _, vt_ = np.linalg.svd(cam.world_to_cam[:, :3].astype(np.float64))
+    r_wc = u_ @ vt_
+    t_wc = cam.world_to_cam[:, 3].astype(np.float64)
+    cam.world_to_cam = np.concatenate([r_wc, t_wc[:, None]], 1)
+    assert np.abs(r_wc - r_wc.T).max() > 0.1  # R and R^T differ
+    rng = np.random.default_rng(8)
+    pts = rng.uniform(-1.5, 1.5, size=(50, 3))
+    xc = pts @ r_wc.T + t_wc
+    u = cam.fx * xc[:, 0] / xc[:, 2] + cam.cx
+    v = cam.fy * xc[:, 1] / xc[:, 2] + cam.cy
+    d = oracle.pixel_directions(cam, _t(u - 0.5), _t(v - 0.5)).numpy()
+    o = cam.origin
+    to_pt = pts - o
+    cross = np.cross(to_pt, d)
+    assert np.abs(np.linalg.norm(d, axis=1) - 1).max() < 1e-14
+    assert (np.einsum("ni,ni->n", to_pt, d) > 0).all()
+    assert (np.linalg.norm(cross, axis=1) / np.linalg.norm(to_pt, axis=1)).max() < 1e-12
+
+
+def test_proxy_axes_follow_the_ellipse_and_a_circle_takes_the_x_axis():
+    """The rectangle's first axis is the projected ellipse's major axis: a
+    prolate Gaussian on the optical axis turned by phi about it projects to an
+    ellipse whose major axis makes the angle phi with the image x axis. A
+    sphere on the axis projects to a circle, which takes the x axis (the
+    orientation reading for a circle)."""
+    cam = W.camera_on_axis(0.0, 200, 160)
+    for phi in (0.3, 1.2, 2.0, -0.7):
+        q = [math.cos(phi / 2), 0.0, 0.0, math.sin(phi / 2)]
+        scene = _single_gaussian_scene([0, 0, 5.0], [0.3, 0.06, 0.05], q, 4.0)
+        p = screen_proxy(scene_tensors(scene), cam, 0.01)
+        e1 = p.axes[0, 0].numpy()
+        assert abs(abs(e1 @ [math.cos(phi), math.sin(phi)]) - 1) < 1e-12
+        assert p.half[0, 0] > 2 * p.half[0, 1]
+        assert abs(p.axes[0, 1].numpy() @ e1) < 1e-15
+    scene = _single_gaussian_scene([0, 0, 5.0], [0.2, 0.2, 0.2], [1, 0, 0, 0], 4.0)
+    p = screen_proxy(scene_tensors(scene), cam, 0.01)
+    assert p.axes[0].numpy().tolist() == [[1.0, 0.0], [-0.0, 1.0]]
 
 
 # ---------------------------------------------------------------------------

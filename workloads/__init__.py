@@ -61,6 +61,15 @@ class Camera:
     t_near: float = 0.2
     background: tuple = (0.0, 0.0, 0.0)
 
+    def __post_init__(self):
+        # the library takes float32 camera parameters: round them here so
+        # every consumer sees exactly the values the GPU path receives
+        f32 = lambda x: float(np.float32(x))
+        self.world_to_cam = np.asarray(self.world_to_cam, np.float32)
+        self.fx, self.fy, self.cx, self.cy = f32(self.fx), f32(self.fy), f32(self.cx), f32(self.cy)
+        self.t_near = f32(self.t_near)
+        self.background = tuple(f32(b) for b in self.background)
+
     @property
     def origin(self) -> np.ndarray:
         r = self.world_to_cam[:, :3].astype(np.float64)
