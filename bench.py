@@ -354,6 +354,18 @@ def surrogate_bench(args):
         ms_sur_fb = timed(sur_fb)
         a = plain[0].cpu().numpy().reshape(-1, 3).astype(np.float64)
         b = sur[0].cpu().numpy().reshape(-1, 3).astype(np.float64)
+        bad = ~(np.isfinite(a).all(-1) & np.isfinite(b).all(-1))
+        if bad.any():
+            # a non-finite image is a failed run: report what the pixels held
+            idx = np.nonzero(bad)[0][:16]
+            _, sv_p, _ = M.render_forward(g, [cam], opts, ws=ws)
+            _, sv_s, _ = M.render_forward_surrogate(g, [cam], opts, packed, ws=ws)
+            diag = {"camera": i, "n_bad": int(bad.sum()), "pixels": idx.tolist(),
+                    "plain": a[idx].tolist(), "surrogate": b[idx].tolist(),
+                    "saved_plain": sv_p[0].reshape(-1, 8)[idx].cpu().tolist(),
+                    "saved_surrogate": sv_s[0].reshape(-1, 8)[idx].cpu().tolist()}
+            print(json.dumps({"error": "non-finite held-out image", "diagnostics": diag}), flush=True)
+            raise SystemExit(3)
         mse = float(((a - b) ** 2).mean())
         rec = {"camera": i, "ms_plain": ms_plain, "ms_surrogate": ms_sur,
                "ms_plain_fwd_bwd": ms_plain_fb, "ms_surrogate_fwd_bwd": ms_sur_fb,
@@ -436,7 +448,8 @@ def main():
             "config": {"workload": "500k Gaussians, 64 clusters, SH3, 1920x1080, K=6, N=3, surrogate "
                                    "forward, 8 held-out cameras", "mode": "surrogate"},
             "plain_ms_per_frame": ms_p, "speedup_vs_plain": ms_p / ms_s,
-            "min_psnr_surrogate_vs_plain": min(c["psnr_surrogate_vs_plain"] or 1e9 for c in cams),
+            "min_psnr_surrogate_vs_plain": min(c["psnr_surrogate_vs_plain"] if c["psnr_surrogate_vs_plain"]
+                                               is not None else math.inf for c in cams),
             "surrogate": sres,
         }
         if all("delta_psnr_db" in c for c in cams):

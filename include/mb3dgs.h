@@ -116,12 +116,15 @@ int64_t mb_pair_capacity(size_t pws_bytes, int32_t n_cams, int32_t width, int32_
 #define MB_ENTRIES_ON_DEVICE (-1)
 
 /* Screen proxies only (App. D), for inspection: per Gaussian writes
- * proxy[n,8] = (centre_x, centre_y, e1_x, e1_y, half_1, half_2, valid, 0)
- * where the oriented rectangle is centre + a e1 + b e2, |a| <= half_1,
- * |b| <= half_2, e2 = (-e1_y, e1_x); valid = 0 for culled Gaussians.
- * proxy: device, caller-allocated. */
+ * proxy[n,8] (double) = (centre_x, centre_y, e1_x, e1_y, half_1, half_2,
+ * valid, 0) where the oriented rectangle is centre + a e1 + b e2,
+ * |a| <= half_1, |b| <= half_2, e2 = (-e1_y, e1_x); e1 is the major axis of
+ * the proxy ellipse at the angle atan2(2 s_xy, s_xx - s_yy) / 2 of its
+ * covariance (an exact circle takes e1 = (1, 0)); valid = 0 for culled
+ * Gaussians. This is the rectangle the pixel coverage test uses, computed in
+ * double from the float32 inputs. proxy: device, caller-allocated. */
 int mb_project(const mb_gaussians *g, const mb_camera *cam, const mb_options *opts,
-               float *proxy, void *stream);
+               double *proxy, void *stream);
 
 /* Stage 1 of a render (Sec. 3.3 culling and proxy): per camera and Gaussian,
  * the screen proxy, the ray-space coefficients and the number of 16x16 tiles

@@ -12,6 +12,8 @@ the moment equations, and
 """
 from __future__ import annotations
 
+import math
+
 import numpy as np
 import torch
 
@@ -77,6 +79,88 @@ def canonical_representation(b: torch.Tensor, eta: torch.Tensor, n: int):
     return x, w
 
 
+# Degenerate measures (a reading: the paper assumes a positive definite
+# Hankel matrix). A sum of Gaussians has positive definite Hankel matrices in
+# exact arithmetic, but a nearly atomic one (ray Gaussians far thinner than
+# their separation) is singular to working precision. The measure counts as
+# degenerate when a Cholesky pivot of the Hankel matrix of its standardised
+# moments E[((y - mean) / sd)^k] (independent of the affine moment variable)
+# is at most PIVOT_REL times its diagonal entry (1e-5: well above the float32
+# rounding a GPU's per-pair moments carry into these pivots, about 1e-7, so a
+# float32 implementation can decide it reliably); it is then replaced by the
+# mixture (1 - eps) mu + eps N(mean, sd^2) with the normal distribution of its
+# own mean and variance, for the first eps in MIX_EPS whose mixture passes the
+# same test. The mixture is a valid measure, transforms with the moment
+# variable, and is differentiable in the moments.
+PIVOT_REL = 1e-5
+MIX_EPS = (1e-3, 1e-2, 1e-1, 1.0)
+
+
+def normal_moments(mean: torch.Tensor, var: torch.Tensor, k_max: int):
+    """[..., k_max + 1] moments E[(mean + sd Z)^k] of N(mean, var):
+    n_k = mean n_{k-1} + (k - 1) var n_{k-2}."""
+    out = [torch.ones_like(mean), mean]
+    for k in range(2, k_max + 1):
+        out.append(mean * out[k - 1] + (k - 1) * var * out[k - 2])
+    return torch.stack(out[:k_max + 1], dim=-1)
+
+
+def standardised_moments(b: torch.Tensor) -> torch.Tensor:
+    """E[((y - mean) / sd)^k] from the moments b_k = E[y^k] (b_0 = 1), by the
+    binomial expansion of (y - mean)^k."""
+    k_max = b.shape[-1] - 1
+    mean = b[..., 1]
+    sd = torch.sqrt(b[..., 2] - mean * mean)
+    out = []
+    for k in range(k_max + 1):
+        c = sum(math.comb(k, j) * b[..., j] * (-mean) ** (k - j) for j in range(k + 1))
+        out.append(c / sd ** k)
+    return torch.stack(out, dim=-1)
+
+
+def _pivots_pass(c: np.ndarray, n: int) -> np.ndarray:
+    """Whether every Cholesky pivot of the Hankel matrix of c (rows) exceeds
+    PIVOT_REL times its diagonal entry."""
+    h = c[..., np.arange(n + 1)[:, None] + np.arange(n + 1)[None, :]]
+    ok = np.ones(c.shape[:-1], bool)
+    lc = np.zeros(h.shape)
+    for j in range(n + 1):
+        piv = h[..., j, j] - (lc[..., j, :j] ** 2).sum(-1)
+        ok &= piv > PIVOT_REL * h[..., j, j]
+        d = np.sqrt(np.maximum(piv, 1e-300))
+        lc[..., j, j] = d
+        for i in range(j + 1, n + 1):
+            lc[..., i, j] = (h[..., i, j] - (lc[..., i, :j] * lc[..., j, :j]).sum(-1)) / d
+    return ok
+
+
+def degenerate_mixture(b: torch.Tensor, n: int):
+    """The moments the bounds use (b itself, or the mixture above) and the
+    mixture weight per row (0: none; -1: no positive variance or non-finite
+    moments, where no bound is defined)."""
+    with torch.no_grad():
+        bd = b.detach()
+        var = bd[..., 2] - bd[..., 1] ** 2
+        fin = torch.isfinite(bd).all(-1) & (var > 0)
+        eps = torch.full(bd.shape[:-1], -1.0, dtype=DT)
+        if bool(fin.any()):
+            c = standardised_moments(torch.where(fin[..., None], bd, _unit_measure_moments(bd.shape, n)))
+            cn = c.numpy()
+            sn = _unit_measure_moments(bd.shape, n).numpy()
+            level = np.where(_pivots_pass(cn, n), 0.0, -1.0)
+            for e in MIX_EPS:
+                todo = level < 0
+                if not todo.any():
+                    break
+                passed = _pivots_pass((1 - e) * cn + e * sn, n)
+                level = np.where(todo & passed, e, level)
+            eps = torch.where(fin, torch.as_tensor(level, dtype=DT), eps)
+    mean = b[..., 1]
+    nm = normal_moments(mean, b[..., 2] - mean * mean, b.shape[-1] - 1)
+    e = eps.clamp_min(0.0)[..., None]
+    return torch.where(eps[..., None] > 0, (1 - e) * b + e * nm, b), eps
+
+
 def bound_tau(m: torch.Tensor, eta: torch.Tensor, n: int, beta: float):
     """Optical depth at ``eta`` from the moments m_0..m_2n of the ray density:
     tau = (1 - beta) L + beta U (Sec. 3.2; the printed "T(tau) = ..." is read
@@ -88,6 +172,7 @@ def bound_tau(m: torch.Tensor, eta: torch.Tensor, n: int, beta: float):
     pos = m0 > 0
     b = torch.where(pos[..., None], m / torch.where(pos, m0, torch.ones_like(m0))[..., None],
                     _unit_measure_moments(m.shape, n))
+    b, _ = degenerate_mixture(b, n)
     x, w = canonical_representation(b, eta, n)
     below = (x[..., 1:] < eta[..., None]).to(DT)
     lower = (w[..., 1:] * below).sum(-1)

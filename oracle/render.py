@@ -18,7 +18,7 @@ from typing import Dict, Optional
 import numpy as np
 import torch
 
-from .bounds import bound_tau
+from .bounds import bound_tau, degenerate_mixture
 from .geometry import DT, camera_matrices, pixel_directions, quat_to_rot, ray_gaussian, sh_rgb
 from .moments import particle_moments, warp
 from .proxy import MARGIN_TOL, ORIENT_EPS, covering_pairs, screen_proxy
@@ -53,6 +53,7 @@ class PixelResult:
     pair_y: torch.Tensor     # [pairs, N+1] moment variable at the quadrature edges
     pair_tau: torch.Tensor   # [pairs, N+1] reconstructed optical depth there
     penalty: torch.Tensor    # [P] consistency penalty sum_i P_i (App. E)
+    fallback: torch.Tensor   # [P] bool: the pixel's measure is degenerate (bounds.degenerate_mixture)
 
 
 def _standardised_basis(slot, mu, sigma, omega, t_near, n_pix):
@@ -108,7 +109,14 @@ def render_pixels(scene_t, scene, cam, opts, px: torch.Tensor, py: torch.Tensor,
 
     def tau_at(y):
         if tau_model is not None:
-            return tau_model(mom_q, y.reshape(-1)).reshape(y.shape)
+            # the moment bounds grow with depth; a model standing in for them
+            # is made non-decreasing along each Gaussian's edges (running
+            # maximum: a later edge takes over only when strictly larger)
+            tau = tau_model(mom_q, y.reshape(-1)).reshape(y.shape)
+            run = [tau[..., 0]]
+            for e in range(1, tau.shape[-1]):
+                run.append(torch.where(tau[..., e] > run[-1], tau[..., e], run[-1]))
+            return torch.stack(run, dim=-1)
         tau, _, _ = bound_tau(mom_q, y.reshape(-1), n_half, opts.beta)
         return tau.reshape(y.shape)
 
@@ -128,8 +136,23 @@ def render_pixels(scene_t, scene, cam, opts, px: torch.Tensor, py: torch.Tensor,
     s_rgb = torch.zeros(n_pix, 3, dtype=DT).index_add(0, slot, q[:, None] * rgb_all[gid])
     o = torch.zeros(n_pix, dtype=DT).index_add(0, slot, q)
     image = rescale(mom[:, 0], s_rgb, o, opts.eps, cam.background)
+    with torch.no_grad():
+        m0 = mom[:, 0].detach()
+        live = m0 > 1e-20  # (reading: a pixel below this depth renders background only)
+        b = mom.detach() / torch.where(live, m0, torch.ones_like(m0))[:, None]
+        b = torch.where(live[:, None], b, _unit_moments(k_mom))
+        _, eps = degenerate_mixture(b, n_half)
+        fallback = live & (eps != 0)
     return PixelResult(image, s_rgb, o, mom, centre, scale, amb, int(slot.shape[0]),
-                       slot, gid, q, y_e, tau_e, penalty)
+                       slot, gid, q, y_e, tau_e, penalty, fallback)
+
+
+def _unit_moments(k_mom):
+    """Standard normal moments (a stand-in for pixels without density)."""
+    mom = [1.0, 0.0]
+    for j in range(2, k_mom + 1):
+        mom.append((j - 1) * mom[j - 2])
+    return torch.tensor(mom, dtype=DT)
 
 
 def _pixel_chunks(cam, px, py, max_pixels):
@@ -152,7 +175,7 @@ def render_image(scene, cam, opts, pixels: Optional[np.ndarray] = None,
     pix = torch.as_tensor(np.asarray(pixels), dtype=torch.long)
     px_all, py_all = pix % cam.width, pix // cam.width
     outs = {k: [] for k in ("image", "s_rgb", "opacity", "moments", "centre",
-                            "scale", "ambiguous", "penalty")}
+                            "scale", "ambiguous", "penalty", "fallback")}
     n_pairs = 0
     with torch.no_grad():
         for _, px, py in _pixel_chunks(cam, px_all, py_all, max_pixels):
@@ -166,6 +189,7 @@ def render_image(scene, cam, opts, pixels: Optional[np.ndarray] = None,
             outs["scale"].append(r.scale)
             outs["ambiguous"].append(r.ambiguous)
             outs["penalty"].append(r.penalty)
+            outs["fallback"].append(r.fallback)
             n_pairs += r.n_pairs
     res = {k: torch.cat(v).numpy() for k, v in outs.items()}
     res["n_pairs"] = n_pairs

@@ -95,6 +95,7 @@ struct Carver {
 
 struct GaussWs {
   float4* rec;
+  double2* rectd;
   int4* tbox;
   int* counts;
   int* offsets;
@@ -108,6 +109,7 @@ GaussWs carve_gauss(void* p, int64_t n, int n_cams) {
   int64_t m = n * n_cams;
   GaussWs w;
   w.rec = c.take<float4>((size_t)m * kRecF4);
+  w.rectd = c.take<double2>((size_t)m * 3);
   w.tbox = c.take<int4>((size_t)m);
   w.counts = c.take<int>((size_t)m);
   w.offsets = c.take<int>((size_t)m);
@@ -216,7 +218,7 @@ CamSet make_cams(const mb_camera* cams, int n_cams) {
   return s;
 }
 
-float conf_term(float c) { return (float)std::log(-std::log1p(-(double)c) / std::sqrt(2.0 * M_PI)); }
+double conf_term(float c) { return std::log(-std::log1p(-(double)c) / std::sqrt(2.0 * M_PI)); }
 
 // Standard-normal quantile by Newton's method on the normal CDF
 // Phi(x) = erfc(-x / sqrt2) / 2 (App. B sample spacing).
@@ -324,7 +326,7 @@ int forward_setup(const mb_gaussians* g, const mb_camera* cams, int32_t n_cams, 
   f.cs = make_cams(cams, n_cams);
   RenderArgs& ra = f.ra;
   memset(&ra, 0, sizeof(ra));
-  ra.rec = f.w.rec; ra.sorted_rec = f.p.sorted_rec; ra.ranges = f.p.ranges; ra.order = f.p.order;
+  ra.rec = f.w.rec; ra.rectd = f.w.rectd; ra.sorted_rec = f.p.sorted_rec; ra.ranges = f.p.ranges; ra.order = f.p.order;
   ra.masks = f.p.masks;
   ra.pix_mom = f.p.pix_mom;
   ra.n_pix = (long long)n_cams * cams[0].width * cams[0].height;
@@ -443,7 +445,7 @@ int mb_entry_count(int32_t n_gaussians, int32_t n_cams, const void* gws, size_t 
   return MB_OK;
 }
 
-int mb_project(const mb_gaussians* g, const mb_camera* cam, const mb_options* o, float* proxy, void* stream) {
+int mb_project(const mb_gaussians* g, const mb_camera* cam, const mb_options* o, double* proxy, void* stream) {
   int rc = check_common(g, cam, 1, o);
   if (rc) return rc;
   if (g->n > 0 && !proxy) return fail(MB_ERR_ARG, "null proxy output");
@@ -476,7 +478,7 @@ int mb_prepare(const mb_gaussians* g, const mb_camera* cams, int32_t n_cams, con
   a.tiles_x = tiles_of(cams[0].width); a.tiles_y = tiles_of(cams[0].height);
   a.conf_term = conf_term(o->conf_c);
   a.full_coverage = o->full_coverage;
-  a.rec = w.rec; a.tbox = w.tbox; a.counts = w.counts;
+  a.rec = w.rec; a.rectd = w.rectd; a.tbox = w.tbox; a.counts = w.counts;
   CamSet cs = make_cams(cams, n_cams);
   hipError_t e;
   {

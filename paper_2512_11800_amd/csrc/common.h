@@ -148,11 +148,13 @@ __device__ __forceinline__ Dual operator/(Dual a, Dual b) {
 __device__ __forceinline__ Dual& operator+=(Dual& a, Dual b) { a = a + b; return a; }
 __device__ __forceinline__ Dual dsqrt(Dual a) { float s = sqrtf(a.v); return Dual(s, a.d * 0.5f / s); }
 __device__ __forceinline__ float dsqrt(float a) { return sqrtf(a); }
+__device__ __forceinline__ double dsqrt(double a) { return sqrt(a); }
 __device__ __forceinline__ float val(float a) { return a; }
 __device__ __forceinline__ float val(Dual a) { return a.v; }
 
 // ---------------------------------------------------------------------------
-// Per (camera, Gaussian) ray-space coefficients, templated on float / Dual.
+// Per (camera, Gaussian) ray-space coefficients, templated on the arithmetic
+// type (the preprocess evaluates them in double).
 // ---------------------------------------------------------------------------
 template <class T>
 struct Coefs {
@@ -203,7 +205,7 @@ __device__ __forceinline__ void compute_coefs(const T mean[3], const T scale[3],
   o.p0y = T(c.cy) + T(c.fy) * o.muc[1] * iz;
   // G = B J: columns B[:,0]/fx and B[:,1]/fy
   T gx[3], gy[3], g0[3];
-  T ifx = T(1.f / c.fx), ify = T(1.f / c.fy);
+  T ifx = T(1.f) / T(c.fx), ify = T(1.f) / T(c.fy);
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     gx[k] = b[k * 3 + 0] * ifx;

@@ -11,12 +11,13 @@ namespace mb {
 struct PrepArgs {
   const float *means, *scales, *quats, *dens, *colors;
   int n, sh_degree, tiles_x, tiles_y;
-  float conf_term;  // log(-log(1 - c) / sqrt(2 pi))
+  double conf_term; // log(-log(1 - c) / sqrt(2 pi))
   int full_coverage;
   float4* rec;      // [C*n*6] render records
+  double2* rectd;   // [C*n*3] exact rectangles: centre, major axis, halves
   int4* tbox;       // [C*n] tile box (tx0, ty0, tx1, ty1)
   int* counts;      // [C*n] overlapped tiles
-  float* proxy_out; // optional [n*8] (camera 0)
+  double* proxy_out; // optional [n*8] (camera 0)
 };
 
 hipError_t launch_preprocess(const PrepArgs& a, const CamSet& cams, hipStream_t s);
@@ -104,6 +105,7 @@ hipError_t launch_tile_order(const int2* ranges, int n_keys, int split, int* blo
 
 struct RenderArgs {
   const float4* rec;
+  const double2* rectd;  // [C*n*3] exact rectangles (the coverage test near an edge)
   const int* sorted_rec;
   const int2* ranges;
   const int* order;  // [render_blocks(n_keys)] block list (see launch_tile_order)

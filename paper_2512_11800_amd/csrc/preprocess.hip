@@ -6,56 +6,55 @@
 
 namespace mb {
 
-// Oriented rectangle of the level set omega(d) = C (App. D).
+// Oriented rectangle of the level set omega(d) = C (App. D), in double.
 // With delta = 2 (log w - log C), the pixel offset satisfies omega >= C iff
 // X(delta) <= delta D(delta) (the paper's conic p^T W p >= 0 with
 // W = m m^T - kappa M, kappa = mean^T A mean - delta, rewritten around the
 // projected mean): Q = X2 - delta D2, centre Q^-1 (delta D1), and
-// Sigma_2d = (delta D0 + delta D1 . centre) Q^-1, whose eigenpairs span the box.
+// Sigma_2d = (delta D0 + delta D1 . centre) Q^-1. The first axis is the
+// ellipse's major axis at theta = atan2(2 s_xy, s_xx - s_yy) / 2 of Sigma_2d,
+// which is proportional to [[q_yy, -q_xy], [-q_xy, q_xx]]; a circle takes
+// theta = 0. Every decision of the render (cull, rectangle, pixel coverage)
+// is taken in double, so it is fixed by the float32 inputs alone.
+struct RectD {
+  double rcx, rcy, e1x, e1y, h1, h2;  // centre offset from the projected mean, major axis, halves
+};
+
+__device__ __forceinline__ bool proxy_rect(const Coefs<double>& cf, double w, double conf_term, RectD& r) {
+  double quad = cf.mug[0] * cf.mug[0] + cf.mug[1] * cf.mug[1] + cf.mug[2] * cf.mug[2];
+  double mc2 = cf.muc[0] * cf.muc[0] + cf.muc[1] * cf.muc[1] + cf.muc[2] * cf.muc[2];
+  if (!(w > 0.0)) return false;
+  double log_c = conf_term + 0.5 * log(quad / mc2);
+  double delta = 2.0 * (log(w) - log_c);
+  // real ellipse: peak opacity above c (delta > 0) and the camera outside the
+  // confidence region (kappa = quad - delta > 0)
+  if (!(delta > 0.0) || !(delta < quad)) return false;
+  double qxx = cf.Xxx - delta * cf.D2xx;
+  double qxy = cf.Xxy - delta * cf.D2xy;
+  double qyy = cf.Xyy - delta * cf.D2yy;
+  double det = qxx * qyy - qxy * qxy;
+  if (!(qxx > 0.0) || !(qyy > 0.0) || !(det > 0.0)) return false;
+  double bx = delta * cf.D1x, by = delta * cf.D1y;
+  double cx = (qyy * bx - qxy * by) / det;
+  double cy = (qxx * by - qxy * bx) / det;
+  double r2 = delta * cf.D0 + bx * cx + by * cy;
+  if (!(r2 > 0.0)) return false;
+  double mid = 0.5 * (qxx + qyy);
+  double rad = sqrt(0.25 * (qxx - qyy) * (qxx - qyy) + qxy * qxy);
+  double ql = mid + rad;  // larger eigenvalue of Q: the minor axis of the ellipse
+  double qs = det / ql;
+  double th = 0.5 * atan2(-qxy, 0.5 * (qyy - qxx));
+  r.rcx = cx; r.rcy = cy;
+  r.e1x = cos(th); r.e1y = sin(th);
+  r.h1 = sqrt(r2 / qs);
+  r.h2 = sqrt(r2 / ql);
+  return isfinite(r.h1) && isfinite(r.h2) && isfinite(cx) && isfinite(cy);
+}
+
+// float copy of the rectangle for the binning and the render record
 struct Rect {
   float rcx, rcy, e1x, e1y, h1, h2;
 };
-
-__device__ __forceinline__ bool proxy_rect(const Coefs<float>& cf, float w, float conf_term, Rect& r) {
-  float quad = cf.mug[0] * cf.mug[0] + cf.mug[1] * cf.mug[1] + cf.mug[2] * cf.mug[2];
-  float mc2 = cf.muc[0] * cf.muc[0] + cf.muc[1] * cf.muc[1] + cf.muc[2] * cf.muc[2];
-  if (!(w > 0.f)) return false;
-  float log_c = conf_term + 0.5f * logf(quad / mc2);
-  float delta = 2.f * (logf(w) - log_c);
-  // real ellipse: peak opacity above c (delta > 0) and the camera outside the
-  // confidence region (kappa = quad - delta > 0)
-  if (!(delta > 0.f) || !(delta < quad)) return false;
-  float qxx = cf.Xxx - delta * cf.D2xx;
-  float qxy = cf.Xxy - delta * cf.D2xy;
-  float qyy = cf.Xyy - delta * cf.D2yy;
-  float det = qxx * qyy - qxy * qxy;
-  if (!(qxx > 0.f) || !(qyy > 0.f) || !(det > 0.f)) return false;
-  float bx = delta * cf.D1x, by = delta * cf.D1y;
-  float cx = (qyy * bx - qxy * by) / det;
-  float cy = (qxx * by - qxy * bx) / det;
-  float r2 = delta * cf.D0 + bx * cx + by * cy;
-  if (!(r2 > 0.f)) return false;
-  float mid = 0.5f * (qxx + qyy);
-  float rad = sqrtf(0.25f * (qxx - qyy) * (qxx - qyy) + qxy * qxy);
-  float ql = mid + rad;
-  float qs = det / ql;
-  // eigenvector of the larger eigenvalue of Q (shorter axis of the ellipse)
-  float ax = qxy, ay = ql - qxx;
-  float bx2 = ql - qyy, by2 = qxy;
-  float na = ax * ax + ay * ay, nb = bx2 * bx2 + by2 * by2;
-  float ex, ey;
-  if (na >= nb) { ex = ax; ey = ay; } else { ex = bx2; ey = by2; na = nb; }
-  if (na > 0.f) {
-    float inv = rsqrtf(na);
-    ex *= inv; ey *= inv;
-  } else {
-    ex = 1.f; ey = 0.f;
-  }
-  r.rcx = cx; r.rcy = cy; r.e1x = ex; r.e1y = ey;
-  r.h1 = sqrtf(r2 / ql);
-  r.h2 = sqrtf(r2 / qs);
-  return isfinite(r.h1) && isfinite(r.h2) && isfinite(cx) && isfinite(cy);
-}
 
 // Does the rectangle (centre m, axes e1/e2, halves h) reach a pixel centre
 // of tile (tx, ty)? Separating-axis test of the rectangle against the box of
@@ -108,44 +107,47 @@ __global__ __launch_bounds__(256) void k_preprocess(PrepArgs a, CamSet cams) {
   if (g >= a.n) return;
   const CamConst& c = cams.c[ci];
   size_t idx = (size_t)ci * a.n + g;
-  float mean[3] = {a.means[3 * g], a.means[3 * g + 1], a.means[3 * g + 2]};
-  float scale[3] = {a.scales[3 * g], a.scales[3 * g + 1], a.scales[3 * g + 2]};
-  float quat[4] = {a.quats[4 * g], a.quats[4 * g + 1], a.quats[4 * g + 2], a.quats[4 * g + 3]};
-  float w = a.dens[g];
+  const double mean[3] = {a.means[3 * g], a.means[3 * g + 1], a.means[3 * g + 2]};
+  const double scale[3] = {a.scales[3 * g], a.scales[3 * g + 1], a.scales[3 * g + 2]};
+  const double quat[4] = {a.quats[4 * g], a.quats[4 * g + 1], a.quats[4 * g + 2], a.quats[4 * g + 3]};
+  const float w = a.dens[g];
 
-  Coefs<float> cf;
+  Coefs<double> cf;
   compute_coefs(mean, scale, quat, c, cf);
 
   // --- culling: bounding sphere r = max diag S against the frustum --------
-  float rad = fmaxf(scale[0], fmaxf(scale[1], scale[2]));
-  float z = cf.muc[2];
-  bool keep = (z > c.tn) && (z + rad >= c.tn);
+  const double rad = fmax(scale[0], fmax(scale[1], scale[2]));
+  const double z = cf.muc[2], tn = c.tn;
+  bool keep = (z > tn) && (z + rad >= tn);
   {
-    float nl[3] = {c.fx, 0.f, c.cx};
-    float nr[3] = {-c.fx, 0.f, (float)c.width - c.cx};
-    float nt[3] = {0.f, c.fy, c.cy};
-    float nb[3] = {0.f, -c.fy, (float)c.height - c.cy};
-    const float* ns[4] = {nl, nr, nt, nb};
+    const double fx = c.fx, fy = c.fy, cx = c.cx, cy = c.cy;
+    const double nv[4][3] = {{fx, 0.0, cx}, {-fx, 0.0, (double)c.width - cx},
+                             {0.0, fy, cy}, {0.0, -fy, (double)c.height - cy}};
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      const float* nv = ns[k];
-      float inv = rsqrtf(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
-      float d = (nv[0] * cf.muc[0] + nv[1] * cf.muc[1] + nv[2] * cf.muc[2]) * inv + rad;
-      keep = keep && (d >= 0.f);
+      const double len = sqrt(nv[k][0] * nv[k][0] + nv[k][1] * nv[k][1] + nv[k][2] * nv[k][2]);
+      const double d = (nv[k][0] * cf.muc[0] + nv[k][1] * cf.muc[1] + nv[k][2] * cf.muc[2]) / len + rad;
+      keep = keep && (d >= 0.0);
     }
   }
-  Rect r;
+  // the render record keeps the projected mean in float; the rectangle's
+  // centre is stored as an offset from that float position
+  const float p0x = (float)cf.p0x, p0y = (float)cf.p0y;
+  RectD rd{0.0, 0.0, 1.0, 0.0, 0.0, 0.0};
   if (a.full_coverage) {
-    keep = z > 0.f;
-    r.rcx = 0.5f * (float)c.width - cf.p0x;
-    r.rcy = 0.5f * (float)c.height - cf.p0y;
-    r.e1x = 1.f; r.e1y = 0.f;
-    r.h1 = 0.5f * (float)c.width + 1.f;
-    r.h2 = 0.5f * (float)c.height + 1.f;
+    keep = z > 0.0;
+    rd.rcx = 0.5 * c.width - (double)p0x;
+    rd.rcy = 0.5 * c.height - (double)p0y;
+    rd.e1x = 1.0; rd.e1y = 0.0;
+    rd.h1 = 0.5 * c.width + 1.0;
+    rd.h2 = 0.5 * c.height + 1.0;
   } else {
-    keep = keep && proxy_rect(cf, w, a.conf_term, r);
+    keep = keep && proxy_rect(cf, (double)w, a.conf_term, rd);
+    rd.rcx += cf.p0x - (double)p0x;
+    rd.rcy += cf.p0y - (double)p0y;
   }
-  float mx = cf.p0x + r.rcx, my = cf.p0y + r.rcy;
+  const Rect r{(float)rd.rcx, (float)rd.rcy, (float)rd.e1x, (float)rd.e1y, (float)rd.h1, (float)rd.h2};
+  float mx = p0x + r.rcx, my = p0y + r.rcy;
   int4 box = make_int4(0, 0, -1, -1);
   int count = 0;
   if (keep && tile_box(mx, my, r, c.width, c.height, a.tiles_x, a.tiles_y, box)) {
@@ -156,9 +158,10 @@ __global__ __launch_bounds__(256) void k_preprocess(PrepArgs a, CamSet cams) {
     keep = false;
   }
   if (a.proxy_out != nullptr && ci == 0) {
-    float* po = a.proxy_out + 8 * (size_t)g;
-    po[0] = mx; po[1] = my; po[2] = r.e1x; po[3] = r.e1y; po[4] = r.h1; po[5] = r.h2;
-    po[6] = keep ? 1.f : 0.f; po[7] = 0.f;
+    double* po = a.proxy_out + 8 * (size_t)g;
+    po[0] = (double)p0x + rd.rcx; po[1] = (double)p0y + rd.rcy;
+    po[2] = rd.e1x; po[3] = rd.e1y; po[4] = rd.h1; po[5] = rd.h2;
+    po[6] = keep ? 1.0 : 0.0; po[7] = 0.0;
   }
   if (a.counts == nullptr) return;
   a.counts[idx] = count;
@@ -172,7 +175,7 @@ __global__ __launch_bounds__(256) void k_preprocess(PrepArgs a, CamSet cams) {
     rgb[0] = f[0]; rgb[1] = f[1]; rgb[2] = f[2];
   } else {
     constexpr int nb = (DEG + 1) * (DEG + 1);
-    float dx = mean[0] - c.o[0], dy = mean[1] - c.o[1], dz = mean[2] - c.o[2];
+    float dx = a.means[3 * g] - c.o[0], dy = a.means[3 * g + 1] - c.o[1], dz = a.means[3 * g + 2] - c.o[2];
     float inv = rsqrtf(dx * dx + dy * dy + dz * dz);
     float basis[16];
     sh_basis(dx * inv, dy * inv, dz * inv, DEG, basis);
@@ -185,12 +188,17 @@ __global__ __launch_bounds__(256) void k_preprocess(PrepArgs a, CamSet cams) {
     }
   }
   float4* out = a.rec + idx * kRecF4;
-  out[0] = make_float4(cf.p0x, cf.p0y, r.rcx, r.rcy);
+  out[0] = make_float4(p0x, p0y, r.rcx, r.rcy);
   out[1] = make_float4(r.e1x, r.e1y, r.h1, r.h2);
-  out[2] = make_float4(cf.D0, cf.D1x, cf.D1y, cf.D2xx);
-  out[3] = make_float4(cf.D2xy, cf.D2yy, cf.E0, cf.Ex);
-  out[4] = make_float4(cf.Ey, cf.Xxx, cf.Xxy, cf.Xyy);
+  out[2] = make_float4((float)cf.D0, (float)cf.D1x, (float)cf.D1y, (float)cf.D2xx);
+  out[3] = make_float4((float)cf.D2xy, (float)cf.D2yy, (float)cf.E0, (float)cf.Ex);
+  out[4] = make_float4((float)cf.Ey, (float)cf.Xxx, (float)cf.Xxy, (float)cf.Xyy);
   out[5] = make_float4(w, rgb[0], rgb[1], rgb[2]);
+  // the exact rectangle: absolute centre, major axis, halves
+  double2* od = a.rectd + idx * 3;
+  od[0] = make_double2((double)p0x + rd.rcx, (double)p0y + rd.rcy);
+  od[1] = make_double2(rd.e1x, rd.e1y);
+  od[2] = make_double2(rd.h1, rd.h2);
 }
 
 hipError_t launch_preprocess(const PrepArgs& a, const CamSet& cams, hipStream_t s) {

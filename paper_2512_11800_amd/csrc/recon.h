@@ -317,48 +317,141 @@ __device__ __forceinline__ void hermite_adjoint(float y, const float* xs, const 
   dlam_y = dl;
 }
 
-// Per-pixel factorisation of the Hankel matrix of b (b_0 = 1). Returns false
-// (and regularises the diagonal) when H is not numerically positive definite.
+// ---------------------------------------------------------------------------
+// Per-pixel set-up of the bounds: the Cholesky factor of the Hankel matrix of
+// the normalised moments b (b_0 = 1), kept as L^-1 in float.
+//
+// Degenerate measures. A ray density is a sum of Gaussians, so its Hankel
+// matrices are positive definite in exact arithmetic; a measure that is
+// nearly atomic (ray Gaussians far thinner than their separation) is singular
+// to working precision. The test is taken on the standardised moments
+// c_k = E[((y - mean) / sd)^k], which do not depend on the affine moment
+// variable: the measure is degenerate when a Cholesky pivot of their Hankel
+// matrix falls below kPivotRel times its diagonal entry (1e-5: a hundred times
+// the float32 rounding the per-pair moments carry into these pivots, so the
+// decision does not hinge on rounding). A degenerate measure
+// is replaced by its mixture (1 - eps) mu + eps N(mean, sd^2) with the normal
+// distribution of its own mean and variance, for the first eps of
+// kMixEps[] that passes the test (the smallest, 1e-3, keeps the mixture's
+// Hankel matrix conditioned to about 1e3, so its bounds and their adjoint
+// stay accurate in float). The mixture is a valid measure with a
+// positive definite Hankel matrix, it transforms with the moment variable, and
+// it is differentiable in b (the backward pass applies its Jacobian). A moment
+// vector without a positive variance or with non-finite entries gets the
+// identity factor (finite, meaningless bounds). Both outcomes are flagged.
+// ---------------------------------------------------------------------------
+constexpr double kPivotRel = 1e-5;
+constexpr int kMixLevels = 4;
+__device__ constexpr double kMixEps[kMixLevels] = {1e-3, 1e-2, 1e-1, 1.0};
+
+// Cholesky of the Hankel matrix of c (c_0 = 1): every pivot above kPivotRel
+// times its diagonal entry, and the factor in lc when so.
+template <int M>
+__device__ __forceinline__ bool hankel_chol(const double* c, double (&lc)[M][M]) {
+  bool ok = true;
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    double s = c[2 * j];
+#pragma unroll
+    for (int k = 0; k < j; ++k) s -= lc[j][k] * lc[j][k];
+    ok = ok && (s > kPivotRel * c[2 * j]);
+    const double d = sqrt(fmax(s, 1e-300));
+    lc[j][j] = d;
+#pragma unroll
+    for (int i = j + 1; i < M; ++i) {
+      double t = c[i + j];
+#pragma unroll
+      for (int k = 0; k < j; ++k) t -= lc[i][k] * lc[j][k];
+      lc[i][j] = t / d;
+    }
+  }
+  return ok;
+}
+
+// moments E[(m + sd Z)^k], k = 0..2n, of N(m, v): n_k = m n_{k-1} + (k - 1) v n_{k-2}
+template <int NK>
+__device__ __forceinline__ void normal_moments(double m, double v, double* nm) {
+  nm[0] = 1.0;
+  nm[1] = m;
+#pragma unroll
+  for (int k = 2; k < NK; ++k) nm[k] = m * nm[k - 1] + (double)(k - 1) * v * nm[k - 2];
+}
+
+// Returns the mixture weight eps used (0: none; -1: identity factor) and the
+// moments the factor belongs to in bmix[0..2 NH].
 template <int NH>
-__device__ __forceinline__ bool hankel_factor(const double* b, LInv<NH>& out) {
+__device__ __forceinline__ double hankel_factor(const double* b, LInv<NH>& out, double* bmix) {
   constexpr int M = NH + 1;
-  double h[M][M];
+  constexpr int NK = 2 * NH + 1;
+  const double mean = b[1], var = b[2] - b[1] * b[1];
+  bool finite = true;
+#pragma unroll
+  for (int k = 0; k < NK; ++k) finite = finite && isfinite(b[k]);
+  double eps = -1.0;
+  if (finite && var > 0.0) {
+    // standardised moments c_k = sum_j C(k, j) b_j (-mean)^(k - j) / sd^k
+    const double is = 1.0 / sqrt(var);
+    double c[NK], sn[NK];
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+      double acc = 0.0, binom = 1.0, pw = 1.0;
+#pragma unroll
+      for (int j = k; j >= 0; --j) {
+        acc += binom * b[j] * pw;
+        binom = binom * (double)j / (double)(k - j + 1);
+        pw *= -mean;
+      }
+      double sk = 1.0;
+#pragma unroll
+      for (int i = 0; i < k; ++i) sk *= is;
+      c[k] = acc * sk;
+    }
+    normal_moments<NK>(0.0, 1.0, sn);
+    double lc[M][M];
+    if (hankel_chol<M>(c, lc)) {
+      eps = 0.0;
+    } else {
+#pragma unroll 1
+      for (int l = 0; l < kMixLevels && eps < 0.0; ++l) {
+        double cm[NK];
+#pragma unroll
+        for (int k = 0; k < NK; ++k) cm[k] = (1.0 - kMixEps[l]) * c[k] + kMixEps[l] * sn[k];
+        if (hankel_chol<M>(cm, lc)) eps = kMixEps[l];
+      }
+    }
+  }
+  double nm[NK];
+  normal_moments<NK>(mean, var, nm);
+#pragma unroll
+  for (int k = 0; k < NK; ++k) bmix[k] = eps > 0.0 ? (1.0 - eps) * b[k] + eps * nm[k] : b[k];
+  // the factor in the pixel's moment variable
+  double lc[M][M];
 #pragma unroll
   for (int i = 0; i < M; ++i)
 #pragma unroll
-    for (int j = 0; j < M; ++j) h[i][j] = b[i + j];
-  bool ok = true;
-  double lc[M][M];
-  for (int attempt = 0; attempt < 5; ++attempt) {
-    ok = true;
-#pragma unroll
-    for (int i = 0; i < M; ++i)
-#pragma unroll
-      for (int j = 0; j < M; ++j) lc[i][j] = 0.0;
+    for (int j = 0; j < M; ++j) lc[i][j] = 0.0;
+  bool ok = eps >= 0.0;
+  if (ok) {
 #pragma unroll
     for (int j = 0; j < M; ++j) {
-      double s = h[j][j];
+      double s = bmix[2 * j];
 #pragma unroll
       for (int k = 0; k < j; ++k) s -= lc[j][k] * lc[j][k];
-      if (!(s > 1e-14 * h[j][j])) { ok = false; s = 1e-14 * h[j][j] + 1e-300; }
-      double d = sqrt(s);
+      ok = ok && s > 0.0;
+      const double d = sqrt(fmax(s, 1e-300));
       lc[j][j] = d;
 #pragma unroll
       for (int i = j + 1; i < M; ++i) {
-        double t = h[i][j];
+        double t = bmix[i + j];
 #pragma unroll
         for (int k = 0; k < j; ++k) t -= lc[i][k] * lc[j][k];
         lc[i][j] = t / d;
       }
     }
-    if (ok) break;
-    // fallback: bias the diagonal (1e-6 .. 1 relative); flagged to the caller
-    const double bias = attempt == 0 ? 1e-6 : attempt == 1 ? 1e-3 : attempt == 2 ? 1e-1 : 1.0;
-#pragma unroll
-    for (int i = 0; i < M; ++i) h[i][i] = h[i][i] * (1.0 + bias) + 1e-30;
   }
   if (!ok) {
-    // still indefinite: keep the arithmetic finite with the identity
+    // no positive definite matrix: keep the arithmetic finite with the identity
+    eps = -1.0;
 #pragma unroll
     for (int i = 0; i < M; ++i)
 #pragma unroll
@@ -386,7 +479,28 @@ __device__ __forceinline__ bool hankel_factor(const double* b, LInv<NH>& out) {
     for (int j = 0; j <= i; ++j) out.l[o + j] = (float)li[i][j];
     o += i + 1;
   }
-  return ok;
+  return eps;
+}
+
+// Adjoint of the mixture b' = (1 - eps) b + eps n(b_1, b_2 - b_1^2) (n: the
+// normal moments above) for k = 1..2n: given D = dL/db' (D[0] unused),
+// returns dL/db in D. dn_k/dmean = k n_{k-1}, dn_k/dvar = k (k - 1) / 2 n_{k-2}.
+template <int NK>
+__device__ __forceinline__ void mixture_adjoint(const double* b, double eps, double* D) {
+  const double mean = b[1], var = b[2] - b[1] * b[1];
+  double nm[NK];
+  normal_moments<NK>(mean, var, nm);
+  double gm = 0.0, gv = 0.0;
+#pragma unroll
+  for (int k = 1; k < NK; ++k) {
+    gm += D[k] * (double)k * nm[k - 1];
+    if (k >= 2) gv += D[k] * 0.5 * (double)(k * (k - 1)) * nm[k - 2];
+  }
+#pragma unroll
+  for (int k = 1; k < NK; ++k) D[k] *= 1.0 - eps;
+  // mean = b_1, var = b_2 - b_1^2
+  D[1] += eps * (gm - 2.0 * mean * gv);
+  D[2] += eps * gv;
 }
 
 }  // namespace mb

@@ -486,15 +486,16 @@ __global__ __launch_bounds__(256, (K <= 6 && NQ == 4 && !SUR) ? 3 : 2) void k_re
   LInv<NH> L;
   float bk[K + 1];
   bk[0] = 1.f;
+  float mix_eps = 0.f;  // the forward pass's mixture weight (degenerate measures)
   if (live && !SUR) {
-    double bn[K + 1];
+    double bn[K + 1], bmix[K + 1];
     bn[0] = 1.0;
 #pragma unroll
     for (int k = 1; k <= K; ++k) {
       bn[k] = acc[k] / acc[0];
       bk[k] = (float)bn[k];
     }
-    hankel_factor<NH>(bn, L);
+    mix_eps = (float)hankel_factor<NH>(bn, L, bmix);
   } else {
 #pragma unroll
     for (int k = 1; k <= K; ++k) bk[k] = 0.f;
@@ -569,21 +570,36 @@ __global__ __launch_bounds__(256, (K <= 6 && NQ == 4 && !SUR) ? 3 : 2) void k_re
         // F as the forward pass used it; its input gradient beside it
         const long long qi = qbase_p + (long long)rank * NQ;
         const float* qg = a.q_g + qi * 8;
+        // the forward pass's running maximum: edge e takes the optical depth
+        // of edge src[e] (the last edge at or before e that raised it)
+        int src[NQ];
 #pragma unroll
         for (int e = 0; e < NQ; ++e) {
           s.F[e] = a.q_f[qi + e];
-          s.tau[e] = m0p * s.F[e];
+          const float te = m0p * s.F[e];
+          const bool up = e == 0 || te > s.tau[e > 0 ? e - 1 : 0];
+          s.tau[e] = up ? te : s.tau[e > 0 ? e - 1 : 0];
+          src[e] = up ? e : src[e > 0 ? e - 1 : 0];
         }
         quad_terms<NH, NQ>(g, tn, s);
         float4 f5 = st.f[5][j];
         const float gbar = gap[0] * f5.y + gap[1] * f5.z + gap[2] * f5.w + gbp;
+        // dL/dtau gathered onto the edges whose queries supplied it
+        float wsrc[NQ];
+#pragma unroll
+        for (int e = 0; e < NQ; ++e) wsrc[e] = 0.f;
+#pragma unroll
+        for (int e = 0; e < NQ; ++e) {
+#pragma unroll
+          for (int e2 = 0; e2 <= e; ++e2) wsrc[e2] += src[e] == e2 ? gbar * s.A[e] : 0.f;
+        }
         float c[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         float gmu = 0.f, gsig = 0.f, gom = 0.f;
         const float isg = fast_rcp(ssigp);
 #pragma unroll
         for (int e = 0; e < NQ; ++e) {
           const float* ge = qg + e * 8;
-          const float wgt = gbar * s.A[e];
+          const float wgt = wsrc[e];
           c[0] += wgt * s.F[e];  // tau = m_0 F at fixed inputs
 #pragma unroll
           for (int k = 0; k < 6; ++k) c[1 + k] += wgt * m0p * ge[1 + k];
@@ -830,6 +846,33 @@ __global__ __launch_bounds__(256, (K <= 6 && NQ == 4 && !SUR) ? 3 : 2) void k_re
       for (int w = 0; w < 4; ++w) t += xf[(w * (K + 1) + k) * 64 + lane];
       dm[k] = t;
     }
+  }
+
+  if (!SUR && active && mix_eps != 0.f) {
+    // a degenerate pixel: the pairs took dL/db' at the mixture b' (dm[1..K]);
+    // back to b through the mixture, and dm[0]'s share -sum_k b_k dL/db_k
+    // follows the changed dL/db. With the identity factor F does not depend
+    // on b, and the moments pass no gradient but m_0's.
+    double bn[K + 1], D[K + 1];
+    bn[0] = 1.0;
+    D[0] = 0.0;
+#pragma unroll
+    for (int k = 1; k <= K; ++k) {
+      bn[k] = (double)bk[k];
+      D[k] = dm[k];
+    }
+    if (mix_eps > 0.f) {
+      mixture_adjoint<K + 1>(bn, (double)mix_eps, D);
+    } else {
+#pragma unroll
+      for (int k = 1; k <= K; ++k) D[k] = 0.0;
+    }
+    double corr = 0.0;
+#pragma unroll
+    for (int k = 1; k <= K; ++k) corr += (double)bk[k] * ((double)dm[k] - D[k]);
+    dm[0] += (float)corr;
+#pragma unroll
+    for (int k = 1; k <= K; ++k) dm[k] = (float)D[k];
   }
 
   // ---- pass 3: the moment part of the Gradient stage ------------------------

@@ -160,15 +160,53 @@ __device__ __forceinline__ void load_batch(Stage& st, const float4* rec, const i
   }
 }
 
-__device__ __forceinline__ bool covers(const Stage& st, int j, float u, float v, bool inside, float& dx,
-                                       float& dy) {
-  float4 f0 = st.f[0][j], f1 = st.f[1][j];
-  dx = u - f0.x;
-  dy = v - f0.y;
-  float ax = dx - f0.z, ay = dy - f0.w;
-  float c1 = ax * f1.x + ay * f1.y;
-  float c2 = -ax * f1.y + ay * f1.x;
-  return inside && fabsf(c1) <= f1.z && fabsf(c2) <= f1.w;
+// Coverage of the pixel centre (u, v) by staged entry j (record index
+// sorted_rec[b + j]), the decision of the exact rectangle (rectd, double).
+// The float test on the staged record decides wherever its margin to an edge
+// exceeds a bound on its rounding error (the record's centre, axis and halves
+// are the double values rounded to float, and the test's own operations round
+// relative 2^-24: 1e-6 relative is 17 times that bound); near an edge the
+// wave re-tests in double against rectd. Only the first pass tests coverage:
+// every later pass, forward and backward, reads the masks it stores.
+__device__ __forceinline__ bool covers(const Stage& st, const double2* rectd, const int* sorted_rec, int b, int j,
+                                       float u, float v, bool inside) {
+  const float4 f0 = st.f[0][j], f1 = st.f[1][j];
+  const float dx = u - f0.x, dy = v - f0.y;
+  const float ax = dx - f0.z, ay = dy - f0.w;
+  const float c1 = ax * f1.x + ay * f1.y;
+  const float c2 = -ax * f1.y + ay * f1.x;
+  const float m = fminf(f1.z - fabsf(c1), f1.w - fabsf(c2));
+  const float band = 1e-6f * (1.f + fabsf(dx) + fabsf(dy) + fabsf(f0.z) + fabsf(f0.w) + f1.z + f1.w);
+  bool cov = inside && m >= 0.f;
+  const bool amb = inside && fabsf(m) < band;
+  if (__ballot(amb) != 0) {
+    const int rid = __builtin_amdgcn_readfirstlane(sorted_rec[b + j]);
+    const double2 cd = rectd[(size_t)rid * 3], ed = rectd[(size_t)rid * 3 + 1], hd = rectd[(size_t)rid * 3 + 2];
+    if (amb) {
+      const double axd = (double)u - cd.x, ayd = (double)v - cd.y;
+      const double c1d = axd * ed.x + ayd * ed.y;
+      const double c2d = -axd * ed.y + ayd * ed.x;
+      cov = fabs(c1d) <= hd.x && fabs(c2d) <= hd.y;
+    }
+  }
+  return cov;
+}
+
+// Mask walk without a queue: calls body(j, m) for every entry j of the staged
+// batch [b, b + nb) whose 64-bit coverage mask m for this wave's pixel block
+// `quad` is not zero, in list order (wave-uniform j and m).
+template <class Body>
+__device__ __forceinline__ void for_each_masked(const uint64_t* masks, int b, int nb, int quad, int lane,
+                                                Body&& body) {
+  for (int j0 = 0; j0 < nb; j0 += 64) {
+    const uint64_t mk = j0 + lane < nb ? masks[(size_t)(b + j0 + lane) * 4 + quad] : 0ull;
+    uint64_t nz = __ballot(mk != 0);
+    while (nz) {
+      const int l = __builtin_ctzll(nz);
+      nz &= nz - 1;
+      body(j0 + l, (uint64_t)__shfl(mk, l, 64));
+    }
+  }
 }
 
 // Which 8x8 quadrants of the tile at (x0, y0) the axis-aligned box of entry

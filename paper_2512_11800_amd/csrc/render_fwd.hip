@@ -185,8 +185,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
         while (todo) {
           const int j = j0 + __builtin_ctzll(todo);
           todo &= todo - 1;
-          float dx, dy;
-          bool cov = covers(st, j, u, v, inside, dx, dy);
+          const bool cov = covers(st, a.rectd, a.sorted_rec, b, j, u, v, inside);
           uint64_t mask = __ballot(cov);
           if (lane == 0) a.masks[(size_t)(b + j) * 4 + quad] = mask;
           if (mask == 0) continue;
@@ -311,11 +310,11 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
   LInv<NH> L;
   bool fallback = false;
   if (live && MODE != kModeEmit) {
-    double bn[K + 1];
+    double bn[K + 1], bmix[K + 1];
     bn[0] = 1.0;
 #pragma unroll
     for (int k = 1; k <= K; ++k) bn[k] = acc[k] / acc[0];
-    fallback = !hankel_factor<NH>(bn, L);
+    fallback = hankel_factor<NH>(bn, L, bmix) != 0.0;
   } else {
 #pragma unroll
     for (int i = 0; i < (NH + 1) * (NH + 2) / 2; ++i) L.l[i] = 0.f;
@@ -384,11 +383,10 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
       __syncthreads();
       load_batch(st, a.rec, a.sorted_rec, b, nb);
       __syncthreads();
-      for (int j = 0; j < nb; ++j) {
-        float dx, dy;
-        bool cov = covers(st, j, u, v, inside && live, dx, dy);
-        if (__ballot(cov) == 0) continue;
-        if (cov) {
+      // the pairs of the coverage masks pass 0 stored (their count is n_cov)
+      for_each_masked(a.masks, b, nb, quad, lane, [&](int j, uint64_t m) __attribute__((always_inline)) {
+        if (inside && live && ((m >> lane) & 1ull)) {
+          const float dx = u - st.f[0][j].x, dy = v - st.f[0][j].y;
           RayG g = ray_params(st, j, dx, dy, lam);
           QEdges<NQ> e;
           quad_edges<NQ>(g, pb, tn, a, e);
@@ -402,7 +400,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
           }
           ++i_pair;
         }
-      }
+      });
     }
     return;
   } else {
@@ -527,7 +525,8 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
   float4* sv = reinterpret_cast<float4*>(a.saved + pix * MB_SAVED_FLOATS_PER_PIXEL);
   sv[0] = make_float4(sr, sg, sb, so);
   if (want_pen) a.penalty[pix] = spen;
-  // covering count; stored as -(count + 1) when the Hankel factor needed a fallback
+  // covering count; stored as -(count + 1) when the pixel's measure was
+  // degenerate (mixed with a normal, or the identity factor; see hankel_factor)
   sv[1] = make_float4(tc, sd, m0, fallback ? -(float)(n_cov + 1) : (float)n_cov);
 }
 
@@ -567,17 +566,22 @@ __global__ __launch_bounds__(256) void k_render_consume(RenderArgs a, CamSet cam
     __syncthreads();
     load_batch(st, a.rec, a.sorted_rec, b, nb);
     __syncthreads();
-    for (int j = 0; j < nb; ++j) {
-      float dx, dy;
-      bool cov = covers(st, j, u, v, active, dx, dy);
-      if (__ballot(cov) == 0) continue;
-      if (cov) {
+    // the pairs of the forward pass's coverage masks, in the emit pass's order
+    for_each_masked(a.masks, b, nb, wave, lane, [&](int j, uint64_t m) __attribute__((always_inline)) {
+      if (active && ((m >> lane) & 1ull)) {
+        const float dx = u - st.f[0][j].x, dy = v - st.f[0][j].y;
         RayG g = ray_params(st, j, dx, dy, lam);
         QEdges<NQ> e;
         quad_edges<NQ>(g, pb, tn, a, e);
         const float* fq = a.q_f + qbase + (long long)i_pair * NQ;
+        // the bounds the surrogate stands for grow with depth: its optical
+        // depth along the edges is made non-decreasing (running maximum; a
+        // later edge takes over only when strictly larger)
 #pragma unroll
-        for (int k = 0; k < NQ; ++k) e.tau[k] = m0 * fq[k];
+        for (int k = 0; k < NQ; ++k) {
+          const float tk = m0 * fq[k];
+          e.tau[k] = (k == 0 || tk > e.tau[k > 0 ? k - 1 : 0]) ? tk : e.tau[k > 0 ? k - 1 : 0];
+        }
         float q = quad_sum<NQ>(g, tn, e);
         float4 f5 = st.f[5][j];
         sr += q * f5.y;
@@ -586,7 +590,7 @@ __global__ __launch_bounds__(256) void k_render_consume(RenderArgs a, CamSet cam
         so += q;
         ++i_pair;
       }
-    }
+    });
   }
   if (!inside) return;
   float alpha = -expm1f(-m0);

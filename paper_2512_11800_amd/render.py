@@ -146,9 +146,10 @@ def _cams(cams: Sequence) -> ctypes.Array:
 
 
 def project(g: Gaussians, cam, opts=None) -> torch.Tensor:
-    """Screen proxies [n, 8] (centre, e1, half lengths, kept flag) via mb_project."""
+    """Screen proxies [n, 8] float64 (centre, major axis e1, half lengths, kept
+    flag) via mb_project: the rectangles the coverage test uses."""
     lib = L.load()
-    out = torch.empty(g.n, 8, dtype=torch.float32, device=g.means.device)
+    out = torch.empty(g.n, 8, dtype=torch.float64, device=g.means.device)
     L.check(lib.mb_project(ctypes.byref(g.struct()), ctypes.byref(camera_struct(cam)),
                            ctypes.byref(options_struct(opts)), _ptr(out), _stream()))
     return out

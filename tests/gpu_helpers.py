@@ -7,7 +7,7 @@ import numpy as np
 import torch
 
 import oracle
-from oracle.proxy import screen_proxy
+from oracle.proxy import MARGIN_TOL, ORIENT_EPS, screen_proxy
 from oracle.render import scene_tensors
 
 
@@ -34,14 +34,18 @@ def gpu_render(scene, cams, opts, on_device=False):
 
 
 def proxy_error(scene, cam, opts):
-    """Max discrepancy (pixels) between the GPU and oracle proxy rectangles over
-    Gaussians both keep, and the count of keep/cull disagreements."""
+    """Discrepancy between the GPU's rectangles (mb_project: the double
+    rectangles its coverage test uses) and the oracle's, over Gaussians both
+    keep: centre and half lengths (pixels), the axis angle and the angle times
+    the axes' conditioning (1 - minor^2 / major^2), and the count of keep/cull
+    disagreements outside the oracle's ambiguous decisions."""
     import paper_2512_11800_amd as M
     g = M.Gaussians.from_scene(scene)
-    gp = M.project(g, cam, opts).cpu().numpy().astype(np.float64)
+    gp = M.project(g, cam, opts).cpu().numpy()
     op = screen_proxy(scene_tensors(scene), cam, opts.conf_c)
     keep_o = op.valid.numpy()
-    # the GPU keeps a Gaussian only if its rectangle's box reaches a pixel centre
+    amb_o = op.ambiguous.numpy()
+    # the GPU also drops a Gaussian whose rectangle's box reaches no pixel centre
     ext = (np.abs(op.axes.numpy()) * op.half.numpy()[:, :, None]).sum(1)
     m2 = op.mean2d.numpy()
     x0 = np.ceil(m2[:, 0] - ext[:, 0] - 0.5)
@@ -53,36 +57,41 @@ def proxy_error(scene, cam, opts):
     near_edge = ((np.abs(x0 - (cam.width - 1)) <= 1) | (np.abs(x1) <= 1)
                  | (np.abs(y0 - (cam.height - 1)) <= 1) | (np.abs(y1) <= 1))
     keep_g = gp[:, 6] > 0
-    amb_o = op.ambiguous.numpy()
-    # decisions that must agree: clearly on screen, or culled by the oracle
-    mismatch_n = int((keep_o & on_screen & ~near_edge & ~keep_g & ~amb_o).sum()
-                     + (keep_g & ~keep_o & ~amb_o).sum())
-    # the GPU also drops Gaussians whose rectangle misses the image
+    mismatch = int((keep_o & on_screen & ~near_edge & ~keep_g & ~amb_o).sum()
+                   + (keep_g & ~keep_o & ~amb_o).sum())
     both = keep_o & keep_g
-    c_err = np.abs(gp[both, :2] - op.mean2d.numpy()[both]).max(initial=0.0)
-    h_err = np.abs(gp[both, 4:6] - op.half.numpy()[both]).max(initial=0.0)
+    c_err = np.abs(gp[both, :2] - m2[both]).max(initial=0.0)
+    h = op.half.numpy()[both]
+    h_err = np.abs(gp[both, 4:6] - h).max(initial=0.0)
     eg = gp[both, 2:4]
     eo = op.axes.numpy()[both, 0]
-    # sine of the angle between the axes from the cross product (accurate for
-    # small angles, unlike sqrt(1 - cos^2) of float32 unit vectors)
-    angle = np.abs(eg[:, 0] * eo[:, 1] - eg[:, 1] * eo[:, 0]) / (
-        np.linalg.norm(eg, axis=1) * np.linalg.norm(eo, axis=1))
-    h = op.half.numpy()[both]
-    # axis angle error relative to the conditioning of the eigenvectors
-    orient = (angle * (1 - (h[:, 0] / np.maximum(h[:, 1], 1e-300)) ** 2)).max(initial=0.0)
-    mismatch = mismatch_n
-    return dict(centre=c_err, half=h_err, orient=orient, angle=angle.max(initial=0.0),
-                mismatch=mismatch, amb=int(op.ambiguous.numpy().sum()), n_keep=int(both.sum()))
+    # sine of the angle between the major axes (either sign)
+    sin_a = np.abs(eg[:, 0] * eo[:, 1] - eg[:, 1] * eo[:, 0])
+    # the angle error in units of the axes' conditioning, which the band
+    # ORIENT_EPS / (1 - minor^2 / major^2) of the protocol is written in
+    cond = 1 - (h[:, 1] / h[:, 0]) ** 2
+    orient = (sin_a * cond).max(initial=0.0)
+    return dict(centre=c_err, half=h_err, angle=sin_a.max(initial=0.0), orient=orient,
+                mismatch=mismatch, amb=int(amb_o.sum()), n_keep=int(both.sum()))
 
 
 def tolerances(pe):
-    """Exclusion band for the parity protocol from the measured proxy
-    discrepancy: (margin in pixels, orientation epsilon)."""
-    return max(1e-4, 4.0 * (pe["centre"] + pe["half"])), max(1e-6, 4.0 * pe["orient"])
+    """The parity protocol's fixed bands (oracle.proxy: MARGIN_TOL pixels at
+    rectangle edges, ORIENT_EPS for the axes of near-circles), after checking
+    that the measured GPU-oracle rectangle discrepancy sits well inside them."""
+    log(f"[proxy] centre {pe['centre']:.2e} half {pe['half']:.2e} angle {pe['angle']:.2e} "
+        f"angle x conditioning {pe['orient']:.2e} mismatch {pe['mismatch']} kept {pe['n_keep']}")
+    assert pe["mismatch"] == 0
+    assert pe["centre"] + pe["half"] <= 0.1 * MARGIN_TOL, pe
+    assert pe["orient"] <= 0.1 * ORIENT_EPS, pe
+    return MARGIN_TOL, ORIENT_EPS
 
 
-def compare(img_gpu, res_oracle, label, tol=1e-4):
-    """Per-result max-abs error over pixels the parity protocol keeps."""
+def compare(img_gpu, res_oracle, label, tol=1e-4, max_excluded=0.0):
+    """Per-result max-abs error over pixels the parity protocol keeps. The
+    excluded pixels (a coverage or cull decision within the protocol's band)
+    are counted, logged and bounded: at most ``max_excluded`` of the pixels
+    (a fraction; 0 requires none)."""
     ref = res_oracle["image"]
     amb = res_oracle["ambiguous"]
     err = np.abs(img_gpu - ref).max(-1)
@@ -90,6 +99,9 @@ def compare(img_gpu, res_oracle, label, tol=1e-4):
     mx = float(err[keep].max(initial=0.0))
     p9999 = float(np.quantile(err[keep], 0.9999)) if keep.any() else 0.0
     worst = int(np.argmax(np.where(keep, err, -1)))
-    log(f"[parity] {label}: pixels={len(err)} excluded={int(amb.sum())} "
+    n_ex = int(amb.sum())
+    log(f"[parity] {label}: pixels={len(err)} excluded={n_ex} "
         f"max_abs={mx:.3e} p99.99={p9999:.3e} worst_slot={worst} tol={tol:g}")
+    assert n_ex <= max_excluded * len(err), f"{label}: {n_ex} of {len(err)} pixels excluded"
+    assert np.all(np.isfinite(img_gpu)), f"{label}: non-finite GPU pixels"
     return mx, worst

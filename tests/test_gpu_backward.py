@@ -1,15 +1,19 @@
 """Backward parity: GPU gradients (through the C ABI) against float64 autograd
 of the CPU oracle and against central finite differences.
 
-Bar: relative error ||g_gpu - g_ref|| / ||g_ref|| <= 1e-3 per parameter group.
-The upstream gradient is a seeded input; pixels whose coverage decision is
-ambiguous (parity protocol) get a zero upstream gradient."""
+Bar, per parameter group: relative error ||g_gpu - g_ref|| / ||g_ref|| <= 1e-3,
+and element by element max |g_gpu - g_ref| <= 1e-3 max |g_ref| (so a few wrong
+Gaussians cannot hide in the group norm). The upstream gradient is a seeded
+input; pixels whose coverage decision is ambiguous (parity protocol) get a
+zero upstream gradient."""
 import numpy as np
 import pytest
 import torch
 
 import oracle
 import workloads as W
+from oracle.proxy import screen_proxy
+from oracle.render import scene_tensors
 from tests.gpu_helpers import log, proxy_error, tolerances
 
 pytestmark = pytest.mark.gpu
@@ -38,15 +42,18 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
 
 
-def _check(gpu, ref, label, idx=None, tol=1e-3):
+def _check(gpu, ref, label, idx=None, ref_idx=None, tol=1e-3):
     ok = True
     for k in GROUPS:
         a, b = gpu[k], ref[k]
         if idx is not None:
-            a, b = a[idx], b[idx]
+            a = a[idx]
+            b = b[idx if ref_idx is None else ref_idx]
         r = _rel(a, b)
-        log(f"[grad] {label} {k}: rel_err={r:.3e} |ref|={np.linalg.norm(b):.3e}")
-        ok = ok and r <= tol
+        el = float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-30))
+        log(f"[grad] {label} {k}: rel_err={r:.3e} max_elem_err/max|ref|={el:.3e} "
+            f"|ref|={np.linalg.norm(b):.3e}")
+        ok = ok and r <= tol and el <= tol
     return ok
 
 
@@ -68,7 +75,7 @@ def test_fd_subset_k6_vs_oracle_autograd():
     g_img = rng.normal(size=(64 * 64, 3))
     gpu, _ = _gpu_grads(scene, cams, opts, g_img)
     ref = oracle.render_backward(scene, cams[0], opts, g_img)
-    assert _check(gpu, ref, "fd-subset K=6", tol=3e-3)
+    assert _check(gpu, ref, "fd-subset K=6")
 
 
 def test_fd_subset_k8_vs_oracle_autograd():
@@ -81,7 +88,7 @@ def test_fd_subset_k8_vs_oracle_autograd():
     g_img = rng.normal(size=(64 * 64, 3))
     gpu, _ = _gpu_grads(scene, cams, opts, g_img)
     ref = oracle.render_backward(scene, cams[0], opts, g_img)
-    assert _check(gpu, ref, "fd-subset K=8", tol=3e-3)
+    assert _check(gpu, ref, "fd-subset K=8")
 
 
 @pytest.mark.parametrize("k_mom", [4, 6, 8])
@@ -95,7 +102,7 @@ def test_fd_subset_five_intervals_vs_oracle_autograd(k_mom):
     g_img = rng.normal(size=(64 * 64, 3))
     gpu, _ = _gpu_grads(scene, cams, opts, g_img)
     ref = oracle.render_backward(scene, cams[0], opts, g_img)
-    assert _check(gpu, ref, f"fd-subset K={k_mom} N=5", tol=3e-3)
+    assert _check(gpu, ref, f"fd-subset K={k_mom} N=5")
 
 
 def test_w1_proxy_coverage_vs_oracle_autograd():
@@ -113,41 +120,92 @@ def test_w1_proxy_coverage_vs_oracle_autograd():
     assert _check(gpu, ref, "W1")
 
 
-def test_w3_full_size_sampled_gaussians():
+@pytest.mark.parametrize("k_mom", [4, 6])
+def test_w3_full_size_sampled_gaussians(k_mom):
     """1M Gaussians at 1600x1064 (the benchmark's training configuration, in
-    its launch configuration): gradients of sampled Gaussians, each computed
-    by the oracle from every pixel it covers."""
+    its launch configuration): gradients of sampled Gaussians, each computed by
+    the oracle from every pixel its rectangle's box reaches. The sample mixes
+    small footprints (below the median area), large ones (median to 95th
+    percentile) and Gaussians in the heaviest tiles, whose lists are long
+    enough to be rendered split over four workgroups. The oracle renders only
+    the Gaussians whose box reaches a sampled pixel: the others change no
+    sampled pixel."""
     scene, _, cams, opts = W.w3_train()
+    opts.n_moments = k_mom
     cam = cams[0]
-    from oracle.proxy import screen_proxy
-    from oracle.render import scene_tensors
     prox = screen_proxy(scene_tensors(scene), cam, opts.conf_c)
-    rng = np.random.default_rng(14)
+    rng = np.random.default_rng(14 + k_mom)
+    lo, hi = _boxes(prox, cam)
     valid = np.nonzero(prox.valid.numpy())[0]
-    # small-footprint Gaussians keep the oracle's pixel set bounded
     area = prox.half.numpy()[valid].prod(-1)
-    cand = valid[area < np.quantile(area, 0.5)]
-    sample = rng.choice(cand, 12, replace=False)
+    q50, q95 = np.quantile(area, [0.5, 0.95])
+    small = valid[area < q50]
+    large = valid[(area >= q50) & (area < q95)]
+    # tile list lengths from the boxes (an upper bound of the lists)
+    tiles_x, tiles_y = (cam.width + 15) // 16, (cam.height + 15) // 16
+    cnt = np.zeros((tiles_y + 1, tiles_x + 1), np.int64)
+    t0 = np.clip(lo[valid] // 16, 0, [tiles_x - 1, tiles_y - 1]).astype(int)
+    t1 = np.clip(hi[valid] // 16, 0, [tiles_x - 1, tiles_y - 1]).astype(int)
+    np.add.at(cnt, (t0[:, 1], t0[:, 0]), 1)
+    np.add.at(cnt, (t0[:, 1], t1[:, 0] + 1), -1)
+    np.add.at(cnt, (t1[:, 1] + 1, t0[:, 0]), -1)
+    np.add.at(cnt, (t1[:, 1] + 1, t1[:, 0] + 1), 1)
+    cnt = cnt.cumsum(0).cumsum(1)[:tiles_y, :tiles_x]
+    heavy_t = np.argsort(cnt.ravel())[::-1][:8]
+    log(f"[w3] heaviest tiles hold up to {cnt.ravel()[heavy_t].max()} / {cnt.ravel()[heavy_t].min()} box entries")
+    hty, htx = heavy_t // tiles_x, heavy_t % tiles_x
+    in_heavy = np.zeros(len(valid), bool)
+    for yy, xx in zip(hty, htx):
+        in_heavy |= ((t0[:, 0] <= xx) & (t1[:, 0] >= xx) & (t0[:, 1] <= yy) & (t1[:, 1] >= yy))
+    heavy = valid[in_heavy & (area < q95)]
+    sample = np.unique(np.concatenate([rng.choice(small, 5, replace=False),
+                                       rng.choice(large, 5, replace=False),
+                                       rng.choice(heavy, 5, replace=False)]))
     pix = set()
     for gi in sample:
-        m = prox.mean2d[gi].numpy()
-        r = int(np.ceil(prox.half[gi].numpy().sum())) + 1
-        xs = np.arange(max(0, int(m[0]) - r), min(cam.width, int(m[0]) + r + 1))
-        ys = np.arange(max(0, int(m[1]) - r), min(cam.height, int(m[1]) + r + 1))
+        xs = np.arange(max(0, int(np.floor(lo[gi, 0]))), min(cam.width, int(np.ceil(hi[gi, 0])) + 1))
+        ys = np.arange(max(0, int(np.floor(lo[gi, 1]))), min(cam.height, int(np.ceil(hi[gi, 1])) + 1))
         pix.update((yy * cam.width + xx) for yy in ys for xx in xs)
     pix = np.array(sorted(pix))
-    pe = proxy_error(scene.subset(sample), cam, opts)
-    tol_m, tol_o = tolerances(pe)
-    amb = oracle.render_image(scene, cam, opts, pixels=pix, margin_tol=max(tol_m, 1e-3),
-                              orient_eps=tol_o)["ambiguous"]
+    tol_m, tol_o = tolerances(proxy_error(scene.subset(sample), cam, opts))
+    sub = _touching(prox, lo, hi, cam, pix)
+    assert np.isin(sample, sub).all()
+    sub_scene = scene.subset(sub)
+    amb = oracle.render_image(sub_scene, cam, opts, pixels=pix, margin_tol=tol_m, orient_eps=tol_o,
+                              max_pixels=len(pix))["ambiguous"]
+    assert amb.sum() <= 0.01 * len(pix)
     g_full = np.zeros((cam.width * cam.height, 3))
     vals = rng.normal(size=(len(pix), 3))
     vals[amb] = 0.0
     g_full[pix] = vals
     gpu, _ = _gpu_grads(scene, cams, opts, g_full, on_device=True)
-    ref = oracle.render_backward(scene, cam, opts, vals, pixels=pix)
-    log(f"[w3] sampled {len(sample)} Gaussians over {len(pix)} pixels ({int(amb.sum())} ambiguous)")
-    assert _check(gpu, ref, "W3 sampled", idx=sample, tol=2e-3)
+    ref = oracle.render_backward(sub_scene, cam, opts, vals, pixels=pix, max_pixels=len(pix))
+    log(f"[w3 K={k_mom}] sampled {len(sample)} Gaussians over {len(pix)} pixels "
+        f"({int(amb.sum())} ambiguous), oracle scene {len(sub)} Gaussians")
+    assert _check(gpu, ref, f"W3 K={k_mom} sampled", idx=sample, ref_idx=np.searchsorted(sub, sample))
+
+
+def _boxes(prox, cam):
+    """Axis-aligned pixel-centre boxes [lo, hi] of the oracle's rectangles."""
+    ext = (np.abs(prox.axes.numpy()) * prox.half.numpy()[:, :, None]).sum(1) + 1e-3
+    m = prox.mean2d.numpy()
+    return m - ext - 0.5, m + ext - 0.5
+
+
+def _touching(prox, lo, hi, cam, pix):
+    """Indices of the Gaussians (kept or ambiguous) whose box holds a pixel of
+    `pix` (flat y * W + x), through a summed-area table of the pixel set."""
+    ind = np.zeros((cam.height + 1, cam.width + 1), np.int64)
+    ind[1:, 1:][pix // cam.width, pix % cam.width] = 1
+    sat = ind.cumsum(0).cumsum(1)
+    x0 = np.clip(np.ceil(lo[:, 0]), 0, cam.width).astype(int)
+    x1 = np.clip(np.floor(hi[:, 0]) + 1, 0, cam.width).astype(int)
+    y0 = np.clip(np.ceil(lo[:, 1]), 0, cam.height).astype(int)
+    y1 = np.clip(np.floor(hi[:, 1]) + 1, 0, cam.height).astype(int)
+    x1, y1 = np.maximum(x1, x0), np.maximum(y1, y0)
+    n_in = sat[y1, x1] - sat[y0, x1] - sat[y1, x0] + sat[y0, x0]
+    cand = (prox.valid | prox.ambiguous).numpy()
+    return np.nonzero(cand & (n_in > 0))[0]
 
 
 def test_gpu_finite_differences():

@@ -1,8 +1,14 @@
 """Forward parity: the HIP path (through the C ABI) against the CPU oracle.
 
 Bar: max-abs image error <= 1e-4 in float32 over the pixels the parity
-protocol keeps (pixels whose coverage decision lies within the measured
-proxy discrepancy of a rectangle edge are excluded and counted)."""
+protocol keeps. Both sides take every coverage and cull decision in double
+(or better) from the same float32 inputs; a pixel is excluded only where a
+decision lies within the protocol's fixed band of its threshold (2e-6 px at
+a rectangle edge, set by the oracle's own precision; the axes of near-circles
+to 1e-11 over their conditioning), and the exclusions are counted and
+bounded: none on the 128x128 scene, at most 1% on the sampled 1080p frame."""
+import dataclasses
+
 import numpy as np
 import pytest
 import torch
@@ -17,16 +23,15 @@ TOL = 1e-4
 
 
 def test_proxies_match_oracle():
+    """The GPU's double rectangles against the oracle's (long double) ones,
+    also for a rotated camera with an off-centre principal point."""
     scene, cams, opts = W.w1_small()
-    pe = proxy_error(scene, cams[0], opts)
-    log("[proxy] W1", pe)
-    assert pe["mismatch"] == 0
-    assert pe["centre"] < 1e-3 and pe["half"] < 1e-3 and pe["orient"] < 1e-5
+    tolerances(proxy_error(scene, cams[0], opts))
     scene2, cams2, opts2 = W.w2_clusters(n=100_000)
-    pe2 = proxy_error(scene2, cams2[0], opts2)
-    log("[proxy] W2 subset", pe2)
-    assert pe2["mismatch"] == 0
-    assert pe2["centre"] < 5e-3 and pe2["half"] < 5e-3 and pe2["orient"] < 1e-5
+    tolerances(proxy_error(scene2, cams2[0], opts2))
+    cam3 = W.camera_look_at((4.0, -3.0, -7.0), (0.5, 0.0, 0.2), (0.2, 1.0, 0.1), 640, 400)
+    cam3 = dataclasses.replace(cam3, cx=0.37 * cam3.width, cy=0.58 * cam3.height)
+    tolerances(proxy_error(scene2, cam3, opts2))
 
 
 @pytest.mark.parametrize("k_mom", [4, 6, 8])
@@ -82,18 +87,18 @@ def _sample_pixels(scene, cam, n_random=150, n_dense=150, seed=0):
 @pytest.mark.parametrize("k_mom", [4, 6, 8])
 def test_w2_full_size_sampled(k_mom):
     """500k Gaussians at 1920x1080 in the launch configuration the benchmark
-    times (the list count on the device); the oracle computes a sample of
-    pixels one by one."""
+    times (the list count on the device); the oracle computes 20,000 sampled
+    pixels, half uniform over the frame, half at projected Gaussian means."""
     scene, cams, opts = W.w2_clusters(n_moments=k_mom)
     cam = cams[0]
     img, saved, st = gpu_render(scene, cams, opts, on_device=True)
-    pix = _sample_pixels(scene, cam)
-    pe = proxy_error(scene, cam, opts)
-    log(f"[w2 K={k_mom}] proxy", pe)
-    tol_m, tol_o = tolerances(pe)
-    ref = oracle.render_image(scene, cam, opts, pixels=pix, margin_tol=tol_m, orient_eps=tol_o)
+    pix = _sample_pixels(scene, cam, n_random=10_000, n_dense=10_000)
+    assert len(pix) >= 19_000
+    tol_m, tol_o = tolerances(proxy_error(scene, cam, opts))
+    ref = oracle.render_image(scene, cam, opts, pixels=pix, margin_tol=tol_m, orient_eps=tol_o,
+                              max_pixels=len(pix))
     log(f"[w2 K={k_mom}] entries={st.entry_count()} sampled={len(pix)} pairs={ref['n_pairs']}")
-    mx, worst = compare(img[0].reshape(-1, 3)[pix], ref, f"W2 K={k_mom}")
+    mx, worst = compare(img[0].reshape(-1, 3)[pix], ref, f"W2 K={k_mom}", max_excluded=0.01)
     assert mx <= TOL
 
 

@@ -46,10 +46,11 @@ def test_w5_batched_forward_backward():
     d = float((alone[0] - img[ci]).abs().max())
     log(f"[w5] camera {ci}: batched vs alone max diff {d:.3e}")
     assert d == 0.0
-    pix = _sample_pixels(scene, cam, n_random=40, n_dense=40, seed=5)
-    pe = proxy_error(scene, cam, opts)
-    tol_m, tol_o = tolerances(pe)
+    pix = _sample_pixels(scene, cam, n_random=1000, n_dense=1000, seed=5)
+    assert len(pix) >= 1900
+    tol_m, tol_o = tolerances(proxy_error(scene, cam, opts))
     ref = oracle.render_image(scene, cam, opts, pixels=pix, margin_tol=tol_m, orient_eps=tol_o)
     log(f"[w5] camera {ci}: sampled {len(pix)} pixels, {ref['n_pairs']} pairs")
-    mx, _ = compare(img[ci].cpu().numpy().astype(np.float64).reshape(-1, 3)[pix], ref, "W5 camera 2")
+    mx, _ = compare(img[ci].cpu().numpy().astype(np.float64).reshape(-1, 3)[pix], ref, "W5 camera 2",
+                    max_excluded=0.01)
     assert mx <= TOL

@@ -227,6 +227,104 @@ def test_tau_monotone_and_bounded():
             assert tau.min() >= -1e-12 and tau.max() <= m[0].item() * (1 + 1e-12)
 
 
+def _atoms(n, seed):
+    rng = np.random.default_rng(seed)
+    x = np.sort(rng.uniform(-1.5, 1.5, n))
+    while np.diff(x).min() < 0.3:
+        x = np.sort(rng.uniform(-1.5, 1.5, n))
+    w = rng.uniform(0.2, 1, n)
+    return x, w / w.sum()
+
+
+@pytest.mark.parametrize("n", [2, 3, 4])
+def test_degenerate_measure_is_mixed_with_its_normal(n):
+    """Reading for degenerate measures (oracle.bounds.degenerate_mixture): an
+    n-atom measure has a singular (n+1)x(n+1) Hankel matrix, so it is flagged
+    and replaced by (1 - eps) mu + eps N(mean, var). The mixture's moments
+    match numerical integration of that mixture; its bounds bracket the
+    mixture's own distribution function (Sec. 3.2: the bounds hold for every
+    measure with these moments), are O(eps) apart away from the atoms, and
+    are within O(eps) of the atoms' step function."""
+    from oracle.bounds import MIX_EPS, degenerate_mixture
+    from scipy.stats import norm
+    x, w = _atoms(n, 40 + n)
+    b = np.array([(w * x ** k).sum() for k in range(2 * n + 1)])
+    bu, eps = degenerate_mixture(_t(b)[None], n)
+    assert eps.item() == MIX_EPS[0]
+    e = eps.item()
+    mean, sd = b[1], math.sqrt(b[2] - b[1] ** 2)
+    for k in range(2 * n + 1):
+        nk = integrate.quad(lambda y: y ** k * norm.pdf(y, mean, sd), -np.inf, np.inf,
+                            epsabs=1e-13, epsrel=1e-12)[0]
+        assert bu[0, k].item() == pytest.approx((1 - e) * b[k] + e * nk, rel=1e-10, abs=1e-12)
+    etas = np.concatenate([(x[:-1] + x[1:]) / 2, [x[0] - 0.4, x[-1] + 0.4]])
+    m0 = 1.7
+    tau, lo, up = bound_tau(_t(m0 * b)[None].expand(len(etas), -1), _t(etas), n, 0.25)
+    lo, up = lo.numpy(), up.numpy()
+    step = np.array([w[x < eta].sum() for eta in etas])
+    f_mix = (1 - e) * step + e * norm.cdf(etas, mean, sd)
+    assert np.all(lo <= f_mix + 1e-12) and np.all(f_mix <= up + 1e-12)
+    # U - L is the Christoffel function at eta, the least integral of p^2 over
+    # polynomials of degree n with p(eta) = 1; p = prod (y - x_i) / prod (eta - x_i)
+    # vanishes on the atoms, so U - L <= eps E_N[p^2]
+    for i, eta in enumerate(etas):
+        p2 = integrate.quad(lambda y: np.prod((y - x) / (eta - x)) ** 2 * norm.pdf(y, mean, sd),
+                            -np.inf, np.inf, epsabs=1e-14, epsrel=1e-10)[0]
+        assert up[i] - lo[i] <= e * p2 * (1 + 1e-9)
+        assert abs(lo[i] - step[i]) <= e * p2 + e
+
+
+def test_measures_of_gaussian_sums_are_not_degenerate():
+    """The rule leaves the bounds of sums of moderately wide Gaussians alone."""
+    from oracle.bounds import degenerate_mixture
+    rng = np.random.default_rng(17)
+    grid = np.linspace(-4, 4, 4001)
+    for n in (2, 3, 4):
+        for _ in range(5):
+            dens = sum(rng.uniform(0.1, 1) * np.exp(-(grid - rng.uniform(-2, 2)) ** 2
+                                                     / rng.uniform(0.1, 0.5)) for _ in range(4))
+            b = np.array([(dens * grid ** k).sum() for k in range(2 * n + 1)])
+            _, eps = degenerate_mixture(_t(b / b[0])[None], n)
+            assert eps.item() == 0.0
+
+
+def test_degenerate_rule_is_invariant_under_affine_moment_variable():
+    """The decision and the mixture commute with an increasing affine map of
+    the moment variable, so the bounds do not depend on the pixel's basis."""
+    n = 3
+    x, w = _atoms(n, 7)
+    a_, c_ = 2.7, -0.8
+    b = np.array([(w * x ** k).sum() for k in range(2 * n + 1)])
+    b2 = np.array([(w * (a_ * x + c_) ** k).sum() for k in range(2 * n + 1)])
+    etas = np.array([-1.2, 0.1, 0.9, 1.4])
+    t1, _, _ = bound_tau(_t(b)[None].expand(4, -1), _t(etas), n, 0.25)
+    t2, _, _ = bound_tau(_t(b2)[None].expand(4, -1), _t(a_ * etas + c_), n, 0.25)
+    assert np.abs(t1.numpy() - t2.numpy()).max() < 1e-9
+
+
+def test_gradient_through_the_degenerate_mixture_vs_central_differences():
+    n = 3
+    x, w = _atoms(n, 9)
+    m = _t(1.3 * np.array([(w * x ** k).sum() for k in range(2 * n + 1)]))
+    etas = _t([-0.7, 0.2, 1.1])
+    mt = m.clone().requires_grad_(True)
+    tau, _, _ = bound_tau(mt[None].expand(3, -1), etas, n, 0.25)
+    gw = _t([0.3, -1.1, 0.7])
+    (g,) = torch.autograd.grad((tau * gw).sum(), mt)
+    # the near-atomic measure is sharply curved: central differences converge
+    # as h^2 (4e-5, 4e-7, 1e-8 relative at h = 1e-6, 1e-7, 1e-8)
+    h = 1e-8
+    fd = []
+    for k in range(2 * n + 1):
+        mp, mm = m.clone(), m.clone()
+        mp[k] += h
+        mm[k] -= h
+        fp = (bound_tau(mp[None].expand(3, -1), etas, n, 0.25)[0] * gw).sum().item()
+        fm = (bound_tau(mm[None].expand(3, -1), etas, n, 0.25)[0] * gw).sum().item()
+        fd.append((fp - fm) / (2 * h))
+    assert np.abs(np.array(fd) - g.numpy()).max() <= 1e-6 * np.abs(g.numpy()).max()
+
+
 # ---------------------------------------------------------------------------
 # App. B quadrature.
 # ---------------------------------------------------------------------------
@@ -553,13 +651,14 @@ def test_single_colour_scene_renders_exact_opacity(k_mom):
 def test_single_gaussian_renders_eq16_opacity():
     scene = _tiny_scene(2, 1, rgb=np.array([1.0, 1.0, 1.0]))
     cam = W.camera_on_axis(2.0, 16, 16)
-    r = oracle.render_image(scene, cam, W.Options(full_coverage=True))
+    opts = W.Options(full_coverage=True)
+    r = oracle.render_image(scene, cam, opts)
     op = -np.expm1(-r["moments"][:, 0])
-    ok = r["opacity"] >= 1e-6
+    ok = r["opacity"] >= opts.eps
     assert ok.sum() > 100
     assert np.allclose(r["image"][ok, 0], op[ok], rtol=1e-12, atol=1e-15)
     # where O < eps Eq. 15 divides by eps instead
-    assert np.allclose(r["image"][~ok, 0], op[~ok] * r["s_rgb"][~ok, 0] / 1e-6, rtol=1e-12, atol=1e-300)
+    assert np.allclose(r["image"][~ok, 0], op[~ok] * r["s_rgb"][~ok, 0] / opts.eps, rtol=1e-12, atol=1e-300)
 
 
 def test_image_is_invariant_to_gaussian_order():

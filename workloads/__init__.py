@@ -90,6 +90,11 @@ class Options:
     eps: float = 1e-6           # clamp of Eq. 15's denominator
     full_coverage: bool = False  # debug: every Gaussian covers every pixel
 
+    def __post_init__(self):
+        # the library takes these constants as float32
+        for k in ("kappa", "conf_c", "beta", "eps"):
+            setattr(self, k, float(np.float32(getattr(self, k))))
+
 
 def intrinsics_for(width: int, height: int, vfov_deg: float = 60.0):
     """Pinhole intrinsics for a vertical field of view, square pixels,
