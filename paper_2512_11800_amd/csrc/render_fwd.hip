@@ -113,7 +113,9 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
   __shared__ uint8_t reach[kBlock];  // per staged entry: bit q set if its box reaches the tile's quadrant q
   // per-wave results of the queued pairs: 3 or K + 1 floats per pair in passes
   // 0 and 1, q (r, g, b, 1) in pass 2
-  __shared__ __align__(16) float wres[4][(K + 1) * 64];
+  // (K = 8 passes its moments in double: twice the room)
+  constexpr bool kDblMom = K >= 8;
+  __shared__ __align__(16) float wres[4][(K + 1) * 64 * (kDblMom ? 2 : 1)];
   WaveQueue& q = wq[wave];
   float* res = wres[wave];
   const int x0 = tx * kTile + (quad & 1) * 8, y0 = ty * kTile + (quad >> 1) * 8;
@@ -248,19 +250,27 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
       pp.p15 = from_lane(pb.p15, p);
       pp.amp = from_lane(pb.amp, p);
       const float lamp = from_lane(lam, p);
+      double* resd = reinterpret_cast<double*>(res);
       if (act) {
         RayG g = ray_of(j, p, lamp);
-        float m[K + 1];
-        particle_moments<K>(g, pp, tn, m);
+        if constexpr (kDblMom) {
+          double m[K + 1];
+          particle_moments_d<K>(g, pp, tn, m);
 #pragma unroll
-        for (int k = 0; k <= K; ++k) res[k * 64 + lane] = m[k];
+          for (int k = 0; k <= K; ++k) resd[k * 64 + lane] = m[k];
+        } else {
+          float m[K + 1];
+          particle_moments<K>(g, pp, tn, m);
+#pragma unroll
+          for (int k = 0; k <= K; ++k) res[k * 64 + lane] = m[k];
+        }
       }
       __builtin_amdgcn_wave_barrier();
       while (own) {
         const int i = __builtin_ctzll(own);
         own &= own - 1;
 #pragma unroll
-        for (int k = 0; k <= K; ++k) acc[k] += (double)res[k * 64 + i];
+        for (int k = 0; k <= K; ++k) acc[k] += kDblMom ? resd[k * 64 + i] : (double)res[k * 64 + i];
       }
       __builtin_amdgcn_wave_barrier();
     };
