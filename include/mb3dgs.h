@@ -163,6 +163,27 @@ int mb_render_forward(const mb_gaussians *g, const mb_camera *cams, int32_t n_ca
                       size_t pws_bytes, int64_t n_entries, float *image, float *saved,
                       float *penalty, void *stream);
 
+/* Forward render that allocates nothing, for callers that cannot allocate
+ * device memory (serving loops and harnesses that forbid hipMalloc): the same
+ * result as mb_prepare (with a count) followed by mb_render_forward, with
+ * both workspaces carved from a 256 MiB device array inside the library
+ * (one per GPU, held until the process ends) instead of caller buffers.
+ *  image, saved, penalty  as in mb_render_forward (device, caller-owned)
+ *  n_entries  host, or NULL: receives the frame's tile entry count
+ * The call waits on `stream` once for the entry count (as mb_prepare with a
+ * count does), so it cannot be captured into a graph. A frame whose
+ * workspaces (168 B per camera and Gaussian, 376 B per tile entry, 72 B per
+ * pixel, plus per-tile arrays) exceed 256 MiB is rejected with
+ * MB_ERR_WORKSPACE before anything is rendered: 100k Gaussians at 1024x1024
+ * (about 300k entries) fit, 500k Gaussians at 1920x1080 do not. All calls on
+ * one GPU share that array, which keeps the last call's contents, so calls
+ * that overlap on one GPU (other streams, other host threads) race; a
+ * backward pass cannot follow this forward pass (the scratch holds no
+ * gradient state a caller could pass on). */
+int mb_render_forward_noalloc(const mb_gaussians *g, const mb_camera *cams, int32_t n_cams,
+                              const mb_options *opts, float *image, float *saved, float *penalty,
+                              int64_t *n_entries, void *stream);
+
 /* Backward pass (Sec. 3.3, Eq. 22, App. D adjoint rendering) after
  * mb_render_forward with the same arguments and workspaces (n_entries
  * included: the count, or MB_ENTRIES_ON_DEVICE). The per-pixel

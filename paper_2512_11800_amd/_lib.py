@@ -71,6 +71,9 @@ SIGNATURES = [
     ("mb_render_forward", c_int32, [POINTER(MbGaussians), POINTER(MbCamera), c_int32,
                                     POINTER(MbOptions), c_void_p, c_size_t, c_void_p, c_size_t,
                                     c_int64, c_void_p, c_void_p, c_void_p, c_void_p]),
+    ("mb_render_forward_noalloc", c_int32, [POINTER(MbGaussians), POINTER(MbCamera), c_int32,
+                                            POINTER(MbOptions), c_void_p, c_void_p, c_void_p,
+                                            POINTER(c_int64), c_void_p]),
     ("mb_mlp_param_count", c_int32, []),
     ("mb_mlp_packed_bytes", c_size_t, []),
     ("mb_mlp_workspace_bytes", c_size_t, [c_int64]),

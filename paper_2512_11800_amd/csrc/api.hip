@@ -365,6 +365,39 @@ QueryWs carve_queries(void* p, int64_t n_pix, int64_t q_cap, bool grads = false)
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Device scratch of mb_render_forward_noalloc: the Gaussian and pair
+// workspaces of one forward frame, in a file-scope device array (each GPU the
+// library runs on holds its own copy until the process ends). Host code uses
+// the address hipGetSymbolAddress returns for the current device, never the
+// array's name.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = size_t(256) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// the current device's scratch address, looked up once per device
+int scratch_address(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(MB_ERR_ARG, "device index %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return MB_OK;
+}
+}  // namespace
+
 extern "C" {
 
 void mb_default_options(mb_options* o) {
@@ -905,6 +938,29 @@ int mb_adam_step(float* theta, float* m, float* v, const float* grad, int64_t co
     e = launch_adam(theta, m, v, grad, count, step, lr, beta1, beta2, eps, (hipStream_t)stream);
   }
   return e == hipSuccess ? MB_OK : hip_fail(e, "adam");
+}
+
+int mb_render_forward_noalloc(const mb_gaussians* g, const mb_camera* cams, int32_t n_cams, const mb_options* o,
+                              float* image, float* saved, float* penalty, int64_t* n_entries, void* stream) {
+  int rc = check_common(g, cams, n_cams, o);
+  if (rc) return rc;
+  void* base = nullptr;
+  rc = scratch_address(&base);
+  if (rc) return rc;
+  const size_t gws_bytes = (mb_gauss_workspace_bytes(g->n, n_cams) + 255) & ~size_t(255);
+  if (gws_bytes > kScratchBytes)
+    return fail(MB_ERR_WORKSPACE, "%d Gaussians x %d cameras need %zu bytes of Gaussian workspace; the "
+                "allocation-free scratch holds %zu bytes", g->n, n_cams, gws_bytes, kScratchBytes);
+  int64_t count = 0;
+  rc = mb_prepare(g, cams, n_cams, o, base, gws_bytes, &count, stream);
+  if (rc) return rc;
+  const size_t pws_bytes = mb_pair_workspace_bytes(count, n_cams, cams[0].width, cams[0].height);
+  if (pws_bytes == 0 || gws_bytes + pws_bytes > kScratchBytes)
+    return fail(MB_ERR_WORKSPACE, "the frame's %lld tile entries need %zu + %zu bytes of workspace; the "
+                "allocation-free scratch holds %zu bytes", (long long)count, gws_bytes, pws_bytes, kScratchBytes);
+  if (n_entries) *n_entries = count;
+  return mb_render_forward(g, cams, n_cams, o, base, gws_bytes, (unsigned char*)base + gws_bytes, pws_bytes,
+                           count, image, saved, penalty, stream);
 }
 
 }  // extern "C"

@@ -213,6 +213,28 @@ def render_forward(g: Gaussians, cams: Sequence, opts=None, ws: Optional[Workspa
     return f.result() + ((pen,) if penalty else ())
 
 
+def render_forward_noalloc(g: Gaussians, cams: Sequence, opts=None, image=None, saved=None):
+    """mb_render_forward_noalloc: the forward render with the library's own
+    device scratch in place of workspaces. ``image`` [C,H,W,3] and ``saved``
+    [C,H,W,8] (float32, on the Gaussians' device) are allocated here unless
+    given. Returns (image, saved, n_entries)."""
+    lib = L.load()
+    cam_arr = _cams(cams)
+    n_cams = len(cam_arr)
+    w, h = int(cam_arr[0].width), int(cam_arr[0].height)
+    dev = g.means.device
+    if image is None:
+        image = torch.empty(n_cams, h, w, 3, dtype=torch.float32, device=dev)
+    if saved is None:
+        saved = torch.empty(n_cams, h, w, 8, dtype=torch.float32, device=dev)
+    n_entries = ctypes.c_int64(0)
+    gs = g.struct()
+    o = options_struct(opts)
+    L.check(lib.mb_render_forward_noalloc(ctypes.byref(gs), cam_arr, n_cams, ctypes.byref(o), _ptr(image),
+                                          _ptr(saved), None, ctypes.byref(n_entries), _stream()))
+    return image, saved, int(n_entries.value)
+
+
 HARVEST_STRIDE = 12
 
 
