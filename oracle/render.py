@@ -23,6 +23,7 @@ from .geometry import DT, camera_matrices, pixel_directions, quat_to_rot, ray_ga
 from .moments import particle_moments, warp
 from .proxy import MARGIN_TOL, ORIENT_EPS, covering_pairs, screen_proxy
 from .quadrature import consistency_penalty, particle_quadrature, rescale
+from .trig import angle_of, degenerate_flags, particle_trig_moments, trig_bound_tau
 
 PARAMS = ("means", "scales", "quats", "densities", "colors")
 
@@ -100,11 +101,14 @@ def render_pixels(scene_t, scene, cam, opts, px: torch.Tensor, py: torch.Tensor,
     mu, sigma, omega = ray_gaussian(origin, d, means[gid], rot, scene_t["scales"][gid],
                                     scene_t["densities"][gid])
 
+    n_edge = opts.n_intervals + 1
+    if getattr(opts, "basis", "power") == "trigonometric":
+        return _render_pixels_trig(scene_t, cam, opts, n_pix, slot, gid, amb, mu, sigma, omega,
+                                   rgb_all, tau_model)
     centre, scale = _standardised_basis(slot, mu, sigma, omega, t_near, n_pix)
     mom_pair = particle_moments(mu, sigma, omega, t_near, k_mom, centre[slot], scale[slot])
     mom = torch.zeros(n_pix, k_mom + 1, dtype=DT).index_add(0, slot, mom_pair)
 
-    n_edge = opts.n_intervals + 1
     mom_q = mom[slot].repeat_interleave(n_edge, dim=0)
 
     def tau_at(y):
@@ -144,6 +148,63 @@ def render_pixels(scene_t, scene, cam, opts, px: torch.Tensor, py: torch.Tensor,
         _, eps = degenerate_mixture(b, n_half)
         fallback = live & (eps != 0)
     return PixelResult(image, s_rgb, o, mom, centre, scale, amb, int(slot.shape[0]),
+                       slot, gid, q, y_e, tau_e, penalty, fallback)
+
+
+def _render_pixels_trig(scene_t, cam, opts, n_pix, slot, gid, amb, mu, sigma, omega, rgb_all,
+                        tau_model=None) -> PixelResult:
+    """render_pixels with the trigonometric moments of Eqs. 13-14 and the
+    bounds on the circle (oracle.trig): the query of an edge at depth t is
+    the angle (2 pi - theta) g_hat(t); nothing else changes. ``moments`` holds
+    m~_0, then the real and imaginary parts of m~_1..m~_n (K + 1 reals)."""
+    if tau_model is not None:
+        raise ValueError("the learned surrogate takes power moments")
+    n_half = opts.n_moments // 2
+    t_near = cam.t_near
+    n_edge = opts.n_intervals + 1
+    mom_pair = particle_trig_moments(mu, sigma, omega, t_near, n_half)
+    mom_c = torch.zeros(n_pix, n_half + 1, dtype=mom_pair.dtype).index_add(0, slot, mom_pair)
+    mom_q = mom_c[slot].repeat_interleave(n_edge, dim=0)
+
+    def tau_at(psi):
+        tau, _, _ = trig_bound_tau(mom_q, psi.reshape(-1), n_half, opts.beta)
+        tau = tau.reshape(psi.shape)
+        # non-decreasing along the edges (the circle's estimates need not grow
+        # with depth): a later edge takes over only when strictly larger
+        run = [tau[..., 0]]
+        for e in range(1, tau.shape[-1]):
+            run.append(torch.where(tau[..., e] > run[-1], tau[..., e], run[-1]))
+        return torch.stack(run, dim=-1)
+
+    def to_angle(t):
+        return angle_of(t, t_near)
+
+    if slot.shape[0] > 0:
+        q, tau_e, t_e = particle_quadrature(mu, sigma, omega, tau_at, t_near, opts.kappa,
+                                            opts.n_intervals, to_angle)
+        y_e = to_angle(t_e)
+        pen_pair = consistency_penalty(mu, sigma, omega, tau_e, t_e)
+    else:
+        q = torch.zeros(0, dtype=DT)
+        pen_pair = torch.zeros(0, dtype=DT)
+        tau_e = y_e = torch.zeros(0, n_edge, dtype=DT)
+    penalty = torch.zeros(n_pix, dtype=DT).index_add(0, slot, pen_pair)
+    s_rgb = torch.zeros(n_pix, 3, dtype=DT).index_add(0, slot, q[:, None] * rgb_all[gid])
+    o = torch.zeros(n_pix, dtype=DT).index_add(0, slot, q)
+    m0 = mom_c[:, 0].real
+    image = rescale(m0, s_rgb, o, opts.eps, cam.background)
+    parts = [m0]
+    for k in range(1, n_half + 1):
+        parts += [mom_c[:, k].real, mom_c[:, k].imag]
+    mom = torch.stack(parts, dim=-1)
+    with torch.no_grad():
+        live = m0.detach() > 1e-20
+        unit = torch.zeros_like(mom_c)
+        unit[:, 0] = 1.0
+        eps = degenerate_flags(torch.where(live[:, None], mom_c.detach(), unit), n_half)
+        fallback = live & (eps != 0)
+    zeros = torch.zeros(n_pix, dtype=DT)
+    return PixelResult(image, s_rgb, o, mom, zeros, zeros + 1.0, amb, int(slot.shape[0]),
                        slot, gid, q, y_e, tau_e, penalty, fallback)
 
 

@@ -1305,3 +1305,165 @@ def test_ssim_identity_symmetry_and_gradient():
         xm = x.copy(); xm[idx] -= h
         fd = (Ls.dssim(xp, y) - Ls.dssim(xm, y)) / (2 * h)
         assert gx[idx] == pytest.approx(fd, rel=1e-5, abs=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Trigonometric moments (Sec. 3.2, Eqs. 13-14, App. C) and bounds on the circle.
+# ---------------------------------------------------------------------------
+
+def test_trig_zeroth_moment_is_the_exact_optical_depth():
+    from oracle.trig import particle_trig_moments
+    rng = np.random.default_rng(21)
+    mu, sig, om = _t(rng.uniform(-0.5, 6, 20)), _t(rng.uniform(0.02, 1.0, 20)), _t(rng.lognormal(0, 1, 20))
+    tn = 0.2
+    m = particle_trig_moments(mu, sig, om, tn, 3)
+    for i in range(20):
+        ref = integrate.quad(lambda t: om[i].item() * math.exp(-(t - mu[i].item()) ** 2 / (2 * sig[i].item() ** 2)),
+                             tn, np.inf, epsabs=1e-13, epsrel=1e-11)[0]
+        assert m[i, 0].real.item() == pytest.approx(ref, rel=1e-9, abs=1e-14)
+        assert m[i, 0].imag.item() == 0.0
+
+
+def test_trig_moment_closed_form_with_exact_erf_integrates_the_linearised_warp():
+    """Eq. 14 with the complex erf evaluated exactly equals numerical
+    integration of e^{i k (2 pi - theta)(G + G' (t - mu))} sigma(t) over
+    [t_n, inf): the completion of the square and the t_f -> inf limit of the
+    appendix's derivation."""
+    from oracle.moments import warp, warp_prime
+    from oracle.trig import THETA, particle_trig_moments
+    rng = np.random.default_rng(22)
+    tn = 0.2
+    for _ in range(12):
+        mu, sig, om = rng.uniform(-0.3, 5), rng.uniform(0.05, 1.5), rng.lognormal(0, 1)
+        m = particle_trig_moments(_t([mu]), _t([sig]), _t([om]), tn, 3, exact_erf=True)[0]
+        ms = max(mu, tn)
+        gp = warp_prime(_t(ms), tn).item()
+        g = warp(_t(ms), tn).item() + gp * (mu - ms)
+        for k in range(4):
+            a = k * (2 * math.pi - THETA)
+            f = lambda t, part: om * math.exp(-(t - mu) ** 2 / (2 * sig * sig)) * part(a * (g + gp * (t - mu)))
+            re = integrate.quad(lambda t: f(t, math.cos), tn, mu + 40 * sig + 1, limit=400, epsabs=1e-13)[0]
+            im = integrate.quad(lambda t: f(t, math.sin), tn, mu + 40 * sig + 1, limit=400, epsabs=1e-13)[0]
+            assert m[k].real.item() == pytest.approx(re, rel=1e-7, abs=1e-11)
+            assert m[k].imag.item() == pytest.approx(im, rel=1e-7, abs=1e-11)
+
+
+def test_trig_first_order_erf_error_is_second_order_and_local():
+    """App. C's first-order expansion of erf in the imaginary direction: the
+    error of 1 - erf(a - i b) shrinks at least as b^2 (halving b at least
+    quarters it) and carries the factor e^{-a^2} (it fades away from the
+    near bound)."""
+    from scipy.special import erf as cerf
+    for a in (-1.0, -0.3, 0.0, 0.4, 1.2):
+        errs = []
+        for b in (0.08, 0.04, 0.02):
+            exact = 1 - cerf(a - 1j * b)
+            approx = math.erfc(a) + 1j * b * 2 / math.sqrt(math.pi) * math.exp(-a * a)
+            errs.append(abs(exact - approx))
+        # at least second order (third where erf'' vanishes, at a = 0)
+        assert errs[1] / errs[0] <= 0.27 and errs[2] / errs[1] <= 0.27
+        # |second derivative of erf| = (4 / sqrt(pi)) |a| e^{-a^2}; the next term is b^3 order
+        assert errs[0] <= 0.08 ** 2 / 2 * (4 / math.sqrt(math.pi)) * (abs(a) + 0.1) * math.exp(-a * a) + 1e-3
+
+
+def _circle_measure(n_atoms, seed, arc=(0.0, 1.8 * math.pi)):
+    rng = np.random.default_rng(seed)
+    phi = np.sort(rng.uniform(*arc, n_atoms))
+    while np.diff(phi).min() < 0.2:
+        phi = np.sort(rng.uniform(*arc, n_atoms))
+    w = rng.uniform(0.2, 1, n_atoms)
+    return phi, w / w.sum()
+
+
+def _trig_moments_of(phi, w, n):
+    return np.array([(w * np.exp(1j * k * phi)).sum() for k in range(n + 1)])
+
+
+@pytest.mark.parametrize("n", [2, 3])
+def test_circle_canonical_representation_recovers_atomic_measure(n):
+    """n + 1 atoms on the circle queried at one of them: the canonical
+    representation is the measure itself (uniqueness of the Szego quadrature
+    through a point)."""
+    from oracle.trig import circle_canonical
+    phi, w = _circle_measure(n + 1, 30 + n)
+    c = torch.as_tensor(_trig_moments_of(phi, w, n))
+    for j in range(n + 1):
+        z, lam = circle_canonical(c[None], torch.as_tensor([np.exp(1j * phi[j])]), n)
+        ang = np.mod(np.angle(z[0].numpy()), 2 * np.pi)
+        order = np.argsort(ang)
+        assert np.abs(ang[order] - phi).max() < 1e-9
+        assert np.abs(lam[0].numpy()[order] - w).max() < 1e-9
+
+
+@pytest.mark.parametrize("n", [2, 3])
+def test_circle_nodes_on_the_circle_reproduce_the_moments(n):
+    """For a measure with more than n + 1 atoms (positive definite Toeplitz
+    matrix) the kernel polynomial's zeros lie on the unit circle and the
+    atoms with their Christoffel weights reproduce c_0..c_n."""
+    from oracle.trig import circle_canonical
+    phi, w = _circle_measure(7, 40 + n)
+    c = torch.as_tensor(_trig_moments_of(phi, w, n))
+    for psi in (0.3, 2.0, 4.1, 5.5):
+        z, lam = circle_canonical(c[None], torch.as_tensor([np.exp(1j * psi)]), n)
+        zz, ll = z[0].numpy(), lam[0].numpy()
+        assert np.abs(np.abs(zz) - 1).max() < 1e-10
+        assert np.all(ll > 0)
+        for k in range(n + 1):
+            assert abs((ll * zz ** k).sum() - c[k].item()) < 1e-10
+
+
+@pytest.mark.parametrize("n", [2, 3])
+def test_circle_query_weight_is_the_largest_point_mass(n):
+    """U - L, the weight at the query, is the Christoffel number: the least
+    integral of |p|^2 over polynomials of degree n with p(w) = 1 (solved as
+    least squares on the measure's atoms) and the largest mass any measure on
+    the circle with these moments can put at w (linear programming over a
+    grid of the circle through w)."""
+    from oracle.trig import circle_canonical
+    phi, w = _circle_measure(9, 50 + n)
+    c = _trig_moments_of(phi, w, n)
+    for psi in (1.0, 3.3):
+        z, lam = circle_canonical(torch.as_tensor(c)[None], torch.as_tensor([np.exp(1j * psi)]), n)
+        v = np.exp(1j * np.outer(phi, np.arange(n + 1)))
+        vw = np.exp(1j * psi * np.arange(n + 1))
+        g = (v.conj().T * w) @ v
+        a = np.linalg.solve(g, vw.conj())
+        a /= vw @ a
+        assert lam[0, 0].item() == pytest.approx(np.real(a.conj() @ g @ a), rel=1e-9)
+        grid = np.mod(psi + np.linspace(0, 2 * math.pi, 2401)[:-1], 2 * math.pi)  # grid[0] = psi
+        a_eq = np.vstack([np.cos(np.outer(np.arange(n + 1), grid)),
+                          np.sin(np.outer(np.arange(1, n + 1), grid))])
+        b_eq = np.concatenate([c.real, c.imag[1:]])
+        obj = np.zeros(len(grid))
+        obj[0] = -1.0
+        lp = linprog(obj, A_eq=a_eq, b_eq=b_eq, bounds=(0, None), method="highs")
+        assert lp.status == 0
+        assert -lp.fun == pytest.approx(lam[0, 0].item(), rel=1e-3)
+
+
+def test_circle_estimates_bracket_a_measure_whose_nodes_it_is():
+    """With the query at one of n + 1 atoms of a depth measure, L and U are
+    the measure's mass before the atom and through it (the estimate is exact
+    there; the ordering starts at the wrapping zone)."""
+    from oracle.trig import THETA, trig_bound_tau
+    n = 3
+    phi, w = _circle_measure(n + 1, 77, arc=(0.1, 2 * math.pi - THETA - 0.1))
+    m = torch.as_tensor(1.3 * _trig_moments_of(phi, w, n))
+    for j in range(n + 1):
+        tau, lo, up = trig_bound_tau(m[None], _t([phi[j]]), n, 0.25)
+        assert lo.item() == pytest.approx(w[:j].sum(), abs=1e-9)
+        assert up.item() == pytest.approx(w[:j + 1].sum(), abs=1e-9)
+
+
+def test_trig_single_colour_scene_renders_exact_opacity():
+    """Eq. 15 with trigonometric moments: a single-colour scene renders
+    c (1 - e^{-m_0}) + e^{-m_0} bg, whatever the reconstruction."""
+    scene = _tiny_scene(4, 6, rgb=np.array([0.3, 0.6, 0.9]))
+    cam = W.camera_on_axis(2.5, 24, 24)
+    opts = W.Options(n_moments=4, basis="trigonometric")
+    r = oracle.render_image(scene, cam, opts)
+    m0 = r["moments"][:, 0]
+    ok = r["opacity"] >= opts.eps
+    expect = np.array([0.3, 0.6, 0.9])[None] * (1 - np.exp(-m0))[:, None]
+    assert ok.sum() > 50
+    assert np.allclose(r["image"][ok], expect[ok], atol=1e-12)

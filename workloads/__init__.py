@@ -89,6 +89,7 @@ class Options:
     beta: float = 0.25          # bound interpolation, Sec. 3.2
     eps: float = 1e-6           # clamp of Eq. 15's denominator
     full_coverage: bool = False  # debug: every Gaussian covers every pixel
+    basis: str = "power"        # moment basis: "power" (Eqs. 10-12) or "trigonometric" (Eqs. 13-14)
 
     def __post_init__(self):
         # the library takes these constants as float32
