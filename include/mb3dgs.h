@@ -82,7 +82,9 @@ typedef struct mb_options {
   float conf_c;        /* confidence level c of the proxy, App. D (0.01)     */
   float beta;          /* interpolation between the bounds, Sec. 3.2 (0.25)  */
   float eps;           /* clamp of Eq. 15's denominator (1e-6)               */
-  int32_t recon;       /* reserved, 0 (the surrogate has its own entry point) */
+  int32_t basis;       /* moment basis: 0 power moments (Eqs. 10-12), 1
+                          trigonometric moments (Eqs. 13-14; forward only,
+                          n_moments = 4, i.e. two complex moments)        */
   const void *surrogate; /* reserved, NULL                                   */
   int32_t full_coverage; /* debug: every Gaussian covers every pixel        */
   int32_t reserved;
@@ -266,6 +268,28 @@ int mb_render_forward_surrogate(const mb_gaussians *g, const mb_camera *cams, in
                                 size_t pws_bytes, int64_t n_entries, const void *mlp_packed,
                                 void *qws, size_t qws_bytes, int64_t query_capacity,
                                 float *image, float *saved, void *stream);
+
+/* The tabulated schedule of the reconstruction (not part of the paper): per
+ * pixel, the normalised optical depth F is evaluated at n_nodes equally
+ * spaced nodes z_g of the standardised query on [-4, 4] (the query mapped by
+ * the mean and standard deviation of the pixel's normalised measure in its
+ * moment variable), and every quadrature edge interpolates that table
+ * linearly at its own standardised query, clamped to the table's ends; the
+ * optical depth along a Gaussian's edges is then made non-decreasing
+ * (running maximum). F at the nodes is the moment bounds' interpolation of
+ * Sec. 3.2 (mlp_packed NULL; n_moments 4 or 6) or the learned surrogate
+ * (mlp_packed from mb_mlp_pack; n_moments 6), so the two reconstructions run
+ * in the same schedule. Otherwise as mb_render_forward (power moments; no
+ * penalty; saved[7] flags a degenerate measure only for the bounds).
+ *  n_nodes  2..256 (32 is the default of the bindings)
+ *  tws      device, mb_table_workspace_bytes(n_cams, width, height, n_nodes)
+ *           bytes: per pixel 12 floats of record and n_nodes of table */
+size_t mb_table_workspace_bytes(int32_t n_cams, int32_t width, int32_t height, int32_t n_nodes);
+int mb_render_forward_tabulated(const mb_gaussians *g, const mb_camera *cams, int32_t n_cams,
+                                const mb_options *opts, void *gws, size_t gws_bytes, void *pws,
+                                size_t pws_bytes, int64_t n_entries, const void *mlp_packed,
+                                int32_t n_nodes, void *tws, size_t tws_bytes, float *image,
+                                float *saved, void *stream);
 
 /* Backward pass through the surrogate render: the adjoint of
  * mb_render_forward_surrogate, after it, with the same arguments,

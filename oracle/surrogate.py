@@ -212,6 +212,56 @@ def exact_model(beta: float, max_z: float = MAX_Z):
     return model
 
 
+def bounds_model(n_half: int, beta: float):
+    """The moment bounds' interpolation of Sec. 3.2 (with the degenerate-
+    measure rule) in the (mom_q, y) -> tau form, for any number of moments
+    2 n_half: what the renderer uses when no model is given."""
+    from .bounds import bound_tau
+
+    def model(mom_q, y):
+        tau, _, _ = bound_tau(mom_q, y, n_half, beta)
+        return tau
+    return model
+
+
+TAB_NODES = 32
+TAB_Z = 4.0
+
+
+def tabulated(model, n_nodes: int = TAB_NODES, z_max: float = TAB_Z):
+    """A reconstruction evaluated once per pixel at n_nodes equally spaced
+    nodes z_g of the standardised query on [-z_max, z_max] (the table of the
+    pixel) and linearly interpolated at each query's standardised position,
+    clamped to the table's ends (an evaluation schedule, not in the paper:
+    it applies to the plain bounds and to the learned surrogate alike). The
+    nodes sit at y_g = mean + std z_g in the pixel's moment variable (mean and
+    std of its normalised measure), so the table does not depend on that
+    variable. ``model`` has the oracle renderer's (mom_q, y) -> tau form."""
+    import torch
+    zs = np.linspace(-z_max, z_max, n_nodes)
+
+    def tab_model(mom_q, y):
+        m = mom_q.detach().numpy() if hasattr(mom_q, "detach") else np.asarray(mom_q)
+        yy = y.detach().numpy() if hasattr(y, "detach") else np.asarray(y)
+        rows, inv = np.unique(m, axis=0, return_inverse=True)
+        inv = inv.reshape(-1)
+        m0 = np.where(rows[:, 0] > 0, rows[:, 0], 1.0)
+        mean = rows[:, 1] / m0
+        var = rows[:, 2] / m0 - mean * mean
+        std = np.sqrt(np.where(var > 0, var, 1.0))
+        node_y = mean[:, None] + std[:, None] * zs[None, :]
+        tau = model(torch.as_tensor(np.repeat(rows, n_nodes, axis=0)),
+                    torch.as_tensor(node_y.reshape(-1)))
+        f = tau.detach().numpy().reshape(len(rows), n_nodes) / m0[:, None]
+        z = np.clip((yy - mean[inv]) / std[inv], -z_max, z_max)
+        u = (z + z_max) / (2 * z_max) * (n_nodes - 1)
+        i0 = np.minimum(np.floor(u).astype(int), n_nodes - 2)
+        fr = u - i0
+        fq = (1 - fr) * f[inv, i0] + fr * f[inv, i0 + 1]
+        return torch.as_tensor(m[:, 0] * fq, dtype=torch.float64)
+    return tab_model
+
+
 # ---------------------------------------------------------------------------
 # Differentiable version (torch float64) for the gradient of a render through
 # the surrogate. The bf16 rounding points of the kernels are kept in the

@@ -4,10 +4,10 @@ include/mb3dgs.h, with a thin ctypes binding and a torch.autograd wrapper."""
 from ._lib import LIB_PATH, MbError, load
 from .render import (HARVEST_STRIDE, Gaussians, RenderState, Workspace, camera_struct,
                      options_struct, project, render, render_backward, render_forward,
-                     render_forward_harvest, render_forward_noalloc, render_forward_surrogate, render_backward_surrogate,
-                     render_surrogate)
+                     render_forward_harvest, render_forward_noalloc, render_forward_tabulated,
+                     render_forward_surrogate, render_backward_surrogate, render_surrogate)
 
 __all__ = ["LIB_PATH", "MbError", "load", "HARVEST_STRIDE", "Gaussians", "RenderState", "Workspace",
            "camera_struct", "options_struct", "project", "render", "render_backward",
-           "render_forward", "render_forward_harvest", "render_forward_noalloc", "render_forward_surrogate",
-           "render_backward_surrogate", "render_surrogate"]
+           "render_forward", "render_forward_harvest", "render_forward_noalloc", "render_forward_tabulated",
+           "render_forward_surrogate", "render_backward_surrogate", "render_surrogate"]

@@ -39,7 +39,7 @@ class MbCamera(ctypes.Structure):
 
 class MbOptions(ctypes.Structure):
     _fields_ = [("n_moments", c_int32), ("n_intervals", c_int32), ("kappa", c_float),
-                ("conf_c", c_float), ("beta", c_float), ("eps", c_float), ("recon", c_int32),
+                ("conf_c", c_float), ("beta", c_float), ("eps", c_float), ("basis", c_int32),
                 ("surrogate", c_void_p), ("full_coverage", c_int32), ("reserved", c_int32)]
 
 
@@ -74,6 +74,11 @@ SIGNATURES = [
     ("mb_render_forward_noalloc", c_int32, [POINTER(MbGaussians), POINTER(MbCamera), c_int32,
                                             POINTER(MbOptions), c_void_p, c_void_p, c_void_p,
                                             POINTER(c_int64), c_void_p]),
+    ("mb_table_workspace_bytes", c_size_t, [c_int32, c_int32, c_int32, c_int32]),
+    ("mb_render_forward_tabulated", c_int32, [POINTER(MbGaussians), POINTER(MbCamera), c_int32,
+                                              POINTER(MbOptions), c_void_p, c_size_t, c_void_p, c_size_t,
+                                              c_int64, c_void_p, c_int32, c_void_p, c_size_t, c_void_p,
+                                              c_void_p, c_void_p]),
     ("mb_mlp_param_count", c_int32, []),
     ("mb_mlp_packed_bytes", c_size_t, []),
     ("mb_mlp_workspace_bytes", c_size_t, [c_int64]),

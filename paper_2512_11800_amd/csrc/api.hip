@@ -188,7 +188,9 @@ int check_common(const mb_gaussians* g, const mb_camera* cams, int n_cams, const
   if (!(o->conf_c > 0.f && o->conf_c < 1.f)) return fail(MB_ERR_ARG, "conf_c must be in (0, 1)");
   if (!(o->kappa >= 1.f)) return fail(MB_ERR_ARG, "kappa must be >= 1");
   if (!(o->eps > 0.f)) return fail(MB_ERR_ARG, "eps must be positive");
-  if (o->recon != 0) return fail(MB_ERR_UNSUPPORTED, "recon %d not available in this entry point", o->recon);
+  if (o->basis != 0 && o->basis != 1) return fail(MB_ERR_ARG, "basis %d: 0 (power) or 1 (trigonometric)", o->basis);
+  if (o->basis == 1 && o->n_moments != 4)
+    return fail(MB_ERR_UNSUPPORTED, "trigonometric moments: n_moments 4 (two complex moments) only");
   int64_t keys = (int64_t)tiles_of(cams[0].width) * tiles_of(cams[0].height) * n_cams;
   if (keys >= (1ll << 30)) return fail(MB_ERR_ARG, "too many tiles");
   if ((int64_t)g->n * n_cams >= (1ll << 31)) return fail(MB_ERR_ARG, "too many Gaussian-camera pairs");
@@ -548,7 +550,7 @@ int mb_render_forward(const mb_gaussians* g, const mb_camera* cams, int32_t n_ca
   hipError_t e;
   {
     StageTimer t(S_RENDER_FWD, s);
-    e = launch_render_forward(f.ra, f.cs, o->n_moments, o->n_intervals, s);
+    e = launch_render_forward(f.ra, f.cs, o->n_moments, o->n_intervals, s, o->basis == 1 ? kModeTrig : kModePlain);
   }
   if (e != hipSuccess) return hip_fail(e, "render_forward");
   return MB_OK;
@@ -633,6 +635,58 @@ int mb_render_forward_surrogate(const mb_gaussians* g, const mb_camera* cams, in
     e = launch_render_consume(ra, f.cs, o->n_intervals, s);
   }
   if (e != hipSuccess) return hip_fail(e, "render_forward (surrogate quadrature)");
+  return MB_OK;
+}
+
+size_t mb_table_workspace_bytes(int32_t n_cams, int32_t width, int32_t height, int32_t n_nodes) {
+  if (n_cams < 1 || width <= 0 || height <= 0 || n_nodes < 2 || n_nodes > kTabMaxNodes) return 0;
+  const size_t n_pix = (size_t)n_cams * width * height;
+  Carver c(nullptr);
+  c.take<float>(n_pix * kPixFeat);
+  c.take<float>(n_pix * (size_t)n_nodes);
+  return c.off;
+}
+
+int mb_render_forward_tabulated(const mb_gaussians* g, const mb_camera* cams, int32_t n_cams, const mb_options* o,
+                                void* gws, size_t gws_bytes, void* pws, size_t pws_bytes, int64_t n_entries,
+                                const void* mlp_packed, int32_t n_nodes, void* tws, size_t tws_bytes, float* image,
+                                float* saved, void* stream) {
+  FwdSetup f;
+  int rc = forward_setup(g, cams, n_cams, o, gws, gws_bytes, pws, pws_bytes, n_entries, image, saved, f);
+  if (rc) return rc;
+  if (o->basis != 0) return fail(MB_ERR_UNSUPPORTED, "the tabulated schedule takes power moments (basis 0)");
+  if (mlp_packed && o->n_moments != 6) return fail(MB_ERR_ARG, "the surrogate takes n_moments = 6");
+  if (!mlp_packed && o->n_moments == 8) return fail(MB_ERR_UNSUPPORTED, "tabulated bounds: n_moments 4 or 6");
+  if (n_nodes < 2 || n_nodes > kTabMaxNodes) return fail(MB_ERR_ARG, "n_nodes must lie in [2, %d]", kTabMaxNodes);
+  const int64_t n_pix = (int64_t)n_cams * cams[0].width * cams[0].height;
+  const size_t need = mb_table_workspace_bytes(n_cams, cams[0].width, cams[0].height, n_nodes);
+  if (!tws || tws_bytes < need) return fail(MB_ERR_WORKSPACE, "table workspace needs %zu bytes, got %zu", need, tws_bytes);
+  Carver c(tws);
+  float* pixfeat = c.take<float>((size_t)n_pix * kPixFeat);
+  float* tab = c.take<float>((size_t)n_pix * n_nodes);
+  hipStream_t s = (hipStream_t)stream;
+  rc = build_lists(g, f.w, f.p, n_cams, f.ra.tiles_x, f.ra.tiles_y, o->full_coverage, n_entries, nullptr, s, false);
+  if (rc) return rc;
+  RenderArgs& ra = f.ra;
+  ra.pixfeat = pixfeat;
+  ra.tab = tab;
+  ra.tab_nodes = n_nodes;
+  hipError_t e;
+  {
+    StageTimer t(S_RENDER_FWD, s);
+    e = launch_render_forward(ra, f.cs, o->n_moments, o->n_intervals, s, mlp_packed ? kModeTabSur : kModeTabPlain);
+  }
+  if (e != hipSuccess) return hip_fail(e, "render_forward (tabulated schedule)");
+  if (mlp_packed) {
+    StageTimer t(S_MLP, s);
+    e = launch_mlp_table(mlp_packed, pixfeat, n_pix, n_nodes, tab, s);
+    if (e != hipSuccess) return hip_fail(e, "surrogate table");
+  }
+  {
+    StageTimer t(S_CONSUME, s);
+    e = launch_render_consume_tab(ra, f.cs, o->n_intervals, s);
+  }
+  if (e != hipSuccess) return hip_fail(e, "render_forward (tabulated quadrature)");
   return MB_OK;
 }
 
@@ -729,6 +783,7 @@ int mb_render_backward(const mb_gaussians* g, const mb_camera* cams, int32_t n_c
   int rc = check_backward_args(g, cams, n_cams, o, n_entries, saved, grad_image, g_means, g_scales, g_quats,
                                g_densities, g_colors, true);
   if (rc) return rc;
+  if (o->basis != 0) return fail(MB_ERR_UNSUPPORTED, "the backward pass takes power moments (basis 0)");
   return backward_common(g, cams, n_cams, o, gws, gws_bytes, pws, pws_bytes, n_entries, saved, grad_image,
                          grad_penalty, g_means, g_scales, g_quats, g_densities, g_colors, (hipStream_t)stream,
                          nullptr, nullptr, 0);

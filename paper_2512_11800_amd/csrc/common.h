@@ -28,9 +28,14 @@ constexpr float kSqrtHalfPi = 1.2533141373155003f;  // sqrt(pi/2)
 constexpr float kInvSqrt2 = 0.7071067811865476f;
 constexpr double kMinDepth = 1e-20;  // optical depth below which a pixel is empty
 // surrogate: per-pixel record (6 features, m0, basis centre, basis scale,
-// covering count) and harvested training sample (6 features, query, m0,
+// covering count, mean and standard deviation of the normalised measure in
+// the moment variable) and harvested training sample (6 features, query, m0,
 // transmittance, selection hash bits, pixel index, record * (N+1) + edge)
-constexpr int kPixFeat = 10;
+constexpr int kPixFeat = 12;
+// tabulated schedule: the reconstruction per pixel at equally spaced nodes of
+// the standardised query on [-kTabZ, kTabZ], linearly interpolated
+constexpr float kTabZ = 4.f;
+constexpr int kTabMaxNodes = 256;
 constexpr int kMaxMoments = 8;  // highest moment order K supported
 // Heavy tiles (more list entries than kSplitEntries) are rendered by four
 // workgroups, one per 8x8 quadrant, whose four waves share the quadrant's

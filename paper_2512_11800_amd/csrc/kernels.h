@@ -129,6 +129,9 @@ struct RenderArgs {
   int* q_pix;                     // [q_cap] flat pixel index
   const float* q_f;               // [q_cap] surrogate output F
   const float* q_g;               // [q_cap][8] F and dF/d(inputs) (backward through the surrogate)
+  // tabulated schedule: [C*H*W][tab_nodes] reconstruction at the nodes
+  float* tab;
+  int tab_nodes;
   // training-sample harvest (harvest variant)
   float* harvest;                 // [harvest_cap, kHarvestStride]
   int* harvest_count;
@@ -136,10 +139,16 @@ struct RenderArgs {
   float harvest_rate;
   uint32_t seed;
 };
-enum RenderMode { kModePlain = 0, kModeHarvest = 1, kModeEmit = 2 };
+// kModeTrig: the plain path with the trigonometric moments of Eqs. 13-14;
+// kModeTabPlain / kModeTabSur: passes 0-1 and the per-pixel record of the
+// tabulated schedule, with the table of the moment bounds (TabPlain) or the
+// surrogate's inputs (TabSur); k_render_consume_tab completes the frame
+enum RenderMode { kModePlain = 0, kModeHarvest = 1, kModeEmit = 2, kModeTrig = 3, kModeTabPlain = 4,
+                  kModeTabSur = 5 };
 hipError_t launch_render_forward(const RenderArgs& a, const CamSet& cams, int n_moments,
                                  int n_intervals, hipStream_t s, int mode = kModePlain);
 hipError_t launch_render_consume(const RenderArgs& a, const CamSet& cams, int n_intervals, hipStream_t s);
+hipError_t launch_render_consume_tab(const RenderArgs& a, const CamSet& cams, int n_intervals, hipStream_t s);
 
 hipError_t launch_render_backward(const RenderArgs& r, const float* saved, const float* grad_image,
                                   const float* grad_penalty, const int* sorted_k, float* partials,
@@ -168,6 +177,9 @@ hipError_t launch_mlp_forward(const void* packed, const float* x, int64_t n, flo
 hipError_t launch_mlp_forward_gather(const void* packed, const float* pixfeat, int64_t n_pix, const int* q_pix,
                                      const float* q_z, const unsigned long long* q_count, int64_t q_cap, float* f,
                                      hipStream_t s);
+// the surrogate at the n_nodes nodes of every pixel's table: tab[p][g] = F(features of p, z_g)
+hipError_t launch_mlp_table(const void* packed, const float* pixfeat, int64_t n_pix, int n_nodes, float* tab,
+                            hipStream_t s);
 // F and dF/dinputs [q][8] for the render's query list (backward through the surrogate)
 hipError_t launch_mlp_input_grad_gather(const void* packed, const float* pixfeat, int64_t n_pix, const int* q_pix,
                                         const float* q_z, const unsigned long long* q_count, int64_t q_cap,

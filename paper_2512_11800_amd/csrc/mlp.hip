@@ -308,6 +308,43 @@ __global__ __launch_bounds__(256) void k_mlp_forward_gather(const MlpPacked* gp,
   }
 }
 
+// The network at the nodes of every pixel's table (the tabulated schedule):
+// entry q = p * n_nodes + g takes the six features of pixel p and the
+// standardised query z_g = -kTabZ + g 2 kTabZ / (n_nodes - 1).
+__global__ __launch_bounds__(256) void k_mlp_table(const MlpPacked* gp, const float* pixfeat, int64_t n_pix,
+                                                   int n_nodes, float* tab) {
+  __shared__ MlpPacked P;
+  __shared__ FwdLds ws[4];
+  const int64_t n = n_pix * n_nodes;
+  {
+    const float4* src = reinterpret_cast<const float4*>(gp);
+    float4* dst = reinterpret_cast<float4*>(&P);
+    for (int i = threadIdx.x; i < (int)(sizeof(MlpPacked) / 16); i += blockDim.x) dst[i] = src[i];
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  FwdLds& w = ws[wave];
+  const float dz = 2.f * kTabZ / (float)(n_nodes - 1);
+  const int64_t chunks = (n + 63) / 64;
+  const int64_t per_block = ((chunks + gridDim.x - 1) / gridDim.x + 3) / 4 * 4;
+  for (int64_t it = 0; it < per_block; it += 4) {
+    const int64_t q = ((int64_t)blockIdx.x * per_block + it + wave) * 64 + lane;
+    const bool valid = q < n;
+    const int64_t p = valid ? q / n_nodes : 0;
+    const int g = valid ? (int)(q - p * n_nodes) : 0;
+    const float* pf = pixfeat + (size_t)p * kPixFeat;
+    float v[kIn];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) v[k] = valid ? pf[k] : 0.f;
+    v[6] = -kTabZ + dz * (float)g;
+    stage_inputs(w, v, lane);
+    __syncthreads();
+    f32x16 z1[2][2], z2[2][2];
+    float out = mlp_forward_wave(w, P, lane, z1, z2);
+    if (valid) tab[q] = sigmoid(out);
+  }
+}
+
 // F and its gradient dF/dx with respect to the 7 inputs for every query of
 // the render's list (for the backward pass through the surrogate): the
 // forward pass as above, then dZ2 = F (1 - F) w3 GELU'(Z2) (bf16) on the
@@ -646,6 +683,14 @@ hipError_t launch_mlp_forward_gather(const void* packed, const float* pixfeat, i
   if (q_cap <= 0 || n_pix <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_mlp_forward_gather, dim3(mlp_grid(q_cap, 4)), dim3(256), 0, s, (const MlpPacked*)packed,
                      pixfeat, q_pix, q_z, q_count, q_cap, n_pix, f);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_table(const void* packed, const float* pixfeat, int64_t n_pix, int n_nodes, float* tab,
+                            hipStream_t s) {
+  if (n_pix <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mlp_table, dim3(mlp_grid(n_pix * n_nodes, 4)), dim3(256), 0, s, (const MlpPacked*)packed,
+                     pixfeat, n_pix, n_nodes, tab);
   return hipGetLastError();
 }
 

@@ -20,6 +20,7 @@
 //                 bound evaluation; k_render_consume completes the quadrature
 //                 from the surrogate's outputs.
 #include "render_common.h"
+#include "trig.h"
 
 namespace mb {
 
@@ -113,8 +114,10 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
   __shared__ uint8_t reach[kBlock];  // per staged entry: bit q set if its box reaches the tile's quadrant q
   // per-wave results of the queued pairs: 3 or K + 1 floats per pair in passes
   // 0 and 1, q (r, g, b, 1) in pass 2
-  // (K = 8 passes its moments in double: twice the room)
-  constexpr bool kDblMom = K >= 8;
+  // (K = 8 and the trigonometric moments pass their moments in double:
+  // twice the room)
+  constexpr bool kTrig = MODE == kModeTrig;
+  constexpr bool kDblMom = K >= 8 || kTrig;
   __shared__ __align__(16) float wres[4][(K + 1) * 64 * (kDblMom ? 2 : 1)];
   WaveQueue& q = wq[wave];
   float* res = wres[wave];
@@ -253,7 +256,12 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
       double* resd = reinterpret_cast<double*>(res);
       if (act) {
         RayG g = ray_of(j, p, lamp);
-        if constexpr (kDblMom) {
+        if constexpr (kTrig) {
+          double m[K + 1];
+          particle_trig_moments_d<NH>(g, tn, m);
+#pragma unroll
+          for (int k = 0; k <= K; ++k) resd[k * 64 + lane] = m[k];
+        } else if constexpr (kDblMom) {
           double m[K + 1];
           particle_moments_d<K>(g, pp, tn, m);
 #pragma unroll
@@ -318,8 +326,13 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
   // to the float32 underflow range to define a measure
   const bool live = acc[0] > kMinDepth;
   LInv<NH> L;
+  TrigLInv<kTrig ? NH : 1> TL;
   bool fallback = false;
-  if (live && MODE != kModeEmit) {
+  if constexpr (kTrig) {
+    if (live) fallback = trig_factor<NH>(acc, TL) != 0.0;
+#pragma unroll
+    for (int i = 0; i < (NH + 1) * (NH + 2) / 2; ++i) L.l[i] = 0.f;
+  } else if (live && MODE != kModeEmit && MODE != kModeTabSur) {
     double bn[K + 1], bmix[K + 1];
     bn[0] = 1.0;
 #pragma unroll
@@ -332,9 +345,41 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
 
   float feat[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   float smu = 0.f, ssig = 1.f;
-  if constexpr (MODE != kModePlain) {
+  if constexpr (MODE == kModeHarvest || MODE == kModeEmit || MODE == kModeTabSur) {
     static_assert(K == 6, "the surrogate takes six moments");
     if (live) surrogate_features(acc, feat, smu, ssig);
+  }
+
+  // ---- tabulated schedule: the pixel's record (and the bounds' table) -------
+  if constexpr (MODE == kModeTabPlain || MODE == kModeTabSur) {
+    if constexpr (MODE == kModeTabPlain) {
+      if (live) {
+        const double mb = acc[1] / acc[0];
+        const double var = acc[2] / acc[0] - mb * mb;
+        smu = (float)mb;
+        ssig = (float)(var > 0.0 ? sqrt(var) : 1.0);
+      }
+    }
+    if (inside && own4 <= 0) {
+      float* pf = a.pixfeat + pix * kPixFeat;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) pf[k] = feat[k];
+      pf[6] = live ? m0 : 0.f;
+      pf[7] = tc;
+      pf[8] = sd;
+      // covering count, as -(count + 1) where the bounds' measure was degenerate
+      pf[9] = fallback ? -(float)(n_cov + 1) : (float)n_cov;
+      pf[10] = smu;
+      pf[11] = ssig;
+      if constexpr (MODE == kModeTabPlain) {
+        // the moment bounds at the nodes y_g = mean + sd z_g
+        const float dz = 2.f * kTabZ / (float)(a.tab_nodes - 1);
+        float* tp = a.tab + pix * a.tab_nodes;
+        for (int g = 0; g < a.tab_nodes; ++g)
+          tp[g] = live ? bound_F<NH>(L, smu + ssig * (-kTabZ + dz * (float)g), a.beta) : 0.f;
+      }
+    }
+    return;
   }
 
   // ---- surrogate query list: this tile's range, pixel by pixel --------------
@@ -430,8 +475,17 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
       pp.p15 = from_lane(pb.p15, p);
       pp.amp = from_lane(pb.amp, p);
       LInv<NH> Lp;
+      TrigLInv<kTrig ? NH : 1> TLp;
+      if constexpr (kTrig) {
 #pragma unroll
-      for (int i = 0; i < (NH + 1) * (NH + 2) / 2; ++i) Lp.l[i] = from_lane(L.l[i], p);
+        for (int i = 0; i < (NH + 1) * (NH + 2) / 2; ++i) {
+          TLp.re[i] = from_lane(TL.re[i], p);
+          TLp.im[i] = from_lane(TL.im[i], p);
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < (NH + 1) * (NH + 2) / 2; ++i) Lp.l[i] = from_lane(L.l[i], p);
+      }
       const float m0p = from_lane(m0, p), lamp = from_lane(lam, p);
       float featp[6], smup = 0.f, ssigp = 1.f;
       if constexpr (MODE == kModeHarvest) {
@@ -446,7 +500,12 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
         const float dy = (float)ppy + 0.5f - st.f[0][j].y;
         RayG g = ray_params(st, j, dx, dy, lamp);
         QEdges<NQ> e;
-        float qv = particle_quadrature<NH, NQ>(g, pp, Lp, m0p, tn, a, e);
+        float qv;
+        if constexpr (kTrig) {
+          qv = particle_quadrature_trig<NH, NQ>(g, TLp, m0p, tn, a, e);
+        } else {
+          qv = particle_quadrature<NH, NQ>(g, pp, Lp, m0p, tn, a, e);
+        }
         if constexpr (MODE == kModeHarvest) {
           const uint32_t rid = (uint32_t)a.sorted_rec[b + j];
           const size_t pixp = ((size_t)ci * c.height + ppy) * c.width + ppx;
@@ -615,6 +674,95 @@ __global__ __launch_bounds__(256) void k_render_consume(RenderArgs a, CamSet cam
   sv[1] = make_float4(pf[7], pf[8], m0, pf[9]);
 }
 
+// Second half of the tabulated schedule: Eq. 7 and Eq. 15 with the optical
+// depth at every edge interpolated linearly in the pixel's table at the
+// edge's standardised query (clamped to the table's ends), made
+// non-decreasing along the edges (a running maximum; the surrogate's table
+// need not grow, the bounds' table does).
+template <int NQ>
+__global__ __launch_bounds__(256) void k_render_consume_tab(RenderArgs a, CamSet cams) {
+  __shared__ Stage st;
+  const int tiles_per_cam = a.tiles_x * a.tiles_y;
+  const int n_keys = tiles_per_cam * a.n_cams;
+  const int key = block_work(a).key;  // the tabulated schedule splits no tile
+  if (key >= n_keys) return;
+  const int ci = key / tiles_per_cam;
+  const int tile = key - ci * tiles_per_cam;
+  const int ty = tile / a.tiles_x, tx = tile - ty * a.tiles_x;
+  const CamConst& c = cams.c[ci];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int px = tx * kTile + (wave & 1) * 8 + (lane & 7);
+  const int py = ty * kTile + (wave >> 1) * 8 + (lane >> 3);
+  const bool inside = px < c.width && py < c.height;
+  const float u = (float)px + 0.5f, v = (float)py + 0.5f;
+  const float rx = (u - c.cx) / c.fx, ry = (v - c.cy) / c.fy;
+  const float lam = sqrtf(1.f + rx * rx + ry * ry);
+  const float tn = c.tn;
+  const int2 rg = a.ranges[key];
+  const size_t pix = ((size_t)ci * c.height + (inside ? py : 0)) * c.width + (inside ? px : 0);
+  const float* pf = a.pixfeat + pix * kPixFeat;
+  const float m0 = inside ? pf[6] : 0.f;
+  const bool active = inside && m0 > 0.f;
+  const PixelBasis pb = make_basis(inside ? pf[7] : tn, inside ? pf[8] : 1.f, tn);
+  const float smu = inside ? pf[10] : 0.f, isig = inside ? 1.f / pf[11] : 1.f;
+  const float* tp = a.tab + pix * a.tab_nodes;
+  const float ucoef = (float)(a.tab_nodes - 1) / (2.f * kTabZ);
+  float sr = 0.f, sg = 0.f, sb = 0.f, so = 0.f;
+  for (int b = rg.x; b < rg.y; b += kBlock) {
+    int nb = min(kBlock, rg.y - b);
+    __syncthreads();
+    load_batch(st, a.rec, a.sorted_rec, b, nb);
+    __syncthreads();
+    for_each_masked(a.masks, b, nb, wave, lane, [&](int j, uint64_t m) __attribute__((always_inline)) {
+      if (active && ((m >> lane) & 1ull)) {
+        const float dx = u - st.f[0][j].x, dy = v - st.f[0][j].y;
+        RayG g = ray_params(st, j, dx, dy, lam);
+        QEdges<NQ> e;
+        quad_edges<NQ>(g, pb, tn, a, e);
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) {
+          const float z = fminf(fmaxf((e.y[k] - smu) * isig, -kTabZ), kTabZ);
+          const float uu = (z + kTabZ) * ucoef;
+          const int i0 = min((int)uu, a.tab_nodes - 2);
+          const float fr = uu - (float)i0;
+          const float f = fmaf(fr, tp[i0 + 1] - tp[i0], tp[i0]);
+          const float tk = m0 * f;
+          e.tau[k] = (k == 0 || tk > e.tau[k > 0 ? k - 1 : 0]) ? tk : e.tau[k > 0 ? k - 1 : 0];
+        }
+        float q = quad_sum<NQ>(g, tn, e);
+        float4 f5 = st.f[5][j];
+        sr += q * f5.y;
+        sg += q * f5.z;
+        sb += q * f5.w;
+        so += q;
+      }
+    });
+  }
+  if (!inside) return;
+  float alpha = -expm1f(-m0);
+  float tr = expf(-m0);
+  float inv_o = 1.f / fmaxf(a.eps, so);
+  float* out = a.image + pix * 3;
+  out[0] = alpha * sr * inv_o + tr * c.bg[0];
+  out[1] = alpha * sg * inv_o + tr * c.bg[1];
+  out[2] = alpha * sb * inv_o + tr * c.bg[2];
+  float4* sv = reinterpret_cast<float4*>(a.saved + pix * MB_SAVED_FLOATS_PER_PIXEL);
+  sv[0] = make_float4(sr, sg, sb, so);
+  sv[1] = make_float4(pf[7], pf[8], m0, pf[9]);
+}
+
+hipError_t launch_render_consume_tab(const RenderArgs& a, const CamSet& cams, int n_intervals, hipStream_t s) {
+  int n_keys = a.tiles_x * a.tiles_y * a.n_cams;
+  dim3 grid(render_blocks(n_keys)), block(kBlock);
+  if (n_intervals == 3)
+    hipLaunchKernelGGL(k_render_consume_tab<4>, grid, block, 0, s, a, cams);
+  else if (n_intervals == 5)
+    hipLaunchKernelGGL(k_render_consume_tab<6>, grid, block, 0, s, a, cams);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
 hipError_t launch_render_forward(const RenderArgs& a, const CamSet& cams, int n_moments, int n_intervals,
                                  hipStream_t s, int mode) {
   int n_keys = a.tiles_x * a.tiles_y * a.n_cams;
@@ -634,6 +782,14 @@ hipError_t launch_render_forward(const RenderArgs& a, const CamSet& cams, int n_
   MB_LAUNCH(6, 5, kModeHarvest)
   MB_LAUNCH(6, 3, kModeEmit)
   MB_LAUNCH(6, 5, kModeEmit)
+  MB_LAUNCH(4, 3, kModeTrig)
+  MB_LAUNCH(4, 5, kModeTrig)
+  MB_LAUNCH(4, 3, kModeTabPlain)
+  MB_LAUNCH(6, 3, kModeTabPlain)
+  MB_LAUNCH(4, 5, kModeTabPlain)
+  MB_LAUNCH(6, 5, kModeTabPlain)
+  MB_LAUNCH(6, 3, kModeTabSur)
+  MB_LAUNCH(6, 5, kModeTabSur)
 #undef MB_LAUNCH
   return hipErrorInvalidValue;
 }

@@ -79,6 +79,10 @@ def options_struct(opts=None) -> L.MbOptions:
         o.beta = float(opts.beta)
         o.eps = float(opts.eps)
         o.full_coverage = int(bool(getattr(opts, "full_coverage", False)))
+        basis = getattr(opts, "basis", "power")
+        if basis not in ("power", "trigonometric"):
+            raise ValueError(f"moment basis {basis!r}: 'power' or 'trigonometric'")
+        o.basis = 1 if basis == "trigonometric" else 0
     return o
 
 
@@ -90,6 +94,7 @@ class Workspace:
         self.gws: Optional[torch.Tensor] = None
         self.pws: Optional[torch.Tensor] = None
         self.qws: Optional[torch.Tensor] = None
+        self.tws: Optional[torch.Tensor] = None  # the tabulated schedule's per-pixel records and tables
         self.q_cap: int = 0
         self.capacity: int = 0  # list entries of renders with the count on the device
 
@@ -287,6 +292,21 @@ def render_forward_surrogate(g: Gaussians, cams: Sequence, opts, mlp_packed: tor
     img, saved, state = f.result()
     state.q_cap = ws.q_cap
     return img, saved, state
+
+
+def render_forward_tabulated(g: Gaussians, cams: Sequence, opts, mlp_packed: Optional[torch.Tensor] = None,
+                             n_nodes: int = 32, ws: Optional[Workspace] = None):
+    """mb_prepare + mb_render_forward_tabulated: the reconstruction tabulated
+    per pixel at ``n_nodes`` nodes of the standardised query and interpolated
+    linearly; the moment bounds (``mlp_packed`` None) or the surrogate at the
+    nodes. Returns (image, saved, state)."""
+    lib = L.load()
+    f = _Frame(g, cams, opts, ws)
+    need = lib.mb_table_workspace_bytes(f.n_cams, f.width, f.height, int(n_nodes))
+    tws = f.ws._ensure("tws", need)
+    L.check(lib.mb_render_forward_tabulated(*f.head(), _ptr(mlp_packed), int(n_nodes), _ptr(tws), tws.numel(),
+                                            _ptr(f.image), _ptr(f.saved), _stream()))
+    return f.result()
 
 
 def _grad_outputs(g: Gaussians):

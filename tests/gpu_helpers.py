@@ -87,13 +87,20 @@ def tolerances(pe):
     return MARGIN_TOL, ORIENT_EPS
 
 
-def compare(img_gpu, res_oracle, label, tol=1e-4, max_excluded=0.0):
+def compare(img_gpu, res_oracle, label, tol=1e-4, max_excluded=0.0, gpu_saved=None):
     """Per-result max-abs error over pixels the parity protocol keeps. The
-    excluded pixels (a coverage or cull decision within the protocol's band)
-    are counted, logged and bounded: at most ``max_excluded`` of the pixels
-    (a fraction; 0 requires none)."""
+    excluded pixels (a coverage or cull decision within the protocol's band;
+    with ``gpu_saved`` [P, 8] also pixels whose degenerate-measure flag,
+    saved[7] < 0, differs from the oracle's) are counted, logged and bounded:
+    at most ``max_excluded`` of the pixels (a fraction; 0 requires none)."""
     ref = res_oracle["image"]
-    amb = res_oracle["ambiguous"]
+    amb = res_oracle["ambiguous"].copy()
+    if gpu_saved is not None:
+        flag_gpu = gpu_saved[:, 7] < 0
+        disagree = flag_gpu != res_oracle["fallback"]
+        log(f"[parity] {label}: degenerate pixels gpu={int(flag_gpu.sum())} "
+            f"oracle={int(res_oracle['fallback'].sum())} disagree={int(disagree.sum())}")
+        amb |= disagree
     err = np.abs(img_gpu - ref).max(-1)
     keep = ~amb
     mx = float(err[keep].max(initial=0.0))

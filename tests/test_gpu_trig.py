@@ -1,0 +1,69 @@
+"""Trigonometric moments (Sec. 3.2, Eqs. 13-14, App. C) on the GPU against the
+oracle (oracle.trig): the moments of every covering Gaussian on the circle,
+the reconstruction on the circle at each quadrature edge, Eq. 7 and Eq. 15.
+
+Bar: max-abs image error <= 1e-4 over the pixels the parity protocol keeps;
+besides the coverage band it excludes pixels whose degenerate-measure flag
+(the Toeplitz matrix mixed with the uniform measure) differs between the two
+sides, counted and bounded."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from tests.gpu_helpers import compare, gpu_render, log, proxy_error, tolerances
+from tests.test_gpu_forward import _sample_pixels
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+
+
+@pytest.mark.parametrize("n_int", [3, 5])
+def test_trig_w1_full_image(n_int):
+    scene, cams, opts = W.w1_small()
+    opts.basis = "trigonometric"
+    opts.n_intervals = n_int
+    img, saved, st = gpu_render(scene, cams, opts)
+    tol_m, tol_o = tolerances(proxy_error(scene, cams[0], opts))
+    ref = oracle.render_image(scene, cams[0], opts, margin_tol=tol_m, orient_eps=tol_o)
+    mx, _ = compare(img[0].reshape(-1, 3), ref, f"trig W1 N={n_int}", max_excluded=0.01,
+                    gpu_saved=saved[0].reshape(-1, 8))
+    assert mx <= TOL
+    m0_err = np.abs(saved[0].reshape(-1, 8)[:, 6] - ref["moments"][:, 0])
+    assert m0_err.max() < 1e-4 * max(1.0, ref["moments"][:, 0].max())
+
+
+def test_trig_w2_full_size_sampled():
+    """500k Gaussians at 1920x1080 in the benchmark's launch configuration;
+    20,000 sampled pixels."""
+    scene, cams, opts = W.w2_clusters(n_moments=4)
+    opts.basis = "trigonometric"
+    cam = cams[0]
+    img, saved, st = gpu_render(scene, cams, opts, on_device=True)
+    pix = _sample_pixels(scene, cam, n_random=10_000, n_dense=10_000)
+    tol_m, tol_o = tolerances(proxy_error(scene, cam, opts))
+    ref = oracle.render_image(scene, cam, opts, pixels=pix, margin_tol=tol_m, orient_eps=tol_o,
+                              max_pixels=len(pix))
+    log(f"[trig w2] sampled={len(pix)} pairs={ref['n_pairs']}")
+    mx, _ = compare(img[0].reshape(-1, 3)[pix], ref, "trig W2", max_excluded=0.01,
+                    gpu_saved=saved[0].reshape(-1, 8)[pix])
+    assert mx <= TOL
+
+
+def test_trig_single_colour_scene_is_exact_and_backward_is_refused():
+    import paper_2512_11800_amd as M
+    import torch
+    scene, cams, opts = W.w1_small()
+    opts.basis = "trigonometric"
+    scene.colors[:] = np.array([0.3, 0.6, 0.9], np.float32)
+    img, saved, st = gpu_render(scene, cams, opts)
+    m0 = saved[0].reshape(-1, 8)[:, 6]
+    o = saved[0].reshape(-1, 8)[:, 3]
+    ok = o >= 1e-6
+    expect = np.array([0.3, 0.6, 0.9])[None] * (1 - np.exp(-m0))[:, None]
+    assert np.abs(img[0].reshape(-1, 3)[ok] - expect[ok]).max() < 2e-6
+    g = M.Gaussians.from_scene(scene)
+    image, sv, rs = M.render_forward(g, cams, opts)
+    with pytest.raises(M.MbError, match="power moments"):
+        M.render_backward(g, cams, opts, rs, sv, torch.zeros_like(image))

@@ -1467,3 +1467,27 @@ def test_trig_single_colour_scene_renders_exact_opacity():
     expect = np.array([0.3, 0.6, 0.9])[None] * (1 - np.exp(-m0))[:, None]
     assert ok.sum() > 50
     assert np.allclose(r["image"][ok], expect[ok], atol=1e-12)
+
+
+def test_tabulated_reconstruction_interpolates_and_converges():
+    """The tabulated schedule (oracle.surrogate.tabulated): exact at the
+    nodes, linear between them, and converging to the untabulated
+    reconstruction as the nodes get denser (second order in their spacing)."""
+    from oracle.surrogate import exact_model, tabulated
+    rng = np.random.default_rng(90)
+    grid = np.linspace(-3, 3, 2001)
+    dens = sum(rng.uniform(0.2, 1) * np.exp(-(grid - rng.uniform(-2, 2)) ** 2 / rng.uniform(0.1, 0.5))
+               for _ in range(4))
+    mom = np.array([(dens * grid ** k).sum() for k in range(7)]) * 0.01
+    b = mom / mom[0]
+    mean, std = b[1], math.sqrt(b[2] - b[1] ** 2)
+    base = exact_model(0.25, max_z=np.inf)
+    y_nodes = mean + std * np.linspace(-4, 4, 32)
+    tab = tabulated(base, 32, 4.0)
+    q = lambda model, ys: model(torch.as_tensor(np.tile(mom, (len(ys), 1))), _t(ys)).numpy()
+    assert np.abs(q(tab, y_nodes) - q(base, y_nodes)).max() < 1e-12
+    mid = 0.5 * (y_nodes[:-1] + y_nodes[1:])
+    assert np.abs(q(tab, mid) - 0.5 * (q(base, y_nodes[:-1]) + q(base, y_nodes[1:]))).max() < 1e-12
+    ys = mean + std * rng.uniform(-3.5, 3.5, 400)
+    errs = [np.abs(q(tabulated(base, g, 4.0), ys) - q(base, ys)).max() for g in (33, 65, 129)]
+    assert errs[1] < 0.35 * errs[0] and errs[2] < 0.35 * errs[1]
