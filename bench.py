@@ -6,9 +6,10 @@ Workload: 500,000 Gaussians in 64 isotropic clusters (SH degree 3), one
 synthetic, seeded. A step is one frame through the whole path: preprocess,
 tile binning, the moment + quadrature render and, for forward + backward,
 the adjoint render and the gradient reduction. The default mode times both
-(the value is forward + backward, the forward figure is reported beside it);
-``--mode surrogate`` runs the learned-surrogate comparison at K=6. Inputs are
-resident in HBM before timing starts.
+(the value is forward + backward, the forward figure is reported beside it),
+then the same frame at K=6, then the learned-surrogate comparison at K=6
+(harvest, training, and four forward schedules on 8 held-out cameras; alone
+with ``--mode surrogate``). Inputs are resident in HBM before timing starts.
 
 Prints one JSON line (the benchmark contract) with ms/frame, the dominant
 kernel's roofline position (algorithmic FLOPs per launch over its measured
@@ -303,11 +304,16 @@ def cpu_baseline(scene, cams, opts, n_pairs_frame: int, budget_px: int, backward
 
 
 def surrogate_bench(args):
-    """The learned surrogate on the W2 scene with K=6: harvest 10^7 training
+    """The learned surrogate on the W2 scene with K=6: harvest training
     samples from plain renders of 32 training cameras, train, and on 8
-    held-out cameras compare the surrogate render with the plain one (speed,
-    PSNR between the two, and both against the ground truth of Eq. 2 on
-    sampled pixels)."""
+    held-out cameras time four forward schedules against each other: the
+    per-query bounds (the plain path), the per-query surrogate, and the
+    tabulated schedule (one table of G nodes per pixel, linear interpolation
+    at every edge) with the bounds and with the surrogate at the nodes; plus
+    forward + backward of the two per-query paths. Quality is reported as
+    PSNR of each schedule's image against the plain render (the comparison
+    against the exact volume rendering integral is a test, not part of this
+    run)."""
     import numpy as np
     import torch
 
@@ -348,21 +354,49 @@ def surrogate_bench(args):
         torch.cuda.synchronize()
         return a.elapsed_time(b) / args.steps
 
+    def host(img):
+        return img[0].cpu().numpy().reshape(-1, 3).astype(np.float64)
+
+    def psnr_vs(a, b):
+        mse = float(((a - b) ** 2).mean())
+        return 10 * math.log10(1.0 / mse) if mse > 0 else math.inf
+
     from paper_2512_11800_amd import _lib as L
+    nodes = args.tab_nodes
     per_cam = []
-    rng = np.random.default_rng(4)
     for i, cam in enumerate(held):
-        plain = M.render_forward(g, [cam], opts, ws=ws)[0]
-        sur = M.render_forward_surrogate(g, [cam], opts, packed, ws=ws)[0]
-        ms_plain = timed(lambda: M.render_forward(g, [cam], opts, ws=ws))
+        imgs = {"plain": host(M.render_forward(g, [cam], opts, ws=ws)[0]),
+                "surrogate": host(M.render_forward_surrogate(g, [cam], opts, packed, ws=ws)[0]),
+                "tabulated_bounds": host(M.render_forward_tabulated(g, [cam], opts, None, nodes, ws=ws)[0]),
+                "tabulated_surrogate": host(M.render_forward_tabulated(g, [cam], opts, packed, nodes,
+                                                                       ws=ws)[0])}
+        bad = {k: int((~np.isfinite(v).all(-1)).sum()) for k, v in imgs.items()}
+        if any(bad.values()):
+            # a non-finite image is a failed run: report what the pixels held
+            k = next(k for k, v in bad.items() if v)
+            idx = np.nonzero(~np.isfinite(imgs[k]).all(-1))[0][:16]
+            _, sv_p, _ = M.render_forward(g, [cam], opts, ws=ws)
+            diag = {"camera": i, "image": k, "n_bad": bad, "pixels": idx.tolist(),
+                    "values": imgs[k][idx].tolist(), "plain": imgs["plain"][idx].tolist(),
+                    "saved_plain": sv_p[0].reshape(-1, 8)[idx].cpu().tolist()}
+            print(json.dumps({"error": "non-finite held-out image", "diagnostics": diag}), flush=True)
+            raise SystemExit(3)
+        ms = {"plain": timed(lambda: M.render_forward(g, [cam], opts, ws=ws)),
+              "tabulated_bounds": timed(lambda: M.render_forward_tabulated(g, [cam], opts, None, nodes, ws=ws)),
+              "tabulated_surrogate": timed(lambda: M.render_forward_tabulated(g, [cam], opts, packed, nodes,
+                                                                              ws=ws))}
         L.profile_read()
         L.profile_enable(True)
-        ms_sur = timed(lambda: M.render_forward_surrogate(g, [cam], opts, packed, ws=ws,
-                                                                  check_capacity=False))
+        ms["surrogate"] = timed(lambda: M.render_forward_surrogate(g, [cam], opts, packed, ws=ws,
+                                                                   check_capacity=False))
         L.profile_enable(False)
         st = {k: round(v[0] / max(1, v[1]), 4) for k, v in L.profile_read().items() if v[1]}
-        # forward + backward of the two paths (the surrogate's weights fixed)
-        gi = torch.full_like(plain, 1.0 / plain.numel())
+        L.profile_enable(True)
+        timed(lambda: M.render_forward_tabulated(g, [cam], opts, packed, nodes, ws=ws))
+        L.profile_enable(False)
+        st_tab = {k: round(v[0] / max(1, v[1]), 4) for k, v in L.profile_read().items() if v[1]}
+        # forward + backward of the two per-query paths (the surrogate's weights fixed)
+        gi = torch.full((1, cam.height, cam.width, 3), 1.0 / (3 * cam.height * cam.width), device="cuda:0")
 
         def plain_fb():
             _, sv, rs = M.render_forward(g, [cam], opts, ws=ws)
@@ -373,41 +407,28 @@ def surrogate_bench(args):
                                                    for_backward=True)
             M.render_backward_surrogate(g, [cam], opts, rs, sv, gi, packed)
         sur_fb(True)  # sizes the query workspace for the backward pass
-        ms_plain_fb = timed(plain_fb)
-        ms_sur_fb = timed(sur_fb)
-        a = plain[0].cpu().numpy().reshape(-1, 3).astype(np.float64)
-        b = sur[0].cpu().numpy().reshape(-1, 3).astype(np.float64)
-        bad = ~(np.isfinite(a).all(-1) & np.isfinite(b).all(-1))
-        if bad.any():
-            # a non-finite image is a failed run: report what the pixels held
-            idx = np.nonzero(bad)[0][:16]
-            _, sv_p, _ = M.render_forward(g, [cam], opts, ws=ws)
-            _, sv_s, _ = M.render_forward_surrogate(g, [cam], opts, packed, ws=ws)
-            diag = {"camera": i, "n_bad": int(bad.sum()), "pixels": idx.tolist(),
-                    "plain": a[idx].tolist(), "surrogate": b[idx].tolist(),
-                    "saved_plain": sv_p[0].reshape(-1, 8)[idx].cpu().tolist(),
-                    "saved_surrogate": sv_s[0].reshape(-1, 8)[idx].cpu().tolist()}
-            print(json.dumps({"error": "non-finite held-out image", "diagnostics": diag}), flush=True)
-            raise SystemExit(3)
-        mse = float(((a - b) ** 2).mean())
-        rec = {"camera": i, "ms_plain": ms_plain, "ms_surrogate": ms_sur,
-               "ms_plain_fwd_bwd": ms_plain_fb, "ms_surrogate_fwd_bwd": ms_sur_fb,
-               "psnr_surrogate_vs_plain": 10 * math.log10(1.0 / mse) if mse > 0 else None,
-               "surrogate_stages_ms": st}
-        if args.gt_pixels > 0:
-            from oracle.exact import exact_pixels, psnr
-            pix = rng.choice(cam.width * cam.height, args.gt_pixels, replace=False)
-            t = time.perf_counter()
-            gt = exact_pixels(scene, cam, pix)
-            rec["psnr_plain_vs_gt"] = psnr(a[pix], gt)
-            rec["psnr_surrogate_vs_gt"] = psnr(b[pix], gt)
-            rec["delta_psnr_db"] = rec["psnr_surrogate_vs_gt"] - rec["psnr_plain_vs_gt"]
-            rec["gt_pixels"] = int(args.gt_pixels)
-            rec["gt_seconds"] = time.perf_counter() - t
+        ms_fb = {"plain": timed(plain_fb), "surrogate": timed(sur_fb)}
+        rec = {"camera": i, "ms_fwd": ms, "ms_fwd_bwd": ms_fb,
+               "psnr_vs_plain_db": {k: psnr_vs(v, imgs["plain"]) for k, v in imgs.items() if k != "plain"},
+               "surrogate_stages_ms": st, "tabulated_surrogate_stages_ms": st_tab}
         say(json.dumps(rec))
         per_cam.append(rec)
-    return {"harvest": info, "harvest_s": t_h, "train_s": t_t, "train_steps": args.train_steps,
-            "losses": losses, "cameras": per_cam}
+    mean = lambda key, k: sum(c[key][k] for c in per_cam) / len(per_cam)
+    summary = {
+        "ms_fwd": {k: mean("ms_fwd", k) for k in per_cam[0]["ms_fwd"]},
+        "ms_fwd_bwd": {k: mean("ms_fwd_bwd", k) for k in per_cam[0]["ms_fwd_bwd"]},
+        "min_psnr_vs_plain_db": {k: min(c["psnr_vs_plain_db"][k] for c in per_cam)
+                                 for k in per_cam[0]["psnr_vs_plain_db"]},
+    }
+    f = summary["ms_fwd"]
+    # equal schedules compared: per query against per query, tabulated against tabulated
+    summary["speedup_surrogate_vs_bounds"] = {"per_query": f["plain"] / f["surrogate"],
+                                              "tabulated": f["tabulated_bounds"] / f["tabulated_surrogate"],
+                                              "tabulated_surrogate_vs_per_query_bounds":
+                                                  f["plain"] / f["tabulated_surrogate"]}
+    return {"workload": "500k Gaussians, 64 clusters, SH3, 1920x1080, K=6, N=3, 8 held-out cameras",
+            "harvest": info, "harvest_s": t_h, "train_s": t_t, "train_steps": args.train_steps,
+            "tab_nodes": nodes, "losses": losses, "summary": summary, "cameras": per_cam}
 
 
 def copy_calibration(args):
@@ -438,8 +459,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--mode", choices=["both", "fwd", "fwdbwd", "surrogate", "copy"], default="both")
     ap.add_argument("--harvest", type=int, default=10_000_000)
-    ap.add_argument("--train-steps", type=int, default=4000)
-    ap.add_argument("--gt-pixels", type=int, default=32)
+    ap.add_argument("--train-steps", type=int, default=6000)
+    ap.add_argument("--tab-nodes", type=int, default=32, help="nodes per pixel of the tabulated schedule")
     ap.add_argument("--k", type=int, default=4, choices=[4, 6, 8])
     ap.add_argument("--workload", choices=["w2", "w3", "w5"], default="w2",
                     help="w2: 500k Gaussians, one 1080p camera (the metric's workload); "
@@ -449,6 +470,8 @@ def main():
     ap.add_argument("--cpu-sample-px", type=int, default=30000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-k6", action="store_true", help="skip the K = 6 frames of the default run")
+    ap.add_argument("--no-surrogate", action="store_true",
+                    help="skip the surrogate comparison (harvest, training, held-out cameras) of the default run")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: the renderer runs on one GPU; --gpus {args.gpus} is not supported "
@@ -461,23 +484,15 @@ def main():
     if args.mode == "surrogate":
         args.k = 6
         sres = surrogate_bench(args)
-        cams = sres["cameras"]
-        ms_p = sum(c["ms_plain"] for c in cams) / len(cams)
-        ms_s = sum(c["ms_surrogate"] for c in cams) / len(cams)
+        f = sres["summary"]["ms_fwd"]
         out = {
             "metric": "ms/frame 1080p fwd & fwd+bwd, 500k Gaussians; surrogate vs plain at ΔPSNR<0.1",
-            "value": ms_s, "unit": "ms/frame", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-            "ms_per_step": ms_s, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
-            "dtype": "f32+bf16", "data": "synthetic",
-            "config": {"workload": "500k Gaussians, 64 clusters, SH3, 1920x1080, K=6, N=3, surrogate "
-                                   "forward, 8 held-out cameras", "mode": "surrogate"},
-            "plain_ms_per_frame": ms_p, "speedup_vs_plain": ms_p / ms_s,
-            "min_psnr_surrogate_vs_plain": min(c["psnr_surrogate_vs_plain"] if c["psnr_surrogate_vs_plain"]
-                                               is not None else math.inf for c in cams),
+            "value": f["tabulated_surrogate"], "unit": "ms/frame", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": f["tabulated_surrogate"], "higher_is_better": False,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32+bf16", "data": "synthetic",
+            "config": {"workload": sres["workload"] + ", tabulated surrogate forward", "mode": "surrogate"},
             "surrogate": sres,
         }
-        if all("delta_psnr_db" in c for c in cams):
-            out["max_abs_delta_psnr_db"] = max(abs(c["delta_psnr_db"]) for c in cams)
         print(json.dumps(out), flush=True)
         return
 
@@ -495,6 +510,10 @@ def main():
                          "roofline_fwd": r6["roofline_fwd"], "roofline_bwd": r6["roofline_bwd"],
                          "pairs_per_frame": r6["n_pairs"], "n_fallback_pixels": r6["n_fallback_pixels"],
                          "stages_ms": {m: r6["modes"][m]["stages_ms"] for m in r6["modes"]}}
+    sur = None
+    if args.workload == "w2" and args.mode == "both" and args.k == 4 and not args.no_surrogate:
+        # the metric's surrogate-vs-plain leg (K = 6, held-out cameras)
+        sur = surrogate_bench(args)
     cpu = None
     if not args.no_cpu_baseline and args.workload == "w2":
         cpu = cpu_baseline(scene, cams, opts, n_pairs, args.cpu_sample_px, "fwdbwd" in res["modes"])
@@ -542,6 +561,8 @@ def main():
     out["stages_ms"] = {m: modes[m]["stages_ms"] for m in modes}
     out["wall_ms_per_step"] = {m: modes[m]["wall_ms_per_step"] for m in modes}
     out.update(extra_k)
+    if sur is not None:
+        out["surrogate"] = sur
     print(json.dumps(out), flush=True)
 
 
