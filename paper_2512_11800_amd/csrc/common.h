@@ -76,6 +76,11 @@ struct CamSet {
   CamConst c[MB_MAX_CAMERAS];
 };
 
+// e^(-x / 2), the constant folded into one multiply before the exp2
+__device__ __forceinline__ float exp_neg_half(float x) {
+  return __builtin_amdgcn_exp2f(-0.72134752044448170f * x);  // -log2(e) / 2
+}
+
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float fast_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }

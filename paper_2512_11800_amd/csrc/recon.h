@@ -30,9 +30,9 @@ __device__ __forceinline__ void linv_apply(const LInv<NH>& L, float x, float* z)
   int o = 0;
 #pragma unroll
   for (int i = 0; i <= NH; ++i) {
-    float s = 0.f;
+    float s = L.l[o];  // p[0] = 1; the sums start from their first term (no 0 + x)
 #pragma unroll
-    for (int j = 0; j <= i; ++j) s += L.l[o + j] * p[j];
+    for (int j = 1; j <= i; ++j) s = fmaf(L.l[o + j], p[j], s);
     z[i] = s;
     o += i + 1;
   }
@@ -42,23 +42,22 @@ template <int NH>
 __device__ __forceinline__ float christoffel(const LInv<NH>& L, float x) {
   float z[NH + 1];
   linv_apply<NH>(L, x, z);
-  float s = 0.f;
+  float s = z[0] * z[0];
 #pragma unroll
-  for (int i = 0; i <= NH; ++i) s += z[i] * z[i];
+  for (int i = 1; i <= NH; ++i) s = fmaf(z[i], z[i], s);
   return fast_rcp(s);
 }
 
 // c = L^-T z
 template <int NH>
 __device__ __forceinline__ void linv_t_apply(const LInv<NH>& L, const float* z, float* c) {
+  // c_j = sum_{i >= j} L[i][j] z_i, from the last row up (row i starts at i (i + 1) / 2)
 #pragma unroll
-  for (int j = 0; j <= NH; ++j) c[j] = 0.f;
-  int o = 0;
+  for (int j = 0; j <= NH; ++j) c[j] = L.l[NH * (NH + 1) / 2 + j] * z[NH];
 #pragma unroll
-  for (int i = 0; i <= NH; ++i) {
+  for (int i = NH - 1; i >= 0; --i) {
 #pragma unroll
-    for (int j = 0; j <= i; ++j) c[j] += L.l[o + j] * z[i];
-    o += i + 1;
+    for (int j = 0; j <= i; ++j) c[j] = fmaf(L.l[i * (i + 1) / 2 + j], z[i], c[j]);
   }
 }
 
@@ -210,34 +209,65 @@ __device__ __forceinline__ void kernel_roots(const float* c, float* x) {
     roots4(c, x);
 }
 
-struct Canon {  // canonical representation at one query, n <= 4
-  float x[4];
-  float w[4];
-  float w0;
-};
+// sum_{x_i < y} w_i from the count of atoms below y: the weights of the
+// canonical representation sum to b_0 = 1, so with c of the NH atoms below,
+// the sum is 0 (c = 0), 1 - w_0 (c = NH), and otherwise the Christoffel
+// weights of the smaller side: the atoms below when c <= NH / 2, else 1 - w_0
+// less the atoms above. At most one weight is evaluated for NH <= 3 and two
+// for NH = 4. A root that is not a number counts as an atom above
+// everything with no weight.
+template <int NH>
+__device__ __forceinline__ float mass_below(const LInv<NH>& L, float y, float w0, float* x) {
+  int cnt = 0;
+#pragma unroll
+  for (int i = 0; i < NH; ++i) {
+    x[i] = x[i] == x[i] ? x[i] : 1e30f;
+    cnt += x[i] < y ? 1 : 0;
+  }
+  auto weight = [&](float xs) __attribute__((always_inline)) {
+    const float w = christoffel<NH>(L, xs);
+    return isfinite(w) ? w : 0.f;
+  };
+  if constexpr (NH == 2) {
+    const float ws = weight(x[0] < y ? x[0] : x[1]);
+    return cnt == 1 ? ws : (cnt == 2 ? 1.f - w0 : 0.f);
+  } else if constexpr (NH == 3) {
+    const float lo = fminf(fminf(x[0], x[1]), x[2]);
+    const float hi = fmaxf(fmaxf(x[0], x[1]), x[2]);
+    const float ws = weight(cnt <= 1 ? lo : hi);
+    return cnt == 0 ? 0.f : (cnt == 1 ? ws : (cnt == 2 ? 1.f - w0 - ws : 1.f - w0));
+  } else {
+    // sorting network: s0 <= s1 <= s2 <= s3
+    float s0 = fminf(x[0], x[1]), s1 = fmaxf(x[0], x[1]);
+    float s2 = fminf(x[2], x[3]), s3 = fmaxf(x[2], x[3]);
+    float t = fminf(s0, s2);
+    s2 = fmaxf(s0, s2);
+    s0 = t;
+    t = fmaxf(s1, s3);
+    s1 = fminf(s1, s3);
+    s3 = t;
+    t = fminf(s1, s2);
+    s2 = fmaxf(s1, s2);
+    s1 = t;
+    const float wa = weight(cnt <= 2 ? s0 : s3);
+    const float wb = weight(s1);
+    return cnt == 0 ? 0.f
+                    : (cnt == 1 ? wa : (cnt == 2 ? wa + wb : (cnt == 3 ? 1.f - w0 - wa : 1.f - w0)));
+  }
+}
 
 // Normalised interpolated bound F(y) = sum_{x_i<y} w_i + beta w_0.
 template <int NH>
-__device__ __forceinline__ float bound_F(const LInv<NH>& L, float y, float beta, Canon* out = nullptr) {
+__device__ __forceinline__ float bound_F(const LInv<NH>& L, float y, float beta) {
   float z[NH + 1], c[NH + 1], x[NH];
   linv_apply<NH>(L, y, z);
-  float zz = 0.f;
+  float zz = z[0] * z[0];
 #pragma unroll
-  for (int i = 0; i <= NH; ++i) zz += z[i] * z[i];
-  float w0 = fast_rcp(zz);
+  for (int i = 1; i <= NH; ++i) zz = fmaf(z[i], z[i], zz);
+  const float w0 = fast_rcp(zz);
   linv_t_apply<NH>(L, z, c);
   kernel_roots<NH>(c, x);
-  float lo = 0.f;
-#pragma unroll
-  for (int i = 0; i < NH; ++i) {
-    float wi = christoffel<NH>(L, x[i]);
-    bool below = x[i] < y;
-    wi = isfinite(wi) ? wi : 0.f;
-    lo += below ? wi : 0.f;
-    if (out) { out->x[i] = x[i]; out->w[i] = wi; }
-  }
-  if (out) out->w0 = w0;
-  return lo + beta * w0;
+  return mass_below<NH>(L, y, w0, x) + beta * w0;
 }
 
 // Canonical representation at y with its atoms (for the adjoint): returns F
@@ -247,20 +277,15 @@ __device__ __forceinline__ float canon_at(const LInv<NH>& L, float y, float beta
                                           float& w0) {
   float z[NH + 1], c[NH + 1];
   linv_apply<NH>(L, y, z);
-  float zz = 0.f;
+  float zz = z[0] * z[0];
 #pragma unroll
-  for (int i = 0; i <= NH; ++i) zz += z[i] * z[i];
+  for (int i = 1; i <= NH; ++i) zz = fmaf(z[i], z[i], zz);
   w0 = fast_rcp(zz);
   linv_t_apply<NH>(L, z, c);
   kernel_roots<NH>(c, x);
-  float lo = 0.f;
+  const float lo = mass_below<NH>(L, y, w0, x);
 #pragma unroll
-  for (int i = 0; i < NH; ++i) {
-    float wi = christoffel<NH>(L, x[i]);
-    wi = isfinite(wi) ? wi : 0.f;
-    below[i] = x[i] < y;
-    lo += below[i] ? wi : 0.f;
-  }
+  for (int i = 0; i < NH; ++i) below[i] = x[i] < y;
   return lo + beta * w0;
 }
 
@@ -268,11 +293,43 @@ __device__ __forceinline__ float canon_at(const LInv<NH>& L, float y, float beta
 // equations sum_i w_i x_i^k = b_k (k = 0..2n, x_0 = y): the polynomial
 // Lambda of degree 2n with Lambda(x_i) = [x_i < y], Lambda'(x_i) = 0 (i >= 1)
 // and Lambda(y) = beta has coefficients dF/db_k, and dF/dy = -w_0 Lambda'(y).
-// Built by Hermite interpolation (Newton divided differences on the nodes
-// x_1, x_1, .., x_n, x_n, y), then expanded to monomial coefficients.
+// Built by Hermite interpolation, then expanded to monomial coefficients.
+// NH = 2 in closed form: Lambda = A + C P with A the cubic Hermite
+// interpolant of the two atoms with zero slopes, A(x) = f1 + (f2 - f1)
+// S((x - x1) / (x2 - x1)), S(t) = 3 t^2 - 2 t^3, P(x) = (x - x1)^2 (x - x2)^2
+// and C = (beta - A(y)) / P(y), expanded to monomial coefficients.
+__device__ __forceinline__ void hermite_adjoint2(float y, const float* xs, const bool* below, float beta,
+                                                 float* lam, float& dlam_y) {
+  const float x1 = fminf(fmaxf(xs[0], -1e6f), 1e6f), x2 = fminf(fmaxf(xs[1], -1e6f), 1e6f);
+  const float f1 = below[0] ? 1.f : 0.f, f2 = below[1] ? 1.f : 0.f;
+  const float D = f2 - f1;  // nonzero only for distinct atoms on either side of y
+  const float h = x2 - x1;
+  const float r = (D != 0.f && h != 0.f) ? fast_rcp(h) : 0.f;
+  const float Dr2 = D * r * r, Dr3 = Dr2 * r;
+  // A(x) = f1 + 3 D r^2 (x - x1)^2 - 2 D r^3 (x - x1)^3
+  const float a3 = -2.f * Dr3;
+  const float a2 = 3.f * Dr2 + 6.f * Dr3 * x1;
+  const float a1 = -6.f * x1 * (Dr2 + Dr3 * x1);
+  const float a0 = f1 + x1 * x1 * (3.f * Dr2 + 2.f * Dr3 * x1);
+  const float uy = y - x1, vy = y - x2;
+  const float ay = f1 + uy * uy * (3.f * Dr2 - 2.f * Dr3 * uy);
+  const float sq = uy * vy;
+  const float py = sq * sq;
+  const float C = py != 0.f ? (beta - ay) * fast_rcp(py) : 0.f;
+  // P(x) = x^4 - 2 s x^3 + (s^2 + 2 p) x^2 - 2 s p x + p^2
+  const float sm = x1 + x2, pr = x1 * x2;
+  lam[4] = C;
+  lam[3] = a3 - 2.f * sm * C;
+  lam[2] = a2 + (sm * sm + 2.f * pr) * C;
+  lam[1] = a1 - 2.f * sm * pr * C;
+  lam[0] = a0 + pr * pr * C;
+  dlam_y = ((4.f * lam[4] * y + 3.f * lam[3]) * y + 2.f * lam[2]) * y + lam[1];
+}
+
+// Any NH: Newton divided differences on the nodes x_1, x_1, .., x_n, x_n, y.
 template <int NH>
-__device__ __forceinline__ void hermite_adjoint(float y, const float* xs, const bool* below, float beta,
-                                                float* lam, float& dlam_y) {
+__device__ __forceinline__ void hermite_adjoint_dd(float y, const float* xs, const bool* below, float beta,
+                                                   float* lam, float& dlam_y) {
   constexpr int NN = 2 * NH + 1;
   float z[NN], f[NN], coef[NN];
 #pragma unroll
@@ -315,6 +372,15 @@ __device__ __forceinline__ void hermite_adjoint(float y, const float* xs, const 
 #pragma unroll
   for (int k = 0; k < NN; ++k) lam[k] = p[k];
   dlam_y = dl;
+}
+
+template <int NH>
+__device__ __forceinline__ void hermite_adjoint(float y, const float* xs, const bool* below, float beta,
+                                                float* lam, float& dlam_y) {
+  if constexpr (NH == 2)
+    hermite_adjoint2(y, xs, below, beta, lam, dlam_y);
+  else
+    hermite_adjoint_dd<NH>(y, xs, below, beta, lam, dlam_y);
 }
 
 // ---------------------------------------------------------------------------

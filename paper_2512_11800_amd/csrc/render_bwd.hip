@@ -29,23 +29,16 @@ struct QuadState {
   float q;
 };
 
-// phi'(x) = (e^-x - phi(x)) / x: the derivative of phi's series for |x| < 1/2
-// (terms up to x^7), the direct form beyond
-__device__ __forceinline__ float dphi_fn(float x) {
-  // coefficients (-1)^k k / (k+1)!, k = 1..8
-  float s = 8.f / 362880.f;
-  s = fmaf(s, -x, 7.f / 40320.f);
-  s = fmaf(s, -x, 6.f / 5040.f);
-  s = fmaf(s, -x, 5.f / 720.f);
+// phi'(x) = (e^-x - phi(x)) / x from d = e^-x and phi: the derivative of
+// phi's series (terms up to x^4) for |x| < 1/16, the direct form beyond
+__device__ __forceinline__ float dphi_fn(float x, float d, float ph) {
+  // coefficients (-1)^k k / (k+1)!, k = 1..5
+  float s = 5.f / 720.f;
   s = fmaf(s, -x, 4.f / 120.f);
   s = fmaf(s, -x, 3.f / 24.f);
   s = fmaf(s, -x, 2.f / 6.f);
   s = fmaf(s, -x, 0.5f);
-  s = -s;
-  const float e = __expf(-x);
-  const float r = fast_rcp(x);
-  float d = (e - (1.f - e) * r) * r;
-  return fabsf(x) < 0.5f ? s : d;
+  return fabsf(x) < kPhiSeries ? -s : (d - ph) * fast_rcp(x);
 }
 
 // Edges of one Gaussian's quadrature (App. B) and sigma_i there.
@@ -53,6 +46,8 @@ template <int NH, int NQ>
 __device__ __forceinline__ void quad_geom(const RayG& g, const PixelBasis& pb, float tn, const RenderArgs& a,
                                           QuadState<NH, NQ>& s) {
   float dtc = g.mu - pb.tc;
+  const float rn = (tn - g.mu) * fast_rcp(g.sig);  // edges moved onto the near bound
+  const float en = exp_neg_half(rn * rn);
 #pragma unroll
   for (int j = 0; j < NQ; ++j) {
     s.off[j] = a.kappa * g.sig * a.xq[j];
@@ -61,8 +56,7 @@ __device__ __forceinline__ void quad_geom(const RayG& g, const PixelBasis& pb, f
     float dtj = s.cl[j] ? (tn - pb.tc) : (dtc + s.off[j]);
     s.t[j] = s.cl[j] ? tn : t;
     s.y[j] = warp_y(pb, s.t[j], dtj);
-    float r = (s.t[j] - g.mu) * fast_rcp(g.sig);
-    s.sr[j] = s.cl[j] ? __expf(-0.5f * r * r) : a.eq[j];
+    s.sr[j] = s.cl[j] ? en : a.eq[j];
   }
 }
 
@@ -70,8 +64,7 @@ __device__ __forceinline__ void quad_geom(const RayG& g, const PixelBasis& pb, f
 // A[j] = dq / dtau_j.
 template <int NH, int NQ>
 __device__ __forceinline__ void quad_terms(const RayG& g, float tn, QuadState<NH, NQ>& s) {
-#pragma unroll
-  for (int j = 0; j < NQ; ++j) s.T[j] = __expf(-s.tau[j]);
+  s.T[0] = __expf(-s.tau[0]);
   s.q = 0.f;
 #pragma unroll
   for (int j = 0; j < NQ; ++j) s.A[j] = 0.f;
@@ -79,8 +72,10 @@ __device__ __forceinline__ void quad_terms(const RayG& g, float tn, QuadState<NH
   for (int j = 0; j + 1 < NQ; ++j) {
     s.dt[j] = s.cl[j + 1] ? 0.f : (s.cl[j] ? (g.mu + s.off[j + 1] - tn) : (s.off[j + 1] - s.off[j]));
     float dtau = s.tau[j + 1] - s.tau[j];
-    s.ph[j] = phi_fn(dtau);
-    s.dph[j] = dphi_fn(dtau);
+    const float d = __expf(-dtau);
+    s.T[j + 1] = s.T[j] * d;
+    s.ph[j] = phi_fn(dtau, d);
+    s.dph[j] = dphi_fn(dtau, d, s.ph[j]);
     float tds = s.T[j] * s.dt[j] * g.omega * s.sr[j];
     s.q += tds * s.ph[j];
     // dq/dtau_j and dq/dtau_{j+1} of this interval's term
@@ -275,14 +270,16 @@ __device__ __forceinline__ ScanMasks scan_masks(int lane, int seg_start) {
   s.m[5] = (lane >> 5) && seg_start <= 31 ? 1.f : 0.f;         // takes lane 31
   return s;
 }
-// The scan of all 18 gradient fields in one block of v_fmac_f32 with a DPP
+// The scan of the gradient fields in one block of v_fmac_f32 with a DPP
 // source (v += (v moved) * mask; the compiler would emit a separate move for
-// each), step by step over the fields. A DPP read of a VGPR written by a
-// VALU instruction needs two wait states: within the block every read comes
-// 18 instructions after the write it depends on, and the s_nop covers the
-// values written just before the block.
-static_assert(G_COUNT == 18, "the scan block is written for 18 fields");
-#define MB_SCAN_STEP(M, CTRL) \
+// each), step by step over the fields: all 18, or the 15 record fields when
+// the colour fields are zero in every lane (the moment part of the Gradient
+// stage). A DPP read of a VGPR written by a VALU instruction needs two wait
+// states: within the block every read comes 15 or more instructions after
+// the write it depends on, and the s_nop covers the values written just
+// before the block.
+static_assert(G_COUNT == 18 && G_CR == 15, "the scan blocks are written for 15 record and 3 colour fields");
+#define MB_SCAN15(M, CTRL) \
   "v_fmac_f32_dpp %0, %0, " M " " CTRL "\n\t" \
   "v_fmac_f32_dpp %1, %1, " M " " CTRL "\n\t" \
   "v_fmac_f32_dpp %2, %2, " M " " CTRL "\n\t" \
@@ -297,27 +294,46 @@ static_assert(G_COUNT == 18, "the scan block is written for 18 fields");
   "v_fmac_f32_dpp %11, %11, " M " " CTRL "\n\t" \
   "v_fmac_f32_dpp %12, %12, " M " " CTRL "\n\t" \
   "v_fmac_f32_dpp %13, %13, " M " " CTRL "\n\t" \
-  "v_fmac_f32_dpp %14, %14, " M " " CTRL "\n\t" \
+  "v_fmac_f32_dpp %14, %14, " M " " CTRL "\n\t"
+#define MB_SCAN18(M, CTRL) \
+  MB_SCAN15(M, CTRL) \
   "v_fmac_f32_dpp %15, %15, " M " " CTRL "\n\t" \
   "v_fmac_f32_dpp %16, %16, " M " " CTRL "\n\t" \
-  "v_fmac_f32_dpp %17, %17, " M " " CTRL "\n\t" \
+  "v_fmac_f32_dpp %17, %17, " M " " CTRL "\n\t"
 
 #define MB_ROW(C) "row_shr:" C " row_mask:0xf bank_mask:0xf bound_ctrl:1"
+#define MB_BCAST15 "row_bcast:15 row_mask:0xa bank_mask:0xf bound_ctrl:1"
+#define MB_BCAST31 "row_bcast:31 row_mask:0xc bank_mask:0xf bound_ctrl:1"
 __device__ __forceinline__ void segment_scan18(float* g, const ScanMasks& s) {
   asm("s_nop 1\n\t"
-      MB_SCAN_STEP("%18", MB_ROW("1"))
-      MB_SCAN_STEP("%19", MB_ROW("2"))
-      MB_SCAN_STEP("%20", MB_ROW("4"))
-      MB_SCAN_STEP("%21", MB_ROW("8"))
-      MB_SCAN_STEP("%22", "row_bcast:15 row_mask:0xa bank_mask:0xf bound_ctrl:1")
-      MB_SCAN_STEP("%23", "row_bcast:31 row_mask:0xc bank_mask:0xf bound_ctrl:1")
+      MB_SCAN18("%18", MB_ROW("1"))
+      MB_SCAN18("%19", MB_ROW("2"))
+      MB_SCAN18("%20", MB_ROW("4"))
+      MB_SCAN18("%21", MB_ROW("8"))
+      MB_SCAN18("%22", MB_BCAST15)
+      MB_SCAN18("%23", MB_BCAST31)
       : "+v"(g[0]), "+v"(g[1]), "+v"(g[2]), "+v"(g[3]), "+v"(g[4]), "+v"(g[5]), "+v"(g[6]), "+v"(g[7]),
         "+v"(g[8]), "+v"(g[9]), "+v"(g[10]), "+v"(g[11]), "+v"(g[12]), "+v"(g[13]), "+v"(g[14]),
         "+v"(g[15]), "+v"(g[16]), "+v"(g[17])
       : "v"(s.m[0]), "v"(s.m[1]), "v"(s.m[2]), "v"(s.m[3]), "v"(s.m[4]), "v"(s.m[5]));
 }
+__device__ __forceinline__ void segment_scan15(float* g, const ScanMasks& s) {
+  asm("s_nop 1\n\t"
+      MB_SCAN15("%15", MB_ROW("1"))
+      MB_SCAN15("%16", MB_ROW("2"))
+      MB_SCAN15("%17", MB_ROW("4"))
+      MB_SCAN15("%18", MB_ROW("8"))
+      MB_SCAN15("%19", MB_BCAST15)
+      MB_SCAN15("%20", MB_BCAST31)
+      : "+v"(g[0]), "+v"(g[1]), "+v"(g[2]), "+v"(g[3]), "+v"(g[4]), "+v"(g[5]), "+v"(g[6]), "+v"(g[7]),
+        "+v"(g[8]), "+v"(g[9]), "+v"(g[10]), "+v"(g[11]), "+v"(g[12]), "+v"(g[13]), "+v"(g[14])
+      : "v"(s.m[0]), "v"(s.m[1]), "v"(s.m[2]), "v"(s.m[3]), "v"(s.m[4]), "v"(s.m[5]));
+}
+#undef MB_BCAST31
+#undef MB_BCAST15
 #undef MB_ROW
-#undef MB_SCAN_STEP
+#undef MB_SCAN18
+#undef MB_SCAN15
 
 // Per-entry sums of the gradients gr[] of the evaluated queue positions
 // [0, n): queued pairs of one entry are contiguous, a segmented scan over the
@@ -335,14 +351,11 @@ __device__ __forceinline__ bool writes_slot(bool act, int j, int n, int lane, in
   return last && !(lane == n - 1 && j == cont_j);
 }
 __device__ __forceinline__ SlotVals load_slot(bool w, int j, const float* partials, const int* sk, int wave) {
-  SlotVals v;
+  SlotVals v;  // read only by the lanes that load it
   if (w) {
     const float4* slot = reinterpret_cast<const float4*>(partials + ((size_t)sk[j] * 4 + wave) * kGradStride);
 #pragma unroll
     for (int f = 0; f < 5; ++f) v.s[f] = slot[f];
-  } else {
-#pragma unroll
-    for (int f = 0; f < 5; ++f) v.s[f] = make_float4(0.f, 0.f, 0.f, 0.f);
   }
   return v;
 }
@@ -360,7 +373,11 @@ __device__ __forceinline__ void reduce_to_slots(float* gr, bool act, int j, int 
   const int seg_start = 63 - __builtin_clzll(heads & upto);
   const int jnext = __shfl_down(j, 1, 64);
   const bool last = act && (lane == n - 1 || jnext != j);
-  segment_scan18(gr, scan_masks(lane, seg_start));
+  // the moment part (ADD) leaves the colour fields zero: they need no scan
+  if constexpr (ADD)
+    segment_scan15(gr, scan_masks(lane, seg_start));
+  else
+    segment_scan18(gr, scan_masks(lane, seg_start));
   if (last) {
     if (seg_start == 0 && j == carry_j) {
 #pragma unroll

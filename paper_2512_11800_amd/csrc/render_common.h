@@ -160,25 +160,66 @@ __device__ __forceinline__ void load_batch(Stage& st, const float4* rec, const i
   }
 }
 
-// Coverage of the pixel centre (u, v) by staged entry j (record index
-// sorted_rec[b + j]), the decision of the exact rectangle (rectd, double).
-// The float test on the staged record decides wherever its margin to an edge
-// exceeds a bound on its rounding error (the record's centre, axis and halves
-// are the double values rounded to float, and the test's own operations round
-// relative 2^-24: 1e-6 relative is 17 times that bound); near an edge the
-// wave re-tests in double against rectd. Only the first pass tests coverage:
-// every later pass, forward and backward, reads the masks it stores.
-__device__ __forceinline__ bool covers(const Stage& st, const double2* rectd, const int* sorted_rec, int b, int j,
-                                       float u, float v, bool inside) {
+// Coverage of the pixel centres of a tile by staged entry j, in the
+// rectangle's axis coordinates c1 = (p - C) . e1, c2 = (p - C) . e2 (C, e1,
+// e2 = e1 rotated by +90 degrees, halves h1, h2 from the record; covered iff
+// |c1| <= h1 and |c2| <= h2). cover_setup evaluates (c1, c2) once per entry at
+// the tile's first pixel centre (x_t + 1/2, y_t + 1/2); the per-pixel test
+// adds the pixel's offset (i, j) inside the tile, c1 + i e1x + j e1y and
+// c2 - i e1y + j e1x, two fused multiply-adds each. The float test decides
+// wherever its margin to an edge exceeds `band`, a bound on its rounding
+// error: the record's centre offset, axis and halves are the double values
+// rounded to float (relative 2^-24), and the set-up and per-pixel operations
+// round relative 2^-24 each on values of at most |a| + 32 + h (a: the tile
+// origin's offset from the centre); 2e-6 times the sum of those magnitudes is
+// more than ten times the worst case. Near an edge the wave re-tests in
+// double against rectd. Only the first pass tests coverage: every later
+// pass, forward and backward, reads the masks it stores.
+//
+// cover_setup also returns the 8x8 quadrants of the tile the rectangle can
+// reach (bit q for quadrant q = 2 row + column): those whose pixel-centre
+// square overlaps the rectangle's axis-aligned box, and whose centre lies
+// within h + 3.5 (|e1x| + |e1y|) of the rectangle along both of its axes
+// (the separating-axis test of two rectangles); a margin beyond the
+// rounding bound keeps the bits from ever missing a covered pixel.
+__device__ __forceinline__ uint8_t cover_setup(const Stage& st, int j, int xt, int yt, float4& cb) {
   const float4 f0 = st.f[0][j], f1 = st.f[1][j];
-  const float dx = u - f0.x, dy = v - f0.y;
-  const float ax = dx - f0.z, ay = dy - f0.w;
-  const float c1 = ax * f1.x + ay * f1.y;
-  const float c2 = -ax * f1.y + ay * f1.x;
+  const float ax = ((float)xt + 0.5f - f0.x) - f0.z;
+  const float ay = ((float)yt + 0.5f - f0.y) - f0.w;
+  const float a1 = ax * f1.x + ay * f1.y;
+  const float a2 = ay * f1.x - ax * f1.y;
+  const float band = 2e-6f * (33.f + fabsf(ax) + fabsf(ay) + fabsf(f0.z) + fabsf(f0.w) + f1.z + f1.w);
+  cb = make_float4(a1, a2, band, 0.f);
+  const float cx = f0.x + f0.z, cy = f0.y + f0.w;
+  const float eax = fabsf(f1.x), eay = fabsf(f1.y);
+  const float mx = 0.01f + 1e-5f * fabsf(cx), my = 0.01f + 1e-5f * fabsf(cy);
+  const float bx = eax * f1.z + eay * f1.w + mx, by = eay * f1.z + eax * f1.w + my;
+  const float reach = 3.5f * (eax + eay) + band + 0.01f;
+  uint8_t bits = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const float lx = (float)(xt + (q & 1) * 8) + 0.5f, ly = (float)(yt + (q >> 1) * 8) + 0.5f;
+    const bool box = cx + bx >= lx && cx - bx <= lx + 7.f && cy + by >= ly && cy - by <= ly + 7.f;
+    const float qi = 8.f * (float)(q & 1) + 3.5f, qj = 8.f * (float)(q >> 1) + 3.5f;
+    const float c1 = a1 + qi * f1.x + qj * f1.y;
+    const float c2 = a2 - qi * f1.y + qj * f1.x;
+    const bool sat = fabsf(c1) <= f1.z + reach && fabsf(c2) <= f1.w + reach;
+    bits |= (box && sat) ? (uint8_t)(1u << q) : (uint8_t)0;
+  }
+  return bits;
+}
+
+// The per-pixel test of entry j (cb: its cover_setup values) for the pixel at
+// offset (fi, fj) from the tile's first pixel, centre (u, v).
+__device__ __forceinline__ bool covers(const Stage& st, const float4* cbase, const double2* rectd,
+                                       const int* sorted_rec, int b, int j, float fi, float fj, float u, float v,
+                                       bool inside) {
+  const float4 cb = cbase[j], f1 = st.f[1][j];
+  const float c1 = fmaf(fj, f1.y, fmaf(fi, f1.x, cb.x));
+  const float c2 = fmaf(fj, f1.x, fmaf(fi, -f1.y, cb.y));
   const float m = fminf(f1.z - fabsf(c1), f1.w - fabsf(c2));
-  const float band = 1e-6f * (1.f + fabsf(dx) + fabsf(dy) + fabsf(f0.z) + fabsf(f0.w) + f1.z + f1.w);
   bool cov = inside && m >= 0.f;
-  const bool amb = inside && fabsf(m) < band;
+  const bool amb = inside && fabsf(m) < cb.z;
   if (__ballot(amb) != 0) {
     const int rid = __builtin_amdgcn_readfirstlane(sorted_rec[b + j]);
     const double2 cd = rectd[(size_t)rid * 3], ed = rectd[(size_t)rid * 3 + 1], hd = rectd[(size_t)rid * 3 + 2];
@@ -209,27 +250,6 @@ __device__ __forceinline__ void for_each_masked(const uint64_t* masks, int b, in
   }
 }
 
-// Which 8x8 quadrants of the tile at (x0, y0) the axis-aligned box of entry
-// j's rectangle reaches (bit q for quadrant q = 2 row + column). A pixel
-// centre inside the rectangle lies inside the box, whose half extents are
-// |e1x| h1 + |e1y| h2 and |e1y| h1 + |e1x| h2; the margin absorbs the
-// rounding of the per-pixel test, so the bits never miss a covered pixel.
-__device__ __forceinline__ uint8_t quadrants_reached(const Stage& st, int j, int x0, int y0) {
-  const float4 f0 = st.f[0][j], f1 = st.f[1][j];
-  const float cx = f0.x + f0.z, cy = f0.y + f0.w;
-  const float ax = fabsf(f1.x), ay = fabsf(f1.y);
-  const float mx = 0.01f + 1e-5f * fabsf(cx), my = 0.01f + 1e-5f * fabsf(cy);
-  const float ex = ax * f1.z + ay * f1.w + mx, ey = ay * f1.z + ax * f1.w + my;
-  uint8_t bits = 0;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const float lx = (float)(x0 + (q & 1) * 8) + 0.5f, ly = (float)(y0 + (q >> 1) * 8) + 0.5f;
-    const bool hit = cx + ex >= lx && cx - ex <= lx + 7.f && cy + ey >= ly && cy - ey <= ly + 7.f;
-    bits |= hit ? (uint8_t)(1u << q) : (uint8_t)0;
-  }
-  return bits;
-}
-
 // Eqs. 4-6 for the pixel ray in the projected-mean frame (see common.h)
 __device__ __forceinline__ RayG ray_params(const Stage& st, int j, float dx, float dy, float lam) {
   float4 f2 = st.f[2][j], f3 = st.f[3][j], f4 = st.f[4][j];
@@ -241,7 +261,7 @@ __device__ __forceinline__ RayG ray_params(const Stage& st, int j, float dx, flo
   RayG g;
   g.id = id;
   g.xid = x * id;
-  g.ek = __expf(-0.5f * g.xid);
+  g.ek = exp_neg_half(g.xid);
   g.mu = lam * e * id;
   g.sig = lam * fast_rsq(d);
   g.omega = w * g.ek;
@@ -301,21 +321,17 @@ __device__ __forceinline__ void particle_moments_d(const RayG& g, const PixelBas
   }
 }
 
-// phi(x) = (1 - e^-x) / x: its Taylor series up to x^8 for |x| < 1/2
-// (truncation below 1e-8 relative), the direct form beyond (no cancellation
-// there: 1 - e^-x > 0.39)
-__device__ __forceinline__ float phi_fn(float x) {
-  float s = 1.f / 362880.f;
-  s = fmaf(s, -x, 1.f / 40320.f);
-  s = fmaf(s, -x, 1.f / 5040.f);
-  s = fmaf(s, -x, 1.f / 720.f);
-  s = fmaf(s, -x, 1.f / 120.f);
+// phi(x) = (1 - e^-x) / x from d = e^-x: the Taylor series up to x^4 for
+// |x| < 1/16 (truncation below 2e-9 relative), the direct form beyond (where
+// 1 - d > 0.06, so its rounding stays below 1e-6 relative)
+constexpr float kPhiSeries = 0.0625f;
+__device__ __forceinline__ float phi_fn(float x, float d) {
+  float s = 1.f / 120.f;
   s = fmaf(s, -x, 1.f / 24.f);
   s = fmaf(s, -x, 1.f / 6.f);
   s = fmaf(s, -x, 0.5f);
   s = fmaf(s, -x, 1.f);
-  float d = (1.f - __expf(-x)) * fast_rcp(x);
-  return fabsf(x) < 0.5f ? s : d;
+  return fabsf(x) < kPhiSeries ? s : (1.f - d) * fast_rcp(x);
 }
 
 // Interval edges of one Gaussian's quadrature (App. B sample spacing): edge
@@ -331,6 +347,9 @@ template <int NQ>
 __device__ __forceinline__ void quad_edges(const RayG& g, const PixelBasis& pb, float tn, const RenderArgs& a,
                                            QEdges<NQ>& e) {
   float dtc = g.mu - pb.tc;
+  // every edge left of the near bound is moved onto it: one density there
+  const float rn = (tn - g.mu) * fast_rcp(g.sig);
+  const float en = exp_neg_half(rn * rn);
 #pragma unroll
   for (int j = 0; j < NQ; ++j) {
     e.off[j] = a.kappa * g.sig * a.xq[j];
@@ -339,8 +358,7 @@ __device__ __forceinline__ void quad_edges(const RayG& g, const PixelBasis& pb, 
     float dt = e.cl[j] ? (tn - pb.tc) : (dtc + e.off[j]);
     t = e.cl[j] ? tn : t;
     e.y[j] = warp_y(pb, t, dt);
-    float r = (t - g.mu) * fast_rcp(g.sig);
-    e.sj[j] = g.omega * (e.cl[j] ? __expf(-0.5f * r * r) : a.eq[j]);
+    e.sj[j] = g.omega * (e.cl[j] ? en : a.eq[j]);
   }
 }
 
@@ -348,10 +366,14 @@ __device__ __forceinline__ void quad_edges(const RayG& g, const PixelBasis& pb, 
 template <int NQ>
 __device__ __forceinline__ float quad_sum(const RayG& g, float tn, const QEdges<NQ>& e) {
   float q = 0.f;
+  float T = __expf(-e.tau[0]);  // transmittance at edge j, carried along the edges
 #pragma unroll
   for (int j = 0; j + 1 < NQ; ++j) {
     float delta = e.cl[j + 1] ? 0.f : (e.cl[j] ? (g.mu + e.off[j + 1] - tn) : (e.off[j + 1] - e.off[j]));
-    q += __expf(-e.tau[j]) * delta * phi_fn(e.tau[j + 1] - e.tau[j]) * e.sj[j];
+    const float x = e.tau[j + 1] - e.tau[j];
+    const float d = __expf(-x);
+    q += T * delta * phi_fn(x, d) * e.sj[j];
+    T *= d;
   }
   return q;
 }

@@ -104,6 +104,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
   const int py = ty * kTile + (quad >> 1) * 8 + (lane >> 3);
   const bool inside = px < c.width && py < c.height;
   const float u = (float)px + 0.5f, v = (float)py + 0.5f;
+  const float fi = (float)(px - tx * kTile), fj = (float)(py - ty * kTile);  // offset inside the tile
   const float rx = (u - c.cx) / c.fx, ry = (v - c.cy) / c.fy;
   const float lam = sqrtf(1.f + rx * rx + ry * ry);
   const float tn = c.tn;
@@ -111,7 +112,8 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
   const size_t pix = ((size_t)ci * c.height + (inside ? py : 0)) * c.width + (inside ? px : 0);
 
   __shared__ WaveQueue wq[4];
-  __shared__ uint8_t reach[kBlock];  // per staged entry: bit q set if its box reaches the tile's quadrant q
+  __shared__ uint8_t reach[kBlock];  // per staged entry: bit q set if it can reach the tile's quadrant q
+  __shared__ float4 cbase[kBlock];   // per staged entry: its coverage test's set-up (cover_setup)
   // per-wave results of the queued pairs: 3 or K + 1 floats per pair in passes
   // 0 and 1, q (r, g, b, 1) in pass 2
   // (K = 8 and the trigonometric moments pass their moments in double:
@@ -174,7 +176,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
       __syncthreads();
       load_batch(st, a.rec, a.sorted_rec, b, nb);
       // each thread reads back the record it staged itself
-      if (tid < nb) reach[tid] = quadrants_reached(st, tid, tx * kTile, ty * kTile);
+      if (tid < nb) reach[tid] = cover_setup(st, tid, tx * kTile, ty * kTile, cbase[tid]);
       __syncthreads();
       QueueCursor qc;
       queue_reset(qc);
@@ -190,7 +192,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
         while (todo) {
           const int j = j0 + __builtin_ctzll(todo);
           todo &= todo - 1;
-          const bool cov = covers(st, a.rectd, a.sorted_rec, b, j, u, v, inside);
+          const bool cov = covers(st, cbase, a.rectd, a.sorted_rec, b, j, fi, fj, u, v, inside);
           uint64_t mask = __ballot(cov);
           if (lane == 0) a.masks[(size_t)(b + j) * 4 + quad] = mask;
           if (mask == 0) continue;

@@ -309,7 +309,7 @@ __device__ __forceinline__ float particle_quadrature_trig(const RayG& g, const T
     t = e.cl[j] ? tn : t;
     e.y[j] = kTrigSpan * warp_abs(t, tn);
     const float r = (t - g.mu) * fast_rcp(g.sig);
-    e.sj[j] = g.omega * (e.cl[j] ? __expf(-0.5f * r * r) : a.eq[j]);
+    e.sj[j] = g.omega * (e.cl[j] ? exp_neg_half(r * r) : a.eq[j]);
     const float tj = m0 * trig_F<NH>(L, e.y[j], a.beta);
     e.tau[j] = (j == 0 || tj > e.tau[j > 0 ? j - 1 : 0]) ? tj : e.tau[j > 0 ? j - 1 : 0];
   }
