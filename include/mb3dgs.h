@@ -83,8 +83,9 @@ typedef struct mb_options {
   float beta;          /* interpolation between the bounds, Sec. 3.2 (0.25)  */
   float eps;           /* clamp of Eq. 15's denominator (1e-6)               */
   int32_t basis;       /* moment basis: 0 power moments (Eqs. 10-12), 1
-                          trigonometric moments (Eqs. 13-14; forward only,
-                          n_moments = 4, i.e. two complex moments)        */
+                          trigonometric moments (Eqs. 13-14; n_moments = 4,
+                          i.e. two complex moments; not with the surrogate
+                          or the tabulated schedule)                       */
   const void *surrogate; /* reserved, NULL                                   */
   int32_t full_coverage; /* debug: every Gaussian covers every pixel        */
   int32_t reserved;
@@ -191,7 +192,10 @@ int mb_render_forward_noalloc(const mb_gaussians *g, const mb_camera *cams, int3
  * included: the count, or MB_ENTRIES_ON_DEVICE). The per-pixel
  * moment sums come from the pair workspace, where the forward pass left them;
  * nothing per (pixel, Gaussian) pair is stored, the pairs' terms are
- * recomputed.
+ * recomputed. Both moment bases: with trigonometric moments the adjoint of
+ * the reconstruction on the circle and of Eq. 14 replace the power
+ * moments' (the atoms and flags of the canonical representation are held
+ * fixed, as the flags of the power moments' bounds are).
  *  saved         [C,H,W,8] device, from mb_render_forward
  *  grad_image    [C,H,W,3] device, dL/dimage
  *  grad_penalty  [C,H,W] device, dL/dpenalty, or NULL (no penalty term)

@@ -740,8 +740,10 @@ int backward_common(const mb_gaussians* g, const mb_camera* cams, int32_t n_cams
   }
   {
     StageTimer t(S_RENDER_BWD, s);
+    // 0: power moments, 1: the surrogate, 2: trigonometric moments
+    const int mode = q != nullptr ? 1 : (o->basis == 1 ? 2 : 0);
     e = launch_render_backward(ra, saved, grad_image, grad_penalty, p.vals_a, p.partials, cs, o->n_moments,
-                               o->n_intervals, s, q != nullptr);
+                               o->n_intervals, s, mode);
   }
   if (e != hipSuccess) return hip_fail(e, "render_backward");
   GradArgs ga;
@@ -783,7 +785,6 @@ int mb_render_backward(const mb_gaussians* g, const mb_camera* cams, int32_t n_c
   int rc = check_backward_args(g, cams, n_cams, o, n_entries, saved, grad_image, g_means, g_scales, g_quats,
                                g_densities, g_colors, true);
   if (rc) return rc;
-  if (o->basis != 0) return fail(MB_ERR_UNSUPPORTED, "the backward pass takes power moments (basis 0)");
   return backward_common(g, cams, n_cams, o, gws, gws_bytes, pws, pws_bytes, n_entries, saved, grad_image,
                          grad_penalty, g_means, g_scales, g_quats, g_densities, g_colors, (hipStream_t)stream,
                          nullptr, nullptr, 0);

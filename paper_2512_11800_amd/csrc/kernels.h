@@ -153,7 +153,7 @@ hipError_t launch_render_consume_tab(const RenderArgs& a, const CamSet& cams, in
 hipError_t launch_render_backward(const RenderArgs& r, const float* saved, const float* grad_image,
                                   const float* grad_penalty, const int* sorted_k, float* partials,
                                   const CamSet& cams, int n_moments, int n_intervals, hipStream_t s,
-                                  bool surrogate = false);
+                                  int mode = 0);
 
 struct GradArgs {
   const float *means, *scales, *quats, *dens, *colors;

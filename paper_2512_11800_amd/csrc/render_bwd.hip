@@ -15,6 +15,7 @@
 // kernel then sums the slots: one reduction, no atomics, deterministic.
 // The passes walk the coverage masks the forward pass stored.
 #include "render_common.h"
+#include "trig.h"
 
 namespace mb {
 
@@ -94,6 +95,33 @@ __device__ __forceinline__ void quad_state(const RayG& g, const PixelBasis& pb, 
     s.tau[j] = m0 * s.F[j];
   }
   quad_terms<NH, NQ>(g, tn, s);
+}
+
+// The same for the trigonometric moments (the forward pass's
+// particle_quadrature_trig): the edge at depth t queries the angle
+// psi = (2 pi - theta) g_hat(t) (kept in s.y), the optical depth is a running
+// maximum along the edges, and src[e] names the edge whose query supplied
+// edge e's value (the last edge at or before e that raised it).
+template <int NQ>
+__device__ __forceinline__ void trig_quad_state(const RayG& g, const TrigLInv<2>& L, float m0, float tn,
+                                                const RenderArgs& a, QuadState<2, NQ>& s, TrigCanon* tc,
+                                                int* src) {
+#pragma unroll
+  for (int j = 0; j < NQ; ++j) {
+    s.off[j] = a.kappa * g.sig * a.xq[j];
+    const float t = g.mu + s.off[j];
+    s.cl[j] = t < tn;
+    s.t[j] = s.cl[j] ? tn : t;
+    s.y[j] = kTrigSpan * warp_abs(s.t[j], tn);
+    const float r = (s.t[j] - g.mu) * fast_rcp(g.sig);
+    s.sr[j] = s.cl[j] ? exp_neg_half(r * r) : a.eq[j];
+    s.F[j] = trig_canon<2>(L, s.y[j], a.beta, tc[j]);
+    const float tj = m0 * s.F[j];
+    const bool up = j == 0 || tj > s.tau[j > 0 ? j - 1 : 0];
+    s.tau[j] = up ? tj : s.tau[j > 0 ? j - 1 : 0];
+    src[j] = up ? j : src[j > 0 ? j - 1 : 0];
+  }
+  quad_terms<2, NQ>(g, tn, s);
 }
 
 // Double-precision dual number (one tangent) for the Jacobian of the
@@ -406,12 +434,20 @@ __device__ __forceinline__ void reduce_to_slots(float* gr, bool act, int j, int 
   carry_j = (jl == cont_j) ? cont_j : -1;
 }
 
-// SUR: the backward pass through the learned surrogate (the forward pass was
-// mb_render_forward_surrogate): the optical depth at every edge is m_0 F with
-// F and dF/d(inputs) from the query list, and the adjoint reaches the moments
-// through the surrogate's inputs instead of the moment bounds.
-template <int K, int NQ, int SUR>
-__global__ __launch_bounds__(256, (K <= 6 && NQ == 4 && !SUR) ? 3 : 2) void k_render_bwd(BwdArgs ba, CamSet cams) {
+// MODE 0: the moment bounds of Sec. 3.2 (power moments).
+// MODE 1: the backward pass through the learned surrogate (the forward pass
+// was mb_render_forward_surrogate): the optical depth at every edge is m_0 F
+// with F and dF/d(inputs) from the query list, and the adjoint reaches the
+// moments through the surrogate's inputs instead of the moment bounds.
+// MODE 2: trigonometric moments (K = 4: two complex moments), the adjoint of
+// the reconstruction on the circle (trig_adjoint) and of Eq. 14
+// (trig_moment_grads) in place of the power moments'.
+template <int K, int NQ, int MODE>
+__global__ __launch_bounds__(256, (K <= 6 && NQ == 4 && MODE == 0) ? 3 : 2) void k_render_bwd(BwdArgs ba,
+                                                                                              CamSet cams) {
+  constexpr bool SUR = MODE == 1;
+  constexpr bool TRIG = MODE == 2;
+  static_assert(!TRIG || K == 4, "the trigonometric path takes two complex moments");
   constexpr int NH = K / 2;
   constexpr int NL = (NH + 1) * (NH + 2) / 2;
   constexpr int RS = (K + 4) / 4 * 4;  // plain pass 2: K + 1 adjoint moments per pair, padded to float4s
@@ -501,6 +537,7 @@ __global__ __launch_bounds__(256, (K <= 6 && NQ == 4 && !SUR) ? 3 : 2) void k_re
   const float m0 = (float)acc[0];
   const bool live = acc[0] > kMinDepth;  // as in the forward pass
   LInv<NH> L;
+  TrigLInv<TRIG ? NH : 1> TL;
   float bk[K + 1];
   bk[0] = 1.f;
   float mix_eps = 0.f;  // the forward pass's mixture weight (degenerate measures)
@@ -512,8 +549,18 @@ __global__ __launch_bounds__(256, (K <= 6 && NQ == 4 && !SUR) ? 3 : 2) void k_re
       bn[k] = acc[k] / acc[0];
       bk[k] = (float)bn[k];
     }
-    mix_eps = (float)hankel_factor<NH>(bn, L, bmix);
+    if constexpr (TRIG) {
+      mix_eps = (float)trig_factor<NH>(acc, TL);
+#pragma unroll
+      for (int i = 0; i < NL; ++i) L.l[i] = 0.f;
+    } else {
+      mix_eps = (float)hankel_factor<NH>(bn, L, bmix);
+    }
   } else {
+    if constexpr (TRIG) {
+#pragma unroll
+      for (int i = 0; i < NL; ++i) TL.re[i] = TL.im[i] = 0.f;
+    }
 #pragma unroll
     for (int k = 1; k <= K; ++k) bk[k] = 0.f;
 #pragma unroll
@@ -708,8 +755,17 @@ __global__ __launch_bounds__(256, (K <= 6 && NQ == 4 && !SUR) ? 3 : 2) void k_re
       const bool act = item_of(n, j, p);
       const PixelBasis pp = basis_of(p);
       LInv<NH> Lp;
+      TrigLInv<TRIG ? NH : 1> TLp;
+      if constexpr (TRIG) {
 #pragma unroll
-      for (int i = 0; i < NL; ++i) Lp.l[i] = from_lane(L.l[i], p);
+        for (int i = 0; i < NL; ++i) {
+          TLp.re[i] = from_lane(TL.re[i], p);
+          TLp.im[i] = from_lane(TL.im[i], p);
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < NL; ++i) Lp.l[i] = from_lane(L.l[i], p);
+      }
       const float lamp = from_lane(lam, p), m0p = from_lane(m0, p);
       float gap[3] = {from_lane(ga[0], p), from_lane(ga[1], p), from_lane(ga[2], p)};
       const float gbp = from_lane(gb, p);
@@ -726,7 +782,13 @@ __global__ __launch_bounds__(256, (K <= 6 && NQ == 4 && !SUR) ? 3 : 2) void k_re
         offsets_of(j, p, dx, dy);
         RayG g = ray_params(st, j, dx, dy, lamp);
         QuadState<NH, NQ> s;
-        quad_state<NH, NQ>(g, pp, Lp, m0p, tn, a, s);
+        TrigCanon tc[TRIG ? NQ : 1];
+        int src[NQ];
+        if constexpr (TRIG) {
+          trig_quad_state<NQ>(g, TLp, m0p, tn, a, s, tc, src);
+        } else {
+          quad_state<NH, NQ>(g, pp, Lp, m0p, tn, a, s);
+        }
         float4 f5 = st.f[5][j];
         float gbar = gap[0] * f5.y + gap[1] * f5.z + gap[2] * f5.w + gbp;
         // consistency penalty (App. E): dP/dtau at the edges (bq, scaled by the
@@ -764,19 +826,43 @@ __global__ __launch_bounds__(256, (K <= 6 && NQ == 4 && !SUR) ? 3 : 2) void k_re
         for (int k = 0; k <= K; ++k) d[k] = 0.f;
         // (radiance + penalty) gradient at fixed moments: through tau at the
         // edges (which move with mu and Sigma) and the Eq. 7 interval terms
+        if constexpr (TRIG) {
+          // dL/dtau gathered onto the edges whose queries supplied it
+          float wsrc[NQ];
 #pragma unroll
-        for (int e = 0; e < NQ; ++e) {
-          float lamk[2 * NH + 1], dl;
-          hermite_adjoint<NH>(s.y[e], s.x[e], s.below[e], a.beta, lamk, dl);
-          float wgt = gbar * s.A[e] + bq[e];
+          for (int e = 0; e < NQ; ++e) wsrc[e] = 0.f;
 #pragma unroll
-          for (int k = 1; k <= K; ++k) d[k] += wgt * lamk[k];
-          d[0] += wgt * s.F[e];  // minus sum_k b_k d[k], taken once after the edges
-          float dtau_dt = -m0p * s.w0[e] * dl * warp_dy(pp, s.t[e]);
-          float dtdmu = s.cl[e] ? 0.f : 1.f;
-          float dtdsig = s.cl[e] ? 0.f : a.kappa * a.xq[e];
-          gmu += wgt * dtau_dt * dtdmu;
-          gsig += wgt * dtau_dt * dtdsig;
+          for (int e = 0; e < NQ; ++e) {
+#pragma unroll
+            for (int e2 = 0; e2 <= e; ++e2) wsrc[e2] += src[e] == e2 ? gbar * s.A[e] + bq[e] : 0.f;
+          }
+#pragma unroll
+          for (int e = 0; e < NQ; ++e) {
+            float gk[5], dpsi;
+            trig_adjoint(s.y[e], tc[e], a.beta, gk, dpsi);
+            const float wgt = wsrc[e];
+#pragma unroll
+            for (int k = 1; k <= K; ++k) d[k] += wgt * gk[k];
+            d[0] += wgt * s.F[e];
+            const float dtau_dt = m0p * dpsi * kTrigSpan * warp_abs_d(s.t[e], tn);
+            gmu += wgt * dtau_dt * (s.cl[e] ? 0.f : 1.f);
+            gsig += wgt * dtau_dt * (s.cl[e] ? 0.f : a.kappa * a.xq[e]);
+          }
+        } else {
+#pragma unroll
+          for (int e = 0; e < NQ; ++e) {
+            float lamk[2 * NH + 1], dl;
+            hermite_adjoint<NH>(s.y[e], s.x[e], s.below[e], a.beta, lamk, dl);
+            float wgt = gbar * s.A[e] + bq[e];
+#pragma unroll
+            for (int k = 1; k <= K; ++k) d[k] += wgt * lamk[k];
+            d[0] += wgt * s.F[e];  // minus sum_k b_k d[k], taken once after the edges
+            float dtau_dt = -m0p * s.w0[e] * dl * warp_dy(pp, s.t[e]);
+            float dtdmu = s.cl[e] ? 0.f : 1.f;
+            float dtdsig = s.cl[e] ? 0.f : a.kappa * a.xq[e];
+            gmu += wgt * dtau_dt * dtdmu;
+            gsig += wgt * dtau_dt * dtdsig;
+          }
         }
 #pragma unroll
         for (int k = 1; k <= K; ++k) d[0] -= bkp[k] * d[k];  // the tau = m_0 F(b) chain at b = m / m_0
@@ -879,7 +965,13 @@ __global__ __launch_bounds__(256, (K <= 6 && NQ == 4 && !SUR) ? 3 : 2) void k_re
       D[k] = dm[k];
     }
     if (mix_eps > 0.f) {
-      mixture_adjoint<K + 1>(bn, (double)mix_eps, D);
+      if constexpr (TRIG) {
+        // mixed with the uniform measure on the circle: c' = (1 - eps) c + eps e_0
+#pragma unroll
+        for (int k = 1; k <= K; ++k) D[k] *= 1.0 - (double)mix_eps;
+      } else {
+        mixture_adjoint<K + 1>(bn, (double)mix_eps, D);
+      }
     } else {
 #pragma unroll
       for (int k = 1; k <= K; ++k) D[k] = 0.0;
@@ -912,7 +1004,10 @@ __global__ __launch_bounds__(256, (K <= 6 && NQ == 4 && !SUR) ? 3 : 2) void k_re
         offsets_of(j, p, dx, dy);
         RayG g = ray_params(st, j, dx, dy, lamp);
         float gm[3];
-        moment_grads<K>(g, pp, tn, dmp, gm);
+        if constexpr (TRIG)
+          trig_moment_grads<NH>(g, tn, dmp, gm);
+        else
+          moment_grads<K>(g, pp, tn, dmp, gm);
         chain_record(gm[0], gm[1], gm[2], g, lamp, dx, dy, st.f[2][j], st.f[3][j], st.f[4][j], gr);
       }
       reduce_to_slots<true>(gr, act, j, n, lane, cont_j, carry_j, cw, ba.partials, sk, quad, &prev);
@@ -938,12 +1033,12 @@ __global__ __launch_bounds__(256, (K <= 6 && NQ == 4 && !SUR) ? 3 : 2) void k_re
 hipError_t launch_render_backward(const RenderArgs& r, const float* saved, const float* grad_image,
                                   const float* grad_penalty, const int* sorted_k, float* partials,
                                   const CamSet& cams, int n_moments, int n_intervals, hipStream_t s,
-                                  bool surrogate) {
+                                  int mode) {
   BwdArgs ba{r, saved, grad_image, grad_penalty, sorted_k, partials};
   int n_keys = r.tiles_x * r.tiles_y * r.n_cams;
   dim3 grid(render_blocks(n_keys)), block(kBlock);
 #define MB_LAUNCH(KK, NN, SS)                                                          \
-  if (n_moments == KK && n_intervals == NN && (int)surrogate == SS) {                  \
+  if (n_moments == KK && n_intervals == NN && mode == SS) {                            \
     hipLaunchKernelGGL((k_render_bwd<KK, NN + 1, SS>), grid, block, 0, s, ba, cams); \
     return hipGetLastError();                                                          \
   }
@@ -955,6 +1050,8 @@ hipError_t launch_render_backward(const RenderArgs& r, const float* saved, const
   MB_LAUNCH(8, 5, 0)
   MB_LAUNCH(6, 3, 1)
   MB_LAUNCH(6, 5, 1)
+  MB_LAUNCH(4, 3, 2)
+  MB_LAUNCH(4, 5, 2)
 #undef MB_LAUNCH
   return hipErrorInvalidValue;
 }

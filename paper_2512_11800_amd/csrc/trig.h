@@ -259,9 +259,16 @@ __device__ __forceinline__ float arc_pos(cfl z) {
   return a < 0.f ? a + 6.283185307179586f : a;
 }
 
-// F = sum_{atoms before w} lambda_i + beta lambda_0 at the query angle psi
+// The canonical representation through w = e^{i psi}: the other atoms, their
+// flags (before w along the cut circle) and the weight lambda_0 at w; returns
+// F = sum_{atoms before w} lambda_i + beta lambda_0.
+struct TrigCanon {
+  cfl z1, z2;
+  bool b1, b2;
+  float lam0;
+};
 template <int NH>
-__device__ __forceinline__ float trig_F(const TrigLInv<NH>& L, float psi, float beta) {
+__device__ __forceinline__ float trig_canon(const TrigLInv<NH>& L, float psi, float beta, TrigCanon& out) {
   static_assert(NH == 2, "the trigonometric reconstruction is built for two complex moments");
   cfl w;
   sincosf(psi, &w.im, &w.re);
@@ -289,10 +296,138 @@ __device__ __forceinline__ float trig_F(const TrigLInv<NH>& L, float psi, float 
   const cfl qq = {-0.5f * (a[1].re + sq.re), -0.5f * (a[1].im + sq.im)};
   const cfl z1 = cdiv(qq, a[2]), z2 = cdiv(a[0], qq);
   const float pw = arc_pos(w);
+  out.z1 = z1;
+  out.z2 = z2;
+  out.b1 = arc_pos(z1) < pw;
+  out.b2 = arc_pos(z2) < pw;
+  out.lam0 = lam0;
   float f = beta * lam0;
-  f += arc_pos(z1) < pw ? trig_christoffel<NH>(L, z1) : 0.f;
-  f += arc_pos(z2) < pw ? trig_christoffel<NH>(L, z2) : 0.f;
+  f += out.b1 ? trig_christoffel<NH>(L, z1) : 0.f;
+  f += out.b2 ? trig_christoffel<NH>(L, z2) : 0.f;
   return f;
+}
+
+// F = sum_{atoms before w} lambda_i + beta lambda_0 at the query angle psi
+template <int NH>
+__device__ __forceinline__ float trig_F(const TrigLInv<NH>& L, float psi, float beta) {
+  TrigCanon c;
+  return trig_canon<NH>(L, psi, beta, c);
+}
+
+// Adjoint of F through the moment equations sum_i lambda_i e^{i k theta_i} =
+// c_k, k = 0, 1, 2 (five real equations; theta_0 = psi fixed; unknowns the
+// three weights and the two other angles): the real trigonometric polynomial
+//   Lambda(theta) = g0 + g1 cos theta + g2 sin theta + g3 cos 2theta + g4 sin 2theta
+// with Lambda(theta_i) = [atom i before w], Lambda'(theta_i) = 0 (i = 1, 2)
+// and Lambda(psi) = beta gives dF/d(c_0, Re c_1, Im c_1, Re c_2, Im c_2) = g,
+// and dF/dpsi = -lambda_0 Lambda'(psi) (differentiate sum_i lambda_i
+// Lambda(theta_i) = sum_k g_k c_k). The 5 x 5 system is solved by Gaussian
+// elimination with partial pivoting; a singular one (coincident atoms) passes
+// no gradient.
+__device__ __forceinline__ void trig_adjoint(float psi, const TrigCanon& c, float beta, float* g, float& dF_dpsi) {
+  float sp, cp;
+  sincosf(psi, &sp, &cp);
+  const float n1 = rsqrtf(fmaxf(cabs2(c.z1), 1e-30f)), n2 = rsqrtf(fmaxf(cabs2(c.z2), 1e-30f));
+  const float c1 = c.z1.re * n1, s1 = c.z1.im * n1, c2 = c.z2.re * n2, s2 = c.z2.im * n2;
+  float M[5][6] = {
+      {1.f, cp, sp, cp * cp - sp * sp, 2.f * cp * sp, beta},
+      {1.f, c1, s1, c1 * c1 - s1 * s1, 2.f * c1 * s1, c.b1 ? 1.f : 0.f},
+      {1.f, c2, s2, c2 * c2 - s2 * s2, 2.f * c2 * s2, c.b2 ? 1.f : 0.f},
+      {0.f, -s1, c1, -4.f * c1 * s1, 2.f * (c1 * c1 - s1 * s1), 0.f},
+      {0.f, -s2, c2, -4.f * c2 * s2, 2.f * (c2 * c2 - s2 * s2), 0.f}};
+  bool ok = true;
+#pragma unroll
+  for (int col = 0; col < 5; ++col) {
+    // partial pivoting over the rows below (selects keep it branch free)
+#pragma unroll
+    for (int r = col + 1; r < 5; ++r) {
+      const bool sw = fabsf(M[r][col]) > fabsf(M[col][col]);
+#pragma unroll
+      for (int k = col; k < 6; ++k) {
+        const float t = M[col][k];
+        M[col][k] = sw ? M[r][k] : t;
+        M[r][k] = sw ? t : M[r][k];
+      }
+    }
+    ok = ok && fabsf(M[col][col]) > 1e-7f;
+    const float ip = ok ? fast_rcp(M[col][col]) : 0.f;
+#pragma unroll
+    for (int r = col + 1; r < 5; ++r) {
+      const float f = M[r][col] * ip;
+#pragma unroll
+      for (int k = col + 1; k < 6; ++k) M[r][k] = fmaf(-f, M[col][k], M[r][k]);
+    }
+  }
+#pragma unroll
+  for (int r = 4; r >= 0; --r) {
+    float v = M[r][5];
+#pragma unroll
+    for (int k = r + 1; k < 5; ++k) v = fmaf(-M[r][k], g[k], v);
+    g[r] = ok ? v * fast_rcp(M[r][r]) : 0.f;
+  }
+  const float dl = -g[1] * sp + g[2] * cp - 4.f * g[3] * cp * sp + 2.f * g[4] * (cp * cp - sp * sp);
+  dF_dpsi = -c.lam0 * dl;
+}
+
+// sum_k dm[k] d c_k / d(mu, Sigma, omega) for one Gaussian's moments (as
+// particle_trig_moments_d computes them; dm over (c_0, Re c_1, Im c_1, ..)),
+// from the derivatives of their factors: amplitude omega Sigma sqrt(pi / 2),
+// erfc(a), the first-order erf term k b e^{-a^2}, the damping D^(k^2) and the
+// phase e^{i k alpha_1 G}.
+template <int NH>
+__device__ __forceinline__ void trig_moment_grads(const RayG& g, float tn, const float* dm, float* out) {
+  const bool unc = g.mu > tn;
+  const float mus = fmaxf(g.mu, tn);
+  const float gp = warp_abs_d(mus, tn);
+  const float gpp = unc ? -2.f * gp * fast_rcp(1.f + 0.8f * mus) : 0.f;  // g_hat'' (0 when linearised at t_n)
+  const float G = warp_abs(mus, tn) + gp * (g.mu - mus);
+  const float is = fast_rcp(g.sig);
+  const float a = (tn - g.mu) * kInvSqrt2 * is;
+  const float E = __expf(-a * a);
+  const float ec = erfc_fast(a);
+  const float amp1 = g.sig * kSqrtHalfPi;  // amplitude over omega
+  const float amp = g.omega * amp1;
+  const float Cb = kTrigSpan * kInvSqrt2 * 1.1283791670955126f;
+  const float eb = Cb * g.sig * gp * E;
+  const float sa = g.sig * kTrigSpan * gp;
+  // d/dmu (index 0) and d/dSigma (index 1) of the factors
+  const float da[2] = {-kInvSqrt2 * is, -a * is};
+  const float dgp[2] = {gpp, 0.f};
+  const float dphi[2] = {kTrigSpan * gp, 0.f};
+  const float damp_rel[2] = {0.f, is};
+  const float dsa[2] = {g.sig * kTrigSpan * gpp, kTrigSpan * gp};
+  float dec[2], deb[2];
+#pragma unroll
+  for (int d = 0; d < 2; ++d) {
+    const float dE = -2.f * a * E * da[d];
+    dec[d] = -1.1283791670955126f * E * da[d];
+    deb[d] = Cb * ((d == 1 ? gp * E : 0.f) + g.sig * (dgp[d] * E + gp * dE));
+  }
+  float gd[2];
+#pragma unroll
+  for (int d = 0; d < 2; ++d) gd[d] = dm[0] * amp * (dec[d] + ec * damp_rel[d]);
+  float gom = dm[0] * amp1 * ec;
+  float sn, cs;
+  sincosf(kTrigSpan * G, &sn, &cs);
+  cfl zk = {1.f, 0.f};
+#pragma unroll
+  for (int k = 1; k <= NH; ++k) {
+    zk = cmul(zk, {cs, sn});
+    const float kf = (float)k;
+    const float Dk = __expf(-0.5f * kf * kf * sa * sa);
+    const cfl base = cmul(zk, {ec * Dk, kf * eb * Dk});  // c_k / amp
+    gom += amp1 * (dm[2 * k - 1] * base.re + dm[2 * k] * base.im);
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+      const float dlnD = -kf * kf * sa * dsa[d];
+      const cfl t1 = cmul(base, {damp_rel[d] + dlnD, kf * dphi[d]});
+      const cfl t2 = cmul(zk, {dec[d] * Dk, kf * deb[d] * Dk});
+      gd[d] += amp * (dm[2 * k - 1] * (t1.re + t2.re) + dm[2 * k] * (t1.im + t2.im));
+    }
+  }
+  out[0] = gd[0];
+  out[1] = gd[1];
+  out[2] = gom;
 }
 
 // Quadrature of Eq. 7 for one Gaussian against the circle's reconstruction:

@@ -728,12 +728,17 @@ def test_multicolour_image_close_to_ray_marched_vre():
 # Gradients: float64 autograd of the oracle vs central finite differences.
 # ---------------------------------------------------------------------------
 
-def test_oracle_gradients_vs_central_differences():
+@pytest.mark.parametrize("basis", ["power", "trigonometric"])
+def test_oracle_gradients_vs_central_differences(basis):
+    """Autograd through the whole oracle render (for the trigonometric basis
+    also through the Toeplitz solves and the kernel polynomial's roots on the
+    circle) against central differences of its image."""
     scene = _tiny_scene(4, 4)
     scene.colors = np.random.default_rng(4).normal(0, 0.3, (4, 4, 3)).astype(np.float32)
     scene.sh_degree = 1
     cam = W.camera_on_axis(2.0, 8, 8)
     opts = W.Options(n_moments=4, full_coverage=True)
+    opts.basis = basis
     g_img = np.random.default_rng(5).normal(size=(64, 3))
     grads = oracle.render_backward(scene, cam, opts, g_img)
 
