@@ -170,11 +170,20 @@ __device__ __forceinline__ void load_batch(Stage& st, const float4* rec, const i
 // wherever its margin to an edge exceeds `band`, a bound on its rounding
 // error: the record's centre offset, axis and halves are the double values
 // rounded to float (relative 2^-24), and the set-up and per-pixel operations
-// round relative 2^-24 each on values of at most |a| + 32 + h (a: the tile
-// origin's offset from the centre); 2e-6 times the sum of those magnitudes is
-// more than ten times the worst case. Near an edge the wave re-tests in
-// double against rectd. Only the first pass tests coverage: every later
-// pass, forward and backward, reads the masks it stores.
+// round relative 2^-24 each; summed, the error stays below
+// 2^-24 (9 (|a_x| + |a_y|) + 2 (|o_x| + |o_y|) + 2 (h1 + h2) + 100) (a: the
+// tile origin's offset from the rectangle's centre, o: the centre's offset
+// from the projected mean), and the band 1e-6 (16 + |a_x| + |a_y| + |o_x| +
+// |o_y| + h1 + h2) is about twice that. Near an edge the wave re-tests in
+// double against rectd. Only the first pass tests coverage: every later pass,
+// forward and backward, reads the masks it stores.
+//
+// The set-up lives in LDS the kernel already holds: (c1, c2) at the tile
+// origin replace the staged record's centre offset (st.f[0][j].zw, which
+// the first pass reads nowhere else and the later passes stage again), and
+// the band shares a 32-bit word with the quadrant bits (cover_word: the band's
+// four low mantissa bits carry them; clearing them lowers the band by a
+// relative 2^-19 at most).
 //
 // cover_setup also returns the 8x8 quadrants of the tile the rectangle can
 // reach (bit q for quadrant q = 2 row + column): those whose pixel-centre
@@ -182,20 +191,20 @@ __device__ __forceinline__ void load_batch(Stage& st, const float4* rec, const i
 // within h + 3.5 (|e1x| + |e1y|) of the rectangle along both of its axes
 // (the separating-axis test of two rectangles); a margin beyond the
 // rounding bound keeps the bits from ever missing a covered pixel.
-__device__ __forceinline__ uint8_t cover_setup(const Stage& st, int j, int xt, int yt, float4& cb) {
+__device__ __forceinline__ uint32_t cover_setup(Stage& st, int j, int xt, int yt) {
   const float4 f0 = st.f[0][j], f1 = st.f[1][j];
   const float ax = ((float)xt + 0.5f - f0.x) - f0.z;
   const float ay = ((float)yt + 0.5f - f0.y) - f0.w;
   const float a1 = ax * f1.x + ay * f1.y;
   const float a2 = ay * f1.x - ax * f1.y;
-  const float band = 2e-6f * (33.f + fabsf(ax) + fabsf(ay) + fabsf(f0.z) + fabsf(f0.w) + f1.z + f1.w);
-  cb = make_float4(a1, a2, band, 0.f);
+  const float band = 1e-6f * (16.f + fabsf(ax) + fabsf(ay) + fabsf(f0.z) + fabsf(f0.w) + f1.z + f1.w);
+  st.f[0][j] = make_float4(f0.x, f0.y, a1, a2);
   const float cx = f0.x + f0.z, cy = f0.y + f0.w;
   const float eax = fabsf(f1.x), eay = fabsf(f1.y);
   const float mx = 0.01f + 1e-5f * fabsf(cx), my = 0.01f + 1e-5f * fabsf(cy);
   const float bx = eax * f1.z + eay * f1.w + mx, by = eay * f1.z + eax * f1.w + my;
   const float reach = 3.5f * (eax + eay) + band + 0.01f;
-  uint8_t bits = 0;
+  uint32_t bits = 0;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const float lx = (float)(xt + (q & 1) * 8) + 0.5f, ly = (float)(yt + (q >> 1) * 8) + 0.5f;
@@ -204,22 +213,24 @@ __device__ __forceinline__ uint8_t cover_setup(const Stage& st, int j, int xt, i
     const float c1 = a1 + qi * f1.x + qj * f1.y;
     const float c2 = a2 - qi * f1.y + qj * f1.x;
     const bool sat = fabsf(c1) <= f1.z + reach && fabsf(c2) <= f1.w + reach;
-    bits |= (box && sat) ? (uint8_t)(1u << q) : (uint8_t)0;
+    bits |= (box && sat) ? (1u << q) : 0u;
   }
-  return bits;
+  return (__float_as_uint(band) & ~15u) | bits;
 }
 
-// The per-pixel test of entry j (cb: its cover_setup values) for the pixel at
-// offset (fi, fj) from the tile's first pixel, centre (u, v).
-__device__ __forceinline__ bool covers(const Stage& st, const float4* cbase, const double2* rectd,
-                                       const int* sorted_rec, int b, int j, float fi, float fj, float u, float v,
-                                       bool inside) {
-  const float4 cb = cbase[j], f1 = st.f[1][j];
-  const float c1 = fmaf(fj, f1.y, fmaf(fi, f1.x, cb.x));
-  const float c2 = fmaf(fj, f1.x, fmaf(fi, -f1.y, cb.y));
+__device__ __forceinline__ bool cover_reaches(uint32_t word, int quad) { return (word >> quad) & 1u; }
+__device__ __forceinline__ float cover_band(uint32_t word) { return __uint_as_float(word & ~15u); }
+
+// The per-pixel test of entry j (after cover_setup; `word` its set-up word)
+// for the pixel at offset (fi, fj) from the tile's first pixel, centre (u, v).
+__device__ __forceinline__ bool covers(const Stage& st, uint32_t word, const double2* rectd, const int* sorted_rec,
+                                       int b, int j, float fi, float fj, float u, float v, bool inside) {
+  const float4 f0 = st.f[0][j], f1 = st.f[1][j];
+  const float c1 = fmaf(fj, f1.y, fmaf(fi, f1.x, f0.z));
+  const float c2 = fmaf(fj, f1.x, fmaf(fi, -f1.y, f0.w));
   const float m = fminf(f1.z - fabsf(c1), f1.w - fabsf(c2));
   bool cov = inside && m >= 0.f;
-  const bool amb = inside && fabsf(m) < cb.z;
+  const bool amb = inside && fabsf(m) < cover_band(word);
   if (__ballot(amb) != 0) {
     const int rid = __builtin_amdgcn_readfirstlane(sorted_rec[b + j]);
     const double2 cd = rectd[(size_t)rid * 3], ed = rectd[(size_t)rid * 3 + 1], hd = rectd[(size_t)rid * 3 + 2];

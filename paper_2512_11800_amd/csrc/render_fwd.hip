@@ -112,8 +112,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
   const size_t pix = ((size_t)ci * c.height + (inside ? py : 0)) * c.width + (inside ? px : 0);
 
   __shared__ WaveQueue wq[4];
-  __shared__ uint8_t reach[kBlock];  // per staged entry: bit q set if it can reach the tile's quadrant q
-  __shared__ float4 cbase[kBlock];   // per staged entry: its coverage test's set-up (cover_setup)
+  __shared__ uint32_t reach[kBlock];  // per staged entry: its coverage set-up word (cover_setup)
   // per-wave results of the queued pairs: 3 or K + 1 floats per pair in passes
   // 0 and 1, q (r, g, b, 1) in pass 2
   // (K = 8 and the trigonometric moments pass their moments in double:
@@ -176,7 +175,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
       __syncthreads();
       load_batch(st, a.rec, a.sorted_rec, b, nb);
       // each thread reads back the record it staged itself
-      if (tid < nb) reach[tid] = cover_setup(st, tid, tx * kTile, ty * kTile, cbase[tid]);
+      if (tid < nb) reach[tid] = cover_setup(st, tid, tx * kTile, ty * kTile);
       __syncthreads();
       QueueCursor qc;
       queue_reset(qc);
@@ -186,13 +185,13 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
       for (int j0 = 0; j0 < nb; j0 += 64) {
         const int jl = j0 + lane;
         const bool mine = jl < nb && (own4 < 0 || (jl & 3) == own4);
-        const bool near = mine && ((reach[mine ? jl : 0] >> quad) & 1);
+        const bool near = mine && cover_reaches(reach[mine ? jl : 0], quad);
         if (mine && !near) a.masks[(size_t)(b + jl) * 4 + quad] = 0ull;
         uint64_t todo = __ballot(near);
         while (todo) {
           const int j = j0 + __builtin_ctzll(todo);
           todo &= todo - 1;
-          const bool cov = covers(st, cbase, a.rectd, a.sorted_rec, b, j, fi, fj, u, v, inside);
+          const bool cov = covers(st, reach[j], a.rectd, a.sorted_rec, b, j, fi, fj, u, v, inside);
           uint64_t mask = __ballot(cov);
           if (lane == 0) a.masks[(size_t)(b + j) * 4 + quad] = mask;
           if (mask == 0) continue;

@@ -14,7 +14,7 @@ import oracle
 import workloads as W
 from oracle.proxy import screen_proxy
 from oracle.render import scene_tensors
-from tests.gpu_helpers import log, proxy_error, tolerances
+from tests.gpu_helpers import gpu_render, log, proxy_error, tolerances
 
 pytestmark = pytest.mark.gpu
 
@@ -120,8 +120,8 @@ def test_w1_proxy_coverage_vs_oracle_autograd():
     assert _check(gpu, ref, "W1")
 
 
-@pytest.mark.parametrize("k_mom", [4, 6])
-def test_w3_full_size_sampled_gaussians(k_mom):
+@pytest.mark.parametrize("k_mom,basis", [(4, "power"), (6, "power"), (4, "trigonometric")])
+def test_w3_full_size_sampled_gaussians(k_mom, basis):
     """1M Gaussians at 1600x1064 (the benchmark's training configuration, in
     its launch configuration): gradients of sampled Gaussians, each computed by
     the oracle from every pixel its rectangle's box reaches. The sample mixes
@@ -132,6 +132,7 @@ def test_w3_full_size_sampled_gaussians(k_mom):
     sampled pixel."""
     scene, _, cams, opts = W.w3_train()
     opts.n_moments = k_mom
+    opts.basis = basis
     cam = cams[0]
     prox = screen_proxy(scene_tensors(scene), cam, opts.conf_c)
     rng = np.random.default_rng(14 + k_mom)
@@ -171,8 +172,13 @@ def test_w3_full_size_sampled_gaussians(k_mom):
     sub = _touching(prox, lo, hi, cam, pix)
     assert np.isin(sample, sub).all()
     sub_scene = scene.subset(sub)
-    amb = oracle.render_image(sub_scene, cam, opts, pixels=pix, margin_tol=tol_m, orient_eps=tol_o,
-                              max_pixels=len(pix))["ambiguous"]
+    ref_img = oracle.render_image(sub_scene, cam, opts, pixels=pix, margin_tol=tol_m, orient_eps=tol_o,
+                                  max_pixels=len(pix))
+    # no upstream gradient where the coverage decision is ambiguous or the
+    # degenerate-measure flags of the two sides differ
+    _, saved, _ = gpu_render(scene, cams, opts, on_device=True)
+    flag_gpu = saved[0].reshape(-1, 8)[pix, 7] < 0
+    amb = ref_img["ambiguous"] | (flag_gpu != ref_img["fallback"])
     assert amb.sum() <= 0.01 * len(pix)
     g_full = np.zeros((cam.width * cam.height, 3))
     vals = rng.normal(size=(len(pix), 3))
@@ -180,9 +186,9 @@ def test_w3_full_size_sampled_gaussians(k_mom):
     g_full[pix] = vals
     gpu, _ = _gpu_grads(scene, cams, opts, g_full, on_device=True)
     ref = oracle.render_backward(sub_scene, cam, opts, vals, pixels=pix, max_pixels=len(pix))
-    log(f"[w3 K={k_mom}] sampled {len(sample)} Gaussians over {len(pix)} pixels "
+    log(f"[w3 K={k_mom} {basis}] sampled {len(sample)} Gaussians over {len(pix)} pixels "
         f"({int(amb.sum())} ambiguous), oracle scene {len(sub)} Gaussians")
-    assert _check(gpu, ref, f"W3 K={k_mom} sampled", idx=sample, ref_idx=np.searchsorted(sub, sample))
+    assert _check(gpu, ref, f"W3 K={k_mom} {basis} sampled", idx=sample, ref_idx=np.searchsorted(sub, sample))
 
 
 def _boxes(prox, cam):
