@@ -90,13 +90,28 @@ __device__ __forceinline__ void queue_pop64(WaveQueue& q, QueueCursor& qc, int l
 // empty (after the restriction).
 // In a split block (see BlockWork) a wave takes only the entries j with
 // j % 4 == its wave index (`own4` >= 0); otherwise every entry (`own4` < 0).
-template <class Full, class Empty>
+// PREFETCH: the masks of the next 64 entries are loaded before the current
+// 64 are queued and evaluated, so that their latency hides behind that work
+// (two more registers live across the evaluation: the forward kernels gain,
+// the register-bound backward does not).
+template <bool PREFETCH = false, class Full, class Empty>
 __device__ __forceinline__ void queue_from_masks(WaveQueue& q, QueueCursor& qc, const uint64_t* masks, int b, int nb,
                                                  int quad, int own4, int lane, uint64_t keep, Full&& on_full,
                                                  Empty&& on_empty, QueueRanks* rank = nullptr) {
+  auto load = [&](int j0) __attribute__((always_inline)) {
+    const bool in = j0 + lane < nb && (own4 < 0 || ((j0 + lane) & 3) == own4);
+    return in ? masks[(size_t)(b + j0 + lane) * 4 + quad] : 0ull;
+  };
+  uint64_t next = PREFETCH ? load(0) : 0ull;
   for (int j0 = 0; j0 < nb; j0 += 64) {
     const bool in = j0 + lane < nb && (own4 < 0 || ((j0 + lane) & 3) == own4);
-    const uint64_t mk = in ? (masks[(size_t)(b + j0 + lane) * 4 + quad] & keep) : 0ull;
+    uint64_t mk;
+    if constexpr (PREFETCH) {
+      mk = next & keep;
+      next = j0 + 64 < nb ? load(j0 + 64) : 0ull;
+    } else {
+      mk = load(j0) & keep;
+    }
     if (in && mk == 0) on_empty(j0 + lane);
     uint64_t nz = __ballot(mk != 0);
     while (nz) {
@@ -250,8 +265,10 @@ __device__ __forceinline__ bool covers(const Stage& st, uint32_t word, const dou
 template <class Body>
 __device__ __forceinline__ void for_each_masked(const uint64_t* masks, int b, int nb, int quad, int lane,
                                                 Body&& body) {
+  uint64_t next = lane < nb ? masks[(size_t)(b + lane) * 4 + quad] : 0ull;
   for (int j0 = 0; j0 < nb; j0 += 64) {
-    const uint64_t mk = j0 + lane < nb ? masks[(size_t)(b + j0 + lane) * 4 + quad] : 0ull;
+    const uint64_t mk = next;  // the next 64 masks load while these are walked
+    next = j0 + 64 + lane < nb ? masks[(size_t)(b + j0 + 64 + lane) * 4 + quad] : 0ull;
     uint64_t nz = __ballot(mk != 0);
     while (nz) {
       const int l = __builtin_ctzll(nz);

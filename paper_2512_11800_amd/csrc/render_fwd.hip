@@ -290,7 +290,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
       __syncthreads();
       QueueCursor qc;
       queue_reset(qc);
-      queue_from_masks(q, qc, a.masks, b, nb, quad, own4, lane, ~0ull,
+      queue_from_masks<true>(q, qc, a.masks, b, nb, quad, own4, lane, ~0ull,
                        [&]() __attribute__((always_inline)) {
                          flush(64, qc.own_lo);
                          queue_pop64(q, qc, lane);
@@ -553,7 +553,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
       __syncthreads();
       QueueCursor qc;
       queue_reset(qc);
-      queue_from_masks(q, qc, a.masks, b, nb, quad, own4, lane, live_mask,
+      queue_from_masks<true>(q, qc, a.masks, b, nb, quad, own4, lane, live_mask,
                        [&]() __attribute__((always_inline)) {
                          flush(64, qc.own_lo, b);
                          queue_pop64(q, qc, lane);
@@ -683,6 +683,8 @@ __global__ __launch_bounds__(256) void k_render_consume(RenderArgs a, CamSet cam
 template <int NQ>
 __global__ __launch_bounds__(256) void k_render_consume_tab(RenderArgs a, CamSet cams) {
   __shared__ Stage st;
+  __shared__ WaveQueue wq[4];
+  __shared__ __align__(16) float4 wres[4][64];
   const int tiles_per_cam = a.tiles_x * a.tiles_y;
   const int n_keys = tiles_per_cam * a.n_cams;
   const int key = block_work(a).key;  // the tabulated schedule splits no tile
@@ -692,8 +694,8 @@ __global__ __launch_bounds__(256) void k_render_consume_tab(RenderArgs a, CamSet
   const int ty = tile / a.tiles_x, tx = tile - ty * a.tiles_x;
   const CamConst& c = cams.c[ci];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int px = tx * kTile + (wave & 1) * 8 + (lane & 7);
-  const int py = ty * kTile + (wave >> 1) * 8 + (lane >> 3);
+  const int x0 = tx * kTile + (wave & 1) * 8, y0 = ty * kTile + (wave >> 1) * 8;
+  const int px = x0 + (lane & 7), py = y0 + (lane >> 3);
   const bool inside = px < c.width && py < c.height;
   const float u = (float)px + 0.5f, v = (float)py + 0.5f;
   const float rx = (u - c.cx) / c.fx, ry = (v - c.cy) / c.fy;
@@ -706,38 +708,73 @@ __global__ __launch_bounds__(256) void k_render_consume_tab(RenderArgs a, CamSet
   const bool active = inside && m0 > 0.f;
   const PixelBasis pb = make_basis(inside ? pf[7] : tn, inside ? pf[8] : 1.f, tn);
   const float smu = inside ? pf[10] : 0.f, isig = inside ? 1.f / pf[11] : 1.f;
-  const float* tp = a.tab + pix * a.tab_nodes;
   const float ucoef = (float)(a.tab_nodes - 1) / (2.f * kTabZ);
+  const uint64_t active_mask = __ballot(active);
+  WaveQueue& q = wq[wave];
+  float4* res = wres[wave];
   float sr = 0.f, sg = 0.f, sb = 0.f, so = 0.f;
+  // as the quadrature pass of k_render_fwd: covering pairs evaluated 64 at a
+  // time, one per lane, the results added by the pixel's own lane in list order
+  auto flush = [&](int n, uint64_t own) __attribute__((always_inline)) {
+    const bool act = lane < n;
+    const int it = act ? (int)q.item[lane] : lane;
+    const int j = act ? (it >> 6) : 0;
+    const int p = it & 63;
+    PixelBasis pp;
+    pp.tc = from_lane(pb.tc, p);
+    pp.p = from_lane(pb.p, p);
+    pp.p15 = from_lane(pb.p15, p);
+    pp.amp = from_lane(pb.amp, p);
+    const float m0p = from_lane(m0, p), lamp = from_lane(lam, p);
+    const float smup = from_lane(smu, p), isigp = from_lane(isig, p);
+    if (act) {
+      const int ppx = x0 + (p & 7), ppy = y0 + (p >> 3);
+      const float dx = (float)ppx + 0.5f - st.f[0][j].x;
+      const float dy = (float)ppy + 0.5f - st.f[0][j].y;
+      RayG g = ray_params(st, j, dx, dy, lamp);
+      QEdges<NQ> e;
+      quad_edges<NQ>(g, pp, tn, a, e);
+      const float* tp = a.tab + (((size_t)ci * c.height + ppy) * c.width + ppx) * a.tab_nodes;
+#pragma unroll
+      for (int k = 0; k < NQ; ++k) {
+        const float z = fminf(fmaxf((e.y[k] - smup) * isigp, -kTabZ), kTabZ);
+        const float uu = (z + kTabZ) * ucoef;
+        const int i0 = min((int)uu, a.tab_nodes - 2);
+        const float fr = uu - (float)i0;
+        const float f = fmaf(fr, tp[i0 + 1] - tp[i0], tp[i0]);
+        const float tk = m0p * f;
+        e.tau[k] = (k == 0 || tk > e.tau[k > 0 ? k - 1 : 0]) ? tk : e.tau[k > 0 ? k - 1 : 0];
+      }
+      const float qv = quad_sum<NQ>(g, tn, e);
+      const float4 f5 = st.f[5][j];
+      res[lane] = make_float4(qv * f5.y, qv * f5.z, qv * f5.w, qv);
+    }
+    __builtin_amdgcn_wave_barrier();
+    while (own) {
+      const int i = __builtin_ctzll(own);
+      own &= own - 1;
+      const float4 c4 = res[i];
+      sr += c4.x;
+      sg += c4.y;
+      sb += c4.z;
+      so += c4.w;
+    }
+    __builtin_amdgcn_wave_barrier();
+  };
   for (int b = rg.x; b < rg.y; b += kBlock) {
     int nb = min(kBlock, rg.y - b);
     __syncthreads();
     load_batch(st, a.rec, a.sorted_rec, b, nb);
     __syncthreads();
-    for_each_masked(a.masks, b, nb, wave, lane, [&](int j, uint64_t m) __attribute__((always_inline)) {
-      if (active && ((m >> lane) & 1ull)) {
-        const float dx = u - st.f[0][j].x, dy = v - st.f[0][j].y;
-        RayG g = ray_params(st, j, dx, dy, lam);
-        QEdges<NQ> e;
-        quad_edges<NQ>(g, pb, tn, a, e);
-#pragma unroll
-        for (int k = 0; k < NQ; ++k) {
-          const float z = fminf(fmaxf((e.y[k] - smu) * isig, -kTabZ), kTabZ);
-          const float uu = (z + kTabZ) * ucoef;
-          const int i0 = min((int)uu, a.tab_nodes - 2);
-          const float fr = uu - (float)i0;
-          const float f = fmaf(fr, tp[i0 + 1] - tp[i0], tp[i0]);
-          const float tk = m0 * f;
-          e.tau[k] = (k == 0 || tk > e.tau[k > 0 ? k - 1 : 0]) ? tk : e.tau[k > 0 ? k - 1 : 0];
-        }
-        float q = quad_sum<NQ>(g, tn, e);
-        float4 f5 = st.f[5][j];
-        sr += q * f5.y;
-        sg += q * f5.z;
-        sb += q * f5.w;
-        so += q;
-      }
-    });
+    QueueCursor qc;
+    queue_reset(qc);
+    queue_from_masks<true>(q, qc, a.masks, b, nb, wave, -1, lane, active_mask,
+                           [&]() __attribute__((always_inline)) {
+                             flush(64, qc.own_lo);
+                             queue_pop64(q, qc, lane);
+                           },
+                           [](int) {});
+    if (qc.cnt > 0) flush(qc.cnt, qc.own_lo);
   }
   if (!inside) return;
   float alpha = -expm1f(-m0);
