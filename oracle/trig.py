@@ -46,12 +46,14 @@ Readings taken here (each listed in the design notes):
 * A Toeplitz matrix singular to working precision (a nearly atomic measure)
   is mixed with the uniform measure on the circle, c' = (1 - eps) c +
   eps (1, 0, .., 0), for the first eps of bounds.MIX_EPS whose matrix has
-  every relative Cholesky pivot above PIVOT_REL_TRIG (the rule of
+  every relative Cholesky pivot above pivot_rel_trig(n) (the rule of
   bounds.degenerate_mixture; the uniform measure is the rotation-invariant
-  stand-in for the normal). The threshold is 1e-4, not the power moments'
-  1e-5: the circle has no affine freedom to condition the matrix, and depth
-  measures on it are narrow arcs, so a float32 reconstruction needs the
-  Toeplitz matrix conditioned to about 1e5 or better.
+  stand-in for the normal). The threshold is 1e-4 for two complex moments
+  and 1e-3 for three, not the power moments' 1e-5: the circle has no affine
+  freedom to condition the matrix, and depth measures on it are narrow arcs,
+  so a float32 reconstruction needs the Toeplitz matrix conditioned well
+  (with three moments at 1e-4, a relative moment change of 3e-7, the float
+  rounding of a moment, moved F by up to 0.09; at 1e-3 by 3e-5).
 """
 from __future__ import annotations
 
@@ -66,7 +68,15 @@ from .geometry import DT
 from .moments import warp, warp_prime
 
 THETA = 0.2 * math.pi
-PIVOT_REL_TRIG = 1e-4
+PIVOT_REL_TRIG = {2: 1e-4, 3: 1e-3}
+
+
+def pivot_rel_trig(n: int) -> float:
+    """Relative Cholesky pivot below which n + 1 complex moments count as
+    degenerate (see the module docstring)."""
+    return PIVOT_REL_TRIG[n]
+
+
 CT = torch.complex128
 
 
@@ -117,7 +127,7 @@ def _powers(z: torch.Tensor, n: int) -> torch.Tensor:
 
 def _pivots_pass(c: np.ndarray, n: int) -> np.ndarray:
     """Every Cholesky pivot of T (rows of normalised c, c_0 = 1) above
-    PIVOT_REL_TRIG times its diagonal entry."""
+    pivot_rel_trig(n) times its diagonal entry."""
     idx = np.arange(n + 1)
     d = idx[None, :] - idx[:, None]  # k - j
     t = np.where(d >= 0, c[..., np.abs(d)], np.conj(c[..., np.abs(d)]))
@@ -125,7 +135,7 @@ def _pivots_pass(c: np.ndarray, n: int) -> np.ndarray:
     lc = np.zeros(t.shape, complex)
     for j in range(n + 1):
         piv = (t[..., j, j] - (np.abs(lc[..., j, :j]) ** 2).sum(-1)).real
-        ok &= piv > PIVOT_REL_TRIG * t[..., j, j].real
+        ok &= piv > pivot_rel_trig(n) * t[..., j, j].real
         dj = np.sqrt(np.maximum(piv, 1e-300))
         lc[..., j, j] = dj
         for i in range(j + 1, n + 1):

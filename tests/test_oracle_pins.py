@@ -728,8 +728,8 @@ def test_multicolour_image_close_to_ray_marched_vre():
 # Gradients: float64 autograd of the oracle vs central finite differences.
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("basis", ["power", "trigonometric"])
-def test_oracle_gradients_vs_central_differences(basis):
+@pytest.mark.parametrize("basis,k_mom", [("power", 4), ("trigonometric", 4), ("trigonometric", 6)])
+def test_oracle_gradients_vs_central_differences(basis, k_mom):
     """Autograd through the whole oracle render (for the trigonometric basis
     also through the Toeplitz solves and the kernel polynomial's roots on the
     circle) against central differences of its image."""
@@ -737,7 +737,7 @@ def test_oracle_gradients_vs_central_differences(basis):
     scene.colors = np.random.default_rng(4).normal(0, 0.3, (4, 4, 3)).astype(np.float32)
     scene.sh_degree = 1
     cam = W.camera_on_axis(2.0, 8, 8)
-    opts = W.Options(n_moments=4, full_coverage=True)
+    opts = W.Options(n_moments=k_mom, full_coverage=True)
     opts.basis = basis
     g_img = np.random.default_rng(5).normal(size=(64, 3))
     grads = oracle.render_backward(scene, cam, opts, g_img)
