@@ -83,9 +83,9 @@ typedef struct mb_options {
   float beta;          /* interpolation between the bounds, Sec. 3.2 (0.25)  */
   float eps;           /* clamp of Eq. 15's denominator (1e-6)               */
   int32_t basis;       /* moment basis: 0 power moments (Eqs. 10-12), 1
-                          trigonometric moments (Eqs. 13-14; n_moments = 4,
-                          i.e. two complex moments; not with the surrogate
-                          or the tabulated schedule)                       */
+                          trigonometric moments (Eqs. 13-14; n_moments 4 or
+                          6, i.e. two or three complex moments; not with the
+                          surrogate or the tabulated schedule)             */
   const void *surrogate; /* reserved, NULL                                   */
   int32_t full_coverage; /* debug: every Gaussian covers every pixel        */
   int32_t reserved;

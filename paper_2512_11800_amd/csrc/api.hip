@@ -189,8 +189,8 @@ int check_common(const mb_gaussians* g, const mb_camera* cams, int n_cams, const
   if (!(o->kappa >= 1.f)) return fail(MB_ERR_ARG, "kappa must be >= 1");
   if (!(o->eps > 0.f)) return fail(MB_ERR_ARG, "eps must be positive");
   if (o->basis != 0 && o->basis != 1) return fail(MB_ERR_ARG, "basis %d: 0 (power) or 1 (trigonometric)", o->basis);
-  if (o->basis == 1 && o->n_moments != 4)
-    return fail(MB_ERR_UNSUPPORTED, "trigonometric moments: n_moments 4 (two complex moments) only");
+  if (o->basis == 1 && o->n_moments != 4 && o->n_moments != 6)
+    return fail(MB_ERR_UNSUPPORTED, "trigonometric moments: n_moments 4 or 6 (two or three complex moments)");
   int64_t keys = (int64_t)tiles_of(cams[0].width) * tiles_of(cams[0].height) * n_cams;
   if (keys >= (1ll << 30)) return fail(MB_ERR_ARG, "too many tiles");
   if ((int64_t)g->n * n_cams >= (1ll << 31)) return fail(MB_ERR_ARG, "too many Gaussian-camera pairs");

@@ -102,9 +102,9 @@ __device__ __forceinline__ void quad_state(const RayG& g, const PixelBasis& pb, 
 // psi = (2 pi - theta) g_hat(t) (kept in s.y), the optical depth is a running
 // maximum along the edges, and src[e] names the edge whose query supplied
 // edge e's value (the last edge at or before e that raised it).
-template <int NQ>
-__device__ __forceinline__ void trig_quad_state(const RayG& g, const TrigLInv<2>& L, float m0, float tn,
-                                                const RenderArgs& a, QuadState<2, NQ>& s, TrigCanon* tc,
+template <int NH, int NQ>
+__device__ __forceinline__ void trig_quad_state(const RayG& g, const TrigLInv<NH>& L, float m0, float tn,
+                                                const RenderArgs& a, QuadState<NH, NQ>& s, TrigCanon<NH>* tc,
                                                 int* src) {
 #pragma unroll
   for (int j = 0; j < NQ; ++j) {
@@ -115,13 +115,13 @@ __device__ __forceinline__ void trig_quad_state(const RayG& g, const TrigLInv<2>
     s.y[j] = kTrigSpan * warp_abs(s.t[j], tn);
     const float r = (s.t[j] - g.mu) * fast_rcp(g.sig);
     s.sr[j] = s.cl[j] ? exp_neg_half(r * r) : a.eq[j];
-    s.F[j] = trig_canon<2>(L, s.y[j], a.beta, tc[j]);
+    s.F[j] = trig_canon<NH>(L, s.y[j], a.beta, tc[j]);
     const float tj = m0 * s.F[j];
     const bool up = j == 0 || tj > s.tau[j > 0 ? j - 1 : 0];
     s.tau[j] = up ? tj : s.tau[j > 0 ? j - 1 : 0];
     src[j] = up ? j : src[j > 0 ? j - 1 : 0];
   }
-  quad_terms<2, NQ>(g, tn, s);
+  quad_terms<NH, NQ>(g, tn, s);
 }
 
 // Double-precision dual number (one tangent) for the Jacobian of the
@@ -439,15 +439,15 @@ __device__ __forceinline__ void reduce_to_slots(float* gr, bool act, int j, int 
 // was mb_render_forward_surrogate): the optical depth at every edge is m_0 F
 // with F and dF/d(inputs) from the query list, and the adjoint reaches the
 // moments through the surrogate's inputs instead of the moment bounds.
-// MODE 2: trigonometric moments (K = 4: two complex moments), the adjoint of
-// the reconstruction on the circle (trig_adjoint) and of Eq. 14
-// (trig_moment_grads) in place of the power moments'.
+// MODE 2: trigonometric moments (K = 4 or 6: two or three complex moments),
+// the adjoint of the reconstruction on the circle (trig_adjoint) and of
+// Eq. 14 (trig_moment_grads) in place of the power moments'.
 template <int K, int NQ, int MODE>
 __global__ __launch_bounds__(256, (K <= 6 && NQ == 4 && MODE == 0) ? 3 : 2) void k_render_bwd(BwdArgs ba,
                                                                                               CamSet cams) {
   constexpr bool SUR = MODE == 1;
   constexpr bool TRIG = MODE == 2;
-  static_assert(!TRIG || K == 4, "the trigonometric path takes two complex moments");
+  static_assert(!TRIG || K == 4 || K == 6, "the trigonometric path takes two or three complex moments");
   constexpr int NH = K / 2;
   constexpr int NL = (NH + 1) * (NH + 2) / 2;
   constexpr int RS = (K + 4) / 4 * 4;  // plain pass 2: K + 1 adjoint moments per pair, padded to float4s
@@ -782,10 +782,10 @@ __global__ __launch_bounds__(256, (K <= 6 && NQ == 4 && MODE == 0) ? 3 : 2) void
         offsets_of(j, p, dx, dy);
         RayG g = ray_params(st, j, dx, dy, lamp);
         QuadState<NH, NQ> s;
-        TrigCanon tc[TRIG ? NQ : 1];
+        TrigCanon<NH> tc[TRIG ? NQ : 1];
         int src[NQ];
         if constexpr (TRIG) {
-          trig_quad_state<NQ>(g, TLp, m0p, tn, a, s, tc, src);
+          trig_quad_state<NH, NQ>(g, TLp, m0p, tn, a, s, tc, src);
         } else {
           quad_state<NH, NQ>(g, pp, Lp, m0p, tn, a, s);
         }
@@ -838,8 +838,8 @@ __global__ __launch_bounds__(256, (K <= 6 && NQ == 4 && MODE == 0) ? 3 : 2) void
           }
 #pragma unroll
           for (int e = 0; e < NQ; ++e) {
-            float gk[5], dpsi;
-            trig_adjoint(s.y[e], tc[e], a.beta, gk, dpsi);
+            float gk[K + 1], dpsi;
+            trig_adjoint<NH>(s.y[e], tc[e], a.beta, gk, dpsi);
             const float wgt = wsrc[e];
 #pragma unroll
             for (int k = 1; k <= K; ++k) d[k] += wgt * gk[k];
@@ -1052,6 +1052,8 @@ hipError_t launch_render_backward(const RenderArgs& r, const float* saved, const
   MB_LAUNCH(6, 5, 1)
   MB_LAUNCH(4, 3, 2)
   MB_LAUNCH(4, 5, 2)
+  MB_LAUNCH(6, 3, 2)
+  MB_LAUNCH(6, 5, 2)
 #undef MB_LAUNCH
   return hipErrorInvalidValue;
 }

@@ -822,6 +822,8 @@ hipError_t launch_render_forward(const RenderArgs& a, const CamSet& cams, int n_
   MB_LAUNCH(6, 5, kModeEmit)
   MB_LAUNCH(4, 3, kModeTrig)
   MB_LAUNCH(4, 5, kModeTrig)
+  MB_LAUNCH(6, 3, kModeTrig)
+  MB_LAUNCH(6, 5, kModeTrig)
   MB_LAUNCH(4, 3, kModeTabPlain)
   MB_LAUNCH(6, 3, kModeTabPlain)
   MB_LAUNCH(4, 5, kModeTabPlain)

@@ -102,14 +102,18 @@ __device__ __forceinline__ void particle_trig_moments_d(const RayG& g, float tn,
 }
 
 // Degenerate measures take the power moments' rule (hankel_factor) with the
-// uniform measure in place of the normal, at a relative pivot of 1e-4: the
-// circle has no affine freedom to condition the Toeplitz matrix, and depth
-// measures on it are narrow arcs, so the float reconstruction needs the
-// matrix conditioned to about 1e5 or better.
-constexpr double kPivotRelTrig = 1e-4;
+// uniform measure in place of the normal, at a relative pivot of 1e-4 for two
+// complex moments and 1e-3 for three: the circle has no affine freedom to
+// condition the Toeplitz matrix, and depth measures on it are narrow arcs, so
+// the float reconstruction needs the matrix well conditioned (with three
+// moments at 1e-4, the float rounding of a moment moved F by up to 0.09).
+template <int NH>
+constexpr double pivot_rel_trig() {
+  return NH == 2 ? 1e-4 : 1e-3;
+}
 
 // Cholesky of the Toeplitz matrix of c (c_0 = 1; c given as re/im), every
-// relative pivot above kPivotRelTrig, and the factor when so.
+// relative pivot above pivot_rel_trig, and the factor when so.
 template <int M>
 __device__ __forceinline__ bool toeplitz_chol(const double* cr, const double* ci, double (&lr)[M][M],
                                               double (&li)[M][M]) {
@@ -119,7 +123,7 @@ __device__ __forceinline__ bool toeplitz_chol(const double* cr, const double* ci
     double s = cr[0];
 #pragma unroll
     for (int k = 0; k < j; ++k) s -= lr[j][k] * lr[j][k] + li[j][k] * li[j][k];
-    ok = ok && (s > kPivotRelTrig * cr[0]);
+    ok = ok && (s > pivot_rel_trig<M - 1>() * cr[0]);
     const double d = sqrt(fmax(s, 1e-300));
     lr[j][j] = d;
     li[j][j] = 0.0;
@@ -259,17 +263,73 @@ __device__ __forceinline__ float arc_pos(cfl z) {
   return a < 0.f ? a + 6.283185307179586f : a;
 }
 
-// The canonical representation through w = e^{i psi}: the other atoms, their
-// flags (before w along the cut circle) and the weight lambda_0 at w; returns
-// F = sum_{atoms before w} lambda_i + beta lambda_0.
+// Zeros of the cubic a_0 + a_1 z + a_2 z^2 + a_3 z^3 (complex coefficients):
+// Laguerre's iteration from the query point w (on the circle, never a zero)
+// finds one zero (cubic convergence from almost any start), the quadratic
+// left after dividing it out is solved in stable form, and every zero gets
+// two Newton steps on the cubic. The Laguerre step is taken as
+//   3 p / (p' +- sqrt(2 (2 p'^2 - 3 p p''))),
+// its usual form multiplied through by p, so that nothing divides by p: at a
+// converged zero the fused evaluation of p can fall far below its rounding
+// level, and the usual form's p' / p and its square then overflow float (a
+// NaN zero). (Durand-Kerner from three fixed points of the circle failed to
+// converge in ten steps on 0.2% of a W1 image's queries, where zeros
+// cluster.)
+__device__ __forceinline__ void cubic_roots(const cfl* a, cfl w, cfl* z) {
+  const cfl ia = cdiv({1.f, 0.f}, a[3]);
+  const cfl b0 = cmul(a[0], ia), b1 = cmul(a[1], ia), b2 = cmul(a[2], ia);
+  auto p = [&](cfl x) __attribute__((always_inline)) {  // monic cubic
+    return cadd(cmul(cadd(cmul(cadd(x, b2), x), b1), x), b0);
+  };
+  auto dp = [&](cfl x) __attribute__((always_inline)) {
+    return cadd(cmul(cadd(cfl{3.f * x.re, 3.f * x.im}, cfl{2.f * b2.re, 2.f * b2.im}), x), b1);
+  };
+  cfl r = w;
+#pragma unroll 1
+  for (int it = 0; it < 8; ++it) {
+    const cfl pz = p(r), d1 = dp(r);
+    const cfl d2 = {6.f * r.re + 2.f * b2.re, 6.f * r.im + 2.f * b2.im};
+    const cfl d11 = cmul(d1, d1), pd2 = cmul(pz, d2);
+    const cfl sq = csqrt({4.f * d11.re - 6.f * pd2.re, 4.f * d11.im - 6.f * pd2.im});
+    const cfl dpl = cadd(d1, sq), dmi = csub(d1, sq);
+    const cfl den = cabs2(dpl) >= cabs2(dmi) ? dpl : dmi;
+    if (!(cabs2(den) > 1e-30f)) break;  // a double zero at r (or a non-finite iterate)
+    const cfl step = cdiv({3.f * pz.re, 3.f * pz.im}, den);
+    r = csub(r, step);
+    if (cabs2(step) < 1e-14f) break;  // converged to float resolution (|r| is about 1)
+  }
+  // p(x) = (x - r)(x^2 + c1 x + c0)
+  const cfl c1 = cadd(b2, r);
+  const cfl c0 = cadd(b1, cmul(r, c1));
+  const cfl disc = csub(cmul(c1, c1), cfl{4.f * c0.re, 4.f * c0.im});
+  cfl sq = csqrt(disc);
+  if (c1.re * sq.re + c1.im * sq.im < 0.f) sq = {-sq.re, -sq.im};
+  const cfl q = {-0.5f * (c1.re + sq.re), -0.5f * (c1.im + sq.im)};
+  z[0] = r;
+  z[1] = q;
+  z[2] = cabs2(q) > 1e-30f ? cdiv(c0, q) : cfl{0.f, 0.f};
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+#pragma unroll
+    for (int s2 = 0; s2 < 2; ++s2) {
+      const cfl d = dp(z[i]);
+      if (cabs2(d) > 1e-30f) z[i] = csub(z[i], cdiv(p(z[i]), d));
+    }
+  }
+}
+
+// The canonical representation through w = e^{i psi}: the NH other atoms,
+// their flags (before w along the cut circle) and the weight lambda_0 at w;
+// returns F = sum_{atoms before w} lambda_i + beta lambda_0.
+template <int NH>
 struct TrigCanon {
-  cfl z1, z2;
-  bool b1, b2;
+  cfl z[NH];
+  bool b[NH];
   float lam0;
 };
 template <int NH>
-__device__ __forceinline__ float trig_canon(const TrigLInv<NH>& L, float psi, float beta, TrigCanon& out) {
-  static_assert(NH == 2, "the trigonometric reconstruction is built for two complex moments");
+__device__ __forceinline__ float trig_canon(const TrigLInv<NH>& L, float psi, float beta, TrigCanon<NH>& out) {
+  static_assert(NH == 2 || NH == 3, "the reconstruction is built for two or three complex moments");
   cfl w;
   sincosf(psi, &w.im, &w.re);
   cfl u[NH + 1];
@@ -289,83 +349,117 @@ __device__ __forceinline__ float trig_canon(const TrigLInv<NH>& L, float psi, fl
     for (int j = 0; j <= i; ++j) a[j] = cadd(a[j], cmul(cconj({L.re[o + j], L.im[o + j]}), u[i]));
     o += i + 1;
   }
-  // zeros of a_0 + a_1 z + a_2 z^2 (stable form)
-  const cfl disc = csub(cmul(a[1], a[1]), cmul({4.f * a[2].re, 4.f * a[2].im}, a[0]));
-  cfl sq = csqrt(disc);
-  if (a[1].re * sq.re + a[1].im * sq.im < 0.f) sq = {-sq.re, -sq.im};
-  const cfl qq = {-0.5f * (a[1].re + sq.re), -0.5f * (a[1].im + sq.im)};
-  const cfl z1 = cdiv(qq, a[2]), z2 = cdiv(a[0], qq);
+  if constexpr (NH == 2) {
+    // zeros of a_0 + a_1 z + a_2 z^2 (stable form)
+    const cfl disc = csub(cmul(a[1], a[1]), cmul({4.f * a[2].re, 4.f * a[2].im}, a[0]));
+    cfl sq = csqrt(disc);
+    if (a[1].re * sq.re + a[1].im * sq.im < 0.f) sq = {-sq.re, -sq.im};
+    const cfl qq = {-0.5f * (a[1].re + sq.re), -0.5f * (a[1].im + sq.im)};
+    out.z[0] = cdiv(qq, a[2]);
+    out.z[1] = cdiv(a[0], qq);
+  } else {
+    cubic_roots(a, w, out.z);
+  }
   const float pw = arc_pos(w);
-  out.z1 = z1;
-  out.z2 = z2;
-  out.b1 = arc_pos(z1) < pw;
-  out.b2 = arc_pos(z2) < pw;
   out.lam0 = lam0;
   float f = beta * lam0;
-  f += out.b1 ? trig_christoffel<NH>(L, z1) : 0.f;
-  f += out.b2 ? trig_christoffel<NH>(L, z2) : 0.f;
+#pragma unroll
+  for (int i = 0; i < NH; ++i) {
+    out.b[i] = arc_pos(out.z[i]) < pw;
+    f += out.b[i] ? trig_christoffel<NH>(L, out.z[i]) : 0.f;
+  }
   return f;
 }
 
 // F = sum_{atoms before w} lambda_i + beta lambda_0 at the query angle psi
 template <int NH>
 __device__ __forceinline__ float trig_F(const TrigLInv<NH>& L, float psi, float beta) {
-  TrigCanon c;
+  TrigCanon<NH> c;
   return trig_canon<NH>(L, psi, beta, c);
 }
 
 // Adjoint of F through the moment equations sum_i lambda_i e^{i k theta_i} =
-// c_k, k = 0, 1, 2 (five real equations; theta_0 = psi fixed; unknowns the
-// three weights and the two other angles): the real trigonometric polynomial
-//   Lambda(theta) = g0 + g1 cos theta + g2 sin theta + g3 cos 2theta + g4 sin 2theta
-// with Lambda(theta_i) = [atom i before w], Lambda'(theta_i) = 0 (i = 1, 2)
-// and Lambda(psi) = beta gives dF/d(c_0, Re c_1, Im c_1, Re c_2, Im c_2) = g,
-// and dF/dpsi = -lambda_0 Lambda'(psi) (differentiate sum_i lambda_i
-// Lambda(theta_i) = sum_k g_k c_k). The 5 x 5 system is solved by Gaussian
-// elimination with partial pivoting; a singular one (coincident atoms) passes
-// no gradient.
-__device__ __forceinline__ void trig_adjoint(float psi, const TrigCanon& c, float beta, float* g, float& dF_dpsi) {
-  float sp, cp;
-  sincosf(psi, &sp, &cp);
-  const float n1 = rsqrtf(fmaxf(cabs2(c.z1), 1e-30f)), n2 = rsqrtf(fmaxf(cabs2(c.z2), 1e-30f));
-  const float c1 = c.z1.re * n1, s1 = c.z1.im * n1, c2 = c.z2.re * n2, s2 = c.z2.im * n2;
-  float M[5][6] = {
-      {1.f, cp, sp, cp * cp - sp * sp, 2.f * cp * sp, beta},
-      {1.f, c1, s1, c1 * c1 - s1 * s1, 2.f * c1 * s1, c.b1 ? 1.f : 0.f},
-      {1.f, c2, s2, c2 * c2 - s2 * s2, 2.f * c2 * s2, c.b2 ? 1.f : 0.f},
-      {0.f, -s1, c1, -4.f * c1 * s1, 2.f * (c1 * c1 - s1 * s1), 0.f},
-      {0.f, -s2, c2, -4.f * c2 * s2, 2.f * (c2 * c2 - s2 * s2), 0.f}};
+// c_k, k = 0..n (2n + 1 real equations; theta_0 = psi fixed; unknowns the
+// n + 1 weights and the n other angles): the real trigonometric polynomial
+//   Lambda(theta) = g_0 + sum_{k=1..n} (g_{2k-1} cos k theta + g_{2k} sin k theta)
+// with Lambda(theta_i) = [atom i before w], Lambda'(theta_i) = 0 (i = 1..n)
+// and Lambda(psi) = beta gives dF/d(c_0, Re c_1, Im c_1, .., Re c_n, Im c_n)
+// = g, and dF/dpsi = -lambda_0 Lambda'(psi) (differentiate sum_i lambda_i
+// Lambda(theta_i) = sum_k g_k c_k). The (2n + 1) x (2n + 1) system is solved
+// by Gaussian elimination with partial pivoting; a singular one (coincident
+// atoms) passes no gradient.
+template <int NH>
+__device__ __forceinline__ void trig_adjoint(float psi, const TrigCanon<NH>& c, float beta, float* g,
+                                             float& dF_dpsi) {
+  constexpr int M = 2 * NH + 1;
+  float M_[M][M + 1];
+  cfl w;
+  sincosf(psi, &w.im, &w.re);
+  // row 0: the query; rows 1..n: the atoms' values; rows n+1..2n: their slopes
+  auto fill_value = [&](int r, cfl z, float rhs) __attribute__((always_inline)) {
+    cfl zk = z;
+    M_[r][0] = 1.f;
+#pragma unroll
+    for (int k = 1; k <= NH; ++k) {
+      M_[r][2 * k - 1] = zk.re;
+      M_[r][2 * k] = zk.im;
+      zk = cmul(zk, z);
+    }
+    M_[r][M] = rhs;
+  };
+  fill_value(0, w, beta);
+#pragma unroll
+  for (int i = 0; i < NH; ++i) {
+    const float nz = rsqrtf(fmaxf(cabs2(c.z[i]), 1e-30f));
+    const cfl z = {c.z[i].re * nz, c.z[i].im * nz};
+    fill_value(1 + i, z, c.b[i] ? 1.f : 0.f);
+    cfl zk = z;
+    const int r = 1 + NH + i;
+    M_[r][0] = 0.f;
+#pragma unroll
+    for (int k = 1; k <= NH; ++k) {
+      M_[r][2 * k - 1] = -(float)k * zk.im;  // d/dtheta cos k theta
+      M_[r][2 * k] = (float)k * zk.re;       // d/dtheta sin k theta
+      zk = cmul(zk, z);
+    }
+    M_[r][M] = 0.f;
+  }
   bool ok = true;
 #pragma unroll
-  for (int col = 0; col < 5; ++col) {
-    // partial pivoting over the rows below (selects keep it branch free)
+  for (int col = 0; col < M; ++col) {
 #pragma unroll
-    for (int r = col + 1; r < 5; ++r) {
-      const bool sw = fabsf(M[r][col]) > fabsf(M[col][col]);
+    for (int r = col + 1; r < M; ++r) {
+      const bool sw = fabsf(M_[r][col]) > fabsf(M_[col][col]);
 #pragma unroll
-      for (int k = col; k < 6; ++k) {
-        const float t = M[col][k];
-        M[col][k] = sw ? M[r][k] : t;
-        M[r][k] = sw ? t : M[r][k];
+      for (int k = col; k <= M; ++k) {
+        const float t = M_[col][k];
+        M_[col][k] = sw ? M_[r][k] : t;
+        M_[r][k] = sw ? t : M_[r][k];
       }
     }
-    ok = ok && fabsf(M[col][col]) > 1e-7f;
-    const float ip = ok ? fast_rcp(M[col][col]) : 0.f;
+    ok = ok && fabsf(M_[col][col]) > 1e-7f;
+    const float ip = ok ? fast_rcp(M_[col][col]) : 0.f;
 #pragma unroll
-    for (int r = col + 1; r < 5; ++r) {
-      const float f = M[r][col] * ip;
+    for (int r = col + 1; r < M; ++r) {
+      const float f = M_[r][col] * ip;
 #pragma unroll
-      for (int k = col + 1; k < 6; ++k) M[r][k] = fmaf(-f, M[col][k], M[r][k]);
+      for (int k = col + 1; k <= M; ++k) M_[r][k] = fmaf(-f, M_[col][k], M_[r][k]);
     }
   }
 #pragma unroll
-  for (int r = 4; r >= 0; --r) {
-    float v = M[r][5];
+  for (int r = M - 1; r >= 0; --r) {
+    float v = M_[r][M];
 #pragma unroll
-    for (int k = r + 1; k < 5; ++k) v = fmaf(-M[r][k], g[k], v);
-    g[r] = ok ? v * fast_rcp(M[r][r]) : 0.f;
+    for (int k = r + 1; k < M; ++k) v = fmaf(-M_[r][k], g[k], v);
+    g[r] = ok ? v * fast_rcp(M_[r][r]) : 0.f;
   }
-  const float dl = -g[1] * sp + g[2] * cp - 4.f * g[3] * cp * sp + 2.f * g[4] * (cp * cp - sp * sp);
+  float dl = 0.f;
+  cfl wk = w;
+#pragma unroll
+  for (int k = 1; k <= NH; ++k) {
+    dl += (float)k * (-g[2 * k - 1] * wk.im + g[2 * k] * wk.re);
+    wk = cmul(wk, w);
+  }
   dF_dpsi = -c.lam0 * dl;
 }
 

@@ -120,7 +120,7 @@ def test_w1_proxy_coverage_vs_oracle_autograd():
     assert _check(gpu, ref, "W1")
 
 
-@pytest.mark.parametrize("k_mom,basis", [(4, "power"), (6, "power"), (4, "trigonometric")])
+@pytest.mark.parametrize("k_mom,basis", [(4, "power"), (6, "power"), (8, "power"), (4, "trigonometric")])
 def test_w3_full_size_sampled_gaussians(k_mom, basis):
     """1M Gaussians at 1600x1064 (the benchmark's training configuration, in
     its launch configuration): gradients of sampled Gaussians, each computed by

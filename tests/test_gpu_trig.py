@@ -21,15 +21,16 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-4
 
 
-@pytest.mark.parametrize("n_int", [3, 5])
-def test_trig_w1_full_image(n_int):
+@pytest.mark.parametrize("k_mom,n_int", [(4, 3), (4, 5), (6, 3), (6, 5)])
+def test_trig_w1_full_image(k_mom, n_int):
     scene, cams, opts = W.w1_small()
     opts.basis = "trigonometric"
+    opts.n_moments = k_mom
     opts.n_intervals = n_int
     img, saved, st = gpu_render(scene, cams, opts)
     tol_m, tol_o = tolerances(proxy_error(scene, cams[0], opts))
     ref = oracle.render_image(scene, cams[0], opts, margin_tol=tol_m, orient_eps=tol_o)
-    mx, _ = compare(img[0].reshape(-1, 3), ref, f"trig W1 N={n_int}", max_excluded=0.01,
+    mx, _ = compare(img[0].reshape(-1, 3), ref, f"trig W1 K={k_mom} N={n_int}", max_excluded=0.01,
                     gpu_saved=saved[0].reshape(-1, 8))
     assert mx <= TOL
     m0_err = np.abs(saved[0].reshape(-1, 8)[:, 6] - ref["moments"][:, 0])
@@ -72,8 +73,8 @@ def _trig_grads(scene, cams, opts, g_img):
     return _gpu_grads(scene, cams, opts, g_img)
 
 
-@pytest.mark.parametrize("n_int", [3, 5])
-def test_trig_backward_fd_subset_vs_oracle_autograd(n_int):
+@pytest.mark.parametrize("k_mom,n_int", [(4, 3), (4, 5), (6, 3)])
+def test_trig_backward_fd_subset_vs_oracle_autograd(k_mom, n_int):
     """200 Gaussians of one cluster, 64x64, full coverage: the GPU adjoint of
     the reconstruction on the circle (trig_adjoint) and of Eq. 14
     (trig_moment_grads) against float64 autograd of the oracle."""
@@ -81,32 +82,35 @@ def test_trig_backward_fd_subset_vs_oracle_autograd(n_int):
     scene, cams, opts = W.w3_fd_subset()
     scene = scene.subset(np.arange(200))
     opts.basis = "trigonometric"
+    opts.n_moments = k_mom
     opts.n_intervals = n_int
-    rng = np.random.default_rng(40 + n_int)
+    rng = np.random.default_rng(40 + n_int + k_mom)
     g_img = rng.normal(size=(64 * 64, 3))
     gpu, _ = _trig_grads(scene, cams, opts, g_img)
     ref = oracle.render_backward(scene, cams[0], opts, g_img)
-    assert _check(gpu, ref, f"trig fd-subset N={n_int}")
+    assert _check(gpu, ref, f"trig fd-subset K={k_mom} N={n_int}")
 
 
-def test_trig_backward_w1_vs_oracle_autograd():
+@pytest.mark.parametrize("k_mom", [4, 6])
+def test_trig_backward_w1_vs_oracle_autograd(k_mom):
     """The real proxy coverage (W1). Pixels whose coverage decision is
     ambiguous, or whose degenerate-measure flag differs between the two sides,
     take no upstream gradient."""
     from tests.test_gpu_backward import _check
     scene, cams, opts = W.w1_small()
     opts.basis = "trigonometric"
+    opts.n_moments = k_mom
     cam = cams[0]
     tol_m, tol_o = tolerances(proxy_error(scene, cam, opts))
     ref_img = oracle.render_image(scene, cam, opts, margin_tol=tol_m, orient_eps=tol_o)
     _, saved, _ = gpu_render(scene, cams, opts)
     flag_gpu = saved[0].reshape(-1, 8)[:, 7] < 0
     skip = ref_img["ambiguous"] | (flag_gpu != ref_img["fallback"])
-    log(f"[trig grad W1] pixels without upstream gradient: {int(skip.sum())}")
+    log(f"[trig grad W1 K={k_mom}] pixels without upstream gradient: {int(skip.sum())}")
     assert skip.sum() <= 0.01 * len(skip)
     rng = np.random.default_rng(47)
     g_img = rng.normal(size=(cam.width * cam.height, 3))
     g_img[skip] = 0.0
     gpu, _ = _trig_grads(scene, cams, opts, g_img)
     ref = oracle.render_backward(scene, cam, opts, g_img)
-    assert _check(gpu, ref, "trig W1")
+    assert _check(gpu, ref, f"trig W1 K={k_mom}")
