@@ -126,6 +126,7 @@ struct PairWs {
   int *order, *order_tmp;
   uint64_t* masks;
   float* partials;
+  uint8_t* used;  // [E,4]: the backward wrote slot (entry, wave)
   double* pix_mom;
   size_t bytes;
 };
@@ -145,6 +146,7 @@ PairWs carve_pairs(void* p, int64_t e, int n_keys, int64_t n_pix) {
   w.order_tmp = c.take<int>(order_tmp_ints(n_keys));
   w.masks = c.take<uint64_t>((size_t)e * 4);
   w.partials = c.take<float>((size_t)e * 4 * kGradStride);  // one slot per (entry, wave)
+  w.used = c.take<uint8_t>((size_t)e * 4);
   w.pix_mom = c.take<double>((size_t)n_pix * (kMaxMoments + 1));
   w.bytes = c.off;
   return w;
@@ -742,14 +744,14 @@ int backward_common(const mb_gaussians* g, const mb_camera* cams, int32_t n_cams
     StageTimer t(S_RENDER_BWD, s);
     // 0: power moments, 1: the surrogate, 2: trigonometric moments
     const int mode = q != nullptr ? 1 : (o->basis == 1 ? 2 : 0);
-    e = launch_render_backward(ra, saved, grad_image, grad_penalty, p.vals_a, p.partials, cs, o->n_moments,
-                               o->n_intervals, s, mode);
+    e = launch_render_backward(ra, saved, grad_image, grad_penalty, p.vals_a, p.partials, p.used, cs,
+                               o->n_moments, o->n_intervals, s, mode);
   }
   if (e != hipSuccess) return hip_fail(e, "render_backward");
   GradArgs ga;
   ga.means = g->means; ga.scales = g->scales; ga.quats = g->quats; ga.dens = g->densities; ga.colors = g->colors;
   ga.n = g->n; ga.sh_degree = g->sh_degree;
-  ga.counts = w.counts; ga.offsets = w.offsets; ga.partials = p.partials;
+  ga.counts = w.counts; ga.offsets = w.offsets; ga.partials = p.partials; ga.used = p.used;
   ga.e_cap = n_entries;
   ga.g_means = g_means; ga.g_scales = g_scales; ga.g_quats = g_quats; ga.g_dens = g_densities;
   ga.g_colors = g_colors;

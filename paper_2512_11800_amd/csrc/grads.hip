@@ -7,14 +7,18 @@
 
 namespace mb {
 
-// Sum of the four wave slots of list entry e (fixed order).
-__device__ __forceinline__ void entry_total(const float* partials, int e, float* r) {
+// Sum of the four wave slots of list entry e (fixed order); a slot the
+// backward pass did not write (its quadrant's coverage mask is empty) counts
+// as zero.
+__device__ __forceinline__ void entry_total(const float* partials, const uint8_t* used, int e, float* r) {
   const float4* sl = reinterpret_cast<const float4*>(partials + (size_t)e * 4 * kGradStride);
+  const uchar4 u = reinterpret_cast<const uchar4*>(used)[e];
+  const bool uw[4] = {u.x != 0, u.y != 0, u.z != 0, u.w != 0};
   float4 v[4][5];
 #pragma unroll
   for (int w = 0; w < 4; ++w)
 #pragma unroll
-    for (int k = 0; k < 5; ++k) v[w][k] = sl[w * (kGradStride / 4) + k];
+    for (int k = 0; k < 5; ++k) v[w][k] = uw[w] ? sl[w * (kGradStride / 4) + k] : make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
     const float x = ((v[0][k].x + v[1][k].x) + v[2][k].x) + v[3][k].x;
@@ -195,7 +199,7 @@ __global__ __launch_bounds__(128) void k_grad_finalize(GradArgs a, CamSet cams) 
         const int e = w0 + lane;
         float r[G_COUNT];
         if (e < end) {
-          entry_total(a.partials, e, r);
+          entry_total(a.partials, a.used, e, r);
         } else {
 #pragma unroll
           for (int f = 0; f < G_COUNT; ++f) r[f] = 0.f;

@@ -152,8 +152,8 @@ hipError_t launch_render_consume_tab(const RenderArgs& a, const CamSet& cams, in
 
 hipError_t launch_render_backward(const RenderArgs& r, const float* saved, const float* grad_image,
                                   const float* grad_penalty, const int* sorted_k, float* partials,
-                                  const CamSet& cams, int n_moments, int n_intervals, hipStream_t s,
-                                  int mode = 0);
+                                  uint8_t* used, const CamSet& cams, int n_moments, int n_intervals,
+                                  hipStream_t s, int mode = 0);
 
 struct GradArgs {
   const float *means, *scales, *quats, *dens, *colors;
@@ -162,6 +162,7 @@ struct GradArgs {
   const int* offsets;    // [C*n]
   int64_t e_cap;         // entries with an index at or beyond e_cap have no slots
   const float* partials; // [E,4,kGradStride]
+  const uint8_t* used;   // [E,4]: slot (entry, wave) holds data; its sum is zero otherwise
   float *g_means, *g_scales, *g_quats, *g_dens, *g_colors;
 };
 hipError_t launch_grad_finalize(const GradArgs& a, const CamSet& cams, hipStream_t s);

@@ -245,6 +245,7 @@ struct BwdArgs {
   const float* grad_penalty;  // [C,H,W] dL/d(consistency penalty), or null
   const int* sorted_k;      // [E] entry index of each sorted list position
   float* partials;          // [E,4,kGradStride]
+  uint8_t* used;            // [E,4]: which of an entry's slots this pass writes
 };
 
 // (mu, Sigma, omega) gradients of one pair -> gradients of its record
@@ -523,10 +524,29 @@ __global__ __launch_bounds__(256, (K <= 6 && NQ == 4 && MODE == 0) ? 3 : 2) void
     dx = (float)(x0 + (p & 7)) + 0.5f - st.f[0][j].x;
     dy = (float)(y0 + (p >> 3)) + 0.5f - st.f[0][j].y;
   };
-  auto stage = [&](int b, int nb, bool keys) __attribute__((always_inline)) {
+  // flags: mark which of the entries' slots this block writes (an entry's
+  // slot for a quadrant whose stored mask is empty is neither written nor
+  // read: its sum is zero)
+  auto stage = [&](int b, int nb, bool flags) __attribute__((always_inline)) {
     __syncthreads();
-    load_batch(st, a.rec, a.sorted_rec, b, nb);
-    if (keys && tid < nb) sk[tid] = ba.sorted_k[b + tid];
+    load_batch_covered(st, a.rec, a.sorted_rec, a.masks, bw.quad, b, nb);
+    if (tid < nb) {
+      const int k = ba.sorted_k[b + tid];
+      sk[tid] = k;
+      if (flags) {
+        const uint64_t* mp = a.masks + (size_t)(b + tid) * 4;
+        if (bw.quad >= 0) {
+          ba.used[(size_t)k * 4 + bw.quad] = mp[bw.quad] != 0ull ? 1 : 0;
+        } else {
+          uchar4 f;
+          f.x = mp[0] != 0ull ? 1 : 0;
+          f.y = mp[1] != 0ull ? 1 : 0;
+          f.z = mp[2] != 0ull ? 1 : 0;
+          f.w = mp[3] != 0ull ? 1 : 0;
+          reinterpret_cast<uchar4*>(ba.used)[k] = f;
+        }
+      }
+    }
     __syncthreads();
   };
 
@@ -1014,7 +1034,7 @@ __global__ __launch_bounds__(256, (K <= 6 && NQ == 4 && MODE == 0) ? 3 : 2) void
     };
     for (int b = rg.x; b < rg.y; b += kBlock) {
       int nb = min(kBlock, rg.y - b);
-      stage(b, nb, true);
+      stage(b, nb, false);
       QueueCursor qc;
       queue_reset(qc);
       carry_j = -1;
@@ -1032,9 +1052,9 @@ __global__ __launch_bounds__(256, (K <= 6 && NQ == 4 && MODE == 0) ? 3 : 2) void
 
 hipError_t launch_render_backward(const RenderArgs& r, const float* saved, const float* grad_image,
                                   const float* grad_penalty, const int* sorted_k, float* partials,
-                                  const CamSet& cams, int n_moments, int n_intervals, hipStream_t s,
-                                  int mode) {
-  BwdArgs ba{r, saved, grad_image, grad_penalty, sorted_k, partials};
+                                  uint8_t* used, const CamSet& cams, int n_moments, int n_intervals,
+                                  hipStream_t s, int mode) {
+  BwdArgs ba{r, saved, grad_image, grad_penalty, sorted_k, partials, used};
   int n_keys = r.tiles_x * r.tiles_y * r.n_cams;
   dim3 grid(render_blocks(n_keys)), block(kBlock);
 #define MB_LAUNCH(KK, NN, SS)                                                          \

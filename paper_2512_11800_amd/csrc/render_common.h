@@ -86,8 +86,8 @@ __device__ __forceinline__ void queue_pop64(WaveQueue& q, QueueCursor& qc, int l
 // Queue the pairs of the staged batch [b, b + nb) from the stored coverage
 // masks of this wave (restricted to the lanes of `keep`), skipping empty
 // entries 64 at a time. on_full() evaluates and pops 64 queued pairs;
-// on_empty(j) is called by the lane that loaded entry j's mask when it is
-// empty (after the restriction).
+// on_empty(j) is called by the lane that loaded entry j's mask when the
+// stored mask has pixels but none of them is kept.
 // In a split block (see BlockWork) a wave takes only the entries j with
 // j % 4 == its wave index (`own4` >= 0); otherwise every entry (`own4` < 0).
 // PREFETCH: the masks of the next 64 entries are loaded before the current
@@ -105,14 +105,15 @@ __device__ __forceinline__ void queue_from_masks(WaveQueue& q, QueueCursor& qc, 
   uint64_t next = PREFETCH ? load(0) : 0ull;
   for (int j0 = 0; j0 < nb; j0 += 64) {
     const bool in = j0 + lane < nb && (own4 < 0 || ((j0 + lane) & 3) == own4);
-    uint64_t mk;
+    uint64_t raw;
     if constexpr (PREFETCH) {
-      mk = next & keep;
+      raw = next;
       next = j0 + 64 < nb ? load(j0 + 64) : 0ull;
     } else {
-      mk = load(j0) & keep;
+      raw = load(j0);
     }
-    if (in && mk == 0) on_empty(j0 + lane);
+    const uint64_t mk = raw & keep;
+    if (in && mk == 0 && raw != 0) on_empty(j0 + lane);
     uint64_t nz = __ballot(mk != 0);
     while (nz) {
       const int l = __builtin_ctzll(nz);
@@ -172,6 +173,32 @@ __device__ __forceinline__ void load_batch(Stage& st, const float4* rec, const i
     const float4* src = rec + (size_t)sorted_rec[b + tid] * kRecF4;
 #pragma unroll
     for (int k = 0; k < kRecF4; ++k) st.f[k][tid] = src[k];
+  }
+}
+
+// load_batch for the passes that walk the stored coverage masks: an entry
+// whose masks are empty for every quadrant the block renders is never
+// evaluated, so its record is not fetched (its staging slot keeps stale
+// data that nothing reads). quad >= 0: a split block's one quadrant; -1: the
+// whole tile (any of the four masks).
+__device__ __forceinline__ void load_batch_covered(Stage& st, const float4* rec, const int* sorted_rec,
+                                                   const uint64_t* masks, int quad, int b, int nb) {
+  int tid = threadIdx.x;
+  if (tid < nb) {
+    const uint64_t* mp = masks + (size_t)(b + tid) * 4;
+    bool need;
+    if (quad >= 0) {
+      need = mp[quad] != 0ull;
+    } else {
+      const ulonglong2 m01 = reinterpret_cast<const ulonglong2*>(mp)[0];
+      const ulonglong2 m23 = reinterpret_cast<const ulonglong2*>(mp)[1];
+      need = (m01.x | m01.y | m23.x | m23.y) != 0ull;
+    }
+    if (need) {
+      const float4* src = rec + (size_t)sorted_rec[b + tid] * kRecF4;
+#pragma unroll
+      for (int k = 0; k < kRecF4; ++k) st.f[k][tid] = src[k];
+    }
   }
 }
 

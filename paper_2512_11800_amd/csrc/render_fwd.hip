@@ -286,7 +286,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
     for (int b = rg.x; b < rg.y; b += kBlock) {
       int nb = min(kBlock, rg.y - b);
       __syncthreads();
-      load_batch(st, a.rec, a.sorted_rec, b, nb);
+      load_batch_covered(st, a.rec, a.sorted_rec, a.masks, bw.quad, b, nb);
       __syncthreads();
       QueueCursor qc;
       queue_reset(qc);
@@ -549,7 +549,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, CamSet cams) {
     for (int b = rg.x; b < rg.y; b += kBlock) {
       int nb = min(kBlock, rg.y - b);
       __syncthreads();
-      load_batch(st, a.rec, a.sorted_rec, b, nb);
+      load_batch_covered(st, a.rec, a.sorted_rec, a.masks, bw.quad, b, nb);
       __syncthreads();
       QueueCursor qc;
       queue_reset(qc);
@@ -764,7 +764,7 @@ __global__ __launch_bounds__(256) void k_render_consume_tab(RenderArgs a, CamSet
   for (int b = rg.x; b < rg.y; b += kBlock) {
     int nb = min(kBlock, rg.y - b);
     __syncthreads();
-    load_batch(st, a.rec, a.sorted_rec, b, nb);
+    load_batch_covered(st, a.rec, a.sorted_rec, a.masks, -1, b, nb);
     __syncthreads();
     QueueCursor qc;
     queue_reset(qc);
