@@ -108,7 +108,7 @@ GaussWs carve_gauss(void* p, int64_t n, int n_cams) {
   Carver c(p);
   int64_t m = n * n_cams;
   GaussWs w;
-  w.rec = c.take<float4>((size_t)m * kRecF4);
+  w.rec = c.take<float4>((size_t)m * kRecStride);
   w.rectd = c.take<double2>((size_t)m * 3);
   w.tbox = c.take<int4>((size_t)m);
   w.counts = c.take<int>((size_t)m);

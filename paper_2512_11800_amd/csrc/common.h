@@ -23,6 +23,9 @@ namespace mb {
 constexpr int kTile = 16;
 constexpr int kBlock = 256;
 constexpr int kRecF4 = 6;  // one render record = 6 float4
+// records sit 8 float4 apart in memory: each fills one 128-byte line, so a
+// gathered record costs one line instead of straddling two
+constexpr int kRecStride = 8;
 constexpr float kPi = 3.14159265358979323846f;
 constexpr float kSqrtHalfPi = 1.2533141373155003f;  // sqrt(pi/2)
 constexpr float kInvSqrt2 = 0.7071067811865476f;

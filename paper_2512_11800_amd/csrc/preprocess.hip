@@ -187,7 +187,7 @@ __global__ __launch_bounds__(256) void k_preprocess(PrepArgs a, CamSet cams) {
       rgb[ch] = fmaxf(v, 0.f);
     }
   }
-  float4* out = a.rec + idx * kRecF4;
+  float4* out = a.rec + idx * kRecStride;
   out[0] = make_float4(p0x, p0y, r.rcx, r.rcy);
   out[1] = make_float4(r.e1x, r.e1y, r.h1, r.h2);
   out[2] = make_float4((float)cf.D0, (float)cf.D1x, (float)cf.D1y, (float)cf.D2xx);
@@ -227,7 +227,7 @@ __global__ __launch_bounds__(256) void k_emit(EmitArgs a) {
   size_t idx = (size_t)ci * a.n + g;
   int4 box = a.tbox[idx];
   if (box.x > box.z) return;
-  const float4* rp = a.rec + idx * kRecF4;
+  const float4* rp = a.rec + idx * kRecStride;
   float4 r0 = rp[0], r1 = rp[1];
   Rect r{r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
   float mx = r0.x + r0.z, my = r0.y + r0.w;

@@ -170,7 +170,7 @@ __device__ __forceinline__ BlockWork block_work(const RenderArgs& a) {
 __device__ __forceinline__ void load_batch(Stage& st, const float4* rec, const int* sorted_rec, int b, int nb) {
   int tid = threadIdx.x;
   if (tid < nb) {
-    const float4* src = rec + (size_t)sorted_rec[b + tid] * kRecF4;
+    const float4* src = rec + (size_t)sorted_rec[b + tid] * kRecStride;
 #pragma unroll
     for (int k = 0; k < kRecF4; ++k) st.f[k][tid] = src[k];
   }
@@ -195,7 +195,7 @@ __device__ __forceinline__ void load_batch_covered(Stage& st, const float4* rec,
       need = (m01.x | m01.y | m23.x | m23.y) != 0ull;
     }
     if (need) {
-      const float4* src = rec + (size_t)sorted_rec[b + tid] * kRecF4;
+      const float4* src = rec + (size_t)sorted_rec[b + tid] * kRecStride;
 #pragma unroll
       for (int k = 0; k < kRecF4; ++k) st.f[k][tid] = src[k];
     }
