@@ -23,7 +23,7 @@ from .geometry import DT, camera_matrices, pixel_directions, quat_to_rot, ray_ga
 from .moments import particle_moments, warp
 from .proxy import MARGIN_TOL, ORIENT_EPS, covering_pairs, screen_proxy
 from .quadrature import consistency_penalty, particle_quadrature, rescale
-from .trig import angle_of, degenerate_flags, particle_trig_moments, trig_bound_tau
+from .trig import CUT_BAND, angle_of, cut_margin, degenerate_flags, particle_trig_moments, trig_bound_tau
 
 PARAMS = ("means", "scales", "quats", "densities", "colors")
 
@@ -184,6 +184,12 @@ def _render_pixels_trig(scene_t, cam, opts, n_pix, slot, gid, amb, mu, sigma, om
                                             opts.n_intervals, to_angle)
         y_e = to_angle(t_e)
         pen_pair = consistency_penalty(mu, sigma, omega, tau_e, t_e)
+        # a pixel with an atom within CUT_BAND of the cut at one of its
+        # queries is decided by input rounding (see oracle.trig): ambiguous
+        with torch.no_grad():
+            marg = cut_margin(mom_q.detach(), y_e.detach().reshape(-1), n_half).reshape(y_e.shape).amin(-1)
+            near_cut = torch.zeros(n_pix, dtype=DT).index_add(0, slot, (marg < CUT_BAND).to(DT)) > 0
+        amb = amb | near_cut
     else:
         q = torch.zeros(0, dtype=DT)
         pen_pair = torch.zeros(0, dtype=DT)

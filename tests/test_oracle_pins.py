@@ -1417,6 +1417,24 @@ def test_circle_nodes_on_the_circle_reproduce_the_moments(n):
             assert abs((ll * zz ** k).sum() - c[k].item()) < 1e-10
 
 
+
+def test_cut_margin_is_the_distance_of_the_nearest_other_atom_to_the_cut():
+    """The canonical representation through one atom of a three-atom measure
+    (n = 2) is the measure itself, so the distance of the nearest other atom
+    to the cut (angle 2 pi - theta / 2) is known in closed form; the query's
+    own position does not count."""
+    from oracle import trig as T
+    cut = 2 * math.pi - 0.5 * T.THETA
+    for d_cut, other, psi in [(0.01, 1.0, 3.0), (-0.02, 2.0, 4.0), (0.3, 2.5, cut + 1e-3)]:
+        phis = np.array([cut + d_cut, other, psi])
+        lam = np.array([0.3, 0.3, 0.4])
+        c = torch.as_tensor([(lam * np.exp(1j * k * phis)).sum() for k in range(3)], dtype=torch.complex128)
+        _, eps = T.uniform_mixture(c[None] / c[0], 2)
+        assert float(eps[0]) == 0.0
+        marg = T.cut_margin(c[None], torch.tensor([psi], dtype=torch.float64), 2)
+        expect = min(abs(d_cut), abs(math.remainder(other - cut, 2 * math.pi)))
+        assert abs(float(marg[0]) - expect) < 1e-9
+
 @pytest.mark.parametrize("n", [2, 3])
 def test_circle_query_weight_is_the_largest_point_mass(n):
     """U - L, the weight at the query, is the Christoffel number: the least
