@@ -68,29 +68,37 @@ __device__ __forceinline__ float warp_abs_d(float t, float tn) {  // d g_hat / d
 // Eq. 14 for one ray Gaussian, k = 0..NH, with the first-order complex erf of
 // App. C: c_k = A D^(k^2) z^k (erfc(a) + i k b (2 / sqrt pi) e^{-a^2}), where
 // A = omega Sigma sqrt(pi / 2), z = e^{i alpha_1 G}, D = e^{-Sigma^2 alpha_1^2 G'^2 / 2},
-// b = Sigma alpha_1 G' / sqrt 2, a = (t_n - mu) / (sqrt2 Sigma). The powers are
-// taken in double from the float primitives, so that every pair's moment
-// vector is, to double rounding, that of one Gaussian (the Toeplitz matrix of
-// a narrow measure keeps its small pivots).
+// b = Sigma alpha_1 G' / sqrt 2, a = (t_n - mu) / (sqrt2 Sigma). The phase
+// alpha_1 G, its sine and cosine, and the damping D are evaluated in double
+// from the float ray Gaussian, and so are the powers: the pixel's Toeplitz
+// matrix of a dense, thin surface is ill-conditioned, and the float rounding
+// of the phase and damping (about 3e-7) moved a W2 pixel's image by 6e-4 at
+// three complex moments, against 5e-8 with these in double.
 template <int NH>
 __device__ __forceinline__ void particle_trig_moments_d(const RayG& g, float tn, double* m) {
+  constexpr double kSpanD = 5.654866776461628;  // 2 pi - theta
   const float mus = fmaxf(g.mu, tn);
   const float gp = warp_abs_d(mus, tn);
-  const float gg = warp_abs(mus, tn) + gp * (g.mu - mus);
+  const double musd = (double)mus;
+  const double xq = 1.0 + 0.8 * musd;
+  const double r = (1.0 + 0.8 * (double)tn) / xq;
+  const double r15 = r * sqrt(r);
+  const double gpd = 1.2 * r15 / xq;                                  // g_hat'(mu*)
+  const double ggd = (1.0 - r15) + gpd * ((double)g.mu - musd);      // G, linearised at mu*
   const float a = (tn - g.mu) * kInvSqrt2 * fast_rcp(g.sig);
   const double ec = (double)erfc_fast(a);
   const double eb = (double)(g.sig * kTrigSpan * gp * kInvSqrt2 * 1.1283791670955126f * __expf(-a * a));
   const double amp = (double)(g.omega * g.sig * kSqrtHalfPi);
-  float sn, cs;
-  sincosf(kTrigSpan * gg, &sn, &cs);
-  const float sa = g.sig * kTrigSpan * gp;
-  const double d1 = (double)__expf(-0.5f * sa * sa);
+  double sn, cs;
+  sincos(kSpanD * ggd, &sn, &cs);
+  const double sa = (double)g.sig * kSpanD * gpd;
+  const double d1 = exp(-0.5 * sa * sa);
   m[0] = amp * ec;
   double zr = 1.0, zi = 0.0, dk = 1.0, dstep = d1;
 #pragma unroll
   for (int k = 1; k <= NH; ++k) {
-    const double nr = zr * (double)cs - zi * (double)sn;
-    zi = zr * (double)sn + zi * (double)cs;
+    const double nr = zr * cs - zi * sn;
+    zi = zr * sn + zi * cs;
     zr = nr;
     dk *= dstep;  // D^(k^2) = D^((k-1)^2) D^(2k-1)
     dstep *= d1 * d1;
