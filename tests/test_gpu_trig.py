@@ -5,7 +5,12 @@ the reconstruction on the circle at each quadrature edge, Eq. 7 and Eq. 15.
 Forward bar: max-abs image error <= 1e-4 over the pixels the parity
 protocol keeps; besides the coverage band it excludes pixels whose
 degenerate-measure flag (the Toeplitz matrix mixed with the uniform measure)
-differs between the two sides, counted and bounded. Backward bar: that of
+differs between the two sides, and pixels where an atom of the
+reconstruction lies within oracle.trig.CUT_BAND of the cut at one of the
+pixel's queries (its side of the cut, which moves the optical depth by the
+atom's weight, is then decided by input rounding), counted and bounded: at
+most 1% of W1's pixels and 2% of W2's sample (measured 0.1-0.2% and
+0.5-1.0%). Backward bar: that of
 the power moments (tests/test_gpu_backward.py), 1e-3 relative per parameter
 group and element by element."""
 import numpy as np
@@ -37,10 +42,11 @@ def test_trig_w1_full_image(k_mom, n_int):
     assert m0_err.max() < 1e-4 * max(1.0, ref["moments"][:, 0].max())
 
 
-def test_trig_w2_full_size_sampled():
+@pytest.mark.parametrize("k_mom", [4, 6])
+def test_trig_w2_full_size_sampled(k_mom):
     """500k Gaussians at 1920x1080 in the benchmark's launch configuration;
     20,000 sampled pixels."""
-    scene, cams, opts = W.w2_clusters(n_moments=4)
+    scene, cams, opts = W.w2_clusters(n_moments=k_mom)
     opts.basis = "trigonometric"
     cam = cams[0]
     img, saved, st = gpu_render(scene, cams, opts, on_device=True)
@@ -48,8 +54,8 @@ def test_trig_w2_full_size_sampled():
     tol_m, tol_o = tolerances(proxy_error(scene, cam, opts))
     ref = oracle.render_image(scene, cam, opts, pixels=pix, margin_tol=tol_m, orient_eps=tol_o,
                               max_pixels=len(pix))
-    log(f"[trig w2] sampled={len(pix)} pairs={ref['n_pairs']}")
-    mx, _ = compare(img[0].reshape(-1, 3)[pix], ref, "trig W2", max_excluded=0.01,
+    log(f"[trig w2 K={k_mom}] sampled={len(pix)} pairs={ref['n_pairs']}")
+    mx, _ = compare(img[0].reshape(-1, 3)[pix], ref, f"trig W2 K={k_mom}", max_excluded=0.02,
                     gpu_saved=saved[0].reshape(-1, 8)[pix])
     assert mx <= TOL
 
