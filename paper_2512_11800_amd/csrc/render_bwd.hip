@@ -1,6 +1,7 @@
 // Backward render: the two-stage adjoint of Sec. 3.3 (Eq. 22, App. D), one
 // workgroup per 16x16 tile as in the forward pass.
-//   pass 1   recompute the pixel's moments (no per-sample state is stored);
+//   pass 1   the pixel's moment sums, as the forward pass stored them (per
+//            pixel; nothing per (pixel, Gaussian) pair is stored);
 //   setup    Hankel factor; the derivative of the Eq. 15 rescaling is folded
 //            in: a = g (1 - e^-m0) / max(eps, O), b = dL/dO, e0 = dL/dm0;
 //   pass 2   Adjoint-Moment stage: dm = e0 e_0 + sum_i (a . c_i + b) dq_i/dm,
@@ -12,7 +13,9 @@
 //   pass 3   the rest of the Gradient stage, dm . dm_i/dtheta_i.
 // Per-pair gradients are summed over the wave's pixels into one slot per
 // (list entry, wave) (pass 2 writes it, pass 3 adds to it); a per-Gaussian
-// kernel then sums the slots: one reduction, no atomics, deterministic.
+// kernel then sums the slots: one reduction, no atomics, deterministic. A
+// byte per slot records whether it was written (the stored coverage mask of
+// that entry and quadrant is non-empty); the reduction skips the others.
 // The passes walk the coverage masks the forward pass stored.
 #include "render_common.h"
 #include "trig.h"
@@ -603,6 +606,8 @@ __global__ __launch_bounds__(256, (K <= 6 && NQ == 4 && MODE == 0) ? 3 : 2) void
   const bool active = inside && live;
   const uint64_t active_mask = __ballot(active);
   float* cw = carry[wave];
+  // the slot of an entry whose stored mask has pixels, none of which this
+  // pass keeps (outside the image, or without density), is written as zero
   auto zero_slot = [&](int j) __attribute__((always_inline)) {
     float4* slot = reinterpret_cast<float4*>(ba.partials + ((size_t)sk[j] * 4 + quad) * kGradStride);
 #pragma unroll
