@@ -175,11 +175,14 @@ def test_w3_full_size_sampled_gaussians(k_mom, basis):
     ref_img = oracle.render_image(sub_scene, cam, opts, pixels=pix, margin_tol=tol_m, orient_eps=tol_o,
                                   max_pixels=len(pix))
     # no upstream gradient where the coverage decision is ambiguous or the
-    # degenerate-measure flags of the two sides differ
+    # degenerate-measure flags of the two sides differ; for the trigonometric
+    # moments the ambiguous pixels also hold those with an atom of the
+    # reconstruction at the circle's cut (oracle.trig.CUT_BAND), bounded as in
+    # the trigonometric image tests
     _, saved, _ = gpu_render(scene, cams, opts, on_device=True)
     flag_gpu = saved[0].reshape(-1, 8)[pix, 7] < 0
     amb = ref_img["ambiguous"] | (flag_gpu != ref_img["fallback"])
-    assert amb.sum() <= 0.01 * len(pix)
+    assert amb.sum() <= (0.02 if basis == "trigonometric" else 0.01) * len(pix)
     g_full = np.zeros((cam.width * cam.height, 3))
     vals = rng.normal(size=(len(pix), 3))
     vals[amb] = 0.0
