@@ -133,6 +133,7 @@ def gpu_bench(args):
 
     torch.cuda.set_device(0)
     scene, cams, opts = _workload(args.k, args.workload)
+    opts.basis = getattr(args, "basis", "power")
     g = M.Gaussians.from_scene(scene, device="cuda:0")
     ws = M.Workspace("cuda:0")
     h, w, nc = cams[0].height, cams[0].width, len(cams)
@@ -208,7 +209,7 @@ def gpu_bench(args):
         kms = raw[0] / max(1, raw[1])
         ach = flops * n_pairs / (kms * 1e-3) / 1e12
         traffic = None
-        if args.workload == "w2" and args.k == 4:
+        if args.workload == "w2" and args.k == 4 and getattr(args, "basis", "power") == "power":
             traffic = _measured_traffic(profiled_name)
         return {"bound": "alu", "kernel": kernel, "achieved": ach, "peak": PEAK_FP32_VALU_TFLOPS,
                 "unit": "TFLOP/s", "frac": ach / PEAK_FP32_VALU_TFLOPS, "traffic": traffic,
@@ -470,6 +471,8 @@ def main():
     ap.add_argument("--cpu-sample-px", type=int, default=30000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-k6", action="store_true", help="skip the K = 6 frames of the default run")
+    ap.add_argument("--no-trig", action="store_true",
+                    help="skip the trigonometric-moment frames (K = 4 and 6) of the default run")
     ap.add_argument("--no-surrogate", action="store_true",
                     help="skip the surrogate comparison (harvest, training, held-out cameras) of the default run")
     args = ap.parse_args()
@@ -510,6 +513,22 @@ def main():
                          "roofline_fwd": r6["roofline_fwd"], "roofline_bwd": r6["roofline_bwd"],
                          "pairs_per_frame": r6["n_pairs"], "n_fallback_pixels": r6["n_fallback_pixels"],
                          "stages_ms": {m: r6["modes"][m]["stages_ms"] for m in r6["modes"]}}
+    if args.workload == "w2" and args.mode == "both" and args.k == 4 and not args.no_trig:
+        # the trigonometric moments (Sec. 3.2, Eqs. 13-14) on the same frame,
+        # times only: the per-pair operation tally is the power moments'
+        import copy
+        trig = {}
+        for kt in (4, 6):
+            at = copy.copy(args)
+            at.k = kt
+            at.basis = "trigonometric"
+            rt = gpu_bench(at)[0]
+            trig[f"k{kt}"] = {"fwd_ms_per_frame": rt["modes"]["fwd"]["ms_per_step"],
+                              "fwdbwd_ms_per_frame": rt["modes"]["fwdbwd"]["ms_per_step"],
+                              "render_kernel_ms": {"forward": rt["roofline_fwd"]["kernel_ms"],
+                                                   "backward": rt["roofline_bwd"]["kernel_ms"]},
+                              "n_fallback_pixels": rt["n_fallback_pixels"]}
+        extra_k["trigonometric"] = trig
     sur = None
     if args.workload == "w2" and args.mode == "both" and args.k == 4 and not args.no_surrogate:
         # the metric's surrogate-vs-plain leg (K = 6, held-out cameras)
