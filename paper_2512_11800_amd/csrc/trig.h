@@ -262,13 +262,25 @@ __device__ __forceinline__ float trig_christoffel(const TrigLInv<NH>& L, cfl z) 
   return fast_rcp(s);
 }
 
-// position along the circle after the cut, in [0, 2 pi)
-__device__ __forceinline__ float arc_pos(cfl z) {
-  // rotate by -cut
+// Order along the circle cut at angle 1.9 pi (the middle of the wrapping
+// zone): z comes before w when its angle after the cut, in [0, 2 pi), is
+// smaller. Both are turned by the cut; the half [0, pi) precedes [pi, 2 pi),
+// and inside one half (angles less than pi apart) the sign of the cross
+// product orders them.
+struct CutPoint {
+  float x, y;
+  bool lower;  // angle after the cut in [pi, 2 pi)
+};
+__device__ __forceinline__ CutPoint cut_point(cfl z) {
   const float cr = 0.9510565162951535f, ci = 0.3090169943749474f;  // e^{-i cut}, cut = 1.9 pi
-  const float xr = z.re * cr - z.im * ci, xi = z.re * ci + z.im * cr;
-  const float a = atan2f(xi, xr);
-  return a < 0.f ? a + 6.283185307179586f : a;
+  CutPoint c;
+  c.x = z.re * cr - z.im * ci;
+  c.y = z.re * ci + z.im * cr;
+  c.lower = c.y < 0.f || (c.y == 0.f && c.x < 0.f);
+  return c;
+}
+__device__ __forceinline__ bool cut_before(const CutPoint& z, const CutPoint& w) {
+  return z.lower != w.lower ? w.lower : (z.x * w.y - z.y * w.x > 0.f);
 }
 
 // Zeros of the cubic a_0 + a_1 z + a_2 z^2 + a_3 z^3 (complex coefficients):
@@ -328,7 +340,11 @@ __device__ __forceinline__ void cubic_roots(const cfl* a, cfl w, cfl* z) {
 
 // The canonical representation through w = e^{i psi}: the NH other atoms,
 // their flags (before w along the cut circle) and the weight lambda_0 at w;
-// returns F = sum_{atoms before w} lambda_i + beta lambda_0.
+// returns F = sum_{atoms before w} lambda_i + beta lambda_0. The weights sum
+// to c_0 = 1, so with c of the NH atoms before w the sum is 0 (c = 0),
+// 1 - lambda_0 (c = NH), the weight of the one atom before w (c = 1), or
+// 1 - lambda_0 less the weight of the one atom after it (c = 2 of three):
+// one Christoffel weight at most.
 template <int NH>
 struct TrigCanon {
   cfl z[NH];
@@ -368,15 +384,24 @@ __device__ __forceinline__ float trig_canon(const TrigLInv<NH>& L, float psi, fl
   } else {
     cubic_roots(a, w, out.z);
   }
-  const float pw = arc_pos(w);
+  const CutPoint cw = cut_point(w);
   out.lam0 = lam0;
-  float f = beta * lam0;
+  int cnt = 0;
 #pragma unroll
   for (int i = 0; i < NH; ++i) {
-    out.b[i] = arc_pos(out.z[i]) < pw;
-    f += out.b[i] ? trig_christoffel<NH>(L, out.z[i]) : 0.f;
+    out.b[i] = cut_before(cut_point(out.z[i]), cw);
+    cnt += out.b[i] ? 1 : 0;
   }
-  return f;
+  // the one atom whose weight is needed: the atom before w (c = 1) or the
+  // atom after it (c = NH - 1 = 2)
+  const bool want = cnt == 1;
+  cfl zs = out.z[NH - 1];
+#pragma unroll
+  for (int i = NH - 2; i >= 0; --i) zs = out.b[i] == want ? out.z[i] : zs;
+  float ws = trig_christoffel<NH>(L, zs);
+  ws = isfinite(ws) ? ws : 0.f;
+  const float below = cnt == 0 ? 0.f : (cnt == NH ? 1.f - lam0 : (cnt == 1 ? ws : 1.f - lam0 - ws));
+  return below + beta * lam0;
 }
 
 // F = sum_{atoms before w} lambda_i + beta lambda_0 at the query angle psi
