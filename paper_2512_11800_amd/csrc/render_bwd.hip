@@ -109,6 +109,7 @@ template <int NH, int NQ>
 __device__ __forceinline__ void trig_quad_state(const RayG& g, const TrigLInv<NH>& L, float m0, float tn,
                                                 const RenderArgs& a, QuadState<NH, NQ>& s, TrigCanon<NH>* tc,
                                                 int* src) {
+  cfl start = {__builtin_nanf(""), 0.f};  // the first edge starts from its query point
 #pragma unroll
   for (int j = 0; j < NQ; ++j) {
     s.off[j] = a.kappa * g.sig * a.xq[j];
@@ -118,7 +119,7 @@ __device__ __forceinline__ void trig_quad_state(const RayG& g, const TrigLInv<NH
     s.y[j] = kTrigSpan * warp_abs(s.t[j], tn);
     const float r = (s.t[j] - g.mu) * fast_rcp(g.sig);
     s.sr[j] = s.cl[j] ? exp_neg_half(r * r) : a.eq[j];
-    s.F[j] = trig_canon<NH>(L, s.y[j], a.beta, tc[j]);
+    s.F[j] = trig_canon<NH>(L, s.y[j], a.beta, tc[j], &start);
     const float tj = m0 * s.F[j];
     const bool up = j == 0 || tj > s.tau[j > 0 ? j - 1 : 0];
     s.tau[j] = up ? tj : s.tau[j > 0 ? j - 1 : 0];

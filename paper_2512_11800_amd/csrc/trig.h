@@ -284,8 +284,9 @@ __device__ __forceinline__ bool cut_before(const CutPoint& z, const CutPoint& w)
 }
 
 // Zeros of the cubic a_0 + a_1 z + a_2 z^2 + a_3 z^3 (complex coefficients):
-// Laguerre's iteration from the query point w (on the circle, never a zero)
-// finds one zero (cubic convergence from almost any start), the quadratic
+// Laguerre's iteration from `start` (the query point w, on the circle and
+// never a zero, or a zero of the previous edge's cubic, which lies near one
+// of this cubic's) finds one zero (cubic convergence from almost any start), the quadratic
 // left after dividing it out is solved in stable form, and every zero gets
 // two Newton steps on the cubic. The Laguerre step is taken as
 //   3 p / (p' +- sqrt(2 (2 p'^2 - 3 p p''))),
@@ -295,7 +296,7 @@ __device__ __forceinline__ bool cut_before(const CutPoint& z, const CutPoint& w)
 // NaN zero). (Durand-Kerner from three fixed points of the circle failed to
 // converge in ten steps on 0.2% of a W1 image's queries, where zeros
 // cluster.)
-__device__ __forceinline__ void cubic_roots(const cfl* a, cfl w, cfl* z) {
+__device__ __forceinline__ void cubic_roots(const cfl* a, cfl start, cfl* z) {
   const cfl ia = cdiv({1.f, 0.f}, a[3]);
   const cfl b0 = cmul(a[0], ia), b1 = cmul(a[1], ia), b2 = cmul(a[2], ia);
   auto p = [&](cfl x) __attribute__((always_inline)) {  // monic cubic
@@ -304,7 +305,7 @@ __device__ __forceinline__ void cubic_roots(const cfl* a, cfl w, cfl* z) {
   auto dp = [&](cfl x) __attribute__((always_inline)) {
     return cadd(cmul(cadd(cfl{3.f * x.re, 3.f * x.im}, cfl{2.f * b2.re, 2.f * b2.im}), x), b1);
   };
-  cfl r = w;
+  cfl r = start;
 #pragma unroll 1
   for (int it = 0; it < 8; ++it) {
     const cfl pz = p(r), d1 = dp(r);
@@ -316,7 +317,10 @@ __device__ __forceinline__ void cubic_roots(const cfl* a, cfl w, cfl* z) {
     if (!(cabs2(den) > 1e-30f)) break;  // a double zero at r (or a non-finite iterate)
     const cfl step = cdiv({3.f * pz.re, 3.f * pz.im}, den);
     r = csub(r, step);
-    if (cabs2(step) < 1e-14f) break;  // converged to float resolution (|r| is about 1)
+    // close enough for the Newton polish below (|r| is about 1); a bound at
+    // float resolution let iterates that stall at the rounding level run all
+    // eight steps (and their wave with them) for no gain in the polished zeros
+    if (cabs2(step) < 1e-10f) break;
   }
   // p(x) = (x - r)(x^2 + c1 x + c0)
   const cfl c1 = cadd(b2, r);
@@ -351,8 +355,12 @@ struct TrigCanon {
   bool b[NH];
   float lam0;
 };
+// start (optional, in and out): the Laguerre start for three moments, the
+// zero it found on return (the zeros move continuously along a Gaussian's
+// edges, so the next edge starts close to one).
 template <int NH>
-__device__ __forceinline__ float trig_canon(const TrigLInv<NH>& L, float psi, float beta, TrigCanon<NH>& out) {
+__device__ __forceinline__ float trig_canon(const TrigLInv<NH>& L, float psi, float beta, TrigCanon<NH>& out,
+                                            cfl* start = nullptr) {
   static_assert(NH == 2 || NH == 3, "the reconstruction is built for two or three complex moments");
   cfl w;
   sincosf(psi, &w.im, &w.re);
@@ -382,7 +390,9 @@ __device__ __forceinline__ float trig_canon(const TrigLInv<NH>& L, float psi, fl
     out.z[0] = cdiv(qq, a[2]);
     out.z[1] = cdiv(a[0], qq);
   } else {
-    cubic_roots(a, w, out.z);
+    const bool warm = start != nullptr && isfinite(start->re) && isfinite(start->im);
+    cubic_roots(a, warm ? *start : w, out.z);
+    if (start) *start = out.z[0];
   }
   const CutPoint cw = cut_point(w);
   out.lam0 = lam0;
@@ -406,9 +416,9 @@ __device__ __forceinline__ float trig_canon(const TrigLInv<NH>& L, float psi, fl
 
 // F = sum_{atoms before w} lambda_i + beta lambda_0 at the query angle psi
 template <int NH>
-__device__ __forceinline__ float trig_F(const TrigLInv<NH>& L, float psi, float beta) {
+__device__ __forceinline__ float trig_F(const TrigLInv<NH>& L, float psi, float beta, cfl* start = nullptr) {
   TrigCanon<NH> c;
-  return trig_canon<NH>(L, psi, beta, c);
+  return trig_canon<NH>(L, psi, beta, c, start);
 }
 
 // Adjoint of F through the moment equations sum_i lambda_i e^{i k theta_i} =
@@ -563,6 +573,7 @@ __device__ __forceinline__ void trig_moment_grads(const RayG& g, float tn, const
 template <int NH, int NQ>
 __device__ __forceinline__ float particle_quadrature_trig(const RayG& g, const TrigLInv<NH>& L, float m0, float tn,
                                                           const RenderArgs& a, QEdges<NQ>& e) {
+  cfl start = {__builtin_nanf(""), 0.f};  // the first edge starts from its query point
 #pragma unroll
   for (int j = 0; j < NQ; ++j) {
     e.off[j] = a.kappa * g.sig * a.xq[j];
@@ -572,7 +583,7 @@ __device__ __forceinline__ float particle_quadrature_trig(const RayG& g, const T
     e.y[j] = kTrigSpan * warp_abs(t, tn);
     const float r = (t - g.mu) * fast_rcp(g.sig);
     e.sj[j] = g.omega * (e.cl[j] ? exp_neg_half(r * r) : a.eq[j]);
-    const float tj = m0 * trig_F<NH>(L, e.y[j], a.beta);
+    const float tj = m0 * trig_F<NH>(L, e.y[j], a.beta, &start);
     e.tau[j] = (j == 0 || tj > e.tau[j > 0 ? j - 1 : 0]) ? tj : e.tau[j > 0 ? j - 1 : 0];
   }
   return quad_sum<NQ>(g, tn, e);
