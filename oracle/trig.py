@@ -61,7 +61,8 @@ optical depth jumps by m~_0 times its weight as it crosses. cut_margin gives
 the distance of the nearest atom to the cut; a result whose queries have an
 atom closer than CUT_BAND is decided by the rounding of its inputs (a float
 rounding of the ray Gaussians, about 3e-7 relative, moved the atoms within
-0.01 rad of the cut by at most 1.5e-4 rad over 1,500 W2 pixels).
+0.01 rad of the cut by at most 1.5e-4 rad over 1,500 pixels of a
+500k-Gaussian 1080p scene).
 """
 from __future__ import annotations
 
