@@ -304,6 +304,76 @@ def cpu_baseline(scene, cams, opts, n_pairs_frame: int, budget_px: int, backward
     return out
 
 
+def w5_surrogate_bench(args):
+    """The learned surrogate at the large batched workload (3M Gaussians in
+    256 clusters, eight 3840x2160 cameras in one launch sequence, K = 6): a
+    network trained on samples harvested from eight 1920x1080 training
+    cameras of the same scene (seed 55), then the eight cameras rendered with
+    the plain path, the tabulated bounds and the tabulated surrogate. Forward
+    only: the per-query surrogate, which the backward through the surrogate
+    uses, needs a list of four queries per pair, about 400 GB for this
+    frame's 8.4e9 pairs, where the tables take 12 GB."""
+    import torch
+
+    import paper_2512_11800_amd as M
+    import workloads as W
+    from paper_2512_11800_amd import surrogate as G
+
+    def say(msg):
+        print(f"[w5 surrogate] {msg}", file=sys.stderr, flush=True)
+
+    torch.cuda.set_device(0)
+    scene, cams, opts = W.w5_large()
+    opts.n_moments = 6
+    train = W.random_cameras(8, 10.0, 1920, 1080, 55)
+    g = M.Gaussians.from_scene(scene, device="cuda:0")
+    ws = M.Workspace("cuda:0")
+    t = time.perf_counter()
+    x, tt, info = G.harvest(g, train, opts, args.harvest, seed=5, ws=ws)
+    torch.cuda.synchronize()
+    say(f"harvest {info} in {time.perf_counter() - t:.1f} s")
+    t = time.perf_counter()
+    theta, packed, losses = G.train(x, tt, steps=args.train_steps, batch=65536, lr=3e-3, lr_final=1e-4,
+                                    log_every=max(1, args.train_steps // 10))
+    torch.cuda.synchronize()
+    say(f"trained {args.train_steps} steps in {time.perf_counter() - t:.1f} s, losses {losses}")
+    del x, tt
+    nodes = args.tab_nodes
+    runs = {"plain": lambda: M.render_forward(g, cams, opts, ws=ws)[0],
+            "tabulated_bounds": lambda: M.render_forward_tabulated(g, cams, opts, None, nodes, ws=ws)[0],
+            "tabulated_surrogate": lambda: M.render_forward_tabulated(g, cams, opts, packed, nodes, ws=ws)[0]}
+    steps, warm = max(1, min(args.steps, 5)), max(1, min(args.warmup, 2))
+    ms, psnr = {}, {}
+    ref = runs["plain"]().clone()
+    for name, fn in runs.items():
+        img = fn()
+        torch.cuda.synchronize()
+        if not bool(torch.isfinite(img).all()):
+            print(json.dumps({"error": f"non-finite W5 image ({name})"}), flush=True)
+            raise SystemExit(3)
+        if name != "plain":
+            mse = ((img.double() - ref.double()) ** 2).mean(dim=(1, 2, 3))
+            psnr[name] = [10 * math.log10(1.0 / float(m)) if float(m) > 0 else math.inf for m in mse]
+        for _ in range(warm):
+            fn()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(steps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        ms[name] = a.elapsed_time(b) / steps
+        say(f"{name}: {ms[name]:.1f} ms for the eight cameras")
+    return {"workload": "3M Gaussians, 256 clusters, SH3, 8 cameras 3840x2160 in one launch sequence, K=6, N=3",
+            "harvest": info, "train_steps": args.train_steps, "tab_nodes": nodes,
+            "ms_fwd_8_cameras": ms, "psnr_vs_plain_db_per_camera": psnr,
+            "min_psnr_vs_plain_db": {k: min(v) for k, v in psnr.items()},
+            "speedup_tabulated_surrogate_vs_plain": ms["plain"] / ms["tabulated_surrogate"],
+            "speedup_tabulated_surrogate_vs_tabulated_bounds": ms["tabulated_bounds"] / ms["tabulated_surrogate"]}
+
+
 def surrogate_bench(args):
     """The learned surrogate on the W2 scene with K=6: harvest training
     samples from plain renders of 32 training cameras, train, and on 8
@@ -533,6 +603,9 @@ def main():
     if args.workload == "w2" and args.mode == "both" and args.k == 4 and not args.no_surrogate:
         # the metric's surrogate-vs-plain leg (K = 6, held-out cameras)
         sur = surrogate_bench(args)
+    if args.workload == "w5" and args.mode == "both" and not args.no_surrogate:
+        # the large workload's surrogate BF16 against the plain reconstruction
+        extra_k["surrogate_w5"] = w5_surrogate_bench(args)
     cpu = None
     if not args.no_cpu_baseline and args.workload == "w2":
         cpu = cpu_baseline(scene, cams, opts, n_pairs, args.cpu_sample_px, "fwdbwd" in res["modes"])
