@@ -209,7 +209,7 @@ def gpu_bench(args):
         kms = raw[0] / max(1, raw[1])
         ach = flops * n_pairs / (kms * 1e-3) / 1e12
         traffic = None
-        if args.workload == "w2" and args.k == 4 and getattr(args, "basis", "power") == "power":
+        if args.workload == "w2" and getattr(args, "basis", "power") == "power":
             traffic = _measured_traffic(profiled_name)
         return {"bound": "alu", "kernel": kernel, "achieved": ach, "peak": PEAK_FP32_VALU_TFLOPS,
                 "unit": "TFLOP/s", "frac": ach / PEAK_FP32_VALU_TFLOPS, "traffic": traffic,
