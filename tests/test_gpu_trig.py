@@ -74,6 +74,27 @@ def test_trig_single_colour_scene_is_exact():
     assert np.abs(img[0].reshape(-1, 3)[ok] - expect[ok]).max() < 2e-6
 
 
+def test_trig_ragged_camera_batch_equals_each_camera_alone():
+    """Two cameras at 100x75 (a ragged tail in both axes) in one launch, K = 6:
+    each batched image equals the camera rendered alone, bit for bit, and the
+    oracle within the forward bar."""
+    scene, _, opts = W.w1_small()
+    opts.basis = "trigonometric"
+    opts.n_moments = 6
+    cams = [W.camera_on_axis(3.0, 100, 75),
+            W.camera_look_at((2.0, 1.0, -2.5), (0, 0, 0), (0, 1, 0), 100, 75)]
+    batch, bsaved, _ = gpu_render(scene, cams, opts)
+    for i, cam in enumerate(cams):
+        single, ssaved, _ = gpu_render(scene, [cam], opts)
+        assert np.array_equal(batch[i], single[0])
+        assert np.array_equal(bsaved[i], ssaved[0])
+        tol_m, tol_o = tolerances(proxy_error(scene, cam, opts))
+        ref = oracle.render_image(scene, cam, opts, margin_tol=tol_m, orient_eps=tol_o)
+        mx, _ = compare(single[0].reshape(-1, 3), ref, f"trig ragged 100x75 camera {i}", max_excluded=0.01,
+                        gpu_saved=ssaved[0].reshape(-1, 8))
+        assert mx <= TOL
+
+
 def _trig_grads(scene, cams, opts, g_img):
     from tests.test_gpu_backward import _gpu_grads
     return _gpu_grads(scene, cams, opts, g_img)
