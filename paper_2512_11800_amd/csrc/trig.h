@@ -289,7 +289,9 @@ __device__ __forceinline__ bool cut_before(const CutPoint& z, const CutPoint& w)
 // never a zero, or a zero of the previous edge's cubic, which lies near one
 // of this cubic's) finds one zero (cubic convergence from almost any
 // start), the quadratic left after dividing it out is solved in stable
-// form, and every zero gets two Newton steps on the cubic. The Laguerre
+// form, and every zero gets one Newton step on the cubic (the Laguerre zero
+// leaves its loop converged, and one step takes a deflated zero from the
+// rounding of the division to that of the cubic). The Laguerre
 // step is taken as
 //   3 p / (p' +- sqrt(2 (2 p'^2 - 3 p p''))),
 // its usual form multiplied through by p, so that nothing divides by p: at a
@@ -336,11 +338,8 @@ __device__ __forceinline__ void cubic_roots(const cfl* a, cfl start, cfl* z) {
   z[2] = cabs2(q) > 1e-30f ? cdiv(c0, q) : cfl{0.f, 0.f};
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-#pragma unroll
-    for (int s2 = 0; s2 < 2; ++s2) {
-      const cfl d = dp(z[i]);
-      if (cabs2(d) > 1e-30f) z[i] = csub(z[i], cdiv(p(z[i]), d));
-    }
+    const cfl d = dp(z[i]);
+    if (cabs2(d) > 1e-30f) z[i] = csub(z[i], cdiv(p(z[i]), d));
   }
 }
 
