@@ -429,73 +429,116 @@ __device__ __forceinline__ float trig_F(const TrigLInv<NH>& L, float psi, float 
 // with Lambda(theta_i) = [atom i before w], Lambda'(theta_i) = 0 (i = 1..n)
 // and Lambda(psi) = beta gives dF/d(c_0, Re c_1, Im c_1, .., Re c_n, Im c_n)
 // = g, and dF/dpsi = -lambda_0 Lambda'(psi) (differentiate sum_i lambda_i
-// Lambda(theta_i) = sum_k g_k c_k). The (2n + 1) x (2n + 1) system is solved
-// by Gaussian elimination with partial pivoting; a singular one (coincident
-// atoms) passes no gradient.
+// Lambda(theta_i) = sum_k g_k c_k). The system is solved in closed form on
+// the unit circle: with z = e^{i theta}, Q(z) = z^n Lambda(theta) is the
+// complex polynomial of degree 2n with Q(z_i) = f_i z_i^n and
+// Q'(z_i) = n f_i z_i^(n-1) (f_i the flag; Lambda'(theta_i) = 0 is
+// z Q'(z) = n Q(z) there) and Q(w) = beta w^n. As for the power moments,
+// Q = A + C P with P(z) = prod_i (z - z_i)^2, C = (beta w^n - A(w)) / P(w),
+// and A the Hermite interpolant of the atoms' data: 0 (no flag set), z^n (all
+// set), or built on the lone atom s of the minority side, A = R_s (one flag
+// set) or z^n - R_s (all but one), where R_s(z) = q(z)^2 (u + v (z - s))
+// vanishes to second order at the other atoms (q(z) = prod_{j != s} (z - z_j))
+// and matches z^n to first order at s: u = s^n / q(s)^2,
+// v = s^(n-1) (n - 2 s q'(s) / q(s)) / q(s)^2. Lambda is real, so its
+// coefficients are read off the upper half of Q:
+// g_0 = Re Q_n, g_{2k-1} = 2 Re Q_{n+k}, g_{2k} = -2 Im Q_{n+k}.
+// Coincident nodes (a singular system) pass no gradient.
 template <int NH>
 __device__ __forceinline__ void trig_adjoint(float psi, const TrigCanon<NH>& c, float beta, float* g,
                                              float& dF_dpsi) {
-  constexpr int M = 2 * NH + 1;
-  float M_[M][M + 1];
+  static_assert(NH == 2 || NH == 3, "the adjoint is built for two or three complex moments");
   cfl w;
   sincosf(psi, &w.im, &w.re);
-  // row 0: the query; rows 1..n: the atoms' values; rows n+1..2n: their slopes
-  auto fill_value = [&](int r, cfl z, float rhs) __attribute__((always_inline)) {
-    cfl zk = z;
-    M_[r][0] = 1.f;
-#pragma unroll
-    for (int k = 1; k <= NH; ++k) {
-      M_[r][2 * k - 1] = zk.re;
-      M_[r][2 * k] = zk.im;
-      zk = cmul(zk, z);
-    }
-    M_[r][M] = rhs;
-  };
-  fill_value(0, w, beta);
+  cfl z[NH];
+  int cnt = 0;
 #pragma unroll
   for (int i = 0; i < NH; ++i) {
     const float nz = rsqrtf(fmaxf(cabs2(c.z[i]), 1e-30f));
-    const cfl z = {c.z[i].re * nz, c.z[i].im * nz};
-    fill_value(1 + i, z, c.b[i] ? 1.f : 0.f);
-    cfl zk = z;
-    const int r = 1 + NH + i;
-    M_[r][0] = 0.f;
-#pragma unroll
-    for (int k = 1; k <= NH; ++k) {
-      M_[r][2 * k - 1] = -(float)k * zk.im;  // d/dtheta cos k theta
-      M_[r][2 * k] = (float)k * zk.re;       // d/dtheta sin k theta
-      zk = cmul(zk, z);
-    }
-    M_[r][M] = 0.f;
+    z[i] = {c.z[i].re * nz, c.z[i].im * nz};
+    cnt += c.b[i] ? 1 : 0;
   }
-  bool ok = true;
-#pragma unroll
-  for (int col = 0; col < M; ++col) {
-#pragma unroll
-    for (int r = col + 1; r < M; ++r) {
-      const bool sw = fabsf(M_[r][col]) > fabsf(M_[col][col]);
-#pragma unroll
-      for (int k = col; k <= M; ++k) {
-        const float t = M_[col][k];
-        M_[col][k] = sw ? M_[r][k] : t;
-        M_[r][k] = sw ? t : M_[r][k];
-      }
-    }
-    ok = ok && fabsf(M_[col][col]) > 1e-7f;
-    const float ip = ok ? fast_rcp(M_[col][col]) : 0.f;
-#pragma unroll
-    for (int r = col + 1; r < M; ++r) {
-      const float f = M_[r][col] * ip;
-#pragma unroll
-      for (int k = col + 1; k <= M; ++k) M_[r][k] = fmaf(-f, M_[col][k], M_[r][k]);
-    }
+  // A = s0 z^n + s1 R_s; the lone atom carries the flag `want`
+  const float s1 = cnt == 1 ? 1.f : ((NH == 3 && cnt == 2) ? -1.f : 0.f);
+  const float s0 = (cnt == NH || s1 < 0.f) ? 1.f : 0.f;
+  const bool want = cnt == 1;
+  const cfl w2 = cmul(w, w);
+  const cfl wn = NH == 2 ? w2 : cmul(w2, w);
+  cfl Qn, Qh[NH];  // Q_n and Q_{n+1}, .., Q_{2n}
+  bool ok;
+  if constexpr (NH == 2) {
+    const bool l1 = c.b[1] == want && c.b[0] != want;  // lone atom z_1 (else z_0)
+    const cfl s = l1 ? z[1] : z[0], a = l1 ? z[0] : z[1];
+    // q(z) = z - a; u = s^2 / q(s)^2, v = -2 a s / q(s)^3
+    const cfl qs = csub(s, a);
+    const bool okq = s1 == 0.f || cabs2(qs) > 1e-20f;
+    const cfl iq = okq && s1 != 0.f ? cdiv({1.f, 0.f}, qs) : cfl{0.f, 0.f};
+    const cfl iq2 = cmul(iq, iq);
+    const cfl u = cmul(cmul(s, s), iq2);
+    const cfl v = cmul(cmul(cmul(a, s), {-2.f * iq2.re, -2.f * iq2.im}), iq);
+    const cfl up = csub(u, cmul(v, s));  // R(z) = (z - a)^2 (up + v z)
+    const cfl R2 = csub(up, cmul(cfl{2.f * a.re, 2.f * a.im}, v)), R3 = v;
+    const cfl wa = csub(w, a);
+    const cfl Rw = cmul(cmul(wa, wa), cadd(up, cmul(v, w)));
+    // p(z) = (z - z_0)(z - z_1) = z^2 + p1 z + p0, P = p^2
+    const cfl p1 = {-(z[0].re + z[1].re), -(z[0].im + z[1].im)}, p0 = cmul(z[0], z[1]);
+    const cfl pw = cmul(csub(w, z[0]), csub(w, z[1]));
+    const cfl Pw = cmul(pw, pw);
+    ok = okq && cabs2(pw) > 1e-20f;
+    const cfl Aw = {s0 * wn.re + s1 * Rw.re, s0 * wn.im + s1 * Rw.im};
+    const cfl C = ok ? cdiv(csub({beta * wn.re, beta * wn.im}, Aw), Pw) : cfl{0.f, 0.f};
+    const cfl P2 = cadd(cmul(p1, p1), {2.f * p0.re, 2.f * p0.im}), P3 = {2.f * p1.re, 2.f * p1.im};
+    Qn = cadd({s0 + s1 * R2.re, s1 * R2.im}, cmul(C, P2));
+    Qh[0] = cadd({s1 * R3.re, s1 * R3.im}, cmul(C, P3));
+    Qh[1] = C;
+  } else {
+    const bool l1 = c.b[1] == want && c.b[0] != want && c.b[2] != want;
+    const bool l2 = c.b[2] == want && c.b[0] != want && c.b[1] != want;
+    // (s, a, b) = (z0, z1, z2), (z1, z0, z2) or (z2, z0, z1)
+    const cfl s = l1 ? z[1] : (l2 ? z[2] : z[0]);
+    const cfl a = (l1 || l2) ? z[0] : z[1];
+    const cfl b = l2 ? z[1] : z[2];
+    // q(z) = (z - a)(z - b) = z^2 + q1 z + q0
+    const cfl q1 = {-(a.re + b.re), -(a.im + b.im)}, q0 = cmul(a, b);
+    const cfl qs = cmul(csub(s, a), csub(s, b));
+    const bool okq = s1 == 0.f || cabs2(qs) > 1e-20f;
+    const cfl iq = okq && s1 != 0.f ? cdiv({1.f, 0.f}, qs) : cfl{0.f, 0.f};
+    const cfl iq2 = cmul(iq, iq);
+    const cfl ss = cmul(s, s);
+    const cfl u = cmul(cmul(ss, s), iq2);
+    // v = s^2 (3 q(s) - 2 s (2 s + q1)) / q(s)^3  (q'(s) = 2 s + q1)
+    const cfl t = csub({3.f * qs.re, 3.f * qs.im}, cmul({2.f * s.re, 2.f * s.im}, cadd({2.f * s.re, 2.f * s.im}, q1)));
+    const cfl v = cmul(cmul(ss, t), cmul(iq2, iq));
+    const cfl up = csub(u, cmul(v, s));  // R(z) = q(z)^2 (up + v z)
+    // q^2 = z^4 + 2 q1 z^3 + (q1^2 + 2 q0) z^2 + ..
+    const cfl q2c2 = cadd(cmul(q1, q1), {2.f * q0.re, 2.f * q0.im}), q2c3 = {2.f * q1.re, 2.f * q1.im};
+    const cfl R3 = cadd(cmul(up, q2c3), cmul(v, q2c2));
+    const cfl R4 = cadd(up, cmul(v, q2c3));
+    const cfl R5 = v;
+    const cfl qw = cmul(csub(w, a), csub(w, b));
+    const cfl Rw = cmul(cmul(qw, qw), cadd(up, cmul(v, w)));
+    // p(z) = (z - z_0)(z - z_1)(z - z_2) = z^3 + p2 z^2 + p1 z + p0, P = p^2
+    const cfl p2 = {-(z[0].re + z[1].re + z[2].re), -(z[0].im + z[1].im + z[2].im)};
+    const cfl z01 = cmul(z[0], z[1]);
+    const cfl p1 = cadd(z01, cmul(cadd(z[0], z[1]), z[2]));
+    const cfl p0 = {-cmul(z01, z[2]).re, -cmul(z01, z[2]).im};
+    const cfl pw = cmul(cmul(csub(w, z[0]), csub(w, z[1])), csub(w, z[2]));
+    const cfl Pw = cmul(pw, pw);
+    ok = okq && cabs2(pw) > 1e-20f;
+    const cfl Aw = {s0 * wn.re + s1 * Rw.re, s0 * wn.im + s1 * Rw.im};
+    const cfl C = ok ? cdiv(csub({beta * wn.re, beta * wn.im}, Aw), Pw) : cfl{0.f, 0.f};
+    const cfl P3 = {2.f * (p0.re + (p1.re * p2.re - p1.im * p2.im)), 2.f * (p0.im + (p1.re * p2.im + p1.im * p2.re))};
+    const cfl P4 = cadd(cmul(p2, p2), {2.f * p1.re, 2.f * p1.im}), P5 = {2.f * p2.re, 2.f * p2.im};
+    Qn = cadd({s0 + s1 * R3.re, s1 * R3.im}, cmul(C, P3));
+    Qh[0] = cadd({s1 * R4.re, s1 * R4.im}, cmul(C, P4));
+    Qh[1] = cadd({s1 * R5.re, s1 * R5.im}, cmul(C, P5));
+    Qh[2] = C;
   }
+  g[0] = ok ? Qn.re : 0.f;
 #pragma unroll
-  for (int r = M - 1; r >= 0; --r) {
-    float v = M_[r][M];
-#pragma unroll
-    for (int k = r + 1; k < M; ++k) v = fmaf(-M_[r][k], g[k], v);
-    g[r] = ok ? v * fast_rcp(M_[r][r]) : 0.f;
+  for (int k = 1; k <= NH; ++k) {
+    g[2 * k - 1] = ok ? 2.f * Qh[k - 1].re : 0.f;
+    g[2 * k] = ok ? -2.f * Qh[k - 1].im : 0.f;
   }
   float dl = 0.f;
   cfl wk = w;
